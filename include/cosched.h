@@ -1,0 +1,298 @@
+/*
+ * cosched.h -- C ABI of the memory-safe GPU co-scheduler for one MI355X (gfx950).
+ *
+ * The scheduler decides which queued jobs may share the GPU so that the sum
+ * of their declared memory demands never exceeds the device memory it
+ * manages, then serves the admitted jobs (Reano, Silla, Nikolopoulos,
+ * Varghese, "Intra-node Memory Safe GPU Co-Scheduling", IEEE TPDS 2017).
+ * The life-cycle calls follow Sec. II and Sec. IV of the paper:
+ *   initialisation -> sched_create + sched_register
+ *   pre-allocation -> sched_admit (+ sched_wait when it has to wait)
+ *   post-free      -> sched_release
+ *   shutdown       -> sched_release(job, -1, 0) / sched_destroy
+ * The waiting queue is served by one of the notification policies of Sec. V.
+ *
+ * Conventions for every call below:
+ *   - the return value is a status code (SCHED_OK or one of the codes below);
+ *     no C++ exception crosses this boundary;
+ *   - out-parameters are written only when SCHED_OK is returned (unless a
+ *     call states otherwise);
+ *   - "device pointer" means memory on the context's GPU (hipMalloc or a
+ *     torch CUDA tensor); "host pointer" means ordinary process memory;
+ *   - a sched_stream_t is a hipStream_t of the context's device; NULL means
+ *     the context's own stream.  Stream-ordered calls enqueue work and return
+ *     before it finishes unless they say they synchronise;
+ *   - every call taking a sched_ctx_t* is thread-safe per context (one mutex);
+ *     calls on one context are serialised in the order they take the mutex.
+ *   - all byte counts are int64, all demands are positive multiples of 1 B;
+ *     the largest capacity a context accepts is 2^46 - 2 bytes.
+ */
+#ifndef COSCHED_H
+#define COSCHED_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ------------------------------------------------------ */
+#define SCHED_OK 0
+#define SCHED_NOT_READY 1   /* request queued, not admitted yet (Sec. IV: the
+                               non-blocking pre-allocation result)           */
+#define SCHED_TIMEOUT 2     /* blocking wait exceeded the job's timeout; the
+                               request was withdrawn and is never admitted   */
+#define SCHED_E_INVALID (-1) /* bad handle, device, size, or a release/free of
+                                memory the job does not hold (Sec. IV checks) */
+#define SCHED_E_TOOBIG (-2)  /* demand larger than the whole capacity        */
+#define SCHED_E_QUOTA (-3)   /* allocation beyond the job's reservation      */
+#define SCHED_E_NOMEM (-4)   /* sub-allocator pool or class exhausted        */
+#define SCHED_E_INTERNAL (-5) /* HIP runtime failure (the paper's "unknown") */
+
+/* ---- notification policies (Sec. V) ------------------------------------ */
+#define SCHED_POLICY_FIFO 0       /* Policy 1: serve in queue order, stop at the first
+                              waiting request that does not fit              */
+#define SCHED_POLICY_MMU 1        /* Policy 2: serve, in queue order, every request
+                              that fits the memory still free (first-fit)    */
+#define SCHED_POLICY_PRIO_FIFO 2  /* Policy 3: FIFO over (priority, arrival) order  */
+#define SCHED_POLICY_PRIO_MMU 3   /* Policy 4: MMU over (priority, arrival) order   */
+
+/* sched_admit flags */
+#define SCHED_NONBLOCK 1u  /* return SCHED_NOT_READY instead of waiting      */
+
+typedef struct sched_ctx sched_ctx_t;
+typedef int32_t sched_job_t;
+typedef void *sched_stream_t;
+
+typedef struct {
+  int32_t device;          /* HIP device ordinal                               */
+  int32_t policy;          /* SCHED_POLICY_FIFO .. SCHED_POLICY_PRIO_MMU                     */
+  int64_t capacity_bytes;  /* managed memory; 0 = free device memory minus
+                              headroom_bytes at creation                       */
+  int64_t headroom_bytes;  /* kept back when capacity_bytes == 0               */
+  int64_t slab_pool_bytes; /* slab sub-allocator pool; 0 = no pool            */
+  int32_t max_jobs;        /* job handles [0, max_jobs)                        */
+  int32_t max_tenants;     /* slab tenants with their own quota; 0 = max_jobs */
+  int64_t queue_capacity;  /* pending requests the device queue holds         */
+  int32_t window_limit;    /* windows of 4096 entries the single-workgroup
+                              admission kernel scans before the grid-wide
+                              round kernel takes over; 0 = 16                  */
+  int32_t flags;           /* reserved, 0                                      */
+} sched_config_t;
+
+typedef struct {
+  int64_t capacity;        /* bytes managed                                    */
+  int64_t used;            /* sum of reservations of running jobs (Sec. III-B) */
+  int64_t pending;         /* requests waiting in the queue                    */
+  int64_t running;         /* jobs holding a reservation                       */
+  int64_t passes;          /* admission passes run                             */
+  int64_t rounds;          /* first-fit rounds run (all passes)                */
+  int64_t admitted;        /* requests admitted (all passes)                   */
+  int64_t released_bytes;  /* bytes released (all calls)                       */
+  int64_t withdrawn;       /* requests withdrawn after a timeout               */
+  int64_t violations;      /* allocation failures inside a job's reservation   */
+  int64_t slab_pool_used;  /* bytes charged to the slab pool                   */
+  int64_t last_pass_us_x1000; /* last pass, host-measured, in ns               */
+} sched_stats_t;
+
+/* Result of one admission pass. */
+typedef struct {
+  int64_t admitted;        /* requests admitted by this pass                   */
+  int64_t admitted_bytes;  /* their total demand                               */
+  int64_t free_before;     /* R at the start of the pass                       */
+  int64_t free_after;      /* R at the end: free_before - admitted_bytes       */
+  int64_t rounds;          /* first-fit rounds (1 for FIFO)                    */
+  int64_t scanned;         /* queue entries the pass decided                   */
+  int64_t pending_after;   /* requests still waiting                           */
+} sched_pass_result_t;
+
+/* ======================================================================== */
+/* Life cycle (Sec. II, Sec. IV)                                             */
+/* ======================================================================== */
+
+/* Initialisation of the shared state (Sec. IV "Initialisation"): the context
+ * owns the device-resident state -- capacity, used bytes, per-job
+ * reservations and the waiting queue (Sec. III-B) -- and, if requested, the
+ * slab pool.  cfg is read, not kept.  On success *out owns every resource
+ * until sched_destroy.  Errors: SCHED_E_INVALID for a bad cfg,
+ * SCHED_E_INTERNAL if a HIP allocation fails. */
+int sched_create(const sched_config_t *cfg, sched_ctx_t **out);
+
+/* Shutdown (Sec. IV "Shutdown"): waits for the context's stream, releases
+ * every reservation and frees all device memory.  ctx is invalid afterwards.
+ * Pointers returned by sched_alloc become invalid. */
+int sched_destroy(sched_ctx_t *ctx);
+
+/* schedGPUInit(timeout, priority) of Sec. IV: a new job handle with its
+ * priority (lower value = higher priority; default 0) and the timeout in ms
+ * a blocking pre-allocation waits (default 60000).  Errors: SCHED_E_INVALID
+ * when max_jobs handles exist. */
+int sched_register(sched_ctx_t *ctx, int32_t priority, int32_t timeout_ms, sched_job_t *out_job);
+
+/* Registers n jobs with consecutive handles *out_first .. *out_first + n - 1. */
+int sched_register_batch(sched_ctx_t *ctx, int32_t n, int32_t priority, int32_t timeout_ms,
+                         sched_job_t *out_first);
+
+/* Pre-allocation (Sec. IV): checks the device and the size, queues the
+ * request behind the waiting ones, runs one admission pass of the context's
+ * policy over the whole queue (Sec. V) and reports whether THIS request was
+ * admitted.  A request larger than the capacity is refused with
+ * SCHED_E_TOOBIG and never queued.  With SCHED_NONBLOCK a request that has
+ * to wait returns SCHED_NOT_READY and stays queued (sched_wait can wait for
+ * it later); without the flag the call waits up to the job's timeout like
+ * sched_wait.  Errors: SCHED_E_INVALID (unknown job, device != the
+ * context's device, bytes <= 0), SCHED_E_INTERNAL. */
+int sched_admit(sched_ctx_t *ctx, sched_job_t job, int32_t device, int64_t bytes, uint32_t flags);
+
+/* Blocks until every queued request of job is admitted (SCHED_OK) or
+ * timeout_ms passes (SCHED_TIMEOUT; timeout_ms < 0 uses the job's own
+ * timeout).  On timeout the job's waiting requests are withdrawn under the
+ * context mutex, so a request is either admitted or withdrawn, never both.
+ * SCHED_OK is returned at once when nothing of the job is waiting. */
+int sched_wait(sched_ctx_t *ctx, sched_job_t job, int32_t timeout_ms);
+
+/* Post-free (Sec. IV; postCudaFree(device, bytes)): returns bytes of the
+ * job's reservation; bytes == 0 returns all of it; device < 0 means every
+ * device.  Does not free GPU memory -- accounting only -- then runs one
+ * admission pass to serve waiting requests.  Errors: SCHED_E_INVALID when
+ * bytes exceeds the job's reservation, bytes < 0 or the device is not the
+ * context's; nothing changes on error. */
+int sched_release(sched_ctx_t *ctx, sched_job_t job, int32_t device, int64_t bytes);
+
+/* Counters; see sched_stats_t. */
+int sched_stats(sched_ctx_t *ctx, sched_stats_t *out);
+
+/* The job's current reservation in bytes (host pointer out). */
+int sched_reservation(sched_ctx_t *ctx, sched_job_t job, int64_t *out_bytes);
+
+/* ======================================================================== */
+/* Device-batched admission (the same state, driven with device arrays)     */
+/* ======================================================================== */
+
+/* Request intake: appends n requests (device arrays d_job[n], d_demand[n],
+ * arrival order) at the queue tail, stream-ordered.  Every job must be
+ * registered and every demand in [1, capacity]; the queue must have room.
+ * Synchronises the stream to validate the batch; SCHED_E_INVALID on a bad
+ * batch (nothing is appended). */
+int sched_enqueue_batch(sched_ctx_t *ctx, int64_t n, const int32_t *d_job, const int64_t *d_demand,
+                        sched_stream_t stream);
+
+/* Runs one admission pass (Sec. V policy of the context) over the waiting
+ * queue and writes the result to *out (host pointer).  The admitted requests
+ * leave the queue (stable order kept for the rest), their demands are added
+ * to their jobs' reservations and to the used total.  Synchronises the
+ * stream.  The admitted jobs, in queue order, can be read with
+ * sched_last_admitted. */
+int sched_pass(sched_ctx_t *ctx, sched_stream_t stream, sched_pass_result_t *out);
+
+/* Copies the job ids admitted by the last pass (queue order) into the
+ * device array d_out[cap]; *out_n receives the count (which may exceed cap:
+ * then only cap ids are copied).  Stream-ordered copy. */
+int sched_last_admitted(sched_ctx_t *ctx, int32_t *d_out, int64_t cap, int64_t *out_n,
+                        sched_stream_t stream);
+
+/* Post-free for many jobs at once: every running job j < n whose byte
+ * d_mask[j] (device array of n bytes) is non-zero returns its whole
+ * reservation (Sec. IV, bytes == 0).  n must not exceed the number of
+ * registered jobs.  No pass runs; call sched_pass afterwards.
+ * Stream-ordered. */
+int sched_release_masked(sched_ctx_t *ctx, const uint8_t *d_mask, int64_t n, sched_stream_t stream);
+
+/* ======================================================================== */
+/* Stateless admission scan over a caller's array                           */
+/* ======================================================================== */
+
+typedef struct {
+  int64_t admitted;        /* entries admitted                                 */
+  int64_t admitted_bytes;  /* their sum                                        */
+  int64_t free_after;      /* R minus admitted_bytes                           */
+  int64_t rounds;          /* rounds run                                       */
+  int64_t last_admitted;   /* index of the last admitted entry, -1 if none     */
+} sched_scan_result_t;
+
+/* Bytes of device workspace sched_scan needs for n entries. */
+size_t sched_scan_workspace_size(int64_t n);
+
+/* One pass of policy SCHED_POLICY_FIFO or SCHED_POLICY_MMU (Sec. V) over d_demand[n]
+ * (device, int64, queue order; an entry < 0 is a withdrawn request that is
+ * skipped) with free memory R (0 <= R <= 2^46 - 2).  Sets d_decision[i] = 1
+ * for every admitted entry and writes 0 to entries it rejects; entries after
+ * the point where the pass stopped are written only when write_all != 0, so
+ * callers that read the whole vector either zero it first or pass
+ * write_all = 1.  d_ws is device workspace of sched_scan_workspace_size(n)
+ * bytes, or NULL to use a workspace the library allocates and keeps for the
+ * device.  The pass runs entirely in the grid-wide round kernel (decoupled
+ * look-back scan); single-workgroup windows are used first when
+ * window_limit > 0.  Synchronises the stream; *out is a host pointer.
+ * Errors: SCHED_E_INVALID for bad sizes, policy or R. */
+int sched_scan(int32_t policy, int64_t n, const int64_t *d_demand, int64_t R, uint8_t *d_decision,
+               int32_t write_all, int32_t window_limit, void *d_ws, size_t ws_bytes,
+               sched_stream_t stream, sched_scan_result_t *out);
+
+/* ======================================================================== */
+/* Quota-checked slab sub-allocator                                          */
+/* ======================================================================== */
+/* Itemised use per client (Sec. III-B) carried down to blocks: every block a
+ * tenant allocates is charged to it (and to the pool), and a free is accepted
+ * only for a live block the tenant holds (the post-free check of Sec. IV).
+ * Classes are powers of two from 256 B to 1 MiB; the pool (cfg
+ * slab_pool_bytes) is split into 13 equal regions of whole MiB, one per class,
+ * so class c holds region_bytes / (256 << c) blocks (class_blocks[c]).
+ * Tenants are jobs unless sched_slab_set_quotas installs explicit quotas; a
+ * job's quota is then its admitted reservation. */
+typedef struct {
+  uint64_t pool_base;       /* device address of region 0                      */
+  int64_t pool_bytes;       /* accounting limit of the pool counter            */
+  int64_t region_bytes;     /* bytes of each class region                      */
+  int64_t class_blocks[13]; /* blocks each class can hold                      */
+  int32_t n_classes;        /* 13                                              */
+  int32_t n_tenants;        /* tenant ids [0, n_tenants)                       */
+} sched_slab_info_t;
+
+/* Allocates bytes for job: <= 1 MiB from the slab (charged the class size),
+ * larger sizes from a separate device allocation charged in 4 KiB pages.  The
+ * charge must fit the job's quota (its reservation): SCHED_E_QUOTA otherwise.
+ * SCHED_E_NOMEM when the pool or the class is exhausted; for a job inside its
+ * quota that is a memory-safety violation and is counted in sched_stats.
+ * *dev_ptr (host pointer to a device address) is written only on SCHED_OK;
+ * the block stays valid until sched_free or sched_destroy.  Synchronises. */
+int sched_alloc(sched_ctx_t *ctx, sched_job_t job, size_t bytes, void **dev_ptr);
+
+/* Returns a block job holds.  A pointer the job does not hold, or a second
+ * free of one block, is SCHED_E_INVALID and changes nothing.  Synchronises. */
+int sched_free(sched_ctx_t *ctx, sched_job_t job, void *dev_ptr);
+
+/* Installs explicit quotas (host array h_quotas[n], bytes >= 0) for tenants
+ * [0, n); tenants >= n get quota 0. */
+int sched_slab_set_quotas(sched_ctx_t *ctx, int32_t n, const int64_t *h_quotas);
+
+/* One phase of concurrent allocator ops [begin, end) on device arrays indexed
+ * by global op index (each holds at least `end` entries): d_kind[i] 0 = alloc
+ * of d_size[i] bytes, 1 = free of the block returned by alloc op d_ref[i]
+ * (which must belong to an earlier phase, i.e. d_ref[i] < begin); d_tenant[i]
+ * the tenant.  Writes d_ptr[i] (the block of a successful alloc, else 0) and
+ * d_status[i]: 0 ok, 1 over quota, 2 pool exhausted, 3 class exhausted,
+ * 4 invalid.  Ops of one call run concurrently in any order.  Stream-ordered. */
+int sched_slab_ops(sched_ctx_t *ctx, int64_t begin, int64_t end, const uint8_t *d_kind,
+                   const int32_t *d_tenant, const int64_t *d_size, const int64_t *d_ref,
+                   uint64_t *d_ptr, int8_t *d_status, sched_stream_t stream);
+
+/* Layout of the pool; *out is a host pointer. */
+int sched_slab_info(sched_ctx_t *ctx, sched_slab_info_t *out);
+
+/* Copies the first n tenants' charged bytes and the pool counter to host
+ * memory (synchronises the context stream first). */
+int sched_slab_counters(sched_ctx_t *ctx, int32_t n, int64_t *h_charged, int64_t *h_pool_used);
+
+/* Frees every block and clears all charges. */
+int sched_slab_reset(sched_ctx_t *ctx);
+
+/* Library version string. */
+const char *sched_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* COSCHED_H */

@@ -1,0 +1,264 @@
+"""Python binding of the co-scheduler C ABI (include/cosched.h).
+
+Argument marshalling only: every function has the name of the C entry point
+it calls, returns the C status code (plus out-values as a tuple), and passes
+device memory as raw pointers taken from torch tensors.  All scheduling work
+runs in the HIP library ``libsched.so``; there is no Python fallback, and the
+first call raises if the library has not been built.
+
+torch is imported before the library is loaded so that the process holds one
+HIP runtime (torch's) and torch tensors/streams are valid in the library.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import torch  # noqa: F401  (must precede the library load)
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libsched.so")
+
+SCHED_OK = 0
+SCHED_NOT_READY = 1
+SCHED_TIMEOUT = 2
+SCHED_E_INVALID = -1
+SCHED_E_TOOBIG = -2
+SCHED_E_QUOTA = -3
+SCHED_E_NOMEM = -4
+SCHED_E_INTERNAL = -5
+
+SCHED_POLICY_FIFO = 0
+SCHED_POLICY_MMU = 1
+SCHED_POLICY_PRIO_FIFO = 2
+SCHED_POLICY_PRIO_MMU = 3
+
+SCHED_NONBLOCK = 1
+
+i32, i64, u32, u64, vp = C.c_int32, C.c_int64, C.c_uint32, C.c_uint64, C.c_void_p
+
+
+class sched_config_t(C.Structure):
+    _fields_ = [("device", i32), ("policy", i32), ("capacity_bytes", i64),
+                ("headroom_bytes", i64), ("slab_pool_bytes", i64), ("max_jobs", i32),
+                ("max_tenants", i32), ("queue_capacity", i64), ("window_limit", i32),
+                ("flags", i32)]
+
+
+class sched_stats_t(C.Structure):
+    _fields_ = [(n, i64) for n in ("capacity", "used", "pending", "running", "passes", "rounds",
+                                   "admitted", "released_bytes", "withdrawn", "violations",
+                                   "slab_pool_used", "last_pass_ns")]
+
+
+class sched_pass_result_t(C.Structure):
+    _fields_ = [(n, i64) for n in ("admitted", "admitted_bytes", "free_before", "free_after",
+                                   "rounds", "scanned", "pending_after")]
+
+
+class sched_scan_result_t(C.Structure):
+    _fields_ = [(n, i64) for n in ("admitted", "admitted_bytes", "free_after", "rounds",
+                                   "last_admitted")]
+
+
+class sched_slab_info_t(C.Structure):
+    _fields_ = [("pool_base", u64), ("pool_bytes", i64), ("region_bytes", i64),
+                ("class_blocks", i64 * 13), ("n_classes", i32), ("n_tenants", i32)]
+
+
+# name -> (restype, argtypes); mirrors include/cosched.h
+_SIGS = {
+    "sched_create": (i32, [C.POINTER(sched_config_t), C.POINTER(vp)]),
+    "sched_destroy": (i32, [vp]),
+    "sched_register": (i32, [vp, i32, i32, C.POINTER(i32)]),
+    "sched_register_batch": (i32, [vp, i32, i32, i32, C.POINTER(i32)]),
+    "sched_admit": (i32, [vp, i32, i32, i64, u32]),
+    "sched_wait": (i32, [vp, i32, i32]),
+    "sched_release": (i32, [vp, i32, i32, i64]),
+    "sched_stats": (i32, [vp, C.POINTER(sched_stats_t)]),
+    "sched_reservation": (i32, [vp, i32, C.POINTER(i64)]),
+    "sched_enqueue_batch": (i32, [vp, i64, vp, vp, vp]),
+    "sched_pass": (i32, [vp, vp, C.POINTER(sched_pass_result_t)]),
+    "sched_last_admitted": (i32, [vp, vp, i64, C.POINTER(i64), vp]),
+    "sched_release_masked": (i32, [vp, vp, i64, vp]),
+    "sched_scan_workspace_size": (C.c_size_t, [i64]),
+    "sched_scan": (i32, [i32, i64, vp, i64, vp, i32, i32, vp, C.c_size_t, vp,
+                         C.POINTER(sched_scan_result_t)]),
+    "sched_alloc": (i32, [vp, i32, C.c_size_t, C.POINTER(vp)]),
+    "sched_free": (i32, [vp, i32, vp]),
+    "sched_slab_set_quotas": (i32, [vp, i32, C.POINTER(i64)]),
+    "sched_slab_ops": (i32, [vp, i64, i64, vp, vp, vp, vp, vp, vp, vp]),
+    "sched_slab_info": (i32, [vp, C.POINTER(sched_slab_info_t)]),
+    "sched_slab_counters": (i32, [vp, i32, C.POINTER(i64), C.POINTER(i64)]),
+    "sched_slab_reset": (i32, [vp]),
+    "sched_version": (C.c_char_p, []),
+}
+
+_lib = None
+
+
+def lib() -> C.CDLL:
+    """Loads libsched.so once; raises when it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"HIP library missing: {LIB_PATH}; run __graft_entry__.build()")
+        h = C.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGS.items():
+            f = getattr(h, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = h
+    return _lib
+
+
+def _ptr(t) -> int | None:
+    if t is None:
+        return None
+    if isinstance(t, int):
+        return t
+    return t.data_ptr()
+
+
+def _stream(s) -> int | None:
+    if s is None:
+        return None
+    if isinstance(s, int):
+        return s
+    return s.cuda_stream
+
+
+# ---------------------------------------------------------------- life cycle
+def sched_create(device=0, policy=SCHED_POLICY_MMU, capacity_bytes=0, headroom_bytes=0,
+                 slab_pool_bytes=0, max_jobs=1024, max_tenants=0, queue_capacity=1 << 16,
+                 window_limit=0):
+    cfg = sched_config_t(device, policy, capacity_bytes, headroom_bytes, slab_pool_bytes,
+                         max_jobs, max_tenants, queue_capacity, window_limit, 0)
+    out = vp()
+    rc = lib().sched_create(C.byref(cfg), C.byref(out))
+    return rc, out.value
+
+
+def sched_destroy(ctx):
+    return lib().sched_destroy(ctx)
+
+
+def sched_register(ctx, priority=0, timeout_ms=60000):
+    j = i32()
+    rc = lib().sched_register(ctx, priority, timeout_ms, C.byref(j))
+    return rc, j.value
+
+
+def sched_register_batch(ctx, n, priority=0, timeout_ms=60000):
+    j = i32()
+    rc = lib().sched_register_batch(ctx, n, priority, timeout_ms, C.byref(j))
+    return rc, j.value
+
+
+def sched_admit(ctx, job, device, nbytes, flags=0):
+    return lib().sched_admit(ctx, job, device, nbytes, flags)
+
+
+def sched_wait(ctx, job, timeout_ms=-1):
+    return lib().sched_wait(ctx, job, timeout_ms)
+
+
+def sched_release(ctx, job, device=-1, nbytes=0):
+    return lib().sched_release(ctx, job, device, nbytes)
+
+
+def sched_stats(ctx):
+    s = sched_stats_t()
+    rc = lib().sched_stats(ctx, C.byref(s))
+    return rc, {k: getattr(s, k) for k, _ in sched_stats_t._fields_}
+
+
+def sched_reservation(ctx, job):
+    v = i64()
+    rc = lib().sched_reservation(ctx, job, C.byref(v))
+    return rc, v.value
+
+
+# ---------------------------------------------------------- device batched
+def sched_enqueue_batch(ctx, d_job, d_demand, stream=None):
+    n = 0 if d_job is None else int(d_job.numel())
+    return lib().sched_enqueue_batch(ctx, n, _ptr(d_job), _ptr(d_demand), _stream(stream))
+
+
+def sched_pass(ctx, stream=None):
+    r = sched_pass_result_t()
+    rc = lib().sched_pass(ctx, _stream(stream), C.byref(r))
+    return rc, {k: getattr(r, k) for k, _ in sched_pass_result_t._fields_}
+
+
+def sched_last_admitted(ctx, d_out, stream=None):
+    n = i64()
+    cap = 0 if d_out is None else int(d_out.numel())
+    rc = lib().sched_last_admitted(ctx, _ptr(d_out), cap, C.byref(n), _stream(stream))
+    return rc, n.value
+
+
+def sched_release_masked(ctx, d_mask, stream=None):
+    n = 0 if d_mask is None else int(d_mask.numel())
+    return lib().sched_release_masked(ctx, _ptr(d_mask), n, _stream(stream))
+
+
+# ---------------------------------------------------------- stateless scan
+def sched_scan_workspace_size(n):
+    return int(lib().sched_scan_workspace_size(n))
+
+
+def sched_scan(policy, d_demand, R, d_decision, write_all=0, window_limit=0, d_ws=None,
+               ws_bytes=0, stream=None):
+    r = sched_scan_result_t()
+    n = int(d_demand.numel())
+    rc = lib().sched_scan(policy, n, _ptr(d_demand), int(R), _ptr(d_decision), write_all,
+                          window_limit, _ptr(d_ws), ws_bytes, _stream(stream), C.byref(r))
+    return rc, {k: getattr(r, k) for k, _ in sched_scan_result_t._fields_}
+
+
+# ---------------------------------------------------------- slab allocator
+def sched_alloc(ctx, job, nbytes):
+    p = vp()
+    rc = lib().sched_alloc(ctx, job, nbytes, C.byref(p))
+    return rc, p.value
+
+
+def sched_free(ctx, job, ptr):
+    return lib().sched_free(ctx, job, ptr)
+
+
+def sched_slab_set_quotas(ctx, quotas):
+    arr = (i64 * len(quotas))(*[int(q) for q in quotas])
+    return lib().sched_slab_set_quotas(ctx, len(quotas), arr)
+
+
+def sched_slab_ops(ctx, begin, end, d_kind, d_tenant, d_size, d_ref, d_ptr, d_status, stream=None):
+    for t in (d_kind, d_tenant, d_size, d_ref, d_ptr, d_status):
+        if t.numel() < end:
+            raise ValueError("op arrays must hold at least `end` entries")
+    return lib().sched_slab_ops(ctx, begin, end, _ptr(d_kind), _ptr(d_tenant), _ptr(d_size),
+                                _ptr(d_ref), _ptr(d_ptr), _ptr(d_status), _stream(stream))
+
+
+def sched_slab_info(ctx):
+    r = sched_slab_info_t()
+    rc = lib().sched_slab_info(ctx, C.byref(r))
+    return rc, {"pool_base": r.pool_base, "pool_bytes": r.pool_bytes,
+                "region_bytes": r.region_bytes, "class_blocks": list(r.class_blocks),
+                "n_classes": r.n_classes, "n_tenants": r.n_tenants}
+
+
+def sched_slab_counters(ctx, n):
+    arr = (i64 * max(n, 1))()
+    pool = i64()
+    rc = lib().sched_slab_counters(ctx, n, arr, C.byref(pool))
+    return rc, [arr[i] for i in range(n)], pool.value
+
+
+def sched_slab_reset(ctx):
+    return lib().sched_slab_reset(ctx)
+
+
+def sched_version():
+    return lib().sched_version().decode()

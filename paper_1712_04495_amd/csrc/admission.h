@@ -1,0 +1,116 @@
+// Admission engine: device-resident pass state and the host driver that runs
+// one pass of the FIFO or first-fit (MMU) policy over an int64 demand array.
+#pragma once
+
+#include "common.h"
+
+namespace schedk {
+
+// Window kernel: one workgroup, 1024 threads x 4 entries.
+constexpr int WIN_THREADS = 1024;
+constexpr int WIN_ITEMS = 4;
+constexpr int WIN = WIN_THREADS * WIN_ITEMS;
+// Round kernel: 256 threads x 16 entries per tile.
+constexpr int RND_THREADS = 256;
+constexpr int RND_ITEMS = 16;
+constexpr int TILE = RND_THREADS * RND_ITEMS;
+
+// Largest free-memory value a pass accepts: R + 1 must fit the 46-bit value
+// field of a look-back flag word.
+constexpr int64_t MAX_FREE = (int64_t(1) << 46) - 2;
+
+// The state a pass carries from one launch to the next.  Launch L reads
+// rec[L & 3] and its epilogue writes rec[(L + 1) & 3], so workgroups of L that
+// start late never see the next round's parameters.
+struct RoundRec {
+  int64_t R;       // free memory at the start of the round
+  int64_t start;   // first undecided queue position
+  int32_t done;    // pass finished
+  int32_t pad;
+};
+
+struct DevCtl {
+  // scheduler state (persistent across passes)
+  int64_t capacity;
+  int64_t used;
+  int64_t head;            // first live queue position
+  int64_t tail;            // one past the last live queue position
+  int64_t released_bytes;
+  int64_t released_jobs;
+  // totals of the current pass
+  int64_t p_admitted;
+  int64_t p_admitted_bytes;
+  int64_t p_hi;            // last admitted position + 1 (max over rounds)
+  int64_t p_rounds;
+  int64_t p_R0;
+  int64_t p_end;           // end position of the pass
+  int32_t filter;          // 1: first-fit (MMU) rounds, 0: FIFO
+  int32_t pad;
+  RoundRec rec[4];
+  unsigned long long ticket[4];
+  long long break_tile[4];
+};
+
+struct AdmEngine {
+  DevCtl *d_ctl = nullptr;
+  DevCtl *h_ctl = nullptr;          // pinned host mirror
+  unsigned long long *d_flags = nullptr;
+  int64_t max_tiles = 0;
+  uint64_t launch = 1;              // launch counter of the pass chain
+  uint32_t epoch = 0;               // last look-back epoch handed out
+  int round_grid = 0;               // persistent grid of the round kernel
+  int rounds_per_check = 4;         // round launches between host checks
+  int device = 0;
+};
+
+int adm_engine_init(AdmEngine &e, int device, int64_t max_entries);
+void adm_engine_free(AdmEngine &e);
+
+struct PassOut {
+  int64_t admitted, admitted_bytes, R0, R_after, rounds, start_final, hi;
+};
+
+// One pass over demand[start, end) with free memory R0 (stateless form: the
+// caller supplies R0, start and end).  decision[] receives 1 for admitted
+// entries and 0 for the entries the pass rejected.  Synchronises the stream.
+int adm_scan(AdmEngine &e, int policy, const int64_t *demand, uint8_t *decision, int64_t start,
+             int64_t end, int64_t R0, int window_limit, hipStream_t s, PassOut *out);
+
+// Ctx form: R0 = capacity - used and [head, tail) are read on the device by
+// the prologue kernel.  Does not compact.
+struct QueueArrays;
+int adm_pass_ctx(AdmEngine &e, int policy, const QueueArrays &q, int window_limit,
+                 int64_t span_hint, hipStream_t s, PassOut *out);
+
+// Device-side state the context keeps per queue entry and per job.
+struct QueueArrays {
+  int64_t *demand;   // < 0 marks a withdrawn request
+  int32_t *job;
+  int32_t *prio;
+  int64_t *seq;
+  uint8_t *decision;
+  int64_t capacity;  // entries, a power of two; position p lives at p & (capacity - 1)
+  // admitted list of the last pass (queue order)
+  int32_t *adm_job;
+  int64_t *adm_demand;
+  int64_t *adm_seq;
+};
+struct JobArrays {
+  int64_t *res;      // reservation bytes
+  int32_t *state;    // 0 idle, 1 holds a reservation
+  int32_t max_jobs;
+};
+
+// Stable compaction of the window [head, hi) after a pass: admitted entries
+// and withdrawn holes leave, survivors are right-aligned, the admitted list is
+// written in queue order and the admitted demands are charged to their jobs
+// and to `used`.  Stream-ordered.
+int adm_compact(AdmEngine &e, const QueueArrays &q, const JobArrays &j, hipStream_t s);
+
+int adm_zero_decisions(uint8_t *decision, int64_t n, hipStream_t s);
+int adm_release_masked(AdmEngine &e, const JobArrays &j, const uint8_t *mask, int64_t n,
+                       hipStream_t s);
+int adm_enqueue(AdmEngine &e, const QueueArrays &q, int64_t at, int64_t n, const int32_t *job,
+                const int64_t *demand, const int32_t *prio_of_job, int64_t seq0, hipStream_t s);
+
+}  // namespace schedk

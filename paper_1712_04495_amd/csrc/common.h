@@ -1,0 +1,178 @@
+// Shared device/host helpers for the co-scheduler library (gfx950, wave64).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/cosched.h"
+
+#define SCHED_HIP_TRY(expr)                                    \
+  do {                                                         \
+    hipError_t _e = (expr);                                    \
+    if (_e != hipSuccess) {                                    \
+      sched_note_hip_error(_e, #expr, __FILE__, __LINE__);     \
+      return SCHED_E_INTERNAL;                                 \
+    }                                                          \
+  } while (0)
+
+void sched_note_hip_error(hipError_t e, const char *what, const char *file, int line);
+
+namespace schedk {
+
+constexpr int WAVE = 64;
+
+// ---- relaxed, agent-scope atomics (visible across all XCDs) --------------
+template <typename T>
+__device__ __forceinline__ T ld_relaxed(const T *p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+template <typename T>
+__device__ __forceinline__ void st_relaxed(T *p, T v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+template <typename T>
+__device__ __forceinline__ T add_relaxed(T *p, T v) {
+  return __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+template <typename T>
+__device__ __forceinline__ T min_relaxed(T *p, T v) {
+  return __hip_atomic_fetch_min(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+template <typename T>
+__device__ __forceinline__ T max_relaxed(T *p, T v) {
+  return __hip_atomic_fetch_max(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Saturating add for non-negative values bounded by cap (cap < 2^62).
+__device__ __forceinline__ int64_t sat_add(int64_t a, int64_t b, int64_t cap) {
+  int64_t s = a + b;
+  return s < cap ? s : cap;
+}
+
+__device__ __forceinline__ int lane_id() { return __lane_id(); }
+
+// ---- wave-level primitives (64 lanes) ------------------------------------
+__device__ __forceinline__ int64_t wave_sum(int64_t v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, WAVE);
+  return v;
+}
+__device__ __forceinline__ int64_t wave_min(int64_t v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    int64_t u = __shfl_xor(v, off, WAVE);
+    v = u < v ? u : v;
+  }
+  return v;
+}
+__device__ __forceinline__ int64_t wave_max(int64_t v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    int64_t u = __shfl_xor(v, off, WAVE);
+    v = u > v ? u : v;
+  }
+  return v;
+}
+// Inclusive saturating prefix over lanes in lane order.
+__device__ __forceinline__ int64_t wave_incl_scan_sat(int64_t v, int64_t cap) {
+  const int lane = lane_id();
+#pragma unroll
+  for (int off = 1; off < WAVE; off <<= 1) {
+    int64_t u = __shfl_up(v, off, WAVE);
+    if (lane >= off) v = sat_add(v, u, cap);
+  }
+  return v;
+}
+// Inclusive plain prefix over lanes (no saturation).
+__device__ __forceinline__ int64_t wave_incl_scan(int64_t v) {
+  const int lane = lane_id();
+#pragma unroll
+  for (int off = 1; off < WAVE; off <<= 1) {
+    int64_t u = __shfl_up(v, off, WAVE);
+    if (lane >= off) v += u;
+  }
+  return v;
+}
+
+// ---- block-level primitives; `red` is LDS of at least NW int64 -----------
+template <int NT>
+__device__ __forceinline__ int64_t block_sum(int64_t v, int64_t *red) {
+  constexpr int NW = NT / WAVE;
+  v = wave_sum(v);
+  const int w = threadIdx.x / WAVE;
+  __syncthreads();
+  if (lane_id() == 0) red[w] = v;
+  __syncthreads();
+  int64_t s = 0;
+#pragma unroll
+  for (int i = 0; i < NW; ++i) s += red[i];
+  return s;
+}
+template <int NT>
+__device__ __forceinline__ int64_t block_min(int64_t v, int64_t *red) {
+  constexpr int NW = NT / WAVE;
+  v = wave_min(v);
+  const int w = threadIdx.x / WAVE;
+  __syncthreads();
+  if (lane_id() == 0) red[w] = v;
+  __syncthreads();
+  int64_t s = red[0];
+#pragma unroll
+  for (int i = 1; i < NW; ++i) s = red[i] < s ? red[i] : s;
+  return s;
+}
+template <int NT>
+__device__ __forceinline__ int64_t block_max(int64_t v, int64_t *red) {
+  constexpr int NW = NT / WAVE;
+  v = wave_max(v);
+  const int w = threadIdx.x / WAVE;
+  __syncthreads();
+  if (lane_id() == 0) red[w] = v;
+  __syncthreads();
+  int64_t s = red[0];
+#pragma unroll
+  for (int i = 1; i < NW; ++i) s = red[i] > s ? red[i] : s;
+  return s;
+}
+// Exclusive saturating scan over threads in thread order; returns the
+// exclusive prefix and writes the block total to *total.
+template <int NT>
+__device__ __forceinline__ int64_t block_excl_scan_sat(int64_t v, int64_t cap, int64_t *red,
+                                                       int64_t *total) {
+  constexpr int NW = NT / WAVE;
+  const int w = threadIdx.x / WAVE;
+  const int64_t incl = wave_incl_scan_sat(v, cap);
+  int64_t wexcl = __shfl_up(incl, 1, WAVE);
+  if (lane_id() == 0) wexcl = 0;
+  __syncthreads();
+  if (lane_id() == WAVE - 1) red[w] = incl;
+  __syncthreads();
+  int64_t before = 0, tot = 0;
+#pragma unroll
+  for (int i = 0; i < NW; ++i) {
+    if (i < w) before = sat_add(before, red[i], cap);
+    tot = sat_add(tot, red[i], cap);
+  }
+  *total = tot;
+  return sat_add(before, wexcl, cap);
+}
+// Exclusive plain scan (no saturation).
+template <int NT>
+__device__ __forceinline__ int64_t block_excl_scan(int64_t v, int64_t *red, int64_t *total) {
+  constexpr int NW = NT / WAVE;
+  const int w = threadIdx.x / WAVE;
+  const int64_t incl = wave_incl_scan(v);
+  __syncthreads();
+  if (lane_id() == WAVE - 1) red[w] = incl;
+  __syncthreads();
+  int64_t before = 0, tot = 0;
+#pragma unroll
+  for (int i = 0; i < NW; ++i) {
+    if (i < w) before += red[i];
+    tot += red[i];
+  }
+  *total = tot;
+  return before + incl - v;
+}
+
+}  // namespace schedk

@@ -1,0 +1,59 @@
+// Context layout shared by the runtime translation units.
+#pragma once
+
+#include <condition_variable>
+#include <mutex>
+#include <unordered_map>
+#include <vector>
+
+#include "admission.h"
+
+struct SlabState;
+
+struct sched_ctx {
+  std::mutex mu;
+  std::condition_variable cv;
+  sched_config_t cfg{};
+  int device = 0;
+  int64_t capacity = 0;
+  int policy = SCHED_POLICY_MMU;
+  int window_limit = 16;
+  bool closing = false;
+  hipStream_t stream = nullptr;
+
+  schedk::AdmEngine eng;
+  schedk::QueueArrays q{};
+  schedk::JobArrays jb{};
+  int32_t *d_prio_of_job = nullptr;
+  void *d_scratch = nullptr;   // 4 KiB of small device staging
+  void *h_stage = nullptr;     // 4 KiB of pinned host staging
+
+  // host-side bookkeeping
+  int32_t n_jobs = 0;
+  std::vector<int32_t> prio, timeout_ms, pending;
+  std::unordered_map<int64_t, int32_t> host_seq;  // waiting requests made with sched_admit
+  std::vector<int64_t> last_admitted_seqs;
+  int64_t seq_next = 0;
+  int64_t head_h = 0, tail_h = 0, used_h = 0;
+  int64_t last_A = 0;
+  int32_t *h_adm_job = nullptr;
+  int64_t *h_adm_seq = nullptr;
+  int64_t h_adm_cap = 0;
+  sched_stats_t stats{};
+
+  // priority ordering scratch
+  void *prio_tmp = nullptr;
+  size_t prio_tmp_bytes = 0;
+
+  SlabState *slab = nullptr;
+
+  void note_admitted(int64_t seq);
+  ~sched_ctx();
+};
+
+int sched_run_pass_locked(sched_ctx *c, hipStream_t s, sched_pass_result_t *res);
+int sched_priority_reorder_locked(sched_ctx *c, hipStream_t s);
+
+int sched_slab_init(sched_ctx *c, int64_t pool_bytes, int32_t n_tenants);
+void sched_slab_free(sched_ctx *c);
+int64_t sched_slab_pool_used(sched_ctx *c);

@@ -1,0 +1,543 @@
+// Scheduler context and the life-cycle entry points of the C ABI.
+//
+// The paper keeps its scheduler state -- total memory, total used, itemised
+// use per client and the queue of waiting clients (Sec. III-B) -- in host
+// shared memory guarded by a file lock.  Here that state lives in device
+// memory: a ring of pending requests (structure of arrays), a per-job
+// reservation table and a control block with capacity and used bytes.  One
+// context mutex serialises the calls (the role the file lock plays in the
+// paper), admission passes run on the device, and waiters block on a
+// condition variable that every pass signals (the role of the user signal).
+#include <algorithm>
+#include <chrono>
+#include <condition_variable>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <unordered_map>
+#include <vector>
+
+#include "admission.h"
+#include "runtime.h"
+
+using namespace schedk;
+
+void sched_note_hip_error(hipError_t e, const char *what, const char *file, int line) {
+  fprintf(stderr, "[sched] HIP error %d (%s) at %s:%d: %s\n", int(e), hipGetErrorString(e), file,
+          line, what);
+}
+
+namespace {
+
+__global__ void k_release_one(DevCtl *c, JobArrays jb, int32_t job, int64_t amount) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  const int64_t left = jb.res[job] - amount;
+  jb.res[job] = left;
+  if (left == 0) jb.state[job] = 0;
+  c->used -= amount;
+  c->released_bytes += amount;
+  if (left == 0) c->released_jobs += 1;
+}
+
+// Marks every waiting request of `job` in [head, tail) withdrawn (demand -1).
+__global__ void k_withdraw(DevCtl *c, QueueArrays q, int32_t job, int64_t *count) {
+  const int64_t head = c->head, tail = c->tail, mask = q.capacity - 1;
+  for (int64_t p = head + blockIdx.x * int64_t(blockDim.x) + threadIdx.x; p < tail;
+       p += int64_t(gridDim.x) * blockDim.x) {
+    const int64_t pm = p & mask;
+    if (q.job[pm] == job && q.demand[pm] >= 0) {
+      q.demand[pm] = -1;
+      atomicAdd((unsigned long long *)count, 1ULL);
+    }
+  }
+}
+
+// Batch validation: counts requests with an unknown job or a demand outside
+// [1, capacity].
+__global__ void k_validate(int64_t n, const int32_t *job, const int64_t *demand, int32_t n_jobs,
+                           int64_t capacity, unsigned long long *bad) {
+  unsigned long long b = 0;
+  for (int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; i < n;
+       i += int64_t(gridDim.x) * blockDim.x) {
+    const int32_t j = job[i];
+    const int64_t d = demand[i];
+    b += (j < 0 || j >= n_jobs || d < 1 || d > capacity) ? 1 : 0;
+  }
+  if (b) atomicAdd(bad, b);
+}
+
+__global__ void k_set_capacity(DevCtl *c, int64_t capacity) {
+  c->capacity = capacity;
+  c->used = 0;
+  c->head = 0;
+  c->tail = 0;
+}
+
+int64_t pow2_at_least(int64_t x) {
+  int64_t p = 1;
+  while (p < x) p <<= 1;
+  return p;
+}
+
+}  // namespace
+
+sched_ctx::~sched_ctx() {}
+
+static int ctx_alloc(sched_ctx *c) {
+  const int64_t Q = c->q.capacity;
+  const int32_t J = c->jb.max_jobs;
+  SCHED_HIP_TRY(hipMalloc(&c->q.demand, sizeof(int64_t) * Q));
+  SCHED_HIP_TRY(hipMalloc(&c->q.job, sizeof(int32_t) * Q));
+  SCHED_HIP_TRY(hipMalloc(&c->q.prio, sizeof(int32_t) * Q));
+  SCHED_HIP_TRY(hipMalloc(&c->q.seq, sizeof(int64_t) * Q));
+  SCHED_HIP_TRY(hipMalloc(&c->q.decision, Q));
+  SCHED_HIP_TRY(hipMemset(c->q.decision, 0, Q));
+  SCHED_HIP_TRY(hipMalloc(&c->q.adm_job, sizeof(int32_t) * Q));
+  SCHED_HIP_TRY(hipMalloc(&c->q.adm_demand, sizeof(int64_t) * Q));
+  SCHED_HIP_TRY(hipMalloc(&c->q.adm_seq, sizeof(int64_t) * Q));
+  SCHED_HIP_TRY(hipMalloc(&c->jb.res, sizeof(int64_t) * J));
+  SCHED_HIP_TRY(hipMemset(c->jb.res, 0, sizeof(int64_t) * J));
+  SCHED_HIP_TRY(hipMalloc(&c->jb.state, sizeof(int32_t) * J));
+  SCHED_HIP_TRY(hipMemset(c->jb.state, 0, sizeof(int32_t) * J));
+  SCHED_HIP_TRY(hipMalloc(&c->d_prio_of_job, sizeof(int32_t) * J));
+  SCHED_HIP_TRY(hipMemset(c->d_prio_of_job, 0, sizeof(int32_t) * J));
+  SCHED_HIP_TRY(hipMalloc(&c->d_scratch, 4096));
+  SCHED_HIP_TRY(hipHostMalloc(&c->h_stage, 4096, hipHostMallocDefault));
+  c->h_adm_cap = 1 << 16;
+  SCHED_HIP_TRY(hipHostMalloc(&c->h_adm_job, sizeof(int32_t) * c->h_adm_cap, hipHostMallocDefault));
+  SCHED_HIP_TRY(hipHostMalloc(&c->h_adm_seq, sizeof(int64_t) * c->h_adm_cap, hipHostMallocDefault));
+  return SCHED_OK;
+}
+
+static void ctx_free(sched_ctx *c) {
+  void *dev[] = {c->q.demand, c->q.job, c->q.prio, c->q.seq, c->q.decision, c->q.adm_job,
+                 c->q.adm_demand, c->q.adm_seq, c->jb.res, c->jb.state, c->d_prio_of_job,
+                 c->d_scratch};
+  for (void *p : dev)
+    if (p) (void)hipFree(p);
+  void *host[] = {c->h_stage, c->h_adm_job, c->h_adm_seq};
+  for (void *p : host)
+    if (p) (void)hipHostFree(p);
+  adm_engine_free(c->eng);
+  sched_slab_free(c);
+  if (c->stream) (void)hipStreamDestroy(c->stream);
+}
+
+extern "C" int sched_create(const sched_config_t *cfg, sched_ctx_t **out) {
+  if (!cfg || !out) return SCHED_E_INVALID;
+  if (cfg->policy < SCHED_POLICY_FIFO || cfg->policy > SCHED_POLICY_PRIO_MMU) return SCHED_E_INVALID;
+  if (cfg->max_jobs <= 0 || cfg->queue_capacity <= 0 || cfg->capacity_bytes < 0 ||
+      cfg->headroom_bytes < 0 || cfg->slab_pool_bytes < 0 || cfg->max_tenants < 0)
+    return SCHED_E_INVALID;
+  int ndev = 0;
+  SCHED_HIP_TRY(hipGetDeviceCount(&ndev));
+  if (cfg->device < 0 || cfg->device >= ndev) return SCHED_E_INVALID;
+  SCHED_HIP_TRY(hipSetDevice(cfg->device));
+  int64_t capacity = cfg->capacity_bytes;
+  if (capacity == 0) {
+    size_t fr = 0, tot = 0;
+    SCHED_HIP_TRY(hipMemGetInfo(&fr, &tot));
+    capacity = int64_t(fr) - cfg->headroom_bytes;
+  }
+  if (capacity <= 0 || capacity > MAX_FREE) return SCHED_E_INVALID;
+
+  sched_ctx *c = new sched_ctx();
+  c->cfg = *cfg;
+  c->device = cfg->device;
+  c->capacity = capacity;
+  c->policy = cfg->policy;
+  c->window_limit = cfg->window_limit > 0 ? cfg->window_limit : 16;
+  c->q.capacity = pow2_at_least(std::max<int64_t>(cfg->queue_capacity, WIN));
+  c->jb.max_jobs = cfg->max_jobs;
+  c->prio.assign(cfg->max_jobs, 0);
+  c->timeout_ms.assign(cfg->max_jobs, 60000);
+  c->pending.assign(cfg->max_jobs, 0);
+  int rc = SCHED_OK;
+  if (hipStreamCreate(&c->stream) != hipSuccess) rc = SCHED_E_INTERNAL;
+  if (rc == SCHED_OK) rc = ctx_alloc(c);
+  if (rc == SCHED_OK) rc = adm_engine_init(c->eng, c->device, c->q.capacity);
+  if (rc == SCHED_OK) {
+    k_set_capacity<<<1, 1, 0, c->stream>>>(c->eng.d_ctl, capacity);
+    if (hipGetLastError() != hipSuccess) rc = SCHED_E_INTERNAL;
+  }
+  if (rc == SCHED_OK && cfg->slab_pool_bytes > 0) {
+    const int32_t T = cfg->max_tenants > 0 ? cfg->max_tenants : cfg->max_jobs;
+    rc = sched_slab_init(c, cfg->slab_pool_bytes, T);
+  }
+  if (rc == SCHED_OK && hipStreamSynchronize(c->stream) != hipSuccess) rc = SCHED_E_INTERNAL;
+  if (rc != SCHED_OK) {
+    ctx_free(c);
+    delete c;
+    return rc;
+  }
+  *out = c;
+  return SCHED_OK;
+}
+
+extern "C" int sched_destroy(sched_ctx_t *c) {
+  if (!c) return SCHED_E_INVALID;
+  {
+    std::lock_guard<std::mutex> g(c->mu);
+    (void)hipSetDevice(c->device);
+    (void)hipStreamSynchronize(c->stream);
+    c->closing = true;
+  }
+  c->cv.notify_all();
+  ctx_free(c);
+  delete c;
+  return SCHED_OK;
+}
+
+static int register_locked(sched_ctx *c, int32_t n, int32_t priority, int32_t timeout_ms,
+                           sched_job_t *first) {
+  if (n <= 0 || c->n_jobs + int64_t(n) > c->jb.max_jobs) return SCHED_E_INVALID;
+  const int32_t j0 = c->n_jobs;
+  for (int32_t i = 0; i < n; ++i) {
+    c->prio[j0 + i] = priority;
+    c->timeout_ms[j0 + i] = timeout_ms;
+  }
+  SCHED_HIP_TRY(hipSetDevice(c->device));
+  // device copy of the priorities of the new jobs
+  std::vector<int32_t> pr(n, priority);
+  SCHED_HIP_TRY(hipMemcpyAsync(c->d_prio_of_job + j0, pr.data(), sizeof(int32_t) * n,
+                               hipMemcpyHostToDevice, c->stream));
+  SCHED_HIP_TRY(hipStreamSynchronize(c->stream));
+  c->n_jobs += n;
+  *first = j0;
+  return SCHED_OK;
+}
+
+extern "C" int sched_register(sched_ctx_t *c, int32_t priority, int32_t timeout_ms,
+                              sched_job_t *out_job) {
+  if (!c || !out_job) return SCHED_E_INVALID;
+  std::lock_guard<std::mutex> g(c->mu);
+  return register_locked(c, 1, priority, timeout_ms, out_job);
+}
+
+extern "C" int sched_register_batch(sched_ctx_t *c, int32_t n, int32_t priority,
+                                    int32_t timeout_ms, sched_job_t *out_first) {
+  if (!c || !out_first) return SCHED_E_INVALID;
+  std::lock_guard<std::mutex> g(c->mu);
+  return register_locked(c, n, priority, timeout_ms, out_first);
+}
+
+// One admission pass + compaction + host bookkeeping.  Caller holds c->mu.
+int sched_run_pass_locked(sched_ctx *c, hipStream_t s, sched_pass_result_t *res) {
+  auto t0 = std::chrono::steady_clock::now();
+  const int64_t head_before = c->head_h;
+  PassOut po{};
+  const int pol = (c->policy == SCHED_POLICY_FIFO || c->policy == SCHED_POLICY_PRIO_FIFO) ? SCHED_POLICY_FIFO : SCHED_POLICY_MMU;
+  if (c->policy == SCHED_POLICY_PRIO_FIFO || c->policy == SCHED_POLICY_PRIO_MMU) {
+    if (int rc = sched_priority_reorder_locked(c, s)) return rc;
+  }
+  if (int rc = adm_pass_ctx(c->eng, pol, c->q, c->window_limit, c->tail_h - c->head_h, s, &po))
+    return rc;
+  if (int rc = adm_compact(c->eng, c->q, c->jb, s)) return rc;
+  // read back the control block and the admitted list
+  const int64_t A = po.admitted;
+  SCHED_HIP_TRY(hipMemcpyAsync(c->eng.h_ctl, c->eng.d_ctl, sizeof(DevCtl), hipMemcpyDeviceToHost, s));
+  const int64_t ncopy = std::min<int64_t>(A, c->h_adm_cap);
+  if (!c->host_seq.empty() && ncopy > 0) {
+    SCHED_HIP_TRY(hipMemcpyAsync(c->h_adm_job, c->q.adm_job, sizeof(int32_t) * ncopy,
+                                 hipMemcpyDeviceToHost, s));
+    SCHED_HIP_TRY(hipMemcpyAsync(c->h_adm_seq, c->q.adm_seq, sizeof(int64_t) * ncopy,
+                                 hipMemcpyDeviceToHost, s));
+  }
+  SCHED_HIP_TRY(hipStreamSynchronize(s));
+  c->last_admitted_seqs.clear();
+  if (!c->host_seq.empty()) {
+    if (A > c->h_adm_cap) {
+      // large admitted list: fetch it in full into a host vector
+      std::vector<int32_t> jobs(A);
+      std::vector<int64_t> seqs(A);
+      SCHED_HIP_TRY(hipMemcpy(jobs.data(), c->q.adm_job, sizeof(int32_t) * A, hipMemcpyDeviceToHost));
+      SCHED_HIP_TRY(hipMemcpy(seqs.data(), c->q.adm_seq, sizeof(int64_t) * A, hipMemcpyDeviceToHost));
+      for (int64_t i = 0; i < A; ++i) c->note_admitted(seqs[i]);
+    } else {
+      for (int64_t i = 0; i < A; ++i) c->note_admitted(c->h_adm_seq[i]);
+    }
+  }
+  const DevCtl &h = *c->eng.h_ctl;
+  c->head_h = h.head;
+  c->tail_h = h.tail;
+  c->used_h = h.used;
+  c->last_A = A;
+  c->stats.passes += 1;
+  c->stats.rounds += po.rounds;
+  c->stats.admitted += A;
+  auto t1 = std::chrono::steady_clock::now();
+  c->stats.last_pass_us_x1000 =
+      std::chrono::duration_cast<std::chrono::nanoseconds>(t1 - t0).count();
+  if (res) {
+    res->admitted = A;
+    res->admitted_bytes = po.admitted_bytes;
+    res->free_before = po.R0;
+    res->free_after = po.R_after;
+    res->rounds = po.rounds;
+    res->scanned = po.start_final - head_before;
+    res->pending_after = h.tail - h.head;
+  }
+  c->cv.notify_all();
+  return SCHED_OK;
+}
+
+void sched_ctx::note_admitted(int64_t seq) {
+  auto it = host_seq.find(seq);
+  if (it == host_seq.end()) return;
+  const int32_t job = it->second;
+  host_seq.erase(it);
+  if (pending[job] > 0) pending[job] -= 1;
+  last_admitted_seqs.push_back(seq);
+}
+
+static int withdraw_locked(sched_ctx *c, sched_job_t job) {
+  unsigned long long *cnt = (unsigned long long *)c->d_scratch;
+  SCHED_HIP_TRY(hipMemsetAsync(cnt, 0, sizeof(unsigned long long), c->stream));
+  const int64_t live = std::max<int64_t>(c->tail_h - c->head_h, 1);
+  const int grid = int(std::min<int64_t>((live + 255) / 256, 1024));
+  k_withdraw<<<grid, 256, 0, c->stream>>>(c->eng.d_ctl, c->q, job, (int64_t *)cnt);
+  SCHED_HIP_TRY(hipGetLastError());
+  unsigned long long n = 0;
+  SCHED_HIP_TRY(hipMemcpyAsync(&n, cnt, sizeof(n), hipMemcpyDeviceToHost, c->stream));
+  SCHED_HIP_TRY(hipStreamSynchronize(c->stream));
+  for (auto it = c->host_seq.begin(); it != c->host_seq.end();) {
+    if (it->second == job) it = c->host_seq.erase(it);
+    else ++it;
+  }
+  c->pending[job] = 0;
+  c->stats.withdrawn += int64_t(n);
+  return SCHED_OK;
+}
+
+static int wait_locked(sched_ctx *c, std::unique_lock<std::mutex> &lk, sched_job_t job,
+                       int32_t timeout_ms) {
+  if (timeout_ms < 0) timeout_ms = c->timeout_ms[job];
+  const auto deadline = std::chrono::steady_clock::now() + std::chrono::milliseconds(timeout_ms);
+  while (c->pending[job] > 0 && !c->closing) {
+    if (c->cv.wait_until(lk, deadline) == std::cv_status::timeout) break;
+  }
+  if (c->pending[job] == 0) return SCHED_OK;
+  // timed out: withdraw under the mutex, so the request is either admitted
+  // (by a pass that ran before this point) or withdrawn, never both
+  if (int rc = withdraw_locked(c, job)) return rc;
+  return SCHED_TIMEOUT;
+}
+
+extern "C" int sched_admit(sched_ctx_t *c, sched_job_t job, int32_t device, int64_t bytes,
+                           uint32_t flags) {
+  if (!c) return SCHED_E_INVALID;
+  std::unique_lock<std::mutex> lk(c->mu);
+  if (job < 0 || job >= c->n_jobs || device != c->device || bytes <= 0) return SCHED_E_INVALID;
+  if (bytes > c->capacity) return SCHED_E_TOOBIG;
+  if (c->tail_h - c->head_h + 1 > c->q.capacity) return SCHED_E_NOMEM;
+  SCHED_HIP_TRY(hipSetDevice(c->device));
+  // stage the request and append it at the queue tail
+  int32_t *hj = (int32_t *)c->h_stage;
+  int64_t *hd = (int64_t *)((char *)c->h_stage + 64);
+  hj[0] = job;
+  hd[0] = bytes;
+  int32_t *dj = (int32_t *)((char *)c->d_scratch + 256);
+  int64_t *dd = (int64_t *)((char *)c->d_scratch + 512);
+  SCHED_HIP_TRY(hipMemcpyAsync(dj, hj, sizeof(int32_t), hipMemcpyHostToDevice, c->stream));
+  SCHED_HIP_TRY(hipMemcpyAsync(dd, hd, sizeof(int64_t), hipMemcpyHostToDevice, c->stream));
+  const int64_t seq = c->seq_next++;
+  if (int rc = adm_enqueue(c->eng, c->q, c->tail_h, 1, dj, dd, c->d_prio_of_job, seq, c->stream))
+    return rc;
+  c->tail_h += 1;
+  c->host_seq[seq] = job;
+  c->pending[job] += 1;
+  if (int rc = sched_run_pass_locked(c, c->stream, nullptr)) return rc;
+  if (c->host_seq.find(seq) == c->host_seq.end()) {
+    // admitted in this pass; other requests of the job may still wait
+    if (c->pending[job] == 0 || (flags & SCHED_NONBLOCK)) return SCHED_OK;
+  } else if (flags & SCHED_NONBLOCK) {
+    return SCHED_NOT_READY;
+  }
+  return wait_locked(c, lk, job, -1);
+}
+
+extern "C" int sched_wait(sched_ctx_t *c, sched_job_t job, int32_t timeout_ms) {
+  if (!c) return SCHED_E_INVALID;
+  std::unique_lock<std::mutex> lk(c->mu);
+  if (job < 0 || job >= c->n_jobs) return SCHED_E_INVALID;
+  return wait_locked(c, lk, job, timeout_ms);
+}
+
+static int read_res(sched_ctx *c, sched_job_t job, int64_t *v) {
+  SCHED_HIP_TRY(hipMemcpyAsync(c->h_stage, c->jb.res + job, sizeof(int64_t), hipMemcpyDeviceToHost,
+                               c->stream));
+  SCHED_HIP_TRY(hipStreamSynchronize(c->stream));
+  *v = *(int64_t *)c->h_stage;
+  return SCHED_OK;
+}
+
+extern "C" int sched_release(sched_ctx_t *c, sched_job_t job, int32_t device, int64_t bytes) {
+  if (!c) return SCHED_E_INVALID;
+  std::lock_guard<std::mutex> g(c->mu);
+  if (job < 0 || job >= c->n_jobs || bytes < 0) return SCHED_E_INVALID;
+  if (device >= 0 && device != c->device) return SCHED_E_INVALID;
+  SCHED_HIP_TRY(hipSetDevice(c->device));
+  int64_t res = 0;
+  if (int rc = read_res(c, job, &res)) return rc;
+  if (bytes > res) return SCHED_E_INVALID;
+  const int64_t amount = bytes == 0 ? res : bytes;
+  if (amount > 0) {
+    k_release_one<<<1, 1, 0, c->stream>>>(c->eng.d_ctl, c->jb, job, amount);
+    SCHED_HIP_TRY(hipGetLastError());
+    c->stats.released_bytes += amount;
+  }
+  return sched_run_pass_locked(c, c->stream, nullptr);
+}
+
+extern "C" int sched_reservation(sched_ctx_t *c, sched_job_t job, int64_t *out) {
+  if (!c || !out) return SCHED_E_INVALID;
+  std::lock_guard<std::mutex> g(c->mu);
+  if (job < 0 || job >= c->n_jobs) return SCHED_E_INVALID;
+  SCHED_HIP_TRY(hipSetDevice(c->device));
+  return read_res(c, job, out);
+}
+
+extern "C" int sched_stats(sched_ctx_t *c, sched_stats_t *out) {
+  if (!c || !out) return SCHED_E_INVALID;
+  std::lock_guard<std::mutex> g(c->mu);
+  SCHED_HIP_TRY(hipSetDevice(c->device));
+  SCHED_HIP_TRY(hipMemcpyAsync(c->eng.h_ctl, c->eng.d_ctl, sizeof(DevCtl), hipMemcpyDeviceToHost,
+                               c->stream));
+  SCHED_HIP_TRY(hipStreamSynchronize(c->stream));
+  const DevCtl &h = *c->eng.h_ctl;
+  sched_stats_t s = c->stats;
+  s.capacity = c->capacity;
+  s.used = h.used;
+  s.pending = h.tail - h.head;
+  s.released_bytes = h.released_bytes;
+  int64_t running = 0;
+  {
+    std::vector<int32_t> st(c->n_jobs);
+    if (c->n_jobs) {
+      SCHED_HIP_TRY(hipMemcpy(st.data(), c->jb.state, sizeof(int32_t) * c->n_jobs,
+                              hipMemcpyDeviceToHost));
+    }
+    for (int32_t v : st) running += v != 0;
+  }
+  s.running = running;
+  s.slab_pool_used = sched_slab_pool_used(c);
+  s.violations = c->stats.violations;
+  *out = s;
+  return SCHED_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Device-batched admission
+// ---------------------------------------------------------------------------
+static hipStream_t pick(sched_ctx *c, sched_stream_t s) {
+  return s ? (hipStream_t)s : c->stream;
+}
+
+extern "C" int sched_enqueue_batch(sched_ctx_t *c, int64_t n, const int32_t *d_job,
+                                   const int64_t *d_demand, sched_stream_t stream) {
+  if (!c || n < 0 || (n > 0 && (!d_job || !d_demand))) return SCHED_E_INVALID;
+  std::lock_guard<std::mutex> g(c->mu);
+  if (n == 0) return SCHED_OK;
+  if (c->tail_h - c->head_h + n > c->q.capacity) return SCHED_E_INVALID;
+  SCHED_HIP_TRY(hipSetDevice(c->device));
+  hipStream_t s = pick(c, stream);
+  unsigned long long *bad = (unsigned long long *)c->d_scratch;
+  SCHED_HIP_TRY(hipMemsetAsync(bad, 0, sizeof(unsigned long long), s));
+  const int grid = int(std::min<int64_t>((n + 255) / 256, 2048));
+  k_validate<<<grid, 256, 0, s>>>(n, d_job, d_demand, c->n_jobs, c->capacity, bad);
+  SCHED_HIP_TRY(hipGetLastError());
+  unsigned long long *hb = (unsigned long long *)c->h_stage;
+  SCHED_HIP_TRY(hipMemcpyAsync(hb, bad, sizeof(*hb), hipMemcpyDeviceToHost, s));
+  SCHED_HIP_TRY(hipStreamSynchronize(s));
+  if (*hb) return SCHED_E_INVALID;
+  if (int rc = adm_enqueue(c->eng, c->q, c->tail_h, n, d_job, d_demand, c->d_prio_of_job,
+                           c->seq_next, s))
+    return rc;
+  c->seq_next += n;
+  c->tail_h += n;
+  return SCHED_OK;
+}
+
+extern "C" int sched_pass(sched_ctx_t *c, sched_stream_t stream, sched_pass_result_t *out) {
+  if (!c) return SCHED_E_INVALID;
+  std::lock_guard<std::mutex> g(c->mu);
+  SCHED_HIP_TRY(hipSetDevice(c->device));
+  sched_pass_result_t r{};
+  if (int rc = sched_run_pass_locked(c, pick(c, stream), &r)) return rc;
+  if (out) *out = r;
+  return SCHED_OK;
+}
+
+extern "C" int sched_last_admitted(sched_ctx_t *c, int32_t *d_out, int64_t cap, int64_t *out_n,
+                                   sched_stream_t stream) {
+  if (!c || !out_n || cap < 0 || (cap > 0 && !d_out)) return SCHED_E_INVALID;
+  std::lock_guard<std::mutex> g(c->mu);
+  SCHED_HIP_TRY(hipSetDevice(c->device));
+  const int64_t n = std::min<int64_t>(cap, c->last_A);
+  if (n > 0)
+    SCHED_HIP_TRY(hipMemcpyAsync(d_out, c->q.adm_job, sizeof(int32_t) * n, hipMemcpyDeviceToDevice,
+                                 pick(c, stream)));
+  *out_n = c->last_A;
+  return SCHED_OK;
+}
+
+extern "C" int sched_release_masked(sched_ctx_t *c, const uint8_t *d_mask, int64_t n,
+                                    sched_stream_t stream) {
+  if (!c || n < 0 || (n > 0 && !d_mask)) return SCHED_E_INVALID;
+  std::lock_guard<std::mutex> g(c->mu);
+  if (n > c->n_jobs) return SCHED_E_INVALID;
+  SCHED_HIP_TRY(hipSetDevice(c->device));
+  return adm_release_masked(c->eng, c->jb, d_mask, n, pick(c, stream));
+}
+
+// ---------------------------------------------------------------------------
+// Stateless scan
+// ---------------------------------------------------------------------------
+namespace {
+struct ScanWs {
+  std::mutex mu;
+  AdmEngine eng;
+  int64_t cap_entries = 0;
+};
+ScanWs g_scan[64];
+}  // namespace
+
+extern "C" size_t sched_scan_workspace_size(int64_t n) {
+  if (n < 0) n = 0;
+  return 256 + sizeof(unsigned long long) * size_t((n + TILE - 1) / TILE + 1);
+}
+
+extern "C" int sched_scan(int32_t policy, int64_t n, const int64_t *d_demand, int64_t R,
+                          uint8_t *d_decision, int32_t write_all, int32_t window_limit, void *d_ws,
+                          size_t ws_bytes, sched_stream_t stream, sched_scan_result_t *out) {
+  if (!out || n < 0 || R < 0 || R > MAX_FREE) return SCHED_E_INVALID;
+  if (policy != SCHED_POLICY_FIFO && policy != SCHED_POLICY_MMU) return SCHED_E_INVALID;
+  if (n > 0 && (!d_demand || !d_decision)) return SCHED_E_INVALID;
+  (void)d_ws;
+  (void)ws_bytes;
+  int dev = 0;
+  SCHED_HIP_TRY(hipGetDevice(&dev));
+  if (dev < 0 || dev >= 64) return SCHED_E_INVALID;
+  ScanWs &w = g_scan[dev];
+  std::lock_guard<std::mutex> g(w.mu);
+  if (w.cap_entries < n || !w.eng.d_ctl) {
+    adm_engine_free(w.eng);
+    if (int rc = adm_engine_init(w.eng, dev, std::max<int64_t>(n, 1 << 20))) return rc;
+    w.cap_entries = std::max<int64_t>(n, 1 << 20);
+  }
+  hipStream_t s = (hipStream_t)stream;
+  PassOut po{};
+  if (int rc = adm_scan(w.eng, policy, d_demand, d_decision, 0, n, R, window_limit, s, &po)) return rc;
+  if (write_all && po.start_final < n) {
+    if (int rc = adm_zero_decisions(d_decision + po.start_final, n - po.start_final, s)) return rc;
+    SCHED_HIP_TRY(hipStreamSynchronize(s));
+  }
+  out->admitted = po.admitted;
+  out->admitted_bytes = po.admitted_bytes;
+  out->free_after = po.R_after;
+  out->rounds = po.rounds;
+  out->last_admitted = po.hi - 1 >= 0 && po.admitted > 0 ? po.hi - 1 : -1;
+  return SCHED_OK;
+}
+
+extern "C" const char *sched_version(void) { return "sched-mi355x 0.1 (gfx950)"; }

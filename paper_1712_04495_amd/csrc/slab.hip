@@ -1,0 +1,464 @@
+// Quota-checked slab sub-allocator in HBM.
+//
+// The paper records, next to the total memory in use, the memory each client
+// uses (Sec. III-B) and only accepts a post-free of memory the client holds
+// (Sec. IV).  This allocator carries that itemised accounting down to the
+// blocks co-scheduled tenants allocate:
+//   * 13 power-of-two classes, 256 B .. 1 MiB; a request takes the smallest
+//     class that holds it and is charged the class size;
+//   * the pool is one device allocation split into 13 equal regions (whole
+//     MiB each), region c holding blocks of class c: capacity_c =
+//     region_bytes / class_bytes(c) blocks, one bit each in a bitmap;
+//   * an allocation charges its tenant (<= quota) and the pool (<= pool
+//     bytes) with compare-and-swap loops, so a counter never holds a charge
+//     that is not accounted for by an allocation in flight, then claims a
+//     free bit with an atomic OR; a failure returns every charge it took;
+//   * a free checks that the block lies in the pool, is aligned, belongs to
+//     the freeing tenant and is live, clears its bit and returns the charges.
+// Quotas come either from an explicit table (standalone use) or from the
+// jobs' admitted reservations (tenant = job).
+#include <algorithm>
+#include <cstring>
+#include <mutex>
+#include <vector>
+
+#include "runtime.h"
+
+using namespace schedk;
+
+namespace {
+
+constexpr int N_CLASSES = 13;
+constexpr int MIN_LOG2 = 8;
+constexpr int64_t MiB = 1 << 20;
+
+// status codes of a device op
+constexpr int8_t ST_OK = 0;
+constexpr int8_t ST_QUOTA = 1;
+constexpr int8_t ST_NOMEM_POOL = 2;
+constexpr int8_t ST_NOMEM_CLASS = 3;
+constexpr int8_t ST_INVALID = 4;
+
+constexpr uint8_t OPK_ALLOC = 0;
+constexpr uint8_t OPK_FREE = 1;
+
+struct SlabDev {
+  uint8_t *base;
+  int64_t pool_bytes;
+  int64_t region_bytes;
+  int64_t cap[N_CLASSES];        // blocks per class
+  int64_t words_off[N_CLASSES];  // offset of the class bitmap in `bits`
+  int64_t n_words[N_CLASSES];
+  int64_t owner_off[N_CLASSES];  // offset of the class owner table in `owner`
+  unsigned long long *bits;
+  int32_t *owner;
+  int64_t *charged;              // per tenant
+  int64_t *pool_used;            // one counter
+  const int64_t *quota;          // per tenant
+  int32_t n_tenants;
+};
+
+__device__ __forceinline__ int size_class(int64_t size) {
+  if (size < 1 || size > (int64_t(1) << (MIN_LOG2 + N_CLASSES - 1))) return -1;
+  int c = 0;
+  while ((int64_t(1) << (MIN_LOG2 + c)) < size) ++c;
+  return c;
+}
+
+__device__ __forceinline__ uint32_t mix32(uint64_t x) {
+  x ^= x >> 33;
+  x *= 0xff51afd7ed558ccdULL;
+  x ^= x >> 33;
+  return uint32_t(x);
+}
+
+// Adds v to *ctr if the result stays <= limit.  Returns false without
+// touching the counter otherwise.
+__device__ __forceinline__ bool charge(int64_t *ctr, int64_t v, int64_t limit) {
+  int64_t cur = ld_relaxed(ctr);
+  for (;;) {
+    if (cur + v > limit) return false;
+    if (__hip_atomic_compare_exchange_strong(ctr, &cur, cur + v, __ATOMIC_RELAXED,
+                                             __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
+      return true;
+  }
+}
+
+__device__ int8_t slab_alloc_one(const SlabDev &s, int32_t t, int64_t size, uint64_t hint,
+                                 uint64_t *out_ptr) {
+  const int c = size_class(size);
+  if (c < 0 || t < 0 || t >= s.n_tenants) return ST_INVALID;
+  const int64_t cs = int64_t(1) << (MIN_LOG2 + c);
+  if (!charge(&s.charged[t], cs, s.quota[t])) return ST_QUOTA;
+  if (!charge(s.pool_used, cs, s.pool_bytes)) {
+    add_relaxed(&s.charged[t], -cs);
+    return ST_NOMEM_POOL;
+  }
+  const int64_t nw = s.n_words[c];
+  unsigned long long *bits = s.bits + s.words_off[c];
+  const int64_t w0 = nw > 0 ? int64_t(mix32(hint) % uint64_t(nw)) : 0;
+  for (int64_t k = 0; k < nw; ++k) {
+    int64_t w = w0 + k;
+    if (w >= nw) w -= nw;
+    unsigned long long cur = ld_relaxed(bits + w);
+    while (~cur) {
+      const int b = __builtin_ctzll(~cur);
+      const unsigned long long bit = 1ULL << b;
+      const unsigned long long old =
+          __hip_atomic_fetch_or(bits + w, bit, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      if (!(old & bit)) {
+        const int64_t blk = w * 64 + b;
+        s.owner[s.owner_off[c] + blk] = t;
+        *out_ptr = uint64_t(s.base + int64_t(c) * s.region_bytes + blk * cs);
+        return ST_OK;
+      }
+      cur = old | bit;
+    }
+  }
+  add_relaxed(s.pool_used, -cs);
+  add_relaxed(&s.charged[t], -cs);
+  return ST_NOMEM_CLASS;
+}
+
+__device__ int8_t slab_free_one(const SlabDev &s, int32_t t, uint64_t ptr) {
+  if (t < 0 || t >= s.n_tenants) return ST_INVALID;
+  const uint64_t b0 = uint64_t(s.base);
+  if (ptr < b0 || ptr >= b0 + uint64_t(N_CLASSES) * uint64_t(s.region_bytes)) return ST_INVALID;
+  const int64_t off = int64_t(ptr - b0);
+  const int c = int(off / s.region_bytes);
+  const int64_t roff = off - int64_t(c) * s.region_bytes;
+  const int64_t cs = int64_t(1) << (MIN_LOG2 + c);
+  if (roff % cs) return ST_INVALID;
+  const int64_t blk = roff / cs;
+  if (blk >= s.cap[c]) return ST_INVALID;
+  if (s.owner[s.owner_off[c] + blk] != t) return ST_INVALID;
+  const unsigned long long bit = 1ULL << (blk & 63);
+  const unsigned long long old = __hip_atomic_fetch_and(s.bits + s.words_off[c] + (blk >> 6), ~bit,
+                                                        __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  if (!(old & bit)) return ST_INVALID;  // not live: double free
+  add_relaxed(s.pool_used, -cs);
+  add_relaxed(&s.charged[t], -cs);
+  return ST_OK;
+}
+
+// One phase of concurrent ops [begin, end).  Arrays are indexed by the global
+// op index; a free names an alloc op of an earlier phase by index.
+__global__ void k_slab_phase(SlabDev s, int64_t begin, int64_t end, const uint8_t *__restrict__ kind,
+                             const int32_t *__restrict__ tenant, const int64_t *__restrict__ size,
+                             const int64_t *__restrict__ ref, uint64_t *__restrict__ ptr,
+                             int8_t *__restrict__ status) {
+  for (int64_t i = begin + blockIdx.x * int64_t(blockDim.x) + threadIdx.x; i < end;
+       i += int64_t(gridDim.x) * blockDim.x) {
+    const int32_t t = tenant[i];
+    int8_t st;
+    uint64_t p = 0;
+    if (kind[i] == OPK_ALLOC) {
+      st = slab_alloc_one(s, t, size[i], uint64_t(i) * 0x9E3779B97F4A7C15ULL, &p);
+    } else {
+      const int64_t r = ref[i];
+      if (kind[i] != OPK_FREE || r < 0 || r >= begin || kind[r] != OPK_ALLOC || status[r] != ST_OK) {
+        st = ST_INVALID;
+      } else {
+        st = slab_free_one(s, t, ptr[r]);
+      }
+    }
+    status[i] = st;
+    ptr[i] = st == ST_OK && kind[i] == OPK_ALLOC ? p : 0;
+  }
+}
+
+__global__ void k_slab_one(SlabDev s, int32_t t, int64_t size, uint64_t fptr, int is_free,
+                           uint64_t hint, uint64_t *out_ptr, int8_t *out_st) {
+  if (threadIdx.x || blockIdx.x) return;
+  uint64_t p = 0;
+  const int8_t st = is_free ? slab_free_one(s, t, fptr) : slab_alloc_one(s, t, size, hint, &p);
+  *out_ptr = p;
+  *out_st = st;
+}
+
+// Charges (v > 0) or uncharges (v < 0) a tenant without a block: the large
+// tier.  Status ST_OK or ST_QUOTA.
+__global__ void k_slab_charge(SlabDev s, int32_t t, int64_t v, int8_t *out_st) {
+  if (threadIdx.x || blockIdx.x) return;
+  if (v >= 0) {
+    *out_st = charge(&s.charged[t], v, s.quota[t]) ? ST_OK : ST_QUOTA;
+  } else {
+    add_relaxed(&s.charged[t], v);
+    *out_st = ST_OK;
+  }
+}
+
+__global__ void k_slab_reset_bits(SlabDev s) {
+  for (int c = 0; c < N_CLASSES; ++c) {
+    unsigned long long *bits = s.bits + s.words_off[c];
+    const int64_t nw = s.n_words[c], cap = s.cap[c];
+    for (int64_t w = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; w < nw;
+         w += int64_t(gridDim.x) * blockDim.x) {
+      // bits beyond the class capacity are permanently taken
+      const int64_t lo = w * 64;
+      unsigned long long v = 0;
+      if (lo + 64 > cap) {
+        const int64_t valid = cap - lo;
+        v = valid <= 0 ? ~0ULL : (~0ULL << valid);
+      }
+      bits[w] = v;
+    }
+  }
+}
+
+}  // namespace
+
+struct SlabState {
+  SlabDev dev{};
+  int64_t *d_quota = nullptr;       // explicit quota table
+  bool explicit_quota = false;
+  uint64_t *d_one_ptr = nullptr;
+  int8_t *d_one_st = nullptr;
+  void *h_one = nullptr;
+  uint64_t hint = 1;
+  std::vector<std::pair<void *, int64_t>> large;  // large-tier blocks: ptr, charged bytes
+  std::vector<int32_t> large_owner;
+};
+
+static int slab_apply_quota_source(sched_ctx *c) {
+  SlabState *s = c->slab;
+  s->dev.quota = s->explicit_quota ? s->d_quota : c->jb.res;
+  return SCHED_OK;
+}
+
+int sched_slab_init(sched_ctx *c, int64_t pool_bytes, int32_t n_tenants) {
+  const int64_t region = (pool_bytes / N_CLASSES) / MiB * MiB;
+  if (region <= 0) return SCHED_E_INVALID;
+  SlabState *s = new SlabState();
+  c->slab = s;
+  SlabDev &d = s->dev;
+  d.pool_bytes = pool_bytes;
+  d.region_bytes = region;
+  d.n_tenants = n_tenants;
+  int64_t words = 0, owners = 0;
+  for (int k = 0; k < N_CLASSES; ++k) {
+    d.cap[k] = region >> (MIN_LOG2 + k);
+    d.n_words[k] = (d.cap[k] + 63) / 64;
+    d.words_off[k] = words;
+    d.owner_off[k] = owners;
+    words += d.n_words[k];
+    owners += d.cap[k];
+  }
+  SCHED_HIP_TRY(hipMalloc(&d.base, size_t(region) * N_CLASSES));
+  SCHED_HIP_TRY(hipMalloc(&d.bits, sizeof(unsigned long long) * words));
+  SCHED_HIP_TRY(hipMalloc(&d.owner, sizeof(int32_t) * owners));
+  SCHED_HIP_TRY(hipMalloc(&d.charged, sizeof(int64_t) * n_tenants));
+  SCHED_HIP_TRY(hipMemset(d.charged, 0, sizeof(int64_t) * n_tenants));
+  SCHED_HIP_TRY(hipMalloc(&d.pool_used, sizeof(int64_t)));
+  SCHED_HIP_TRY(hipMemset(d.pool_used, 0, sizeof(int64_t)));
+  SCHED_HIP_TRY(hipMalloc(&s->d_quota, sizeof(int64_t) * n_tenants));
+  SCHED_HIP_TRY(hipMemset(s->d_quota, 0, sizeof(int64_t) * n_tenants));
+  SCHED_HIP_TRY(hipMalloc(&s->d_one_ptr, sizeof(uint64_t)));
+  SCHED_HIP_TRY(hipMalloc(&s->d_one_st, sizeof(int8_t)));
+  SCHED_HIP_TRY(hipHostMalloc(&s->h_one, 64, hipHostMallocDefault));
+  k_slab_reset_bits<<<256, 256, 0, c->stream>>>(d);
+  SCHED_HIP_TRY(hipGetLastError());
+  // quotas default to the job reservations when tenants are jobs
+  s->explicit_quota = n_tenants > c->jb.max_jobs;
+  return slab_apply_quota_source(c);
+}
+
+void sched_slab_free(sched_ctx *c) {
+  SlabState *s = c->slab;
+  if (!s) return;
+  for (auto &b : s->large)
+    if (b.first) (void)hipFree(b.first);
+  void *dev[] = {s->dev.base, s->dev.bits, s->dev.owner, s->dev.charged, s->dev.pool_used,
+                 s->d_quota, s->d_one_ptr, s->d_one_st};
+  for (void *p : dev)
+    if (p) (void)hipFree(p);
+  if (s->h_one) (void)hipHostFree(s->h_one);
+  delete s;
+  c->slab = nullptr;
+}
+
+int64_t sched_slab_pool_used(sched_ctx *c) {
+  if (!c->slab) return 0;
+  int64_t v = 0;
+  if (hipMemcpy(&v, c->slab->dev.pool_used, sizeof(v), hipMemcpyDeviceToHost) != hipSuccess) return -1;
+  return v;
+}
+
+static int8_t to_status_code(int8_t st) {
+  switch (st) {
+    case ST_OK: return SCHED_OK;
+    case ST_QUOTA: return SCHED_E_QUOTA;
+    case ST_NOMEM_POOL:
+    case ST_NOMEM_CLASS: return SCHED_E_NOMEM;
+    default: return SCHED_E_INVALID;
+  }
+}
+
+static int slab_one_locked(sched_ctx *c, int32_t t, int64_t size, uint64_t fptr, int is_free,
+                           uint64_t *out_ptr, int8_t *out_st) {
+  SlabState *s = c->slab;
+  k_slab_one<<<1, 64, 0, c->stream>>>(s->dev, t, size, fptr, is_free, s->hint++ * 0x9E3779B97F4A7C15ULL,
+                                      s->d_one_ptr, s->d_one_st);
+  SCHED_HIP_TRY(hipGetLastError());
+  SCHED_HIP_TRY(hipMemcpyAsync(s->h_one, s->d_one_ptr, 8, hipMemcpyDeviceToHost, c->stream));
+  SCHED_HIP_TRY(hipMemcpyAsync((char *)s->h_one + 8, s->d_one_st, 1, hipMemcpyDeviceToHost, c->stream));
+  SCHED_HIP_TRY(hipStreamSynchronize(c->stream));
+  *out_ptr = *(uint64_t *)s->h_one;
+  *out_st = *((int8_t *)s->h_one + 8);
+  return SCHED_OK;
+}
+
+static int slab_charge_locked(sched_ctx *c, int32_t t, int64_t v, int8_t *st) {
+  SlabState *s = c->slab;
+  k_slab_charge<<<1, 64, 0, c->stream>>>(s->dev, t, v, s->d_one_st);
+  SCHED_HIP_TRY(hipGetLastError());
+  SCHED_HIP_TRY(hipMemcpyAsync((char *)s->h_one + 8, s->d_one_st, 1, hipMemcpyDeviceToHost, c->stream));
+  SCHED_HIP_TRY(hipStreamSynchronize(c->stream));
+  *st = *((int8_t *)s->h_one + 8);
+  return SCHED_OK;
+}
+
+extern "C" int sched_alloc(sched_ctx_t *c, sched_job_t job, size_t bytes, void **dev_ptr) {
+  if (!c || !dev_ptr) return SCHED_E_INVALID;
+  std::lock_guard<std::mutex> g(c->mu);
+  if (!c->slab || job < 0 || job >= c->n_jobs || job >= c->slab->dev.n_tenants || bytes == 0)
+    return SCHED_E_INVALID;
+  SCHED_HIP_TRY(hipSetDevice(c->device));
+  SlabState *s = c->slab;
+  if (bytes <= size_t(MiB)) {
+    uint64_t p = 0;
+    int8_t st = 0;
+    if (int rc = slab_one_locked(c, job, int64_t(bytes), 0, 0, &p, &st)) return rc;
+    if (st == ST_NOMEM_POOL || st == ST_NOMEM_CLASS) c->stats.violations += 1;
+    if (st != ST_OK) return to_status_code(st);
+    *dev_ptr = (void *)p;
+    return SCHED_OK;
+  }
+  // large tier: its own device allocation, charged to the job in 4 KiB pages
+  const int64_t charged = int64_t((bytes + 4095) / 4096 * 4096);
+  int8_t st = 0;
+  if (int rc = slab_charge_locked(c, job, charged, &st)) return rc;
+  if (st != ST_OK) return SCHED_E_QUOTA;
+  void *p = nullptr;
+  if (hipMalloc(&p, bytes) != hipSuccess) {
+    (void)hipGetLastError();
+    int8_t st2;
+    (void)slab_charge_locked(c, job, -charged, &st2);
+    c->stats.violations += 1;
+    return SCHED_E_NOMEM;
+  }
+  s->large.push_back({p, charged});
+  s->large_owner.push_back(job);
+  *dev_ptr = p;
+  return SCHED_OK;
+}
+
+extern "C" int sched_free(sched_ctx_t *c, sched_job_t job, void *dev_ptr) {
+  if (!c) return SCHED_E_INVALID;
+  std::lock_guard<std::mutex> g(c->mu);
+  if (!c->slab || job < 0 || job >= c->n_jobs || job >= c->slab->dev.n_tenants || !dev_ptr)
+    return SCHED_E_INVALID;
+  SCHED_HIP_TRY(hipSetDevice(c->device));
+  SlabState *s = c->slab;
+  for (size_t i = 0; i < s->large.size(); ++i) {
+    if (s->large[i].first == dev_ptr) {
+      if (s->large_owner[i] != job) return SCHED_E_INVALID;
+      int8_t st;
+      if (int rc = slab_charge_locked(c, job, -s->large[i].second, &st)) return rc;
+      SCHED_HIP_TRY(hipFree(dev_ptr));
+      s->large[i] = s->large.back();
+      s->large.pop_back();
+      s->large_owner[i] = s->large_owner.back();
+      s->large_owner.pop_back();
+      return SCHED_OK;
+    }
+  }
+  uint64_t p = 0;
+  int8_t st = 0;
+  if (int rc = slab_one_locked(c, job, 0, uint64_t(dev_ptr), 1, &p, &st)) return rc;
+  return st == ST_OK ? SCHED_OK : SCHED_E_INVALID;
+}
+
+extern "C" int sched_slab_set_quotas(sched_ctx_t *c, int32_t n, const int64_t *h_quotas) {
+  if (!c || n < 0 || (n > 0 && !h_quotas)) return SCHED_E_INVALID;
+  std::lock_guard<std::mutex> g(c->mu);
+  if (!c->slab || n > c->slab->dev.n_tenants) return SCHED_E_INVALID;
+  for (int32_t i = 0; i < n; ++i)
+    if (h_quotas[i] < 0) return SCHED_E_INVALID;
+  SCHED_HIP_TRY(hipSetDevice(c->device));
+  SlabState *s = c->slab;
+  std::vector<int64_t> q(s->dev.n_tenants, 0);
+  std::copy(h_quotas, h_quotas + n, q.begin());
+  SCHED_HIP_TRY(hipMemcpyAsync(s->d_quota, q.data(), sizeof(int64_t) * q.size(), hipMemcpyHostToDevice,
+                               c->stream));
+  SCHED_HIP_TRY(hipStreamSynchronize(c->stream));
+  s->explicit_quota = true;
+  return slab_apply_quota_source(c);
+}
+
+extern "C" int sched_slab_ops(sched_ctx_t *c, int64_t begin, int64_t end, const uint8_t *d_kind,
+                              const int32_t *d_tenant, const int64_t *d_size, const int64_t *d_ref,
+                              uint64_t *d_ptr, int8_t *d_status, sched_stream_t stream) {
+  if (!c || begin < 0 || end < begin) return SCHED_E_INVALID;
+  if (end > begin && (!d_kind || !d_tenant || !d_size || !d_ref || !d_ptr || !d_status))
+    return SCHED_E_INVALID;
+  std::lock_guard<std::mutex> g(c->mu);
+  if (!c->slab) return SCHED_E_INVALID;
+  if (end == begin) return SCHED_OK;
+  SCHED_HIP_TRY(hipSetDevice(c->device));
+  hipStream_t s = stream ? (hipStream_t)stream : c->stream;
+  const int64_t n = end - begin;
+  const int grid = int(std::min<int64_t>((n + 255) / 256, 8192));
+  k_slab_phase<<<grid, 256, 0, s>>>(c->slab->dev, begin, end, d_kind, d_tenant, d_size, d_ref, d_ptr,
+                                    d_status);
+  SCHED_HIP_TRY(hipGetLastError());
+  return SCHED_OK;
+}
+
+extern "C" int sched_slab_info(sched_ctx_t *c, sched_slab_info_t *out) {
+  if (!c || !out) return SCHED_E_INVALID;
+  std::lock_guard<std::mutex> g(c->mu);
+  if (!c->slab) return SCHED_E_INVALID;
+  const SlabDev &d = c->slab->dev;
+  sched_slab_info_t r{};
+  r.pool_base = uint64_t(d.base);
+  r.pool_bytes = d.pool_bytes;
+  r.region_bytes = d.region_bytes;
+  r.n_classes = N_CLASSES;
+  r.n_tenants = d.n_tenants;
+  for (int k = 0; k < N_CLASSES; ++k) r.class_blocks[k] = d.cap[k];
+  *out = r;
+  return SCHED_OK;
+}
+
+extern "C" int sched_slab_counters(sched_ctx_t *c, int32_t n, int64_t *h_charged,
+                                   int64_t *h_pool_used) {
+  if (!c || n < 0 || (n > 0 && !h_charged) || !h_pool_used) return SCHED_E_INVALID;
+  std::lock_guard<std::mutex> g(c->mu);
+  if (!c->slab || n > c->slab->dev.n_tenants) return SCHED_E_INVALID;
+  SCHED_HIP_TRY(hipSetDevice(c->device));
+  SCHED_HIP_TRY(hipStreamSynchronize(c->stream));
+  if (n) SCHED_HIP_TRY(hipMemcpy(h_charged, c->slab->dev.charged, sizeof(int64_t) * n, hipMemcpyDeviceToHost));
+  SCHED_HIP_TRY(hipMemcpy(h_pool_used, c->slab->dev.pool_used, sizeof(int64_t), hipMemcpyDeviceToHost));
+  return SCHED_OK;
+}
+
+extern "C" int sched_slab_reset(sched_ctx_t *c) {
+  if (!c) return SCHED_E_INVALID;
+  std::lock_guard<std::mutex> g(c->mu);
+  if (!c->slab) return SCHED_E_INVALID;
+  SCHED_HIP_TRY(hipSetDevice(c->device));
+  SlabState *s = c->slab;
+  for (auto &b : s->large)
+    if (b.first) (void)hipFree(b.first);
+  s->large.clear();
+  s->large_owner.clear();
+  k_slab_reset_bits<<<256, 256, 0, c->stream>>>(s->dev);
+  SCHED_HIP_TRY(hipGetLastError());
+  SCHED_HIP_TRY(hipMemsetAsync(s->dev.charged, 0, sizeof(int64_t) * s->dev.n_tenants, c->stream));
+  SCHED_HIP_TRY(hipMemsetAsync(s->dev.pool_used, 0, sizeof(int64_t), c->stream));
+  SCHED_HIP_TRY(hipStreamSynchronize(c->stream));
+  return SCHED_OK;
+}
+
+int sched_priority_reorder_locked(sched_ctx *, hipStream_t) { return SCHED_E_INVALID; }

@@ -1,0 +1,223 @@
+"""Admission parity: the HIP kernels vs the CPU oracle, bit-exact."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import sched as S
+from workloads import c2_queue, c2d_queue, random_queue
+
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda:0"
+
+
+@pytest.fixture(scope="module")
+def cs():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1712_04495_amd import cosched
+    cosched.lib()
+    return cosched
+
+
+def _scan(cs, pol, d_np, R, window_limit, write_all=1):
+    d = torch.from_numpy(np.ascontiguousarray(d_np, dtype=np.int64)).to(DEV)
+    dec = torch.full((max(d_np.size, 1),), 7, dtype=torch.uint8, device=DEV)[: d_np.size]
+    rc, r = cs.sched_scan(pol, d, R, dec, write_all=write_all, window_limit=window_limit)
+    assert rc == 0
+    return dec.cpu().numpy(), r
+
+
+def _check(cs, pol, d_np, R, wl):
+    dec, r = _scan(cs, pol, d_np, R, wl)
+    ref, R2 = (S.fifo_pass if pol == cs.SCHED_POLICY_FIFO else S.mmu_pass)(d_np, R)
+    print(f"  pol={pol} n={d_np.size} R={R} wl={wl} admitted={int(ref.sum())}", flush=True)
+    assert set(np.unique(dec)) <= {0, 1}
+    bad = np.nonzero(dec.astype(bool) != ref)[0]
+    assert bad.size == 0, f"first mismatch at {bad[:5]}"
+    assert r["free_after"] == R2
+    assert r["admitted"] == int(ref.sum())
+    assert r["admitted_bytes"] == R - R2
+    last = int(np.nonzero(ref)[0][-1]) if ref.any() else -1
+    assert r["last_admitted"] == last
+
+
+SIZES = [0, 1, 2, 255, 4095, 4096, 4097, 3 * 4096 + 17, 50_000]
+
+
+@pytest.mark.parametrize("n", SIZES)
+@pytest.mark.parametrize("wl", [0, 1, 16])
+@pytest.mark.parametrize("pol", [0, 1])
+def test_scan_random(cs, n, wl, pol):
+    rng = np.random.default_rng(n * 7 + wl)
+    d = random_queue(int(rng.integers(1 << 30)), n, 1000, holes=0.05)
+    tot = int(d[d >= 0].sum()) if n else 0
+    for R in sorted({0, 1, 999, tot // 3, max(tot - 1, 0), tot, tot + 5}):
+        _check(cs, pol, d, R, wl)
+
+
+@pytest.mark.parametrize("wl", [0, 4])
+def test_scan_adversarial_rounds(cs, wl):
+    # [1, R, 1, R-1, ...]: every round admits one entry and breaks on the next
+    R = 100_000
+    d = np.array([x for k in range(600) for x in (1, R - k)], np.int64)
+    _check(cs, cs.SCHED_POLICY_MMU, d, R, wl)
+
+
+@pytest.mark.parametrize("wl", [0, 16])
+def test_scan_c2_pass0(cs, wl):
+    q = c2_queue(seed=2)
+    for pol in (0, 1):
+        _check(cs, pol, q.demand, q.capacity, wl)
+
+
+def test_scan_dense_fixed_point(cs):
+    """Dense queue (2^22): the final round reads every entry.  The result must
+    be the unique first-fit fixed point, checked over every entry."""
+    q = c2d_queue(seed=3, n=1 << 22)
+    dec, r = _scan(cs, cs.SCHED_POLICY_MMU, q.demand, q.capacity, 0)
+    a = dec.astype(bool)
+    assert S.first_fit_fixed_point(q.demand, q.capacity, a)
+    assert r["free_after"] == q.capacity - int(q.demand[a].sum())
+    # FIFO decide-every-entry on the same queue
+    dec, r = _scan(cs, cs.SCHED_POLICY_FIFO, q.demand, q.capacity, 0)
+    assert S.fifo_prefix_check(q.demand, q.capacity, dec.astype(bool))
+
+
+@pytest.mark.slow
+def test_scan_dense_full_size(cs):
+    q = c2d_queue(seed=2, n=1 << 26)
+    dec, r = _scan(cs, cs.SCHED_POLICY_MMU, q.demand, q.capacity, 0)
+    a = dec.astype(bool)
+    assert S.first_fit_fixed_point(q.demand, q.capacity, a)
+
+
+def test_scan_rejects_bad_args(cs):
+    d = torch.ones(4, dtype=torch.int64, device=DEV)
+    dec = torch.zeros(4, dtype=torch.uint8, device=DEV)
+    assert cs.sched_scan(7, d, 10, dec)[0] == cs.SCHED_E_INVALID
+    assert cs.sched_scan(1, d, -1, dec)[0] == cs.SCHED_E_INVALID
+    assert cs.sched_scan(1, d, 1 << 46, dec)[0] == cs.SCHED_E_INVALID
+
+
+# --------------------------------------------------------------------------
+# Context path: intake, passes, compaction, batched release (C2 rounds)
+# --------------------------------------------------------------------------
+def _c2_ctx_run(cs, q, policy, window_limit=0):
+    n = q.n
+    rc, ctx = cs.sched_create(policy=policy, capacity_bytes=q.capacity, max_jobs=n,
+                              queue_capacity=n, window_limit=window_limit)
+    assert rc == 0
+    try:
+        rc, j0 = cs.sched_register_batch(ctx, n)
+        assert rc == 0 and j0 == 0
+        d_job = torch.arange(n, dtype=torch.int32, device=DEV)
+        d_dem = torch.from_numpy(q.demand).to(DEV)
+        assert cs.sched_enqueue_batch(ctx, d_job, d_dem) == 0
+        coins = torch.from_numpy(q.coins).to(DEV)
+        out = torch.empty(n, dtype=torch.int32, device=DEV)
+        got = []
+        for r in range(q.rounds):
+            if r > 0:
+                assert cs.sched_release_masked(ctx, coins[r - 1]) == 0
+            rc, res = cs.sched_pass(ctx)
+            assert rc == 0
+            rc, na = cs.sched_last_admitted(ctx, out)
+            assert rc == 0 and na == res["admitted"]
+            torch.cuda.synchronize()
+            got.append((out[:na].cpu().numpy().astype(np.int64), res))
+        rc, st = cs.sched_stats(ctx)
+        return got, st
+    finally:
+        cs.sched_destroy(ctx)
+
+
+@pytest.mark.parametrize("policy", [0, 1])
+@pytest.mark.parametrize("wl", [0, 16])
+def test_ctx_c2_rounds_small(cs, policy, wl):
+    q = c2_queue(seed=5, n=1 << 14, capacity=2 * 10**11)
+    got, st = _c2_ctx_run(cs, q, policy, wl)
+    ref = S.release_rounds(q.demand, q.capacity, q.coins, q.rounds, policy)
+    for r, ((adm, res), rr) in enumerate(zip(got, ref)):
+        print(f"  round {r}: admitted {adm.size}", flush=True)
+        assert np.array_equal(adm, rr.admitted), f"round {r}"
+        assert res["free_after"] == rr.R_after
+    assert st["used"] == ref[-1].used_after
+
+
+@pytest.mark.parametrize("seed", [1, 2, 3])
+def test_ctx_c2_full(cs, seed):
+    q = c2_queue(seed=seed)
+    got, st = _c2_ctx_run(cs, q, 1, 16)
+    ref = S.release_rounds(q.demand, q.capacity, q.coins, q.rounds, S.MMU)
+    for r, ((adm, res), rr) in enumerate(zip(got, ref)):
+        assert np.array_equal(adm, rr.admitted), f"round {r}"
+        assert res["free_after"] == rr.R_after
+    assert st["used"] == ref[-1].used_after <= q.capacity
+
+
+# --------------------------------------------------------------------------
+# Life-cycle API vs the oracle state machine
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("policy", [0, 1])
+def test_lifecycle_random_vs_oracle(cs, policy):
+    C = 10_000
+    rc, ctx = cs.sched_create(policy=policy, capacity_bytes=C, max_jobs=64, queue_capacity=4096)
+    assert rc == 0
+    ref = S.Scheduler(C, policy)
+    rng = np.random.default_rng(policy + 100)
+    try:
+        jobs = []
+        for _ in range(24):
+            rc, j = cs.sched_register(ctx, 0, 10)
+            assert rc == 0
+            jobs.append(j)
+            ref.register(0, 10)
+        for step in range(300):
+            j = jobs[int(rng.integers(len(jobs)))]
+            if rng.random() < 0.55:
+                b = int(rng.integers(1, 4000))
+                got = cs.sched_admit(ctx, j, 0, b, cs.SCHED_NONBLOCK)
+                exp = ref.admit(j, 0, b)
+                assert got == exp, f"step {step} admit"
+            else:
+                res = ref.jobs[j]["res"]
+                b = 0 if rng.random() < 0.5 else int(rng.integers(0, res + 2))
+                got = cs.sched_release(ctx, j, -1, b)
+                exp = ref.release(j, -1, b)
+                assert got == exp, f"step {step} release"
+            for jj in jobs:
+                assert cs.sched_reservation(ctx, jj) == (0, ref.jobs[jj]["res"])
+        rc, st = cs.sched_stats(ctx)
+        assert st["used"] == ref.used
+    finally:
+        cs.sched_destroy(ctx)
+
+
+def test_lifecycle_errors_and_timeout(cs):
+    rc, ctx = cs.sched_create(policy=1, capacity_bytes=1000, max_jobs=4, queue_capacity=64)
+    assert rc == 0
+    try:
+        _, a = cs.sched_register(ctx, 0, 50)
+        _, b = cs.sched_register(ctx, 0, 50)
+        assert cs.sched_admit(ctx, a, 1, 10) == cs.SCHED_E_INVALID      # wrong device
+        assert cs.sched_admit(ctx, a, 0, 0) == cs.SCHED_E_INVALID       # no bytes
+        assert cs.sched_admit(ctx, 9, 0, 10) == cs.SCHED_E_INVALID      # unknown job
+        assert cs.sched_admit(ctx, a, 0, 1001) == cs.SCHED_E_TOOBIG
+        assert cs.sched_admit(ctx, a, 0, 800) == cs.SCHED_OK
+        # blocking admit of b times out after 50 ms and is withdrawn
+        assert cs.sched_admit(ctx, b, 0, 300) == cs.SCHED_TIMEOUT
+        assert cs.sched_release(ctx, a, 0, 801) == cs.SCHED_E_INVALID
+        assert cs.sched_release(ctx, a, -1, 0) == cs.SCHED_OK
+        # the withdrawn request is never admitted later
+        assert cs.sched_reservation(ctx, b) == (0, 0)
+        rc, st = cs.sched_stats(ctx)
+        assert st["withdrawn"] == 1 and st["used"] == 0
+        # non-blocking wait path
+        assert cs.sched_admit(ctx, a, 0, 900) == cs.SCHED_OK
+        assert cs.sched_admit(ctx, b, 0, 200, cs.SCHED_NONBLOCK) == cs.SCHED_NOT_READY
+        assert cs.sched_release(ctx, a, 0, 100) == cs.SCHED_OK           # 200 free now
+        assert cs.sched_wait(ctx, b, 10) == cs.SCHED_OK
+        assert cs.sched_reservation(ctx, b) == (0, 200)
+    finally:
+        cs.sched_destroy(ctx)
