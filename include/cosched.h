@@ -288,6 +288,43 @@ int sched_slab_counters(sched_ctx_t *ctx, int32_t n, int64_t *h_charged, int64_t
 /* Frees every block and clears all charges. */
 int sched_slab_reset(sched_ctx_t *ctx);
 
+/* ======================================================================== */
+/* Synthetic tenant jobs                                                     */
+/* ======================================================================== */
+/* The paper co-schedules third-party applications (Sec. VI); the jobs here
+ * are three synthetic kinds with plain definitions.  Contents come from
+ * SplitMix64 (Steele, Lea, Flood 2014) with state seed << 32: output i is
+ * h_i.  All pointers are device pointers; every call is stream-ordered on
+ * `stream` (NULL = the null stream) and returns SCHED_E_INVALID for bad
+ * sizes, NULL or misaligned pointers. */
+#define SCHED_HIST_BINS 4096
+
+/* b[i] = 1 + (h_i & 0xFFFF) / 2^16, c[i] = 1 + ((h_i >> 16) & 0xFFFF) / 2^16. */
+int sched_triad_fill(float *b, float *c, int64_t n, uint64_t seed, sched_stream_t stream);
+
+/* iters sweeps of the STREAM triad a[i] = b[i] + s * c[i] over n fp32
+ * elements, one kernel launch per sweep.  a, b, c 16-byte aligned. */
+int sched_triad(float *a, const float *b, const float *c, float s, int64_t n, int32_t iters,
+                sched_stream_t stream);
+
+/* keys[i] = low 32 bits of h_i. */
+int sched_hist_fill(uint32_t *keys, int64_t n, uint64_t seed, sched_stream_t stream);
+
+/* bins[b] = #{i : (keys[i] & mask) == b} for SCHED_HIST_BINS bins; bins is
+ * zeroed by the call; mask < SCHED_HIST_BINS (4095: all bins; 63: the skewed
+ * case); keys 16-byte aligned. */
+int sched_hist(const uint32_t *keys, int64_t n, uint32_t mask, uint32_t *bins,
+               sched_stream_t stream);
+
+/* x[r * K + k] = bf16 bits of ((h_{r*K+k} & 255) - 128) / 64 (exact). */
+int sched_gemm_fill(uint16_t *x, int64_t rows, int64_t K, uint64_t seed, sched_stream_t stream);
+
+/* C[m * N + n] = sum_k A[m * K + k] * Bt[n * K + k]: bf16 inputs (raw bits),
+ * fp32 accumulation on MFMA, fp32 output.  M and N multiples of 128, K a
+ * multiple of 64; A and Bt 16-byte aligned. */
+int sched_gemm_bf16(const uint16_t *A, const uint16_t *Bt, float *C, int64_t M, int64_t N,
+                    int64_t K, sched_stream_t stream);
+
 /* Library version string. */
 const char *sched_version(void);
 

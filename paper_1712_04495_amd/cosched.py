@@ -91,6 +91,12 @@ _SIGS = {
     "sched_slab_info": (i32, [vp, C.POINTER(sched_slab_info_t)]),
     "sched_slab_counters": (i32, [vp, i32, C.POINTER(i64), C.POINTER(i64)]),
     "sched_slab_reset": (i32, [vp]),
+    "sched_triad_fill": (i32, [vp, vp, i64, u64, vp]),
+    "sched_triad": (i32, [vp, vp, vp, C.c_float, i64, i32, vp]),
+    "sched_hist_fill": (i32, [vp, i64, u64, vp]),
+    "sched_hist": (i32, [vp, i64, u32, vp, vp]),
+    "sched_gemm_fill": (i32, [vp, i64, i64, u64, vp]),
+    "sched_gemm_bf16": (i32, [vp, vp, vp, i64, i64, i64, vp]),
     "sched_version": (C.c_char_p, []),
 }
 
@@ -258,6 +264,35 @@ def sched_slab_counters(ctx, n):
 
 def sched_slab_reset(ctx):
     return lib().sched_slab_reset(ctx)
+
+
+# ---------------------------------------------------------- tenant jobs
+SCHED_HIST_BINS = 4096
+
+
+def sched_triad_fill(b, c, seed, stream=None):
+    return lib().sched_triad_fill(_ptr(b), _ptr(c), int(b.numel()), seed, _stream(stream))
+
+
+def sched_triad(a, b, c, s, iters=10, stream=None):
+    return lib().sched_triad(_ptr(a), _ptr(b), _ptr(c), float(s), int(a.numel()), iters,
+                             _stream(stream))
+
+
+def sched_hist_fill(keys, seed, stream=None):
+    return lib().sched_hist_fill(_ptr(keys), int(keys.numel()), seed, _stream(stream))
+
+
+def sched_hist(keys, bins, mask=4095, stream=None):
+    return lib().sched_hist(_ptr(keys), int(keys.numel()), mask, _ptr(bins), _stream(stream))
+
+
+def sched_gemm_fill(x, rows, K, seed, stream=None):
+    return lib().sched_gemm_fill(_ptr(x), rows, K, seed, _stream(stream))
+
+
+def sched_gemm_bf16(A, Bt, Cout, M, N, K, stream=None):
+    return lib().sched_gemm_bf16(_ptr(A), _ptr(Bt), _ptr(Cout), M, N, K, _stream(stream))
 
 
 def sched_version():

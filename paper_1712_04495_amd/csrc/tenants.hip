@@ -1,0 +1,290 @@
+// Synthetic tenant jobs that the co-scheduler runs side by side:
+//   * STREAM triad a = b + s*c in fp32 (HBM streaming);
+//   * histogram of uint32 keys into 4096 bins (HBM streaming + LDS atomics);
+//   * C = A * B^T with bf16 inputs and fp32 accumulation on MFMA (the one
+//     dense contraction).
+// Input contents are generated on the device from SplitMix64 (Steele, Lea,
+// Flood 2014): output i of the generator whose state starts at s0 is the
+// finaliser applied to s0 + (i + 1) * golden-gamma.
+#include <algorithm>
+
+#include "common.h"
+
+namespace {
+
+__device__ __forceinline__ uint64_t splitmix(uint64_t s0, uint64_t i) {
+  uint64_t z = s0 + (i + 1) * 0x9E3779B97F4A7C15ULL;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
+  return z ^ (z >> 31);
+}
+
+int grid_cap(int64_t items, int threads, int cap) {
+  int64_t g = (items + threads - 1) / threads;
+  return int(std::max<int64_t>(1, std::min<int64_t>(g, cap)));
+}
+
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+
+// ------------------------------------------------------------------- triad
+__global__ void k_triad_fill(float *__restrict__ b, float *__restrict__ c, int64_t n, uint64_t s0) {
+  for (int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; i < n;
+       i += int64_t(gridDim.x) * blockDim.x) {
+    const uint64_t h = splitmix(s0, uint64_t(i));
+    b[i] = 1.0f + float(h & 0xFFFF) * (1.0f / 65536.0f);
+    c[i] = 1.0f + float((h >> 16) & 0xFFFF) * (1.0f / 65536.0f);
+  }
+}
+
+// 16-byte vectors; the scalar tail (n % 4) is done by the first threads.
+__global__ __launch_bounds__(256) void k_triad(float *__restrict__ a, const float *__restrict__ b,
+                                               const float *__restrict__ c, float s, int64_t n) {
+  const int64_t nv = n >> 2;
+  const f32x4 *__restrict__ b4 = reinterpret_cast<const f32x4 *>(b);
+  const f32x4 *__restrict__ c4 = reinterpret_cast<const f32x4 *>(c);
+  f32x4 *__restrict__ a4 = reinterpret_cast<f32x4 *>(a);
+  const int64_t stride = int64_t(gridDim.x) * blockDim.x;
+  int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
+  for (; i + 3 * stride < nv; i += 4 * stride) {
+    f32x4 x[4], y[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      x[u] = __builtin_nontemporal_load(b4 + i + u * stride);
+      y[u] = __builtin_nontemporal_load(c4 + i + u * stride);
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) __builtin_nontemporal_store(x[u] + s * y[u], a4 + i + u * stride);
+  }
+  for (; i < nv; i += stride) a4[i] = b4[i] + s * c4[i];
+  const int64_t t = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
+  if (t < (n & 3)) {
+    const int64_t j = (nv << 2) + t;
+    a[j] = b[j] + s * c[j];
+  }
+}
+
+// --------------------------------------------------------------- histogram
+__global__ void k_hist_fill(uint32_t *__restrict__ keys, int64_t n, uint64_t s0) {
+  for (int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; i < n;
+       i += int64_t(gridDim.x) * blockDim.x)
+    keys[i] = uint32_t(splitmix(s0, uint64_t(i)));
+}
+
+constexpr int HIST_THREADS = 256;
+constexpr int HIST_COPIES = HIST_THREADS / 64;  // one sub-histogram per wave
+
+__global__ __launch_bounds__(HIST_THREADS) void k_hist(const uint32_t *__restrict__ keys, int64_t n,
+                                                       uint32_t mask, uint32_t *__restrict__ bins) {
+  __shared__ uint32_t h[HIST_COPIES][SCHED_HIST_BINS];
+  for (int i = threadIdx.x; i < HIST_COPIES * SCHED_HIST_BINS; i += HIST_THREADS)
+    (&h[0][0])[i] = 0;
+  __syncthreads();
+  uint32_t *mine = h[threadIdx.x / 64];
+  const int64_t nv = n >> 2;
+  const u32x4 *__restrict__ k4 = reinterpret_cast<const u32x4 *>(keys);
+  const int64_t stride = int64_t(gridDim.x) * HIST_THREADS;
+  for (int64_t i = blockIdx.x * int64_t(HIST_THREADS) + threadIdx.x; i < nv; i += stride) {
+    const u32x4 v = __builtin_nontemporal_load(k4 + i);
+    atomicAdd(&mine[v.x & mask], 1u);
+    atomicAdd(&mine[v.y & mask], 1u);
+    atomicAdd(&mine[v.z & mask], 1u);
+    atomicAdd(&mine[v.w & mask], 1u);
+  }
+  const int64_t t = blockIdx.x * int64_t(HIST_THREADS) + threadIdx.x;
+  if (t < (n & 3)) atomicAdd(&mine[keys[(nv << 2) + t] & mask], 1u);
+  __syncthreads();
+  for (int b = threadIdx.x; b < SCHED_HIST_BINS; b += HIST_THREADS) {
+    uint32_t s = 0;
+#pragma unroll
+    for (int k = 0; k < HIST_COPIES; ++k) s += h[k][b];
+    if (s) atomicAdd(&bins[b], s);
+  }
+}
+
+__global__ void k_zero_u32(uint32_t *p, int64_t n) {
+  for (int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; i < n;
+       i += int64_t(gridDim.x) * blockDim.x)
+    p[i] = 0;
+}
+
+// -------------------------------------------------------------------- GEMM
+__global__ void k_gemm_fill(uint16_t *__restrict__ x, int64_t rows, int64_t K, uint64_t s0) {
+  const int64_t n = rows * K;
+  for (int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; i < n;
+       i += int64_t(gridDim.x) * blockDim.x) {
+    const uint64_t h = splitmix(s0, uint64_t(i));
+    const float v = (float(int(h & 0xFF)) - 128.0f) * (1.0f / 64.0f);
+    x[i] = uint16_t(__float_as_uint(v) >> 16);  // exact: v has 8 significant bits
+  }
+}
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+
+constexpr int BM = 128, BN = 128, BK = 64;
+constexpr int GT = 256;            // 4 waves, 2 x 2, each 64 x 64
+constexpr int LDS_ROW = BK + 8;    // bf16 per LDS row: 144 B, breaks bank aliasing
+
+// Each thread moves 4 x 16 B of A and 4 x 16 B of B per BK step: rows r =
+// (tid >> 3) + 32 j, columns (tid & 7) * 8 .. +8.
+struct Stage {
+  u32x4 r0, r1, r2, r3;
+};
+__device__ __forceinline__ Stage g2r(const uint16_t *__restrict__ src, int64_t ld, int64_t row0,
+                                     int64_t k0) {
+  const int c = (threadIdx.x & 7) * 8;
+  const uint16_t *p = src + (row0 + (threadIdx.x >> 3)) * ld + k0 + c;
+  Stage s;
+  s.r0 = *reinterpret_cast<const u32x4 *>(p);
+  s.r1 = *reinterpret_cast<const u32x4 *>(p + 32 * ld);
+  s.r2 = *reinterpret_cast<const u32x4 *>(p + 64 * ld);
+  s.r3 = *reinterpret_cast<const u32x4 *>(p + 96 * ld);
+  return s;
+}
+__device__ __forceinline__ void r2s(uint16_t *dst, const Stage &s) {
+  const int c = (threadIdx.x & 7) * 8;
+  uint16_t *p = dst + (threadIdx.x >> 3) * LDS_ROW + c;
+  *reinterpret_cast<u32x4 *>(p) = s.r0;
+  *reinterpret_cast<u32x4 *>(p + 32 * LDS_ROW) = s.r1;
+  *reinterpret_cast<u32x4 *>(p + 64 * LDS_ROW) = s.r2;
+  *reinterpret_cast<u32x4 *>(p + 96 * LDS_ROW) = s.r3;
+}
+
+// C[m][n] = sum_k A[m][k] * Bt[n][k]; M % 128 == N % 128 == K % 64 == 0.
+// Blocks are ordered so that consecutive workgroups (spread over the XCDs)
+// walk a column of C tiles, sharing the B^T panel through the MALL.
+__global__ __launch_bounds__(GT) void k_gemm_bf16(const uint16_t *__restrict__ A,
+                                                  const uint16_t *__restrict__ Bt,
+                                                  float *__restrict__ C, int64_t M, int64_t N,
+                                                  int64_t K) {
+  __shared__ __attribute__((aligned(16))) uint16_t sA[2][BM * LDS_ROW];
+  __shared__ __attribute__((aligned(16))) uint16_t sB[2][BN * LDS_ROW];
+  const int64_t tiles_m = M / BM;
+  const int64_t bm = blockIdx.x % tiles_m, bn = blockIdx.x / tiles_m;
+  const int64_t m0 = bm * BM, n0 = bn * BN;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int wm = (wave >> 1) * 64, wn = (wave & 1) * 64;
+
+  f32x16 acc[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.0f;
+
+  Stage ra = g2r(A, K, m0, 0);
+  Stage rb = g2r(Bt, K, n0, 0);
+  r2s(sA[0], ra);
+  r2s(sB[0], rb);
+  __syncthreads();
+
+  const int nk = int(K / BK);
+  // operand fragment: row (lane & 31), k offset (lane >> 5) * 8 within a 16-wide k step
+  const int frow = lane & 31, fk = (lane >> 5) * 8;
+  for (int kb = 0; kb < nk; ++kb) {
+    const int cur = kb & 1;
+    if (kb + 1 < nk) {
+      ra = g2r(A, K, m0, int64_t(kb + 1) * BK);
+      rb = g2r(Bt, K, n0, int64_t(kb + 1) * BK);
+    }
+    const uint16_t *a_s = sA[cur];
+    const uint16_t *b_s = sB[cur];
+#pragma unroll
+    for (int ks = 0; ks < BK; ks += 16) {
+      bf16x8 fa[2], fb[2];
+#pragma unroll
+      for (int i = 0; i < 2; ++i) {
+        fa[i] = *reinterpret_cast<const bf16x8 *>(a_s + (wm + 32 * i + frow) * LDS_ROW + ks + fk);
+        fb[i] = *reinterpret_cast<const bf16x8 *>(b_s + (wn + 32 * i + frow) * LDS_ROW + ks + fk);
+      }
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa[i], fb[j], acc[i][j], 0, 0, 0);
+    }
+    if (kb + 1 < nk) {
+      r2s(sA[cur ^ 1], ra);
+      r2s(sB[cur ^ 1], rb);
+    }
+    __syncthreads();
+  }
+  // D layout of a 32 x 32 block: lane -> column (lane & 31); register r -> row
+  // 8 * (r / 4) + 4 * (lane / 32) + (r % 4).
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int64_t row = m0 + wm + 32 * i + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+        const int64_t col = n0 + wn + 32 * j + (lane & 31);
+        C[row * N + col] = acc[i][j][r];
+      }
+}
+
+}  // namespace
+
+extern "C" int sched_triad_fill(float *b, float *c, int64_t n, uint64_t seed, sched_stream_t st) {
+  if (n < 0 || (n > 0 && (!b || !c))) return SCHED_E_INVALID;
+  if (n == 0) return SCHED_OK;
+  k_triad_fill<<<grid_cap(n, 256, 8192), 256, 0, (hipStream_t)st>>>(b, c, n, seed << 32);
+  SCHED_HIP_TRY(hipGetLastError());
+  return SCHED_OK;
+}
+
+extern "C" int sched_triad(float *a, const float *b, const float *c, float s, int64_t n, int32_t iters,
+                           sched_stream_t st) {
+  if (n < 0 || iters < 0 || (n > 0 && (!a || !b || !c))) return SCHED_E_INVALID;
+  if ((uintptr_t(a) | uintptr_t(b) | uintptr_t(c)) & 15) return SCHED_E_INVALID;
+  if (n == 0) return SCHED_OK;
+  const int grid = grid_cap((n + 3) / 4, 256 * 4, 256 * 16);
+  for (int32_t it = 0; it < iters; ++it) {
+    k_triad<<<grid, 256, 0, (hipStream_t)st>>>(a, b, c, s, n);
+    SCHED_HIP_TRY(hipGetLastError());
+  }
+  return SCHED_OK;
+}
+
+extern "C" int sched_hist_fill(uint32_t *keys, int64_t n, uint64_t seed, sched_stream_t st) {
+  if (n < 0 || (n > 0 && !keys)) return SCHED_E_INVALID;
+  if (n == 0) return SCHED_OK;
+  k_hist_fill<<<grid_cap(n, 256, 8192), 256, 0, (hipStream_t)st>>>(keys, n, seed << 32);
+  SCHED_HIP_TRY(hipGetLastError());
+  return SCHED_OK;
+}
+
+extern "C" int sched_hist(const uint32_t *keys, int64_t n, uint32_t mask, uint32_t *bins,
+                          sched_stream_t st) {
+  if (n < 0 || !bins || (n > 0 && !keys) || mask >= SCHED_HIST_BINS) return SCHED_E_INVALID;
+  if (uintptr_t(keys) & 15) return SCHED_E_INVALID;
+  k_zero_u32<<<4, 256, 0, (hipStream_t)st>>>(bins, SCHED_HIST_BINS);
+  SCHED_HIP_TRY(hipGetLastError());
+  if (n == 0) return SCHED_OK;
+  k_hist<<<grid_cap((n + 3) / 4, HIST_THREADS * 8, 256 * 4), HIST_THREADS, 0, (hipStream_t)st>>>(
+      keys, n, mask, bins);
+  SCHED_HIP_TRY(hipGetLastError());
+  return SCHED_OK;
+}
+
+extern "C" int sched_gemm_fill(uint16_t *x, int64_t rows, int64_t K, uint64_t seed, sched_stream_t st) {
+  if (rows < 0 || K < 0 || (rows * K > 0 && !x)) return SCHED_E_INVALID;
+  if (rows * K == 0) return SCHED_OK;
+  k_gemm_fill<<<grid_cap(rows * K, 256, 8192), 256, 0, (hipStream_t)st>>>(x, rows, K, seed << 32);
+  SCHED_HIP_TRY(hipGetLastError());
+  return SCHED_OK;
+}
+
+extern "C" int sched_gemm_bf16(const uint16_t *A, const uint16_t *Bt, float *C, int64_t M, int64_t N,
+                               int64_t K, sched_stream_t st) {
+  if (M <= 0 || N <= 0 || K <= 0 || !A || !Bt || !C) return SCHED_E_INVALID;
+  if (M % BM || N % BN || K % BK) return SCHED_E_INVALID;
+  if ((uintptr_t(A) | uintptr_t(Bt)) & 15) return SCHED_E_INVALID;
+  const int64_t blocks = (M / BM) * (N / BN);
+  if (blocks > 0x7fffffff) return SCHED_E_INVALID;
+  k_gemm_bf16<<<int(blocks), GT, 0, (hipStream_t)st>>>(A, Bt, C, M, N, K);
+  SCHED_HIP_TRY(hipGetLastError());
+  return SCHED_OK;
+}

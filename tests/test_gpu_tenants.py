@@ -1,0 +1,110 @@
+"""Tenant kernels vs the oracle references: triad bit-exact (its values are
+exact in fp32), histogram bit-exact, bf16 GEMM within 2e-2 relative of the
+fp64 product of the exact bf16 inputs."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import tenants as T
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+
+
+@pytest.fixture(scope="module")
+def cs():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1712_04495_amd import cosched
+    cosched.lib()
+    return cosched
+
+
+@pytest.mark.parametrize("n", [1, 3, 4, 1023, 4096 * 257 + 5, 3_000_001])
+def test_triad_exact(cs, n):
+    b = torch.empty(n, dtype=torch.float32, device=DEV)
+    c = torch.empty_like(b)
+    a = torch.full_like(b, -1.0)
+    assert cs.sched_triad_fill(b, c, 7) == 0
+    assert cs.sched_triad(a, b, c, 3.0, 10) == 0
+    torch.cuda.synchronize()
+    idx = np.arange(n)
+    bb, cc = T.triad_inputs(7, idx)
+    assert np.array_equal(b.cpu().numpy().astype(np.float64), bb)
+    assert np.array_equal(c.cpu().numpy().astype(np.float64), cc)
+    assert np.array_equal(a.cpu().numpy().astype(np.float64), T.triad_ref(7, idx))
+
+
+def test_triad_large_sampled(cs):
+    n = (1 << 28) + 12345                       # 1 GiB per array
+    b = torch.empty(n, dtype=torch.float32, device=DEV)
+    c = torch.empty_like(b)
+    a = torch.empty_like(b)
+    assert cs.sched_triad_fill(b, c, 11) == 0
+    assert cs.sched_triad(a, b, c, 3.0, 2) == 0
+    rng = np.random.default_rng(0)
+    idx = np.unique(np.concatenate([rng.integers(0, n, 100_000), np.arange(n - 64, n)]))
+    got = a[torch.from_numpy(idx).to(DEV)].cpu().numpy().astype(np.float64)
+    assert np.array_equal(got, T.triad_ref(11, idx))
+
+
+@pytest.mark.parametrize("n,mask", [(0, 4095), (1, 4095), (7, 4095), (1 << 20, 4095),
+                                    (3 * (1 << 20) + 3, 63), (1 << 24, 4095)])
+def test_hist_exact(cs, n, mask):
+    keys = torch.empty(max(n, 1), dtype=torch.int32, device=DEV)[:n]
+    bins = torch.full((4096,), 123, dtype=torch.int32, device=DEV)
+    assert cs.sched_hist_fill(keys, 5) == 0
+    assert cs.sched_hist(keys, bins, mask) == 0
+    torch.cuda.synchronize()
+    ref = T.hist_ref(5, n, mask=mask)
+    got = bins.cpu().numpy().astype(np.int64)
+    assert np.array_equal(got, ref) and got.sum() == n
+
+
+def _gemm(cs, M, N, K, sa=1, sb=2):
+    A = torch.empty(M * K, dtype=torch.int16, device=DEV)
+    B = torch.empty(N * K, dtype=torch.int16, device=DEV)
+    C = torch.full((M * N,), float("nan"), dtype=torch.float32, device=DEV)
+    assert cs.sched_gemm_fill(A, M, K, sa) == 0
+    assert cs.sched_gemm_fill(B, N, K, sb) == 0
+    assert cs.sched_gemm_bf16(A, B, C, M, N, K) == 0
+    torch.cuda.synchronize()
+    return A, B, C.view(M, N)
+
+
+def test_gemm_operands_exact(cs):
+    A = torch.empty(4 * 64, dtype=torch.int16, device=DEV)
+    assert cs.sched_gemm_fill(A, 4, 64, 9) == 0
+    got = A.view(torch.bfloat16).float().cpu().numpy().astype(np.float64).reshape(4, 64)
+    assert np.array_equal(got, T.gemm_operand(9, np.arange(4), 64))
+
+
+@pytest.mark.parametrize("M,N,K", [(128, 128, 64), (256, 384, 192), (1024, 1024, 1024)])
+def test_gemm_full(cs, M, N, K):
+    _, _, C = _gemm(cs, M, N, K)
+    ref = T.gemm_ref_full(1, 2, M, N, K)
+    got = C.cpu().numpy().astype(np.float64)
+    err = np.abs(got - ref) / np.maximum(np.abs(ref), 1.0)
+    assert err.max() <= 2e-2, err.max()
+
+
+@pytest.mark.parametrize("N", [2048, 4096, 8192])
+def test_gemm_sampled(cs, N):
+    _, _, C = _gemm(cs, N, N, N, 3, 4)
+    rng = np.random.default_rng(N)
+    mi = rng.integers(0, N, 512)
+    ni = rng.integers(0, N, 512)
+    mi[:2] = [0, N - 1]
+    ni[:2] = [0, N - 1]
+    ref = T.gemm_ref_entries(3, 4, N, mi, ni)
+    got = C[torch.from_numpy(mi).to(DEV), torch.from_numpy(ni).to(DEV)].cpu().numpy()
+    err = np.abs(got - ref) / np.maximum(np.abs(ref), 1.0)
+    assert err.max() <= 2e-2, err.max()
+
+
+def test_tenant_bad_args(cs):
+    x = torch.zeros(130, dtype=torch.int16, device=DEV)
+    c = torch.zeros(4, dtype=torch.float32, device=DEV)
+    assert cs.sched_gemm_bf16(x, x, c, 100, 128, 64) == cs.SCHED_E_INVALID
+    k = torch.zeros(8, dtype=torch.int32, device=DEV)
+    assert cs.sched_hist(k, torch.zeros(4096, dtype=torch.int32, device=DEV), 4096) == cs.SCHED_E_INVALID
