@@ -1,0 +1,220 @@
+#!/usr/bin/env python3
+"""Benchmark of the co-scheduler hot path on one MI355X.
+
+Default workload (the admission microbenchmark): a queue of 2^20 pending
+requests whose demands are log-uniform in [4 KiB, 4 GiB) (4 KiB aligned),
+capacity 280e9 B, first-fit admission (FIFO prefix + backfill, the paper's
+MMU policy), 8 rounds of "release a coin-chosen half of the running jobs,
+then one admission pass".  One step = reset + intake of the 2^20 requests +
+the 8 release/admit rounds; inputs are resident in HBM before timing.
+
+Prints one JSON line.  `value` is admissions per second over the timed
+steps.  `roofline` reports the dominant kernel of the step with its
+algorithmic bytes per launch over its event-timed average duration;
+`cpu_baseline` is the CPU oracle timed on the host on the same workload;
+`dense_scan` reports the HBM-bound variant (one first-fit pass that reads a
+2^26-entry queue) against the HBM peak.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "jobs/s + p99 turnaround, co-scheduled vs serial; admissions/s (GB/s of HBM)"
+HBM_PEAK_GBS = 8000.0
+
+
+def parse():
+    ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=30)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--seed", type=int, default=2)
+    ap.add_argument("--queue-log2", type=int, default=20)
+    ap.add_argument("--dense-log2", type=int, default=26)
+    ap.add_argument("--dense-reps", type=int, default=10)
+    ap.add_argument("--cpu-seconds", type=float, default=12.0,
+                    help="bound on the oracle's CPU time for cpu_baseline (0 = skip)")
+    ap.add_argument("--no-profile", action="store_true",
+                    help="time the steps without kernel events (no roofline)")
+    return ap.parse_args()
+
+
+def c2_step(cs, ctx, d_job, d_dem, coins):
+    assert cs.sched_reset(ctx) == 0
+    assert cs.sched_enqueue_batch(ctx, d_job, d_dem) == 0
+    admitted = 0
+    scanned = 0
+    compacted = 0
+    per_pass = []
+    for r in range(coins.shape[0] + 1):
+        if r > 0:
+            assert cs.sched_release_masked(ctx, coins[r - 1]) == 0
+        rc, res = cs.sched_pass(ctx)
+        assert rc == 0
+        admitted += res["admitted"]
+        scanned += res["scanned"]
+        compacted += res["compacted"]
+        per_pass.append((res["admitted"], res["free_after"]))
+    return admitted, scanned, compacted, per_pass
+
+
+def cpu_baseline_c2(q, seconds):
+    """The oracle as it stands, on host cores, on whole C2 steps."""
+    from oracle import sched as S
+    t0 = time.perf_counter()
+    steps = 0
+    admitted = 0
+    per_pass = None
+    while True:
+        res = S.release_rounds(q.demand, q.capacity, q.coins, q.rounds, S.MMU)
+        admitted += sum(int(r.admitted.size) for r in res)
+        per_pass = [(int(r.admitted.size), int(r.R_after)) for r in res]
+        steps += 1
+        if time.perf_counter() - t0 >= seconds:
+            break
+    dt = time.perf_counter() - t0
+    return {"value": admitted / dt, "unit": "admissions/s", "cores": 1, "kind": "oracle",
+            "sample": f"{steps} full steps (8 release/admit passes over 2^{q.n.bit_length() - 1} "
+                      f"requests) in {dt:.1f} s, pure numpy/Python, one thread"}, per_pass
+
+
+def main():
+    args = parse()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; the admission state is "
+                                   "per device (see DESIGN.md on sharding)", "n_gpus": args.gpus}))
+        return 2
+
+    import numpy as np
+    import torch
+
+    from paper_1712_04495_amd import cosched as cs
+    from workloads import c2_queue, c2d_queue
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    dev = "cuda:0"
+    cs.lib()
+    n = 1 << args.queue_log2
+    q = c2_queue(seed=args.seed, n=n)
+    rc, ctx = cs.sched_create(policy=cs.SCHED_POLICY_MMU, capacity_bytes=q.capacity, max_jobs=n,
+                              queue_capacity=n, window_limit=16)
+    assert rc == 0, rc
+    rc, j0 = cs.sched_register_batch(ctx, n)
+    assert rc == 0 and j0 == 0
+    d_job = torch.arange(n, dtype=torch.int32, device=dev)
+    d_dem = torch.from_numpy(q.demand).to(dev)
+    coins = torch.from_numpy(q.coins).to(dev)
+    torch.cuda.synchronize()
+
+    for _ in range(args.warmup):
+        c2_step(cs, ctx, d_job, d_dem, coins)
+    profile = not args.no_profile
+    cs.sched_profile(profile)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    tot_adm = tot_scan = tot_comp = 0
+    last = None
+    for _ in range(args.steps):
+        a, s_, c_, last = c2_step(cs, ctx, d_job, d_dem, coins)
+        tot_adm += a
+        tot_scan += s_
+        tot_comp += c_
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    kern = {}
+    if profile:
+        for k in ("k_window", "k_round", "k_compact", "k_release_masked"):
+            rc, ms, launches = cs.sched_profile_read(k)
+            kern[k] = (ms, launches)
+        cs.sched_profile(0)
+    cs.sched_destroy(ctx)
+
+    out = {
+        "metric": METRIC,
+        "value": tot_adm / dt,
+        "unit": "admissions/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * dt / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "int64",
+        "data": "synthetic",
+        "config": {"workload": f"admission microbench: 2^{args.queue_log2} requests, demands "
+                               "log-uniform 4 KiB-4 GiB (4 KiB aligned), capacity 280e9 B, "
+                               "MMU (FIFO prefix + first-fit backfill), 8 release/admit rounds",
+                   "queue": n, "rounds": q.rounds, "capacity_bytes": q.capacity,
+                   "policy": "mmu", "seed": args.seed,
+                   "admissions_per_step": tot_adm // args.steps,
+                   "us_per_pass": 1e6 * dt / args.steps / q.rounds},
+    }
+    if profile:
+        # algorithmic bytes: 8 B demand read + 1 B decision per decided entry
+        # (scan kernels); 25 B read + 24 B written per entry of the compacted
+        # window (compaction); 17 B per job slot for the masked release
+        alg = {"k_window": 9 * tot_scan, "k_round": 0, "k_compact": 49 * tot_comp,
+               "k_release_masked": 17 * n * (q.rounds - 1) * args.steps}
+        if kern["k_round"][1]:
+            alg["k_window"], alg["k_round"] = 0, 9 * tot_scan  # attributed below if both ran
+            if kern["k_window"][1]:
+                alg["k_window"] = 9 * tot_scan * kern["k_window"][0] / (
+                    kern["k_window"][0] + kern["k_round"][0])
+                alg["k_round"] = 9 * tot_scan - alg["k_window"]
+        dom = max(kern, key=lambda k: kern[k][0])
+        ms, launches = kern[dom]
+        avg_s = ms * 1e-3 / max(launches, 1)
+        bytes_per_launch = alg[dom] / max(launches, 1)
+        ach = bytes_per_launch / avg_s / 1e9 if avg_s > 0 else 0.0
+        out["roofline"] = {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                           "frac": ach / HBM_PEAK_GBS, "traffic": None, "kernel": dom,
+                           "avg_launch_us": avg_s * 1e6, "bytes_per_launch": bytes_per_launch,
+                           "kernels_ms_per_step": {k: v[0] / args.steps for k, v in kern.items()}}
+
+    # ---- dense first-fit pass: every entry must be read (HBM-bound) -------
+    if args.dense_log2 > 0:
+        qd = c2d_queue(seed=args.seed, n=1 << args.dense_log2)
+        dd = torch.from_numpy(qd.demand).to(dev)
+        dec = torch.zeros(qd.n, dtype=torch.uint8, device=dev)
+        rc, r0 = cs.sched_scan(cs.SCHED_POLICY_MMU, dd, qd.capacity, dec)
+        assert rc == 0
+        cs.sched_profile(True)
+        t1 = time.perf_counter()
+        for _ in range(args.dense_reps):
+            rc, r = cs.sched_scan(cs.SCHED_POLICY_MMU, dd, qd.capacity, dec)
+            assert rc == 0
+        torch.cuda.synchronize()
+        ddt = (time.perf_counter() - t1) / args.dense_reps
+        rc, ms, launches = cs.sched_profile_read("k_round")
+        cs.sched_profile(0)
+        from oracle import sched as S
+        ok = S.first_fit_fixed_point(qd.demand, qd.capacity, dec.cpu().numpy().astype(bool))
+        bytes_pass = 9 * qd.n     # each entry read once (8 B) + its decision (1 B)
+        kern_s = ms * 1e-3 / args.dense_reps
+        out["dense_scan"] = {
+            "entries": qd.n, "rounds": r["rounds"], "pass_ms": ddt * 1e3,
+            "round_kernels_ms": kern_s * 1e3, "round_launches_per_pass": launches / args.dense_reps,
+            "GBps_pass": bytes_pass / ddt / 1e9, "GBps_kernels": bytes_pass / kern_s / 1e9,
+            "frac_of_peak": bytes_pass / kern_s / 1e9 / HBM_PEAK_GBS, "fixed_point_ok": bool(ok)}
+        del dd, dec
+
+    if args.cpu_seconds > 0:
+        cb, ref_pass = cpu_baseline_c2(q, args.cpu_seconds)
+        out["cpu_baseline"] = cb
+        out["parity_last_step"] = ref_pass == [(int(a), int(b)) for a, b in last]
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

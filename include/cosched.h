@@ -105,6 +105,7 @@ typedef struct {
   int64_t rounds;          /* first-fit rounds (1 for FIFO)                    */
   int64_t scanned;         /* queue entries the pass decided                   */
   int64_t pending_after;   /* requests still waiting                           */
+  int64_t compacted;       /* queue entries the compaction step rewrote        */
 } sched_pass_result_t;
 
 /* ======================================================================== */
@@ -159,6 +160,11 @@ int sched_wait(sched_ctx_t *ctx, sched_job_t job, int32_t timeout_ms);
  * bytes exceeds the job's reservation, bytes < 0 or the device is not the
  * context's; nothing changes on error. */
 int sched_release(sched_ctx_t *ctx, sched_job_t job, int32_t device, int64_t bytes);
+
+/* Returns the context to its state right after sched_create with every job
+ * still registered: empty queue, no reservations, used = 0.  Slab blocks are
+ * not touched (sched_slab_reset does that).  Synchronises. */
+int sched_reset(sched_ctx_t *ctx);
 
 /* Counters; see sched_stats_t. */
 int sched_stats(sched_ctx_t *ctx, sched_stats_t *out);
@@ -324,6 +330,19 @@ int sched_gemm_fill(uint16_t *x, int64_t rows, int64_t K, uint64_t seed, sched_s
  * multiple of 64; A and Bt 16-byte aligned. */
 int sched_gemm_bf16(const uint16_t *A, const uint16_t *Bt, float *C, int64_t M, int64_t N,
                     int64_t K, sched_stream_t stream);
+
+/* ======================================================================== */
+/* Kernel timing                                                             */
+/* ======================================================================== */
+/* enable != 0 starts bracketing every library kernel launch with a pair of
+ * HIP events on the launch's stream and clears the totals; 0 stops it. */
+int sched_profile(int32_t enable);
+
+/* Total device time in ms and launch count of the kernel named `kernel`
+ * (k_window, k_round, k_compact, k_release_masked, k_triad, k_hist,
+ * k_gemm_bf16, k_slab_phase, ...) since sched_profile(1).  Waits for the
+ * recorded events. */
+int sched_profile_read(const char *kernel, double *total_ms, int64_t *launches);
 
 /* Library version string. */
 const char *sched_version(void);

@@ -53,7 +53,7 @@ class sched_stats_t(C.Structure):
 
 class sched_pass_result_t(C.Structure):
     _fields_ = [(n, i64) for n in ("admitted", "admitted_bytes", "free_before", "free_after",
-                                   "rounds", "scanned", "pending_after")]
+                                   "rounds", "scanned", "pending_after", "compacted")]
 
 
 class sched_scan_result_t(C.Structure):
@@ -97,6 +97,9 @@ _SIGS = {
     "sched_hist": (i32, [vp, i64, u32, vp, vp]),
     "sched_gemm_fill": (i32, [vp, i64, i64, u64, vp]),
     "sched_gemm_bf16": (i32, [vp, vp, vp, i64, i64, i64, vp]),
+    "sched_reset": (i32, [vp]),
+    "sched_profile": (i32, [i32]),
+    "sched_profile_read": (i32, [C.c_char_p, C.POINTER(C.c_double), C.POINTER(i64)]),
     "sched_version": (C.c_char_p, []),
 }
 
@@ -293,6 +296,21 @@ def sched_gemm_fill(x, rows, K, seed, stream=None):
 
 def sched_gemm_bf16(A, Bt, Cout, M, N, K, stream=None):
     return lib().sched_gemm_bf16(_ptr(A), _ptr(Bt), _ptr(Cout), M, N, K, _stream(stream))
+
+
+def sched_reset(ctx):
+    return lib().sched_reset(ctx)
+
+
+def sched_profile(enable):
+    return lib().sched_profile(1 if enable else 0)
+
+
+def sched_profile_read(kernel):
+    ms = C.c_double()
+    n = i64()
+    rc = lib().sched_profile_read(kernel.encode(), C.byref(ms), C.byref(n))
+    return rc, ms.value, n.value
 
 
 def sched_version():

@@ -29,6 +29,7 @@
 #include <cstring>
 
 #include "admission.h"
+#include "prof.h"
 
 namespace schedk {
 
@@ -536,7 +537,9 @@ static int drive_rounds(AdmEngine &e, const int64_t *demand, uint8_t *decision, 
   uint32_t L = uint32_t(e.launch);
   bool done = false;
   if (window_limit > 0) {
-    k_window<<<1, WIN_THREADS, 0, s>>>(e.d_ctl, demand, decision, mask, L, window_limit);
+    SCHED_PROF_LAUNCH("k_window", s,
+                      (k_window<<<1, WIN_THREADS, 0, s>>>(e.d_ctl, demand, decision, mask, L,
+                                                          window_limit)));
     SCHED_HIP_TRY(hipGetLastError());
     L = advance(e);
     if (int rc = sync_ctl(e, s)) return rc;
@@ -551,7 +554,9 @@ static int drive_rounds(AdmEngine &e, const int64_t *demand, uint8_t *decision, 
     for (int i = 0; i < e.rounds_per_check; ++i) {
       uint32_t ep;
       if (int rc = next_epoch(e, s, &ep)) return rc;
-      k_round<<<grid, RND_THREADS, 0, s>>>(e.d_ctl, demand, decision, mask, e.d_flags, L, ep);
+      SCHED_PROF_LAUNCH("k_round", s,
+                        (k_round<<<grid, RND_THREADS, 0, s>>>(e.d_ctl, demand, decision, mask,
+                                                              e.d_flags, L, ep)));
       SCHED_HIP_TRY(hipGetLastError());
       L = advance(e);
     }
@@ -587,7 +592,7 @@ int adm_pass_ctx(AdmEngine &e, int policy, const QueueArrays &q, int window_limi
 }
 
 int adm_compact(AdmEngine &e, const QueueArrays &q, const JobArrays &j, hipStream_t s) {
-  k_compact<<<1, WIN_THREADS, 0, s>>>(e.d_ctl, q, j);
+  SCHED_PROF_LAUNCH("k_compact", s, (k_compact<<<1, WIN_THREADS, 0, s>>>(e.d_ctl, q, j)));
   SCHED_HIP_TRY(hipGetLastError());
   return SCHED_OK;
 }
@@ -595,7 +600,8 @@ int adm_compact(AdmEngine &e, const QueueArrays &q, const JobArrays &j, hipStrea
 int adm_release_masked(AdmEngine &e, const JobArrays &j, const uint8_t *mask, int64_t n,
                        hipStream_t s) {
   if (n <= 0) return SCHED_OK;
-  k_release_masked<<<grid_for(n, 256, 1024), 256, 0, s>>>(e.d_ctl, j, mask, n);
+  SCHED_PROF_LAUNCH("k_release_masked", s,
+                    (k_release_masked<<<grid_for(n, 256, 1024), 256, 0, s>>>(e.d_ctl, j, mask, n)));
   SCHED_HIP_TRY(hipGetLastError());
   return SCHED_OK;
 }

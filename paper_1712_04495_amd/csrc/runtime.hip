@@ -276,6 +276,7 @@ int sched_run_pass_locked(sched_ctx *c, hipStream_t s, sched_pass_result_t *res)
     res->rounds = po.rounds;
     res->scanned = po.start_final - head_before;
     res->pending_after = h.tail - h.head;
+    res->compacted = po.hi - head_before;
   }
   c->cv.notify_all();
   return SCHED_OK;
@@ -537,6 +538,37 @@ extern "C" int sched_scan(int32_t policy, int64_t n, const int64_t *d_demand, in
   out->free_after = po.R_after;
   out->rounds = po.rounds;
   out->last_admitted = po.hi - 1 >= 0 && po.admitted > 0 ? po.hi - 1 : -1;
+  return SCHED_OK;
+}
+
+__global__ void k_reset_jobs(DevCtl *c, JobArrays jb) {
+  for (int64_t j = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; j < jb.max_jobs;
+       j += int64_t(gridDim.x) * blockDim.x) {
+    jb.res[j] = 0;
+    jb.state[j] = 0;
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    c->used = 0;
+    c->head = 0;
+    c->tail = 0;
+    c->released_bytes = 0;
+    c->released_jobs = 0;
+  }
+}
+
+extern "C" int sched_reset(sched_ctx_t *c) {
+  if (!c) return SCHED_E_INVALID;
+  std::lock_guard<std::mutex> g(c->mu);
+  SCHED_HIP_TRY(hipSetDevice(c->device));
+  k_reset_jobs<<<256, 256, 0, c->stream>>>(c->eng.d_ctl, c->jb);
+  SCHED_HIP_TRY(hipGetLastError());
+  if (int rc = adm_zero_decisions(c->q.decision, c->q.capacity, c->stream)) return rc;
+  SCHED_HIP_TRY(hipStreamSynchronize(c->stream));
+  c->host_seq.clear();
+  std::fill(c->pending.begin(), c->pending.end(), 0);
+  c->head_h = c->tail_h = c->used_h = 0;
+  c->last_A = 0;
+  c->cv.notify_all();
   return SCHED_OK;
 }
 

@@ -22,6 +22,7 @@
 #include <mutex>
 #include <vector>
 
+#include "prof.h"
 #include "runtime.h"
 
 using namespace schedk;
@@ -409,8 +410,9 @@ extern "C" int sched_slab_ops(sched_ctx_t *c, int64_t begin, int64_t end, const 
   hipStream_t s = stream ? (hipStream_t)stream : c->stream;
   const int64_t n = end - begin;
   const int grid = int(std::min<int64_t>((n + 255) / 256, 8192));
-  k_slab_phase<<<grid, 256, 0, s>>>(c->slab->dev, begin, end, d_kind, d_tenant, d_size, d_ref, d_ptr,
-                                    d_status);
+  SCHED_PROF_LAUNCH("k_slab_phase", s,
+                    (k_slab_phase<<<grid, 256, 0, s>>>(c->slab->dev, begin, end, d_kind, d_tenant,
+                                                       d_size, d_ref, d_ptr, d_status)));
   SCHED_HIP_TRY(hipGetLastError());
   return SCHED_OK;
 }

@@ -9,6 +9,7 @@
 #include <algorithm>
 
 #include "common.h"
+#include "prof.h"
 
 namespace {
 
@@ -242,7 +243,8 @@ extern "C" int sched_triad(float *a, const float *b, const float *c, float s, in
   if (n == 0) return SCHED_OK;
   const int grid = grid_cap((n + 3) / 4, 256 * 4, 256 * 16);
   for (int32_t it = 0; it < iters; ++it) {
-    k_triad<<<grid, 256, 0, (hipStream_t)st>>>(a, b, c, s, n);
+    SCHED_PROF_LAUNCH("k_triad", (hipStream_t)st,
+                      (k_triad<<<grid, 256, 0, (hipStream_t)st>>>(a, b, c, s, n)));
     SCHED_HIP_TRY(hipGetLastError());
   }
   return SCHED_OK;
@@ -263,8 +265,9 @@ extern "C" int sched_hist(const uint32_t *keys, int64_t n, uint32_t mask, uint32
   k_zero_u32<<<4, 256, 0, (hipStream_t)st>>>(bins, SCHED_HIST_BINS);
   SCHED_HIP_TRY(hipGetLastError());
   if (n == 0) return SCHED_OK;
-  k_hist<<<grid_cap((n + 3) / 4, HIST_THREADS * 8, 256 * 4), HIST_THREADS, 0, (hipStream_t)st>>>(
-      keys, n, mask, bins);
+  SCHED_PROF_LAUNCH("k_hist", (hipStream_t)st,
+                    (k_hist<<<grid_cap((n + 3) / 4, HIST_THREADS * 8, 256 * 4), HIST_THREADS, 0,
+                              (hipStream_t)st>>>(keys, n, mask, bins)));
   SCHED_HIP_TRY(hipGetLastError());
   return SCHED_OK;
 }
@@ -284,7 +287,8 @@ extern "C" int sched_gemm_bf16(const uint16_t *A, const uint16_t *Bt, float *C, 
   if ((uintptr_t(A) | uintptr_t(Bt)) & 15) return SCHED_E_INVALID;
   const int64_t blocks = (M / BM) * (N / BN);
   if (blocks > 0x7fffffff) return SCHED_E_INVALID;
-  k_gemm_bf16<<<int(blocks), GT, 0, (hipStream_t)st>>>(A, Bt, C, M, N, K);
+  SCHED_PROF_LAUNCH("k_gemm_bf16", (hipStream_t)st,
+                    (k_gemm_bf16<<<int(blocks), GT, 0, (hipStream_t)st>>>(A, Bt, C, M, N, K)));
   SCHED_HIP_TRY(hipGetLastError());
   return SCHED_OK;
 }

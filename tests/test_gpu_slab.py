@@ -70,14 +70,39 @@ def test_c3_small_matches_sequential(cs, n_ops):
 
 @pytest.mark.parametrize("seed", [3, 4])
 def test_c3s_stressed_invariants(cs, seed):
-    ops = c3s_ops(seed=seed, n_ops=1 << 18)
-    ops.phase_len = 1 << 12
+    # 2^18 ops hold ~1/16 of the full run's live memory: tighten quotas and
+    # pool by the same factor so that every limit binds
+    ops = c3_ops(seed=seed, n_ops=1 << 18, phase_len=1 << 12, pool=64 << 20, quota_div=64 * 16)
     st, ptr, info, cap, charged, pool_used = run_ops(cs, ops)
     res = A.check_log(ops.kind, ops.tenant, ops.size, ops.ref, ops.quotas, ops.pool, cap,
                       ops.phase_len, st, ptr, info["pool_base"], final_charged=charged,
                       final_pool=pool_used, span=13 * info["region_bytes"])
     print("  ", {k: v for k, v in res.items() if isinstance(v, int)}, flush=True)
-    assert res["quota"] + res["nomem_pool"] + res["nomem_class"] > 0   # limits do bind
+    assert res["quota"] > 0 and res["nomem_pool"] + res["nomem_class"] > 0   # limits bind
+
+
+@pytest.mark.slow
+def test_c3_full_size(cs):
+    """C3 as configured: 2^22 ops in 64 phases of 2^16; nothing binds, so the
+    statuses equal the sequential simulation exactly."""
+    ops = c3_ops(seed=3)
+    st, ptr, info, cap, charged, pool_used = run_ops(cs, ops)
+    seq = A.simulate(ops.kind, ops.tenant, ops.size, ops.ref, ops.quotas, ops.pool, cap)
+    assert np.array_equal(st.astype(np.int64), seq.astype(np.int64))
+    A.check_log(ops.kind, ops.tenant, ops.size, ops.ref, ops.quotas, ops.pool, cap, ops.phase_len,
+                st, ptr, info["pool_base"], final_charged=charged, final_pool=pool_used,
+                span=13 * info["region_bytes"])
+
+
+@pytest.mark.slow
+def test_c3s_full_size(cs):
+    ops = c3s_ops(seed=3)
+    st, ptr, info, cap, charged, pool_used = run_ops(cs, ops)
+    res = A.check_log(ops.kind, ops.tenant, ops.size, ops.ref, ops.quotas, ops.pool, cap,
+                      ops.phase_len, st, ptr, info["pool_base"], final_charged=charged,
+                      final_pool=pool_used, span=13 * info["region_bytes"])
+    print("  ", {k: v for k, v in res.items() if isinstance(v, int)}, flush=True)
+    assert res["quota"] > 0
 
 
 def test_lifecycle_alloc_free_quota(cs):
