@@ -40,6 +40,8 @@ def parse():
     ap.add_argument("--queue-log2", type=int, default=20)
     ap.add_argument("--dense-log2", type=int, default=26)
     ap.add_argument("--dense-reps", type=int, default=10)
+    ap.add_argument("--dense-window", type=int, default=1,
+                    help="single-wave windows before the grid rounds take over")
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
                     help="bound on the oracle's CPU time for cpu_baseline (0 = skip)")
     ap.add_argument("--no-profile", action="store_true",
@@ -186,12 +188,13 @@ def main():
         qd = c2d_queue(seed=args.seed, n=1 << args.dense_log2)
         dd = torch.from_numpy(qd.demand).to(dev)
         dec = torch.zeros(qd.n, dtype=torch.uint8, device=dev)
-        rc, r0 = cs.sched_scan(cs.SCHED_POLICY_MMU, dd, qd.capacity, dec)
+        rc, r0 = cs.sched_scan(cs.SCHED_POLICY_MMU, dd, qd.capacity, dec, window_limit=args.dense_window)
         assert rc == 0
         cs.sched_profile(True)
         t1 = time.perf_counter()
         for _ in range(args.dense_reps):
-            rc, r = cs.sched_scan(cs.SCHED_POLICY_MMU, dd, qd.capacity, dec)
+            rc, r = cs.sched_scan(cs.SCHED_POLICY_MMU, dd, qd.capacity, dec,
+                                  window_limit=args.dense_window)
             assert rc == 0
         torch.cuda.synchronize()
         ddt = (time.perf_counter() - t1) / args.dense_reps

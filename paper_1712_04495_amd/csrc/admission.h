@@ -6,10 +6,14 @@
 
 namespace schedk {
 
-// Window kernel: one workgroup, 1024 threads x 4 entries.
-constexpr int WIN_THREADS = 1024;
-constexpr int WIN_ITEMS = 4;
+// Window kernel: one wave, 64 lanes x 16 consecutive entries.
+constexpr int WIN_THREADS = 64;
+constexpr int WIN_ITEMS = 16;
 constexpr int WIN = WIN_THREADS * WIN_ITEMS;
+// Compaction: one workgroup, 256 threads x 8 entries per chunk.
+constexpr int CMP_THREADS = 256;
+constexpr int CMP_ITEMS = 8;
+constexpr int CMP_CHUNK = CMP_THREADS * CMP_ITEMS;
 // Round kernel: 256 threads x 16 entries per tile.
 constexpr int RND_THREADS = 256;
 constexpr int RND_ITEMS = 16;
@@ -77,10 +81,11 @@ int adm_scan(AdmEngine &e, int policy, const int64_t *demand, uint8_t *decision,
              int64_t end, int64_t R0, int window_limit, hipStream_t s, PassOut *out);
 
 // Ctx form: R0 = capacity - used and [head, tail) are read on the device by
-// the prologue kernel.  Does not compact.
+// the prologue kernel; compaction and accounting follow.  Synchronises.
 struct QueueArrays;
-int adm_pass_ctx(AdmEngine &e, int policy, const QueueArrays &q, int window_limit,
-                 int64_t span_hint, hipStream_t s, PassOut *out);
+struct JobArrays;
+int adm_pass_ctx(AdmEngine &e, int policy, const QueueArrays &q, const JobArrays &jb,
+                 int window_limit, int64_t span_hint, hipStream_t s, PassOut *out);
 
 // Device-side state the context keeps per queue entry and per job.
 struct QueueArrays {
@@ -105,7 +110,8 @@ struct JobArrays {
 // and withdrawn holes leave, survivors are right-aligned, the admitted list is
 // written in queue order and the admitted demands are charged to their jobs
 // and to `used`.  Stream-ordered.
-int adm_compact(AdmEngine &e, const QueueArrays &q, const JobArrays &j, hipStream_t s);
+int adm_compact(AdmEngine &e, const QueueArrays &q, const JobArrays &j, hipStream_t s,
+                int slot = -1);
 
 int adm_zero_decisions(uint8_t *decision, int64_t n, hipStream_t s);
 int adm_release_masked(AdmEngine &e, const JobArrays &j, const uint8_t *mask, int64_t n,

@@ -73,21 +73,23 @@ __global__ void k_prologue(DevCtl *c, uint32_t L, int filter, int from_state, in
 }
 
 // ---------------------------------------------------------------------------
-// Single-workgroup windowed rounds
+// Single-wave windowed rounds
 // ---------------------------------------------------------------------------
+// One wave walks the queue in windows of WIN entries; lane l holds the WIN_ITEMS
+// consecutive entries starting at l * WIN_ITEMS, so a lane-local running sum
+// plus one wave-wide exclusive scan gives every entry its prefix in queue
+// order.  The break of a round is the lowest set bit of a ballot.  No LDS and
+// no barriers: every round costs a few dozen wave instructions.
 __global__ __launch_bounds__(WIN_THREADS) void k_window(DevCtl *c, const int64_t *__restrict__ demand,
                                                         uint8_t *__restrict__ decision, int64_t mask,
                                                         uint32_t L, int max_windows) {
-  __shared__ int64_t red[WIN_THREADS / WAVE];
-  __shared__ int64_t s_brk_sum;
-  const int tid = threadIdx.x;
+  const int lane = threadIdx.x;
   const int s = L & 3, nx = (L + 1) & 3;
   const RoundRec r = c->rec[s];
   const int64_t end = c->p_end;
   const bool filter = c->filter != 0;
   int64_t hi = c->p_hi;
-  __syncthreads();
-  if (tid == 0) reset_next_slot(c, L);
+  if (lane == 0) reset_next_slot(c, L);
   int64_t R = r.R, pos = r.start;
   int done = r.done;
   int64_t adm_cnt = 0, adm_bytes = 0, rounds = 0;
@@ -97,7 +99,7 @@ __global__ __launch_bounds__(WIN_THREADS) void k_window(DevCtl *c, const int64_t
       done = 1;
       break;
     }
-    const int64_t p0 = pos + int64_t(tid) * WIN_ITEMS;
+    const int64_t p0 = pos + int64_t(lane) * WIN_ITEMS;
     int64_t x[WIN_ITEMS];
 #pragma unroll
     for (int k = 0; k < WIN_ITEMS; ++k) x[k] = (p0 + k < end) ? demand[(p0 + k) & mask] : -1;
@@ -105,45 +107,43 @@ __global__ __launch_bounds__(WIN_THREADS) void k_window(DevCtl *c, const int64_t
     for (;;) {
       const int64_t cap = R + 1;
       int64_t incl[WIN_ITEMS];
-      bool cand[WIN_ITEMS];
       int64_t run = 0;
 #pragma unroll
       for (int k = 0; k < WIN_ITEMS; ++k) {
-        const int off = tid * WIN_ITEMS + k;
-        cand[k] = x[k] >= 0 && off >= s_loc && (!filter || x[k] <= R);
-        run = sat_add(run, cand[k] ? x[k] : 0, cap);
-        incl[k] = run;
+        const int off = lane * WIN_ITEMS + k;
+        const bool cd = x[k] >= 0 && off >= s_loc && (!filter || x[k] <= R);
+        run = sat_add(run, cd ? x[k] : 0, cap);
+        incl[k] = cd ? run : -1;  // -1 marks a non-candidate
       }
-      int64_t total;
-      const int64_t ex = block_excl_scan_sat<WIN_THREADS>(run, cap, red, &total);
-      int64_t my_first = WIN;
+      const int64_t wincl = wave_incl_scan_sat(run, cap);
+      int64_t ex = __shfl_up(wincl, 1, WAVE);
+      if (lane == 0) ex = 0;
+      const int64_t total = __shfl(wincl, WAVE - 1, WAVE);
+      int my_first = WIN_ITEMS;
+      int64_t my_before = ex;
 #pragma unroll
       for (int k = WIN_ITEMS - 1; k >= 0; --k) {
-        const int64_t P = sat_add(ex, incl[k], cap);
-        if (cand[k] && P > R) my_first = tid * WIN_ITEMS + k;
+        if (incl[k] >= 0 && sat_add(ex, incl[k], cap) > R) my_first = k;
       }
-      const int64_t first = block_min<WIN_THREADS>(my_first, red);
-      int64_t sum = total;
-      if (first < WIN) {
-        if (my_first == first) {
-          const int k = int(first - tid * WIN_ITEMS);
-          int64_t before = ex;
+      // prefix just before my_first: the last candidate before it, else ex
 #pragma unroll
-          for (int kk = 0; kk < WIN_ITEMS; ++kk)
-            if (kk == k - 1) before = sat_add(ex, incl[kk], cap);
-          s_brk_sum = before;
-        }
-        __syncthreads();
-        sum = s_brk_sum;
+      for (int k = 0; k < WIN_ITEMS; ++k)
+        if (k < my_first && incl[k] >= 0) my_before = sat_add(ex, incl[k], cap);
+      const uint64_t ball = __ballot(my_first < WIN_ITEMS);
+      int64_t first = WIN, sum = total;
+      if (ball) {
+        const int fl = __builtin_ctzll(ball);
+        first = int64_t(fl) * WIN_ITEMS + __shfl(my_first, fl, WAVE);
+        sum = __shfl(my_before, fl, WAVE);
       }
       const int64_t lim = (first < WIN) ? first + 1 : WIN;
       int64_t my_cnt = 0, my_max = -1;
 #pragma unroll
       for (int k = 0; k < WIN_ITEMS; ++k) {
-        const int off = tid * WIN_ITEMS + k;
+        const int off = lane * WIN_ITEMS + k;
         const int64_t p = p0 + k;
         if (off >= s_loc && off < lim && p < end) {
-          const bool a = cand[k] && off < first;
+          const bool a = incl[k] >= 0 && off < first;
           decision[p & mask] = a ? 1 : 0;
           if (a) {
             ++my_cnt;
@@ -151,9 +151,8 @@ __global__ __launch_bounds__(WIN_THREADS) void k_window(DevCtl *c, const int64_t
           }
         }
       }
-      const int64_t cnt = block_sum<WIN_THREADS>(my_cnt, red);
-      const int64_t mx = block_max<WIN_THREADS>(my_max, red);
-      adm_cnt += cnt;
+      adm_cnt += wave_sum(my_cnt);
+      const int64_t mx = wave_max(my_max);
       adm_bytes += sum;
       if (mx + 1 > hi) hi = mx + 1;
       R -= sum;
@@ -175,7 +174,7 @@ __global__ __launch_bounds__(WIN_THREADS) void k_window(DevCtl *c, const int64_t
     }
   }
   if (!done && (pos >= end || R == 0)) done = 1;
-  if (tid == 0) {
+  if (lane == 0) {
     c->rec[nx].R = R;
     c->rec[nx].start = pos < end ? pos : end;
     c->rec[nx].done = done;
@@ -234,39 +233,70 @@ __global__ __launch_bounds__(RND_THREADS) void k_round(DevCtl *c, const int64_t 
     const int64_t Araw = block_sum<RND_THREADS>(tsum, red);
     const int64_t A = Araw < cap ? Araw : cap;
 
-    if (tid == 0) {
+    if (tid < WAVE) {
+      // Wave 0 looks back 64 predecessors at a time: lane l reads the flag of
+      // tile p - l.  The nearest inclusive flag ends the walk once every
+      // nearer predecessor has published its aggregate.
+      const int lane = tid;
       int64_t E = 0;
       if (t == 0) {
-        st_relaxed(&flags[t], pack_flag(epoch, FL_INC, A));
+        if (lane == 0) st_relaxed(&flags[t], pack_flag(epoch, FL_INC, A));
       } else {
-        st_relaxed(&flags[t], pack_flag(epoch, FL_AGG, A));
+        if (lane == 0) st_relaxed(&flags[t], pack_flag(epoch, FL_AGG, A));
         long long p = t - 1;
         for (;;) {
-          const uint64_t f = ld_relaxed(&flags[p]);
+          const long long qq = p - lane;
+          const unsigned long long f =
+              qq >= 0 ? ld_relaxed(&flags[qq]) : pack_flag(epoch, FL_INC, 0);
           const uint64_t st = (f >> 46) & 3;
-          if (uint32_t(f >> 48) == epoch && st != 0) {
-            E = sat_add(E, int64_t(f & VMASK), cap);
-            if (st == FL_INC || E >= cap) break;
-            --p;
-          } else {
+          const bool valid = uint32_t(f >> 48) == epoch && st != 0;
+          const uint64_t inc_b = __ballot(valid && st == FL_INC);
+          const uint64_t bad_b = __ballot(!valid);
+          const int fi = inc_b ? __builtin_ctzll(inc_b) : WAVE;
+          const uint64_t need = fi >= WAVE - 1 ? ~0ULL : ((2ULL << fi) - 1);
+          if (bad_b & need) {
             // a predecessor that saw the break marker first may never publish
             if (ld_relaxed(&c->break_tile[s]) < t) {
               E = cap;
               break;
             }
             __builtin_amdgcn_s_sleep(1);
+            continue;
           }
+          const int64_t v = lane <= fi ? int64_t(f & VMASK) : 0;
+          const int64_t w = wave_sum(v);  // <= 64 * cap, no overflow
+          E = sat_add(E, w < cap ? w : cap, cap);
+          if (fi < WAVE || E >= cap) break;
+          p -= WAVE;
         }
-        st_relaxed(&flags[t], pack_flag(epoch, FL_INC, sat_add(E, A, cap)));
+        if (lane == 0) st_relaxed(&flags[t], pack_flag(epoch, FL_INC, sat_add(E, A, cap)));
       }
-      if (E <= R && sat_add(E, A, cap) > R) min_relaxed(&c->break_tile[s], (long long)t);
-      s_E = E;
+      if (lane == 0) {
+        if (E <= R && sat_add(E, A, cap) > R) min_relaxed(&c->break_tile[s], (long long)t);
+        s_E = E;
+      }
     }
     __syncthreads();
     const int64_t E = s_E;
     if (E > R) continue;  // the break lies in an earlier tile
 
     int64_t tcnt = 0, tmax = -1;
+    if (Araw == 0) {
+      // no candidate in this tile: every entry is rejected for good
+#pragma unroll
+      for (int j = 0; j < RND_ITEMS; ++j) {
+        const int64_t p = base + int64_t(j) * RND_THREADS + tid;
+        if (p < end) decision[p & mask] = 0;
+      }
+      if (tid == 0 && t == n_tiles - 1) {
+        add_relaxed(&c->p_admitted_bytes, E);
+        add_relaxed(&c->p_rounds, (int64_t)1);
+        c->rec[nx].R = R - E;
+        c->rec[nx].start = end;
+        c->rec[nx].done = 1;
+      }
+      continue;
+    }
     if (sat_add(E, A, cap) <= R) {
       // every candidate of this tile is admitted
 #pragma unroll
@@ -367,22 +397,26 @@ __global__ void k_fill_u8(uint8_t *p, int64_t n, uint8_t v) {
 // ---------------------------------------------------------------------------
 // Compaction + accounting (single workgroup, right to left over [head, hi))
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(WIN_THREADS) void k_compact(DevCtl *c, QueueArrays q, JobArrays jb) {
+// slot >= 0: run only if the pass recorded in rec[slot] is done (lets the host
+// enqueue compaction right after the window kernel without a round trip).
+__global__ __launch_bounds__(CMP_THREADS) void k_compact(DevCtl *c, QueueArrays q, JobArrays jb,
+                                                         int slot) {
+  if (slot >= 0 && !c->rec[slot].done) return;
   const int64_t mask = q.capacity - 1;
-  __shared__ int64_t red[WIN_THREADS / WAVE];
+  __shared__ int64_t red[CMP_THREADS / WAVE];
   const int tid = threadIdx.x;
   const int64_t head = c->head, hi = c->p_hi;
   int64_t surv_hi = hi;
   int64_t adm_hi = c->p_admitted;
-  for (int64_t chunk_hi = hi; chunk_hi > head; chunk_hi -= WIN) {
-    const int64_t chunk_lo = chunk_hi - WIN > head ? chunk_hi - WIN : head;
-    const int64_t p0 = chunk_lo + int64_t(tid) * WIN_ITEMS;
-    int64_t d[WIN_ITEMS], sq[WIN_ITEMS];
-    int32_t jo[WIN_ITEMS], pr[WIN_ITEMS];
-    uint8_t adm[WIN_ITEMS], sur[WIN_ITEMS];
+  for (int64_t chunk_hi = hi; chunk_hi > head; chunk_hi -= CMP_CHUNK) {
+    const int64_t chunk_lo = chunk_hi - CMP_CHUNK > head ? chunk_hi - CMP_CHUNK : head;
+    const int64_t p0 = chunk_lo + int64_t(tid) * CMP_ITEMS;
+    int64_t d[CMP_ITEMS], sq[CMP_ITEMS];
+    int32_t jo[CMP_ITEMS], pr[CMP_ITEMS];
+    uint8_t adm[CMP_ITEMS], sur[CMP_ITEMS];
     int64_t a_loc = 0, s_loc = 0;
 #pragma unroll
-    for (int k = 0; k < WIN_ITEMS; ++k) {
+    for (int k = 0; k < CMP_ITEMS; ++k) {
       const int64_t p = p0 + k;
       const bool valid = p < chunk_hi;
       const int64_t pm = p & mask;
@@ -397,12 +431,12 @@ __global__ __launch_bounds__(WIN_THREADS) void k_compact(DevCtl *c, QueueArrays 
       s_loc += sur[k];
     }
     int64_t total;
-    const int64_t ex = block_excl_scan<WIN_THREADS>((a_loc << 32) | s_loc, red, &total);
+    const int64_t ex = block_excl_scan<CMP_THREADS>((a_loc << 32) | s_loc, red, &total);
     const int64_t a_tot = total >> 32, s_tot = total & 0xffffffffLL;
     int64_t a_pos = adm_hi - a_tot + (ex >> 32);
     int64_t s_pos = surv_hi - s_tot + (ex & 0xffffffffLL);
 #pragma unroll
-    for (int k = 0; k < WIN_ITEMS; ++k) {
+    for (int k = 0; k < CMP_ITEMS; ++k) {
       const int64_t p = p0 + k;
       if (p >= chunk_hi) continue;
       q.decision[p & mask] = 0;
@@ -530,26 +564,27 @@ static int sync_ctl(AdmEngine &e, hipStream_t s) {
   return SCHED_OK;
 }
 
-// Runs the window kernel and then round kernels until the pass is done.  The
-// prologue has filled slot e.launch & 3.
-static int drive_rounds(AdmEngine &e, const int64_t *demand, uint8_t *decision, int64_t mask,
-                        int window_limit, int64_t span_hint, hipStream_t s, PassOut *out) {
-  uint32_t L = uint32_t(e.launch);
-  bool done = false;
-  if (window_limit > 0) {
-    SCHED_PROF_LAUNCH("k_window", s,
-                      (k_window<<<1, WIN_THREADS, 0, s>>>(e.d_ctl, demand, decision, mask, L,
-                                                          window_limit)));
-    SCHED_HIP_TRY(hipGetLastError());
-    L = advance(e);
-    if (int rc = sync_ctl(e, s)) return rc;
-    done = e.h_ctl->rec[L & 3].done != 0;
-  }
+static void fill_out(const AdmEngine &e, uint32_t L, PassOut *out) {
+  const DevCtl &h = *e.h_ctl;
+  out->admitted = h.p_admitted;
+  out->admitted_bytes = h.p_admitted_bytes;
+  out->R0 = h.p_R0;
+  out->R_after = h.rec[L & 3].R;
+  out->rounds = h.p_rounds;
+  out->start_final = h.rec[L & 3].start;
+  out->hi = h.p_hi;
+}
+
+// Round kernels until the pass recorded in slot L & 3 is done; returns the
+// launch id whose slot holds the final state.
+static int run_rounds(AdmEngine &e, const int64_t *demand, uint8_t *decision, int64_t mask,
+                      int64_t span_hint, hipStream_t s, uint32_t *Lio) {
+  uint32_t L = *Lio;
   const int grid = grid_for(span_hint, TILE, e.round_grid);
   // every round decides at least one entry, so a pass needs at most
   // span + 1 rounds; anything beyond that is an internal error
   int64_t budget = span_hint + 2 * e.rounds_per_check + 2;
-  while (!done) {
+  for (;;) {
     if ((budget -= e.rounds_per_check) < 0) return SCHED_E_INTERNAL;
     for (int i = 0; i < e.rounds_per_check; ++i) {
       uint32_t ep;
@@ -561,38 +596,67 @@ static int drive_rounds(AdmEngine &e, const int64_t *demand, uint8_t *decision, 
       L = advance(e);
     }
     if (int rc = sync_ctl(e, s)) return rc;
-    done = e.h_ctl->rec[L & 3].done != 0;
+    if (e.h_ctl->rec[L & 3].done) break;
   }
-  const DevCtl &h = *e.h_ctl;
-  out->admitted = h.p_admitted;
-  out->admitted_bytes = h.p_admitted_bytes;
-  out->R0 = h.p_R0;
-  out->R_after = h.rec[L & 3].R;
-  out->rounds = h.p_rounds;
-  out->start_final = h.rec[L & 3].start;
-  out->hi = h.p_hi;
+  *Lio = L;
+  return SCHED_OK;
+}
+
+static int launch_window(AdmEngine &e, const int64_t *demand, uint8_t *decision, int64_t mask,
+                         int window_limit, hipStream_t s, uint32_t *Lio) {
+  const uint32_t L = *Lio;
+  SCHED_PROF_LAUNCH("k_window", s,
+                    (k_window<<<1, WIN_THREADS, 0, s>>>(e.d_ctl, demand, decision, mask, L,
+                                                        window_limit)));
+  SCHED_HIP_TRY(hipGetLastError());
+  *Lio = advance(e);
   return SCHED_OK;
 }
 
 int adm_scan(AdmEngine &e, int policy, const int64_t *demand, uint8_t *decision, int64_t start,
              int64_t end, int64_t R0, int window_limit, hipStream_t s, PassOut *out) {
-  k_prologue<<<1, 64, 0, s>>>(e.d_ctl, uint32_t(e.launch), policy == SCHED_POLICY_MMU ? 1 : 0, 0, R0,
-                              start, end);
+  uint32_t L = uint32_t(e.launch);
+  k_prologue<<<1, 64, 0, s>>>(e.d_ctl, L, policy == SCHED_POLICY_MMU ? 1 : 0, 0, R0, start, end);
   SCHED_HIP_TRY(hipGetLastError());
-  return drive_rounds(e, demand, decision, -1, window_limit, end - start, s, out);
+  bool done = false;
+  if (window_limit > 0) {
+    if (int rc = launch_window(e, demand, decision, -1, window_limit, s, &L)) return rc;
+    if (int rc = sync_ctl(e, s)) return rc;
+    done = e.h_ctl->rec[L & 3].done != 0;
+  }
+  if (!done)
+    if (int rc = run_rounds(e, demand, decision, -1, end - start, s, &L)) return rc;
+  fill_out(e, L, out);
+  return SCHED_OK;
 }
 
-int adm_pass_ctx(AdmEngine &e, int policy, const QueueArrays &q, int window_limit,
-                 int64_t span_hint, hipStream_t s, PassOut *out) {
-  k_prologue<<<1, 64, 0, s>>>(e.d_ctl, uint32_t(e.launch), policy == SCHED_POLICY_MMU ? 1 : 0, 1, 0, 0,
-                              0);
+int adm_pass_ctx(AdmEngine &e, int policy, const QueueArrays &q, const JobArrays &jb,
+                 int window_limit, int64_t span_hint, hipStream_t s, PassOut *out) {
+  uint32_t L = uint32_t(e.launch);
+  k_prologue<<<1, 64, 0, s>>>(e.d_ctl, L, policy == SCHED_POLICY_MMU ? 1 : 0, 1, 0, 0, 0);
   SCHED_HIP_TRY(hipGetLastError());
-  return drive_rounds(e, q.demand, q.decision, q.capacity - 1, window_limit,
-                      span_hint > 0 ? span_hint : TILE, s, out);
+  const int64_t mask = q.capacity - 1;
+  if (span_hint <= 0) span_hint = TILE;
+  if (window_limit > 0) {
+    if (int rc = launch_window(e, q.demand, q.decision, mask, window_limit, s, &L)) return rc;
+    // compaction right behind the window kernel; it skips itself on the
+    // device when the pass still needs grid rounds
+    if (int rc = adm_compact(e, q, jb, s, int(L & 3))) return rc;
+    if (int rc = sync_ctl(e, s)) return rc;
+    if (e.h_ctl->rec[L & 3].done) {
+      fill_out(e, L, out);
+      return SCHED_OK;
+    }
+  }
+  if (int rc = run_rounds(e, q.demand, q.decision, mask, span_hint, s, &L)) return rc;
+  if (int rc = adm_compact(e, q, jb, s, -1)) return rc;
+  if (int rc = sync_ctl(e, s)) return rc;
+  fill_out(e, L, out);
+  return SCHED_OK;
 }
 
-int adm_compact(AdmEngine &e, const QueueArrays &q, const JobArrays &j, hipStream_t s) {
-  SCHED_PROF_LAUNCH("k_compact", s, (k_compact<<<1, WIN_THREADS, 0, s>>>(e.d_ctl, q, j)));
+int adm_compact(AdmEngine &e, const QueueArrays &q, const JobArrays &j, hipStream_t s, int slot) {
+  SCHED_PROF_LAUNCH("k_compact", s, (k_compact<<<1, CMP_THREADS, 0, s>>>(e.d_ctl, q, j, slot)));
   SCHED_HIP_TRY(hipGetLastError());
   return SCHED_OK;
 }

@@ -230,20 +230,19 @@ int sched_run_pass_locked(sched_ctx *c, hipStream_t s, sched_pass_result_t *res)
   if (c->policy == SCHED_POLICY_PRIO_FIFO || c->policy == SCHED_POLICY_PRIO_MMU) {
     if (int rc = sched_priority_reorder_locked(c, s)) return rc;
   }
-  if (int rc = adm_pass_ctx(c->eng, pol, c->q, c->window_limit, c->tail_h - c->head_h, s, &po))
+  if (int rc = adm_pass_ctx(c->eng, pol, c->q, c->jb, c->window_limit, c->tail_h - c->head_h, s,
+                            &po))
     return rc;
-  if (int rc = adm_compact(c->eng, c->q, c->jb, s)) return rc;
-  // read back the control block and the admitted list
+  // read back the admitted list when host-side requests wait on it
   const int64_t A = po.admitted;
-  SCHED_HIP_TRY(hipMemcpyAsync(c->eng.h_ctl, c->eng.d_ctl, sizeof(DevCtl), hipMemcpyDeviceToHost, s));
   const int64_t ncopy = std::min<int64_t>(A, c->h_adm_cap);
   if (!c->host_seq.empty() && ncopy > 0) {
     SCHED_HIP_TRY(hipMemcpyAsync(c->h_adm_job, c->q.adm_job, sizeof(int32_t) * ncopy,
                                  hipMemcpyDeviceToHost, s));
     SCHED_HIP_TRY(hipMemcpyAsync(c->h_adm_seq, c->q.adm_seq, sizeof(int64_t) * ncopy,
                                  hipMemcpyDeviceToHost, s));
+    SCHED_HIP_TRY(hipStreamSynchronize(s));
   }
-  SCHED_HIP_TRY(hipStreamSynchronize(s));
   c->last_admitted_seqs.clear();
   if (!c->host_seq.empty()) {
     if (A > c->h_adm_cap) {

@@ -71,23 +71,24 @@ def test_scan_c2_pass0(cs, wl):
         _check(cs, pol, q.demand, q.capacity, wl)
 
 
-def test_scan_dense_fixed_point(cs):
+@pytest.mark.parametrize("wl", [0, 1])
+def test_scan_dense_fixed_point(cs, wl):
     """Dense queue (2^22): the final round reads every entry.  The result must
     be the unique first-fit fixed point, checked over every entry."""
     q = c2d_queue(seed=3, n=1 << 22)
-    dec, r = _scan(cs, cs.SCHED_POLICY_MMU, q.demand, q.capacity, 0)
+    dec, r = _scan(cs, cs.SCHED_POLICY_MMU, q.demand, q.capacity, wl)
     a = dec.astype(bool)
     assert S.first_fit_fixed_point(q.demand, q.capacity, a)
     assert r["free_after"] == q.capacity - int(q.demand[a].sum())
     # FIFO decide-every-entry on the same queue
-    dec, r = _scan(cs, cs.SCHED_POLICY_FIFO, q.demand, q.capacity, 0)
+    dec, r = _scan(cs, cs.SCHED_POLICY_FIFO, q.demand, q.capacity, wl)
     assert S.fifo_prefix_check(q.demand, q.capacity, dec.astype(bool))
 
 
 @pytest.mark.slow
 def test_scan_dense_full_size(cs):
     q = c2d_queue(seed=2, n=1 << 26)
-    dec, r = _scan(cs, cs.SCHED_POLICY_MMU, q.demand, q.capacity, 0)
+    dec, r = _scan(cs, cs.SCHED_POLICY_MMU, q.demand, q.capacity, 1)
     a = dec.astype(bool)
     assert S.first_fit_fixed_point(q.demand, q.capacity, a)
 
