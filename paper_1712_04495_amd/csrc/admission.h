@@ -14,11 +14,9 @@ constexpr int WIN = WIN_THREADS * WIN_ITEMS;
 constexpr int CMP_THREADS = 256;
 constexpr int CMP_ITEMS = 8;
 constexpr int CMP_CHUNK = CMP_THREADS * CMP_ITEMS;
-// Round kernel: 256 threads x 32 entries per tile; the look-back reads
-// LB_CHUNKS x 64 predecessor flags per round trip.
+// Round kernel: 256 threads x 16 entries per tile.
 constexpr int RND_THREADS = 256;
-constexpr int RND_ITEMS = 32;
-constexpr int LB_CHUNKS = 8;
+constexpr int RND_ITEMS = 16;
 constexpr int TILE = RND_THREADS * RND_ITEMS;
 
 // Largest free-memory value a pass accepts: R + 1 must fit the 46-bit value

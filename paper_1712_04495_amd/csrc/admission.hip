@@ -245,37 +245,17 @@ __global__ __launch_bounds__(RND_THREADS) void k_round(DevCtl *c, const int64_t 
         if (lane == 0) st_relaxed(&flags[t], pack_flag(epoch, FL_AGG, A));
         long long p = t - 1;
         for (;;) {
-          // LB_CHUNKS loads per lane: chunk k covers tiles p - 64k - lane
-          unsigned long long f[LB_CHUNKS];
-#pragma unroll
-          for (int k = 0; k < LB_CHUNKS; ++k) {
-            const long long qq = p - int64_t(k) * WAVE - lane;
-            f[k] = qq >= 0 ? ld_relaxed(&flags[qq]) : pack_flag(epoch, FL_INC, 0);
-          }
-          int64_t w = 0;
-          bool stop = false, retry = false;
-#pragma unroll
-          for (int k = 0; k < LB_CHUNKS; ++k) {
-            if (stop || retry) continue;
-            const uint64_t st = (f[k] >> 46) & 3;
-            const bool valid = uint32_t(f[k] >> 48) == epoch && st != 0;
-            const uint64_t inc_b = __ballot(valid && st == FL_INC);
-            const uint64_t bad_b = __ballot(!valid);
-            const int fi = inc_b ? __builtin_ctzll(inc_b) : WAVE;
-            const uint64_t need = fi >= WAVE - 1 ? ~0ULL : ((2ULL << fi) - 1);
-            if (bad_b & need) {
-              retry = true;
-              continue;
-            }
-            const int64_t v = lane <= fi ? int64_t(f[k] & VMASK) : 0;
-            const int64_t sv = wave_sum(v);  // <= 64 * cap, no overflow
-            w = sat_add(w, sv < cap ? sv : cap, cap);
-            if (fi < WAVE) stop = true;
-          }
-          if (retry) {
-            // an unpublished predecessor inside this window: retry the window
-            // (w is discarded).  A predecessor that saw the break marker first
-            // may never publish.
+          const long long qq = p - lane;
+          const unsigned long long f =
+              qq >= 0 ? ld_relaxed(&flags[qq]) : pack_flag(epoch, FL_INC, 0);
+          const uint64_t st = (f >> 46) & 3;
+          const bool valid = uint32_t(f >> 48) == epoch && st != 0;
+          const uint64_t inc_b = __ballot(valid && st == FL_INC);
+          const uint64_t bad_b = __ballot(!valid);
+          const int fi = inc_b ? __builtin_ctzll(inc_b) : WAVE;
+          const uint64_t need = fi >= WAVE - 1 ? ~0ULL : ((2ULL << fi) - 1);
+          if (bad_b & need) {
+            // a predecessor that saw the break marker first may never publish
             if (ld_relaxed(&c->break_tile[s]) < t) {
               E = cap;
               break;
@@ -283,9 +263,11 @@ __global__ __launch_bounds__(RND_THREADS) void k_round(DevCtl *c, const int64_t 
             __builtin_amdgcn_s_sleep(1);
             continue;
           }
-          E = sat_add(E, w, cap);
-          if (stop || E >= cap) break;
-          p -= int64_t(LB_CHUNKS) * WAVE;
+          const int64_t v = lane <= fi ? int64_t(f & VMASK) : 0;
+          const int64_t w = wave_sum(v);  // <= 64 * cap, no overflow
+          E = sat_add(E, w < cap ? w : cap, cap);
+          if (fi < WAVE || E >= cap) break;
+          p -= WAVE;
         }
         if (lane == 0) st_relaxed(&flags[t], pack_flag(epoch, FL_INC, sat_add(E, A, cap)));
       }
@@ -348,46 +330,40 @@ __global__ __launch_bounds__(RND_THREADS) void k_round(DevCtl *c, const int64_t 
       continue;
     }
 
-    // This tile holds the break: scan it row by row in queue order.  The row
-    // loop is fully unrolled (no early exit) so x[] stays in registers.
+    // This tile holds the break: scan it row by row in queue order.
     int64_t carry = E, brk = -1, brk_sum = 0;
-    bool found = false;
-#pragma unroll
     for (int j = 0; j < RND_ITEMS; ++j) {
-      if (!found) {
-        const int64_t p = base + int64_t(j) * RND_THREADS + tid;
-        const int64_t v = x[j] >= 0 ? x[j] : 0;
-        int64_t rowtot;
-        const int64_t ex = block_excl_scan_sat<RND_THREADS>(v, cap, red, &rowtot);
-        const int64_t P = sat_add(carry, sat_add(ex, v, cap), cap);
-        const bool over = x[j] >= 0 && P > R;
-        const int64_t f = block_min<RND_THREADS>(over ? tid : RND_THREADS, red);
-        if (f < RND_THREADS) {
-          if (tid == f) s_brk_sum = sat_add(carry, ex, cap);
-          if (tid <= f && p < end) {
-            const bool a = x[j] >= 0 && tid < f;
-            decision[p & mask] = a ? 1 : 0;
-            if (a) {
-              ++tcnt;
-              tmax = p;
-            }
+      const int64_t p = base + int64_t(j) * RND_THREADS + tid;
+      const int64_t v = x[j] >= 0 ? x[j] : 0;
+      int64_t rowtot;
+      const int64_t ex = block_excl_scan_sat<RND_THREADS>(v, cap, red, &rowtot);
+      const int64_t P = sat_add(carry, sat_add(ex, v, cap), cap);
+      const bool over = x[j] >= 0 && P > R;
+      const int64_t f = block_min<RND_THREADS>(over ? tid : RND_THREADS, red);
+      if (f < RND_THREADS) {
+        if (tid == f) s_brk_sum = sat_add(carry, ex, cap);
+        if (tid <= f && p < end) {
+          const bool a = x[j] >= 0 && tid < f;
+          decision[p & mask] = a ? 1 : 0;
+          if (a) {
+            ++tcnt;
+            tmax = p;
           }
-          __syncthreads();
-          brk = base + int64_t(j) * RND_THREADS + f;
-          brk_sum = s_brk_sum;
-          found = true;
-        } else {
-          if (p < end) {
-            const bool a = x[j] >= 0;
-            decision[p & mask] = a ? 1 : 0;
-            if (a) {
-              ++tcnt;
-              tmax = p;
-            }
-          }
-          carry = sat_add(carry, rowtot, cap);
+        }
+        __syncthreads();
+        brk = base + int64_t(j) * RND_THREADS + f;
+        brk_sum = s_brk_sum;
+        break;
+      }
+      if (p < end) {
+        const bool a = x[j] >= 0;
+        decision[p & mask] = a ? 1 : 0;
+        if (a) {
+          ++tcnt;
+          tmax = p;
         }
       }
+      carry = sat_add(carry, rowtot, cap);
     }
     const int64_t cnt = block_sum<RND_THREADS>(tcnt, red);
     const int64_t mx = block_max<RND_THREADS>(tmax, red);
@@ -547,11 +523,9 @@ int adm_engine_init(AdmEngine &e, int device, int64_t max_entries) {
   memset(e.h_ctl, 0, sizeof(DevCtl));
   SCHED_HIP_TRY(hipMalloc(&e.d_flags, sizeof(unsigned long long) * e.max_tiles));
   SCHED_HIP_TRY(hipMemset(e.d_flags, 0, sizeof(unsigned long long) * e.max_tiles));
-  int cus = 0, per_cu = 0;
+  int cus = 0;
   SCHED_HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device));
-  SCHED_HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_round, RND_THREADS, 0));
-  // a persistent grid: exactly the workgroups that can be resident at once
-  e.round_grid = cus * (per_cu > 0 ? per_cu : 1);
+  e.round_grid = cus * 8;
   e.launch = 1;
   e.epoch = 0;
   return SCHED_OK;
@@ -610,12 +584,9 @@ static int run_rounds(AdmEngine &e, const int64_t *demand, uint8_t *decision, in
   // every round decides at least one entry, so a pass needs at most
   // span + 1 rounds; anything beyond that is an internal error
   int64_t budget = span_hint + 2 * e.rounds_per_check + 2;
-  // one round first (the common case after the window kernel is a single
-  // final round), then batches of rounds_per_check between host checks
-  int batch = 1;
   for (;;) {
-    if ((budget -= batch) < 0) return SCHED_E_INTERNAL;
-    for (int i = 0; i < batch; ++i) {
+    if ((budget -= e.rounds_per_check) < 0) return SCHED_E_INTERNAL;
+    for (int i = 0; i < e.rounds_per_check; ++i) {
       uint32_t ep;
       if (int rc = next_epoch(e, s, &ep)) return rc;
       SCHED_PROF_LAUNCH("k_round", s,
@@ -626,7 +597,6 @@ static int run_rounds(AdmEngine &e, const int64_t *demand, uint8_t *decision, in
     }
     if (int rc = sync_ctl(e, s)) return rc;
     if (e.h_ctl->rec[L & 3].done) break;
-    batch = e.rounds_per_check;
   }
   *Lio = L;
   return SCHED_OK;
