@@ -332,6 +332,81 @@ int sched_gemm_bf16(const uint16_t *A, const uint16_t *Bt, float *C, int64_t M, 
                     int64_t K, sched_stream_t stream);
 
 /* ======================================================================== */
+/* Serving loop: admission + concurrent execution of a job mix               */
+/* ======================================================================== */
+/* The life cycle of Sec. II for every job of a mix: a job arrives, declares
+ * its demand (pre-allocation, Sec. IV), waits in the queue until the policy
+ * of the context (SCHED_POLICY_FIFO or SCHED_POLICY_MMU, Sec. V) admits it,
+ * runs concurrently with the other admitted jobs, and returns its
+ * reservation when it ends (post-free).  Jobs run on a pool of streams; with
+ * batch_small, admitted triads under small_bytes are packed into one
+ * persistent launch (a HIP graph replay when use_graph) whose block and
+ * chunk shape come from an autotuner (cached in tune_cache when non-NULL).
+ * Each job allocates only what its kind needs, which must fit its declared
+ * demand; an allocation failure inside a reservation is a memory-safety
+ * violation (counted, job status SCHED_E_NOMEM). */
+#define SCHED_JOB_TRIAD 0  /* size = fp32 elements per array (3 arrays)       */
+#define SCHED_JOB_GEMM 1   /* size = N of an N x N x N bf16 GEMM               */
+#define SCHED_JOB_HIST 2   /* size = uint32 keys                              */
+
+#define SCHED_SERVE_REALTIME 0 /* arrivals at their timestamps, real durations */
+#define SCHED_SERVE_VIRTUAL 1  /* event order (time, releases first, job index),
+                                  one pass per event, end = admit + vdur_s;
+                                  no job work runs                             */
+
+typedef struct {
+  double arrival_s;   /* arrival, seconds from the start; non-decreasing      */
+  double vdur_s;      /* duration in the virtual-clock mode                   */
+  int64_t demand;     /* declared bytes (>= what the kind allocates)          */
+  int64_t size;       /* kind's size parameter                                */
+  int32_t kind;       /* SCHED_JOB_*                                          */
+  int32_t priority;   /* lower value = higher priority                        */
+  uint64_t seed;      /* input contents                                       */
+} sched_job_desc_t;
+
+typedef struct {
+  double t_arrive;    /* seconds from the start                               */
+  double t_admit;     /* when the pass that admitted it returned              */
+  double t_start;     /* device time its work could start                     */
+  double t_end;       /* device time its work ended                           */
+  uint64_t digest;    /* sum of the 32-bit words of its output (when digest)  */
+  int32_t status;     /* SCHED_OK, SCHED_E_TOOBIG, SCHED_E_NOMEM, ...         */
+  int32_t batched;    /* 1 if it ran inside a batched launch                  */
+} sched_job_result_t;
+
+typedef struct {
+  int32_t mode;        /* SCHED_SERVE_REALTIME / SCHED_SERVE_VIRTUAL           */
+  int32_t n_streams;   /* stream pool for single-job launches                 */
+  int32_t serial;      /* 1: every demand := capacity (exclusive execution)   */
+  int32_t batch_small; /* 1: persistent batched launch for small triads        */
+  int64_t small_bytes; /* demand threshold for batching                       */
+  int32_t iters;       /* triad sweeps per job                                 */
+  int32_t digest;      /* 1: compute each job's output digest                  */
+  double time_scale;   /* arrival times are multiplied by this (0 = 1)         */
+  int32_t use_graph;   /* 1: replay the batched launch as a HIP graph          */
+  int32_t pad;
+  const char *tune_cache; /* JSON file for the autotuner result, or NULL       */
+} sched_serve_opts_t;
+
+typedef struct {
+  double wall_s;       /* host time of the whole run                           */
+  double makespan_s;   /* last job end                                         */
+  double jobs_per_s;   /* completed / makespan                                 */
+  double p50_wait_s, p99_wait_s, p50_turn_s, p99_turn_s; /* nearest rank       */
+  int64_t completed, rejected, violations, passes, batches, batched_jobs;
+  int64_t peak_used, max_running;
+  int64_t tuned_block, tuned_chunk, tuned_per_cu;
+} sched_serve_summary_t;
+
+/* Runs n jobs (jobs[i] is job handle i; the context needs max_jobs >= n and
+ * is reset first) and fills results[n] and *summary (host pointers).
+ * Synchronises; the context mutex is held for the whole run.  Errors:
+ * SCHED_E_INVALID for bad descriptors or a priority policy. */
+int sched_serve(sched_ctx_t *ctx, int64_t n, const sched_job_desc_t *jobs,
+                const sched_serve_opts_t *opts, sched_job_result_t *results,
+                sched_serve_summary_t *summary);
+
+/* ======================================================================== */
 /* Kernel timing                                                             */
 /* ======================================================================== */
 /* enable != 0 starts bracketing every library kernel launch with a pair of

@@ -66,6 +66,33 @@ class sched_slab_info_t(C.Structure):
                 ("class_blocks", i64 * 13), ("n_classes", i32), ("n_tenants", i32)]
 
 
+class sched_serve_opts_t(C.Structure):
+    _fields_ = [("mode", i32), ("n_streams", i32), ("serial", i32), ("batch_small", i32),
+                ("small_bytes", i64), ("iters", i32), ("digest", i32), ("time_scale", C.c_double),
+                ("use_graph", i32), ("pad", i32), ("tune_cache", C.c_char_p)]
+
+
+class sched_serve_summary_t(C.Structure):
+    _fields_ = ([(n, C.c_double) for n in ("wall_s", "makespan_s", "jobs_per_s", "p50_wait_s",
+                                             "p99_wait_s", "p50_turn_s", "p99_turn_s")]
+                + [(n, i64) for n in ("completed", "rejected", "violations", "passes", "batches",
+                                      "batched_jobs", "peak_used", "max_running", "tuned_block",
+                                      "tuned_chunk", "tuned_per_cu")])
+
+
+SCHED_JOB_TRIAD = 0
+SCHED_JOB_GEMM = 1
+SCHED_JOB_HIST = 2
+SCHED_SERVE_REALTIME = 0
+SCHED_SERVE_VIRTUAL = 1
+
+# numpy layout of sched_job_result_t
+import numpy as _np  # noqa: E402
+
+RESULT_DTYPE = _np.dtype([("t_arrive", "<f8"), ("t_admit", "<f8"), ("t_start", "<f8"),
+                          ("t_end", "<f8"), ("digest", "<u8"), ("status", "<i4"),
+                          ("batched", "<i4")])
+
 # name -> (restype, argtypes); mirrors include/cosched.h
 _SIGS = {
     "sched_create": (i32, [C.POINTER(sched_config_t), C.POINTER(vp)]),
@@ -100,6 +127,8 @@ _SIGS = {
     "sched_reset": (i32, [vp]),
     "sched_profile": (i32, [i32]),
     "sched_profile_read": (i32, [C.c_char_p, C.POINTER(C.c_double), C.POINTER(i64)]),
+    "sched_serve": (i32, [vp, i64, vp, C.POINTER(sched_serve_opts_t), vp,
+                          C.POINTER(sched_serve_summary_t)]),
     "sched_version": (C.c_char_p, []),
 }
 
@@ -311,6 +340,24 @@ def sched_profile_read(kernel):
     n = i64()
     rc = lib().sched_profile_read(kernel.encode(), C.byref(ms), C.byref(n))
     return rc, ms.value, n.value
+
+
+# ---------------------------------------------------------- serving loop
+def sched_serve(ctx, jobs, mode=SCHED_SERVE_REALTIME, n_streams=8, serial=0, batch_small=0,
+                small_bytes=16 << 20, iters=10, digest=0, time_scale=1.0, use_graph=1,
+                tune_cache=None):
+    """jobs: numpy structured array in the layout of sched_job_desc_t
+    (workloads.job_table).  Returns (rc, results structured array, summary dict)."""
+    jobs = _np.ascontiguousarray(jobs)
+    assert jobs.dtype.itemsize == 48
+    res = _np.zeros(jobs.shape[0], dtype=RESULT_DTYPE)
+    o = sched_serve_opts_t(mode, n_streams, serial, batch_small, small_bytes, iters, digest,
+                           time_scale, use_graph, 0,
+                           tune_cache.encode() if tune_cache else None)
+    sm = sched_serve_summary_t()
+    rc = lib().sched_serve(ctx, jobs.shape[0], jobs.ctypes.data, C.byref(o), res.ctypes.data,
+                           C.byref(sm))
+    return rc, res, {k: getattr(sm, k) for k, _ in sched_serve_summary_t._fields_}
 
 
 def sched_version():

@@ -17,3 +17,16 @@ void prof_end(const char *name, hipStream_t s);
     launch;                                     \
     schedk::prof_end(name, stream);             \
   } while (0)
+
+#define SCHED_PROF_LAUNCH_GRAPH(name, stream, call) \
+  do {                                             \
+    schedk::prof_begin(name, stream);              \
+    {                                              \
+      hipError_t _ge = (call);                     \
+      if (_ge != hipSuccess) {                     \
+        schedk::prof_end(name, stream);            \
+        SCHED_HIP_TRY(_ge);                        \
+      }                                            \
+    }                                              \
+    schedk::prof_end(name, stream);                \
+  } while (0)

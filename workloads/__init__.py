@@ -206,6 +206,36 @@ def hist_demand(n_keys):
     return round_up(np.asarray(n_keys, np.int64) * 4, PAGE) + round_up(HIST_BINS * 4, PAGE)
 
 
+NOMINAL_BW = 5.0e12      # bytes/s, for virtual durations only
+NOMINAL_FLOPS = 1.0e15   # flop/s, for virtual durations only
+
+
+def nominal_vdur(kind, size):
+    """Virtual duration of a job from its footprint (a job parameter, used by
+    the virtual-clock schedule): streamed bytes over a nominal bandwidth,
+    GEMM flops over a nominal rate."""
+    kind = np.asarray(kind)
+    size = np.asarray(size, dtype=np.float64)
+    tri = (8.0 + 10 * 12.0) * size / NOMINAL_BW
+    gem = 2.0 * size ** 3 / NOMINAL_FLOPS + 8.0 * size ** 2 / NOMINAL_BW
+    his = 8.0 * size / NOMINAL_BW
+    return np.where(kind == KIND_TRIAD, tri, np.where(kind == KIND_GEMM, gem, his))
+
+
+def job_table(mix: "JobMix"):
+    """The mix as a numpy structured array in the layout of sched_job_desc_t."""
+    dt = np.dtype([("arrival_s", "<f8"), ("vdur_s", "<f8"), ("demand", "<i8"), ("size", "<i8"),
+                   ("kind", "<i4"), ("priority", "<i4"), ("seed", "<u8")])
+    t = np.zeros(mix.n, dtype=dt)
+    t["arrival_s"] = mix.arrival_s
+    t["vdur_s"] = nominal_vdur(mix.kind, mix.size)
+    t["demand"] = mix.demand
+    t["size"] = mix.size
+    t["kind"] = mix.kind
+    t["seed"] = (np.uint64(mix.seed) << np.uint64(20)) + np.arange(mix.n, dtype=np.uint64) + np.uint64(1)
+    return t
+
+
 def c1_jobs(seed: int = 1, n: int = 16, capacity: int = 8 * GiB, gap_s: float = 5e-3) -> JobMix:
     """C1: 16 triad jobs, footprint uniform in [64 MiB, 2 GiB] (4 KiB pages),
     Poisson arrivals with mean gap 5 ms, pool 8 GiB."""
