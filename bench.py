@@ -46,7 +46,59 @@ def parse():
                     help="bound on the oracle's CPU time for cpu_baseline (0 = skip)")
     ap.add_argument("--no-profile", action="store_true",
                     help="time the steps without kernel events (no roofline)")
+    ap.add_argument("--cosched", default="c1,c5",
+                    help="co-scheduled vs serial runs to add (c1, c4, c5; empty = none)")
+    ap.add_argument("--c5-jobs", type=int, default=50_000)
+    ap.add_argument("--c4-jobs", type=int, default=10_000)
     return ap.parse_args()
+
+
+def cosched_run(cs, name, n_jobs, dev_free):
+    """One job mix co-scheduled (MMU, batching of small triads) and exclusive
+    serial (every demand := capacity).  Returns a dict of results."""
+    import numpy as np
+    from workloads import c1_jobs, c4_jobs, c5_jobs, job_table
+    if name == "c1":
+        mix = c1_jobs(1)
+        policy, batch = cs.SCHED_POLICY_FIFO, 0
+    elif name == "c4":
+        cap = min(280 * 10**9, dev_free - (8 << 30))
+        mix = c4_jobs(4, n=n_jobs, capacity=cap)
+        policy, batch = cs.SCHED_POLICY_MMU, 0
+    else:
+        cap = min(280 * 10**9, dev_free - (8 << 30))
+        mix = c5_jobs(5, n=n_jobs, capacity=cap)
+        policy, batch = cs.SCHED_POLICY_MMU, 1
+    jt = job_table(mix)
+    rc, ctx = cs.sched_create(policy=policy, capacity_bytes=mix.capacity, max_jobs=mix.n,
+                              queue_capacity=max(mix.n, 4096), window_limit=16)
+    assert rc == 0, rc
+    out = {"jobs": mix.n, "capacity_bytes": int(mix.capacity),
+           "policy": "fifo" if policy == 0 else "mmu"}
+    try:
+        for label, kw in (("coscheduled", dict(n_streams=16, batch_small=batch, use_graph=1,
+                                               tune_cache=os.path.join(ROOT, "gpurun_out",
+                                                                       "batch_tune.json"))),
+                          ("serial", dict(n_streams=1, serial=1))):
+            rc, res, sm = cs.sched_serve(ctx, jt, **kw)
+            assert rc == 0, rc
+            ok = res["status"] == 0
+            out[label] = {"jobs_per_s": sm["jobs_per_s"], "makespan_s": sm["makespan_s"],
+                          "p50_turnaround_s": sm["p50_turn_s"], "p99_turnaround_s": sm["p99_turn_s"],
+                          "p50_wait_s": sm["p50_wait_s"], "p99_wait_s": sm["p99_wait_s"],
+                          "completed": sm["completed"], "rejected": sm["rejected"],
+                          "violations": sm["violations"], "passes": sm["passes"],
+                          "max_running": sm["max_running"], "batches": sm["batches"],
+                          "batched_jobs": sm["batched_jobs"]}
+            if label == "coscheduled" and batch:
+                out[label]["autotuned"] = {"block": sm["tuned_block"], "chunk": sm["tuned_chunk"],
+                                           "per_cu": sm["tuned_per_cu"]}
+            out[label]["completed_ok"] = int(ok.sum())
+    finally:
+        cs.sched_destroy(ctx)
+    out["speedup_vs_serial"] = (out["coscheduled"]["jobs_per_s"] /
+                                max(out["serial"]["jobs_per_s"], 1e-12))
+    return out
 
 
 def c2_step(cs, ctx, d_job, d_dem, coins):
@@ -210,6 +262,16 @@ def main():
             "GBps_pass": bytes_pass / ddt / 1e9, "GBps_kernels": bytes_pass / kern_s / 1e9,
             "frac_of_peak": bytes_pass / kern_s / 1e9 / HBM_PEAK_GBS, "fixed_point_ok": bool(ok)}
         del dd, dec
+
+    if args.cosched:
+        free, _ = torch.cuda.mem_get_info()
+        out["coschedule"] = {}
+        for name in [x for x in args.cosched.split(",") if x]:
+            out["coschedule"][name] = cosched_run(cs, name,
+                                                  args.c5_jobs if name == "c5" else args.c4_jobs,
+                                                  int(free))
+            print(f"[bench] {name}: {json.dumps(out['coschedule'][name])}", file=sys.stderr,
+                  flush=True)
 
     if args.cpu_seconds > 0:
         cb, ref_pass = cpu_baseline_c2(q, args.cpu_seconds)
