@@ -102,22 +102,32 @@ def cosched_run(cs, name, n_jobs, dev_free):
 
 
 def c2_step(cs, ctx, d_job, d_dem, coins):
+    """reset + intake of the whole queue + the release/admit rounds chained
+    on the device (one host synchronisation per step)."""
+    assert cs.sched_reset(ctx) == 0
+    assert cs.sched_enqueue_batch(ctx, d_job, d_dem) == 0
+    rc, res = cs.sched_pass_chain(ctx, coins.shape[0] + 1, coins)
+    assert rc == 0
+    admitted = sum(r["admitted"] for r in res)
+    scanned = sum(r["scanned"] for r in res)
+    compacted = sum(r["compacted"] for r in res)
+    per_pass = [(r["admitted"], r["free_after"]) for r in res]
+    return admitted, scanned, compacted, per_pass
+
+
+def c2_step_synchronous(cs, ctx, d_job, d_dem, coins):
+    """The same rounds through the per-pass host API (sched_pass after each
+    sched_release_masked): every pass returns to the host."""
     assert cs.sched_reset(ctx) == 0
     assert cs.sched_enqueue_batch(ctx, d_job, d_dem) == 0
     admitted = 0
-    scanned = 0
-    compacted = 0
-    per_pass = []
     for r in range(coins.shape[0] + 1):
         if r > 0:
             assert cs.sched_release_masked(ctx, coins[r - 1]) == 0
         rc, res = cs.sched_pass(ctx)
         assert rc == 0
         admitted += res["admitted"]
-        scanned += res["scanned"]
-        compacted += res["compacted"]
-        per_pass.append((res["admitted"], res["free_after"]))
-    return admitted, scanned, compacted, per_pass
+    return admitted
 
 
 def cpu_baseline_c2(q, seconds):
@@ -190,6 +200,14 @@ def main():
             rc, ms, launches = cs.sched_profile_read(k)
             kern[k] = (ms, launches)
         cs.sched_profile(0)
+    # the per-pass host API on the same rounds, for comparison
+    t1 = time.perf_counter()
+    sync_adm = 0
+    for _ in range(args.steps):
+        sync_adm += c2_step_synchronous(cs, ctx, d_job, d_dem, coins)
+    torch.cuda.synchronize()
+    sync_dt = time.perf_counter() - t1
+    assert sync_adm == tot_adm
     cs.sched_destroy(ctx)
 
     out = {
@@ -211,7 +229,10 @@ def main():
                    "queue": n, "rounds": q.rounds, "capacity_bytes": q.capacity,
                    "policy": "mmu", "seed": args.seed,
                    "admissions_per_step": tot_adm // args.steps,
-                   "us_per_pass": 1e6 * dt / args.steps / q.rounds},
+                   "us_per_pass": 1e6 * dt / args.steps / q.rounds,
+                   "step": "reset + intake of 2^20 requests + 8 rounds chained on the device",
+                   "per_pass_host_api": {"admissions_per_s": sync_adm / sync_dt,
+                                         "us_per_pass": 1e6 * sync_dt / args.steps / q.rounds}},
     }
     if profile:
         # algorithmic bytes: 8 B demand read + 1 B decision per decided entry

@@ -198,6 +198,19 @@ int sched_pass(sched_ctx_t *ctx, sched_stream_t stream, sched_pass_result_t *out
 int sched_last_admitted(sched_ctx_t *ctx, int32_t *d_out, int64_t cap, int64_t *out_n,
                         sched_stream_t stream);
 
+/* `rounds` (1..256) release+admit rounds chained on the device with a single
+ * host synchronisation at the end: round 0 is one pass; round r > 0 first
+ * releases every running job j < n_mask whose byte d_masks[(r-1)*n_mask + j]
+ * is non-zero (Sec. IV post-free with bytes == 0) and then runs one pass.
+ * Every pass runs to completion in the single-wave window kernel.  out (host
+ * array of `rounds`, may be NULL) receives each pass's result; the admitted
+ * job ids of all rounds, concatenated in round and queue order, are copied to
+ * the device array d_admitted[cap] (up to cap of them).  Not allowed while
+ * requests made with sched_admit wait (SCHED_E_INVALID).  Synchronises. */
+int sched_pass_chain(sched_ctx_t *ctx, int32_t rounds, const uint8_t *d_masks, int64_t n_mask,
+                     sched_stream_t stream, sched_pass_result_t *out, int32_t *d_admitted,
+                     int64_t cap);
+
 /* Post-free for many jobs at once: every running job j < n whose byte
  * d_mask[j] (device array of n bytes) is non-zero returns its whole
  * reservation (Sec. IV, bytes == 0).  n must not exceed the number of

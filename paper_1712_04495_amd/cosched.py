@@ -108,6 +108,7 @@ _SIGS = {
     "sched_pass": (i32, [vp, vp, C.POINTER(sched_pass_result_t)]),
     "sched_last_admitted": (i32, [vp, vp, i64, C.POINTER(i64), vp]),
     "sched_release_masked": (i32, [vp, vp, i64, vp]),
+    "sched_pass_chain": (i32, [vp, i32, vp, i64, vp, vp, vp, i64]),
     "sched_scan_workspace_size": (C.c_size_t, [i64]),
     "sched_scan": (i32, [i32, i64, vp, i64, vp, i32, i32, vp, C.c_size_t, vp,
                          C.POINTER(sched_scan_result_t)]),
@@ -239,6 +240,16 @@ def sched_last_admitted(ctx, d_out, stream=None):
 def sched_release_masked(ctx, d_mask, stream=None):
     n = 0 if d_mask is None else int(d_mask.numel())
     return lib().sched_release_masked(ctx, _ptr(d_mask), n, _stream(stream))
+
+
+def sched_pass_chain(ctx, rounds, d_masks=None, d_admitted=None, stream=None):
+    """d_masks: uint8 device tensor [rounds - 1, n_mask] (or None)."""
+    n_mask = 0 if d_masks is None else int(d_masks.shape[-1])
+    res = (sched_pass_result_t * rounds)()
+    cap = 0 if d_admitted is None else int(d_admitted.numel())
+    rc = lib().sched_pass_chain(ctx, rounds, _ptr(d_masks), n_mask, _stream(stream), res,
+                                _ptr(d_admitted), cap)
+    return rc, [{k: getattr(r, k) for k, _ in sched_pass_result_t._fields_} for r in res]
 
 
 # ---------------------------------------------------------- stateless scan

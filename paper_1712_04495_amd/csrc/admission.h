@@ -50,14 +50,26 @@ struct DevCtl {
   int64_t p_end;           // end position of the pass
   int32_t filter;          // 1: first-fit (MMU) rounds, 0: FIFO
   int32_t pad;
+  int64_t adm_base;        // where the next admitted list starts (chains append)
   RoundRec rec[4];
   unsigned long long ticket[4];
   long long break_tile[4];
 };
 
+// What a pass reports to the host; written by the device into host-mapped
+// pinned memory (no copy kernel on the way back).
+struct PassSummary {
+  int64_t admitted, admitted_bytes, R0, R_after, rounds, start_final, hi;
+  int64_t head, tail, used, adm_base;
+  int32_t done, pad;
+};
+constexpr int MAX_CHAIN = 256;
+
 struct AdmEngine {
   DevCtl *d_ctl = nullptr;
   DevCtl *h_ctl = nullptr;          // pinned host mirror
+  PassSummary *h_sum = nullptr;     // host-mapped summaries, host view
+  PassSummary *d_sum = nullptr;     // same memory, device view
   unsigned long long *d_flags = nullptr;
   int64_t max_tiles = 0;
   uint64_t launch = 1;              // launch counter of the pass chain
@@ -72,6 +84,7 @@ void adm_engine_free(AdmEngine &e);
 
 struct PassOut {
   int64_t admitted, admitted_bytes, R0, R_after, rounds, start_final, hi;
+  int64_t head, tail, used;
 };
 
 // One pass over demand[start, end) with free memory R0 (stateless form: the
@@ -110,8 +123,15 @@ struct JobArrays {
 // and withdrawn holes leave, survivors are right-aligned, the admitted list is
 // written in queue order and the admitted demands are charged to their jobs
 // and to `used`.  Stream-ordered.
-int adm_compact(AdmEngine &e, const QueueArrays &q, const JobArrays &j, hipStream_t s,
-                int slot = -1);
+int adm_compact(AdmEngine &e, const QueueArrays &q, const JobArrays &j, hipStream_t s, int slot,
+                PassSummary *d_out, int append);
+
+// `rounds` release+admit rounds chained on the device (one host sync): round
+// r > 0 first releases every running job j < n_mask with masks[(r-1) * n_mask
+// + j] != 0, then runs a full pass (windows until done) and compaction.  The
+// admitted lists of the rounds are appended one after the other.
+int adm_chain(AdmEngine &e, int policy, const QueueArrays &q, const JobArrays &jb, int rounds,
+              const uint8_t *masks, int64_t n_mask, hipStream_t s);
 
 int adm_zero_decisions(uint8_t *decision, int64_t n, hipStream_t s);
 int adm_release_masked(AdmEngine &e, const JobArrays &j, const uint8_t *mask, int64_t n,

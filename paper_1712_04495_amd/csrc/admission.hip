@@ -49,9 +49,8 @@ __device__ __forceinline__ void reset_next_slot(DevCtl *c, uint32_t L) {
   c->break_tile[nx] = LLONG_MAX;
 }
 
-__global__ void k_prologue(DevCtl *c, uint32_t L, int filter, int from_state, int64_t R0,
-                           int64_t start, int64_t end) {
-  if (threadIdx.x != 0) return;
+__device__ __forceinline__ void pass_init(DevCtl *c, uint32_t L, int filter, int from_state,
+                                          int64_t R0, int64_t start, int64_t end, int append) {
   if (from_state) {
     R0 = c->capacity - c->used;
     start = c->head;
@@ -70,6 +69,31 @@ __global__ void k_prologue(DevCtl *c, uint32_t L, int filter, int from_state, in
   c->p_R0 = R0;
   c->p_end = end;
   c->filter = filter;
+  if (!append) c->adm_base = 0;
+}
+
+__global__ void k_prologue(DevCtl *c, uint32_t L, int filter, int from_state, int64_t R0,
+                           int64_t start, int64_t end) {
+  if (threadIdx.x != 0) return;
+  pass_init(c, L, filter, from_state, R0, start, end, 0);
+}
+
+// Pass summary into host-mapped memory (stateless scans).
+__global__ void k_summary(DevCtl *c, uint32_t L, PassSummary *out) {
+  if (threadIdx.x != 0) return;
+  const RoundRec &r = c->rec[L & 3];
+  out->admitted = c->p_admitted;
+  out->admitted_bytes = c->p_admitted_bytes;
+  out->R0 = c->p_R0;
+  out->R_after = r.R;
+  out->rounds = c->p_rounds;
+  out->start_final = r.start;
+  out->hi = c->p_hi;
+  out->head = c->head;
+  out->tail = c->tail;
+  out->used = c->used;
+  out->adm_base = c->adm_base;
+  out->done = r.done;
 }
 
 // ---------------------------------------------------------------------------
@@ -80,18 +104,41 @@ __global__ void k_prologue(DevCtl *c, uint32_t L, int filter, int from_state, in
 // plus one wave-wide exclusive scan gives every entry its prefix in queue
 // order.  The break of a round is the lowest set bit of a ballot.  No LDS and
 // no barriers: every round costs a few dozen wave instructions.
+// init != 0: the kernel also does the prologue (pass start state from the
+// arguments or, with from_state, from the control block).
 __global__ __launch_bounds__(WIN_THREADS) void k_window(DevCtl *c, const int64_t *__restrict__ demand,
                                                         uint8_t *__restrict__ decision, int64_t mask,
-                                                        uint32_t L, int max_windows) {
+                                                        uint32_t L, int max_windows, int init,
+                                                        int filter_arg, int from_state, int64_t R0,
+                                                        int64_t start0, int64_t end0, int append) {
   const int lane = threadIdx.x;
   const int s = L & 3, nx = (L + 1) & 3;
-  const RoundRec r = c->rec[s];
-  const int64_t end = c->p_end;
-  const bool filter = c->filter != 0;
-  int64_t hi = c->p_hi;
+  // pass state in registers: every lane derives it from the same inputs
+  int64_t R, pos, end, hi;
+  int done;
+  bool filter;
+  if (init) {
+    if (from_state) {
+      R0 = c->capacity - c->used;
+      start0 = c->head;
+      end0 = c->tail;
+    }
+    R = R0;
+    pos = start0;
+    end = end0;
+    hi = start0;
+    filter = filter_arg != 0;
+    done = (start0 >= end0 || R0 <= 0) ? 1 : 0;
+  } else {
+    const RoundRec r = c->rec[s];
+    R = r.R;
+    pos = r.start;
+    done = r.done;
+    end = c->p_end;
+    filter = c->filter != 0;
+    hi = c->p_hi;
+  }
   if (lane == 0) reset_next_slot(c, L);
-  int64_t R = r.R, pos = r.start;
-  int done = r.done;
   int64_t adm_cnt = 0, adm_bytes = 0, rounds = 0;
 
   for (int w = 0; w < max_windows && !done; ++w) {
@@ -178,10 +225,21 @@ __global__ __launch_bounds__(WIN_THREADS) void k_window(DevCtl *c, const int64_t
     c->rec[nx].R = R;
     c->rec[nx].start = pos < end ? pos : end;
     c->rec[nx].done = done;
-    c->p_admitted += adm_cnt;
-    c->p_admitted_bytes += adm_bytes;
-    c->p_hi = hi;
-    c->p_rounds += rounds;
+    if (init) {
+      c->p_admitted = adm_cnt;
+      c->p_admitted_bytes = adm_bytes;
+      c->p_hi = hi;
+      c->p_rounds = rounds;
+      c->p_R0 = R0;
+      c->p_end = end;
+      c->filter = filter ? 1 : 0;
+      if (!append) c->adm_base = 0;
+    } else {
+      c->p_admitted += adm_cnt;
+      c->p_admitted_bytes += adm_bytes;
+      c->p_hi = hi;
+      c->p_rounds += rounds;
+    }
   }
 }
 
@@ -399,15 +457,35 @@ __global__ void k_fill_u8(uint8_t *p, int64_t n, uint8_t v) {
 // ---------------------------------------------------------------------------
 // slot >= 0: run only if the pass recorded in rec[slot] is done (lets the host
 // enqueue compaction right after the window kernel without a round trip).
+// The pass summary goes to `out` (host-mapped) either way.
+__device__ void write_summary(DevCtl *c, const RoundRec &r, int done, PassSummary *out) {
+  out->admitted = c->p_admitted;
+  out->admitted_bytes = c->p_admitted_bytes;
+  out->R0 = c->p_R0;
+  out->R_after = r.R;
+  out->rounds = c->p_rounds;
+  out->start_final = r.start;
+  out->hi = c->p_hi;
+  out->head = c->head;
+  out->tail = c->tail;
+  out->used = c->used;
+  out->adm_base = c->adm_base;
+  out->done = done;
+}
+
 __global__ __launch_bounds__(CMP_THREADS) void k_compact(DevCtl *c, QueueArrays q, JobArrays jb,
-                                                         int slot) {
-  if (slot >= 0 && !c->rec[slot].done) return;
+                                                         int slot, PassSummary *out, int append) {
+  if (slot >= 0 && !c->rec[slot].done) {
+    if (threadIdx.x == 0 && out) write_summary(c, c->rec[slot], 0, out);
+    return;
+  }
   const int64_t mask = q.capacity - 1;
   __shared__ int64_t red[CMP_THREADS / WAVE];
   const int tid = threadIdx.x;
   const int64_t head = c->head, hi = c->p_hi;
   int64_t surv_hi = hi;
-  int64_t adm_hi = c->p_admitted;
+  const int64_t adm_base = c->adm_base;
+  int64_t adm_hi = adm_base + c->p_admitted;
   for (int64_t chunk_hi = hi; chunk_hi > head; chunk_hi -= CMP_CHUNK) {
     const int64_t chunk_lo = chunk_hi - CMP_CHUNK > head ? chunk_hi - CMP_CHUNK : head;
     const int64_t p0 = chunk_lo + int64_t(tid) * CMP_ITEMS;
@@ -465,6 +543,11 @@ __global__ __launch_bounds__(CMP_THREADS) void k_compact(DevCtl *c, QueueArrays 
   if (tid == 0) {
     c->head = surv_hi;
     c->used += c->p_admitted_bytes;
+    if (out) {
+      const RoundRec r = slot >= 0 ? c->rec[slot] : RoundRec{c->p_R0 - c->p_admitted_bytes, hi, 1, 0};
+      write_summary(c, r, 1, out);
+    }
+    if (append) c->adm_base = adm_base + c->p_admitted;
   }
 }
 
@@ -521,6 +604,9 @@ int adm_engine_init(AdmEngine &e, int device, int64_t max_entries) {
   SCHED_HIP_TRY(hipMemset(e.d_ctl, 0, sizeof(DevCtl)));
   SCHED_HIP_TRY(hipHostMalloc(&e.h_ctl, sizeof(DevCtl), hipHostMallocDefault));
   memset(e.h_ctl, 0, sizeof(DevCtl));
+  SCHED_HIP_TRY(hipHostMalloc(&e.h_sum, sizeof(PassSummary) * MAX_CHAIN, hipHostMallocMapped));
+  memset(e.h_sum, 0, sizeof(PassSummary) * MAX_CHAIN);
+  SCHED_HIP_TRY(hipHostGetDevicePointer((void **)&e.d_sum, e.h_sum, 0));
   SCHED_HIP_TRY(hipMalloc(&e.d_flags, sizeof(unsigned long long) * e.max_tiles));
   SCHED_HIP_TRY(hipMemset(e.d_flags, 0, sizeof(unsigned long long) * e.max_tiles));
   int cus = 0;
@@ -535,6 +621,9 @@ void adm_engine_free(AdmEngine &e) {
   if (e.d_ctl) (void)hipFree(e.d_ctl);
   if (e.h_ctl) (void)hipHostFree(e.h_ctl);
   if (e.d_flags) (void)hipFree(e.d_flags);
+  if (e.h_sum) (void)hipHostFree(e.h_sum);
+  e.h_sum = nullptr;
+  e.d_sum = nullptr;
   e.d_ctl = nullptr;
   e.h_ctl = nullptr;
   e.d_flags = nullptr;
@@ -558,21 +647,25 @@ static int next_epoch(AdmEngine &e, hipStream_t s, uint32_t *ep) {
   return SCHED_OK;
 }
 
-static int sync_ctl(AdmEngine &e, hipStream_t s) {
-  SCHED_HIP_TRY(hipMemcpyAsync(e.h_ctl, e.d_ctl, sizeof(DevCtl), hipMemcpyDeviceToHost, s));
+// Summary of the pass whose current state is in slot L & 3, into h_sum[0].
+static int read_summary(AdmEngine &e, uint32_t L, hipStream_t s) {
+  k_summary<<<1, 64, 0, s>>>(e.d_ctl, L, e.d_sum);
+  SCHED_HIP_TRY(hipGetLastError());
   SCHED_HIP_TRY(hipStreamSynchronize(s));
   return SCHED_OK;
 }
 
-static void fill_out(const AdmEngine &e, uint32_t L, PassOut *out) {
-  const DevCtl &h = *e.h_ctl;
-  out->admitted = h.p_admitted;
-  out->admitted_bytes = h.p_admitted_bytes;
-  out->R0 = h.p_R0;
-  out->R_after = h.rec[L & 3].R;
-  out->rounds = h.p_rounds;
-  out->start_final = h.rec[L & 3].start;
-  out->hi = h.p_hi;
+static void fill_out(const PassSummary &h, PassOut *out) {
+  out->admitted = h.admitted;
+  out->admitted_bytes = h.admitted_bytes;
+  out->R0 = h.R0;
+  out->R_after = h.R_after;
+  out->rounds = h.rounds;
+  out->start_final = h.start_final;
+  out->hi = h.hi;
+  out->head = h.head;
+  out->tail = h.tail;
+  out->used = h.used;
 }
 
 // Round kernels until the pass recorded in slot L & 3 is done; returns the
@@ -595,19 +688,21 @@ static int run_rounds(AdmEngine &e, const int64_t *demand, uint8_t *decision, in
       SCHED_HIP_TRY(hipGetLastError());
       L = advance(e);
     }
-    if (int rc = sync_ctl(e, s)) return rc;
-    if (e.h_ctl->rec[L & 3].done) break;
+    if (int rc = read_summary(e, L, s)) return rc;
+    if (e.h_sum[0].done) break;
   }
   *Lio = L;
   return SCHED_OK;
 }
 
 static int launch_window(AdmEngine &e, const int64_t *demand, uint8_t *decision, int64_t mask,
-                         int window_limit, hipStream_t s, uint32_t *Lio) {
+                         int window_limit, int filter, int from_state, int64_t R0, int64_t start,
+                         int64_t end, int append, hipStream_t s, uint32_t *Lio) {
   const uint32_t L = *Lio;
   SCHED_PROF_LAUNCH("k_window", s,
                     (k_window<<<1, WIN_THREADS, 0, s>>>(e.d_ctl, demand, decision, mask, L,
-                                                        window_limit)));
+                                                        window_limit, 1, filter, from_state, R0,
+                                                        start, end, append)));
   SCHED_HIP_TRY(hipGetLastError());
   *Lio = advance(e);
   return SCHED_OK;
@@ -616,47 +711,76 @@ static int launch_window(AdmEngine &e, const int64_t *demand, uint8_t *decision,
 int adm_scan(AdmEngine &e, int policy, const int64_t *demand, uint8_t *decision, int64_t start,
              int64_t end, int64_t R0, int window_limit, hipStream_t s, PassOut *out) {
   uint32_t L = uint32_t(e.launch);
-  k_prologue<<<1, 64, 0, s>>>(e.d_ctl, L, policy == SCHED_POLICY_MMU ? 1 : 0, 0, R0, start, end);
-  SCHED_HIP_TRY(hipGetLastError());
+  const int filter = policy == SCHED_POLICY_MMU ? 1 : 0;
   bool done = false;
   if (window_limit > 0) {
-    if (int rc = launch_window(e, demand, decision, -1, window_limit, s, &L)) return rc;
-    if (int rc = sync_ctl(e, s)) return rc;
-    done = e.h_ctl->rec[L & 3].done != 0;
+    if (int rc = launch_window(e, demand, decision, -1, window_limit, filter, 0, R0, start, end, 0,
+                               s, &L))
+      return rc;
+    if (int rc = read_summary(e, L, s)) return rc;
+    done = e.h_sum[0].done != 0;
+  } else {
+    k_prologue<<<1, 64, 0, s>>>(e.d_ctl, L, filter, 0, R0, start, end);
+    SCHED_HIP_TRY(hipGetLastError());
   }
   if (!done)
     if (int rc = run_rounds(e, demand, decision, -1, end - start, s, &L)) return rc;
-  fill_out(e, L, out);
+  fill_out(e.h_sum[0], out);
   return SCHED_OK;
 }
 
 int adm_pass_ctx(AdmEngine &e, int policy, const QueueArrays &q, const JobArrays &jb,
                  int window_limit, int64_t span_hint, hipStream_t s, PassOut *out) {
   uint32_t L = uint32_t(e.launch);
-  k_prologue<<<1, 64, 0, s>>>(e.d_ctl, L, policy == SCHED_POLICY_MMU ? 1 : 0, 1, 0, 0, 0);
-  SCHED_HIP_TRY(hipGetLastError());
+  const int filter = policy == SCHED_POLICY_MMU ? 1 : 0;
   const int64_t mask = q.capacity - 1;
   if (span_hint <= 0) span_hint = TILE;
   if (window_limit > 0) {
-    if (int rc = launch_window(e, q.demand, q.decision, mask, window_limit, s, &L)) return rc;
+    if (int rc = launch_window(e, q.demand, q.decision, mask, window_limit, filter, 1, 0, 0, 0, 0,
+                               s, &L))
+      return rc;
     // compaction right behind the window kernel; it skips itself on the
-    // device when the pass still needs grid rounds
-    if (int rc = adm_compact(e, q, jb, s, int(L & 3))) return rc;
-    if (int rc = sync_ctl(e, s)) return rc;
-    if (e.h_ctl->rec[L & 3].done) {
-      fill_out(e, L, out);
+    // device when the pass still needs grid rounds, and reports either way
+    if (int rc = adm_compact(e, q, jb, s, int(L & 3), e.d_sum, 0)) return rc;
+    SCHED_HIP_TRY(hipStreamSynchronize(s));
+    if (e.h_sum[0].done) {
+      fill_out(e.h_sum[0], out);
       return SCHED_OK;
     }
+  } else {
+    k_prologue<<<1, 64, 0, s>>>(e.d_ctl, L, filter, 1, 0, 0, 0);
+    SCHED_HIP_TRY(hipGetLastError());
   }
   if (int rc = run_rounds(e, q.demand, q.decision, mask, span_hint, s, &L)) return rc;
-  if (int rc = adm_compact(e, q, jb, s, -1)) return rc;
-  if (int rc = sync_ctl(e, s)) return rc;
-  fill_out(e, L, out);
+  if (int rc = adm_compact(e, q, jb, s, int(L & 3), e.d_sum, 0)) return rc;
+  SCHED_HIP_TRY(hipStreamSynchronize(s));
+  fill_out(e.h_sum[0], out);
   return SCHED_OK;
 }
 
-int adm_compact(AdmEngine &e, const QueueArrays &q, const JobArrays &j, hipStream_t s, int slot) {
-  SCHED_PROF_LAUNCH("k_compact", s, (k_compact<<<1, CMP_THREADS, 0, s>>>(e.d_ctl, q, j, slot)));
+int adm_chain(AdmEngine &e, int policy, const QueueArrays &q, const JobArrays &jb, int rounds,
+              const uint8_t *masks, int64_t n_mask, hipStream_t s) {
+  if (rounds <= 0 || rounds > MAX_CHAIN) return SCHED_E_INVALID;
+  const int filter = policy == SCHED_POLICY_MMU ? 1 : 0;
+  const int64_t mask = q.capacity - 1;
+  uint32_t L = uint32_t(e.launch);
+  for (int r = 0; r < rounds; ++r) {
+    if (r > 0 && masks && n_mask > 0)
+      if (int rc = adm_release_masked(e, jb, masks + int64_t(r - 1) * n_mask, n_mask, s)) return rc;
+    // windows until the pass is done: one launch decides the whole pass
+    if (int rc = launch_window(e, q.demand, q.decision, mask, 1 << 30, filter, 1, 0, 0, 0,
+                               r > 0 ? 1 : 0, s, &L))
+      return rc;
+    if (int rc = adm_compact(e, q, jb, s, int(L & 3), e.d_sum + r, 1)) return rc;
+  }
+  SCHED_HIP_TRY(hipStreamSynchronize(s));
+  return SCHED_OK;
+}
+
+int adm_compact(AdmEngine &e, const QueueArrays &q, const JobArrays &j, hipStream_t s, int slot,
+                PassSummary *d_out, int append) {
+  SCHED_PROF_LAUNCH("k_compact", s,
+                    (k_compact<<<1, CMP_THREADS, 0, s>>>(e.d_ctl, q, j, slot, d_out, append)));
   SCHED_HIP_TRY(hipGetLastError());
   return SCHED_OK;
 }

@@ -36,6 +36,7 @@ struct sched_ctx {
   int64_t seq_next = 0;
   int64_t head_h = 0, tail_h = 0, used_h = 0;
   int64_t last_A = 0;
+  int64_t last_adm_off = 0;
   int32_t *h_adm_job = nullptr;
   int64_t *h_adm_seq = nullptr;
   int64_t h_adm_cap = 0;

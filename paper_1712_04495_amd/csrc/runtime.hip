@@ -256,11 +256,11 @@ int sched_run_pass_locked(sched_ctx *c, hipStream_t s, sched_pass_result_t *res)
       for (int64_t i = 0; i < A; ++i) c->note_admitted(c->h_adm_seq[i]);
     }
   }
-  const DevCtl &h = *c->eng.h_ctl;
-  c->head_h = h.head;
-  c->tail_h = h.tail;
-  c->used_h = h.used;
+  c->head_h = po.head;
+  c->tail_h = po.tail;
+  c->used_h = po.used;
   c->last_A = A;
+  c->last_adm_off = 0;
   c->stats.passes += 1;
   c->stats.rounds += po.rounds;
   c->stats.admitted += A;
@@ -274,7 +274,7 @@ int sched_run_pass_locked(sched_ctx *c, hipStream_t s, sched_pass_result_t *res)
     res->free_after = po.R_after;
     res->rounds = po.rounds;
     res->scanned = po.start_final - head_before;
-    res->pending_after = h.tail - h.head;
+    res->pending_after = po.tail - po.head;
     res->compacted = po.hi - head_before;
   }
   c->cv.notify_all();
@@ -475,9 +475,53 @@ extern "C" int sched_last_admitted(sched_ctx_t *c, int32_t *d_out, int64_t cap, 
   SCHED_HIP_TRY(hipSetDevice(c->device));
   const int64_t n = std::min<int64_t>(cap, c->last_A);
   if (n > 0)
-    SCHED_HIP_TRY(hipMemcpyAsync(d_out, c->q.adm_job, sizeof(int32_t) * n, hipMemcpyDeviceToDevice,
-                                 pick(c, stream)));
+    SCHED_HIP_TRY(hipMemcpyAsync(d_out, c->q.adm_job + c->last_adm_off, sizeof(int32_t) * n,
+                                 hipMemcpyDeviceToDevice, pick(c, stream)));
   *out_n = c->last_A;
+  return SCHED_OK;
+}
+
+extern "C" int sched_pass_chain(sched_ctx_t *c, int32_t rounds, const uint8_t *d_masks,
+                                int64_t n_mask, sched_stream_t stream, sched_pass_result_t *out,
+                                int32_t *d_admitted, int64_t cap) {
+  if (!c || rounds <= 0 || rounds > MAX_CHAIN || n_mask < 0 || (rounds > 1 && n_mask > 0 && !d_masks))
+    return SCHED_E_INVALID;
+  if (cap < 0 || (cap > 0 && !d_admitted)) return SCHED_E_INVALID;
+  std::lock_guard<std::mutex> g(c->mu);
+  if (n_mask > c->n_jobs || !c->host_seq.empty()) return SCHED_E_INVALID;
+  if (c->policy != SCHED_POLICY_FIFO && c->policy != SCHED_POLICY_MMU) return SCHED_E_INVALID;
+  SCHED_HIP_TRY(hipSetDevice(c->device));
+  hipStream_t s = pick(c, stream);
+  if (int rc = adm_chain(c->eng, c->policy, c->q, c->jb, rounds, d_masks, n_mask, s)) return rc;
+  int64_t head_before = c->head_h, total = 0;
+  for (int r = 0; r < rounds; ++r) {
+    const PassSummary &h = c->eng.h_sum[r];
+    if (out) {
+      sched_pass_result_t &o = out[r];
+      o.admitted = h.admitted;
+      o.admitted_bytes = h.admitted_bytes;
+      o.free_before = h.R0;
+      o.free_after = h.R_after;
+      o.rounds = h.rounds;
+      o.scanned = h.start_final - head_before;
+      o.pending_after = h.tail - h.head;
+      o.compacted = h.hi - head_before;
+    }
+    head_before = h.head;
+    total += h.admitted;
+    c->stats.passes += 1;
+    c->stats.rounds += h.rounds;
+    c->stats.admitted += h.admitted;
+  }
+  const PassSummary &last = c->eng.h_sum[rounds - 1];
+  c->head_h = last.head;
+  c->tail_h = last.tail;
+  c->used_h = last.used;
+  c->last_A = last.admitted;
+  c->last_adm_off = last.adm_base - last.admitted;
+  if (cap > 0 && total > 0)
+    SCHED_HIP_TRY(hipMemcpyAsync(d_admitted, c->q.adm_job, sizeof(int32_t) * std::min(cap, total),
+                                 hipMemcpyDeviceToDevice, s));
   return SCHED_OK;
 }
 

@@ -157,6 +157,42 @@ def test_ctx_c2_full(cs, seed):
     assert st["used"] == ref[-1].used_after <= q.capacity
 
 
+@pytest.mark.parametrize("policy", [0, 1])
+@pytest.mark.parametrize("seed,n", [(5, 1 << 14), (2, 1 << 20)])
+def test_ctx_chain_equals_oracle(cs, policy, seed, n):
+    """The device-chained release/admit rounds reproduce every round of the
+    oracle: admitted ids (concatenated in round order) and free memory."""
+    q = c2_queue(seed=seed, n=n, capacity=280 * 10**9 if n > 1 << 16 else 2 * 10**11)
+    rc, ctx = cs.sched_create(policy=policy, capacity_bytes=q.capacity, max_jobs=n,
+                              queue_capacity=n, window_limit=16)
+    assert rc == 0
+    try:
+        assert cs.sched_register_batch(ctx, n)[0] == 0
+        d_job = torch.arange(n, dtype=torch.int32, device=DEV)
+        d_dem = torch.from_numpy(q.demand).to(DEV)
+        coins = torch.from_numpy(q.coins).to(DEV)
+        adm = torch.full((n,), -1, dtype=torch.int32, device=DEV)
+        for rep in range(2):            # the same context twice: reset must restore it
+            assert cs.sched_reset(ctx) == 0
+            assert cs.sched_enqueue_batch(ctx, d_job, d_dem) == 0
+            rc, res = cs.sched_pass_chain(ctx, q.rounds, coins, adm)
+            assert rc == 0
+            torch.cuda.synchronize()
+            ref = S.release_rounds(q.demand, q.capacity, q.coins, q.rounds, policy)
+            got = adm.cpu().numpy().astype(np.int64)
+            off = 0
+            for r, (rr, pr) in enumerate(zip(ref, res)):
+                k = rr.admitted.size
+                assert pr["admitted"] == k, f"round {r}"
+                assert np.array_equal(got[off:off + k], rr.admitted), f"round {r}"
+                assert pr["free_after"] == rr.R_after
+                off += k
+            rc, st = cs.sched_stats(ctx)
+            assert st["used"] == ref[-1].used_after
+    finally:
+        cs.sched_destroy(ctx)
+
+
 # --------------------------------------------------------------------------
 # Life-cycle API vs the oracle state machine
 # --------------------------------------------------------------------------
