@@ -54,6 +54,8 @@ struct DevCtl {
   RoundRec rec[4];
   unsigned long long ticket[4];
   long long break_tile[4];
+  unsigned long long tiles_done[4];  // tiles finished in the round of a slot
+  unsigned long long round_sum[4];   // candidate sums of those tiles
 };
 
 // What a pass reports to the host; written by the device into host-mapped

@@ -47,6 +47,28 @@ __device__ __forceinline__ void reset_next_slot(DevCtl *c, uint32_t L) {
   const int nx = (L + 1) & 3;
   c->ticket[nx] = 0;
   c->break_tile[nx] = LLONG_MAX;
+  c->tiles_done[nx] = 0;
+  c->round_sum[nx] = 0;
+}
+
+// Called once per tile that decided its entries.  In a round without a break
+// every such tile admitted all of its candidates, so the round's admitted sum
+// is the sum of the tiles' candidate sums; the tile that finishes last
+// closes the round.  (With a break, the break tile closes it instead.)
+__device__ __forceinline__ void tile_done(DevCtl *c, int s, int nx, int64_t a, int64_t R,
+                                          int64_t end, long long n_tiles) {
+  add_relaxed(&c->round_sum[s], (unsigned long long)a);
+  const unsigned long long prev =
+      __hip_atomic_fetch_add(&c->tiles_done[s], 1ULL, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+  if (prev + 1 != (unsigned long long)n_tiles) return;
+  if (__hip_atomic_load(&c->break_tile[s], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) != LLONG_MAX)
+    return;
+  const int64_t sum = int64_t(ld_relaxed(&c->round_sum[s]));
+  add_relaxed(&c->p_admitted_bytes, sum);
+  add_relaxed(&c->p_rounds, (int64_t)1);
+  c->rec[nx].R = R - sum;
+  c->rec[nx].start = end;
+  c->rec[nx].done = 1;
 }
 
 __device__ __forceinline__ void pass_init(DevCtl *c, uint32_t L, int filter, int from_state,
@@ -62,6 +84,8 @@ __device__ __forceinline__ void pass_init(DevCtl *c, uint32_t L, int filter, int
   c->rec[s].done = (start >= end || R0 <= 0) ? 1 : 0;
   c->ticket[s] = 0;
   c->break_tile[s] = LLONG_MAX;
+  c->tiles_done[s] = 0;
+  c->round_sum[s] = 0;
   c->p_admitted = 0;
   c->p_admitted_bytes = 0;
   c->p_hi = start;
@@ -291,6 +315,20 @@ __global__ __launch_bounds__(RND_THREADS) void k_round(DevCtl *c, const int64_t 
     const int64_t Araw = block_sum<RND_THREADS>(tsum, red);
     const int64_t A = Araw < cap ? Araw : cap;
 
+    if (Araw == 0) {
+      // No candidate in this tile: every entry is rejected whatever the
+      // prefix before it is, so the tile needs no look-back.  It publishes
+      // its zero sum for the tiles after it (tile 0 knows its prefix is 0).
+      if (tid == 0) st_relaxed(&flags[t], pack_flag(epoch, t == 0 ? FL_INC : FL_AGG, 0));
+#pragma unroll
+      for (int j = 0; j < RND_ITEMS; ++j) {
+        const int64_t p = base + int64_t(j) * RND_THREADS + tid;
+        if (p < end) decision[p & mask] = 0;
+      }
+      if (tid == 0) tile_done(c, s, nx, 0, R, end, n_tiles);
+      continue;
+    }
+
     if (tid < WAVE) {
       // Wave 0 looks back 64 predecessors at a time: lane l reads the flag of
       // tile p - l.  The nearest inclusive flag ends the walk once every
@@ -336,25 +374,9 @@ __global__ __launch_bounds__(RND_THREADS) void k_round(DevCtl *c, const int64_t 
     }
     __syncthreads();
     const int64_t E = s_E;
-    if (E > R) continue;  // the break lies in an earlier tile
+    if (E > R) continue;  // the break lies in an earlier tile, which closes the round
 
     int64_t tcnt = 0, tmax = -1;
-    if (Araw == 0) {
-      // no candidate in this tile: every entry is rejected for good
-#pragma unroll
-      for (int j = 0; j < RND_ITEMS; ++j) {
-        const int64_t p = base + int64_t(j) * RND_THREADS + tid;
-        if (p < end) decision[p & mask] = 0;
-      }
-      if (tid == 0 && t == n_tiles - 1) {
-        add_relaxed(&c->p_admitted_bytes, E);
-        add_relaxed(&c->p_rounds, (int64_t)1);
-        c->rec[nx].R = R - E;
-        c->rec[nx].start = end;
-        c->rec[nx].done = 1;
-      }
-      continue;
-    }
     if (sat_add(E, A, cap) <= R) {
       // every candidate of this tile is admitted
 #pragma unroll
@@ -376,14 +398,7 @@ __global__ __launch_bounds__(RND_THREADS) void k_round(DevCtl *c, const int64_t 
           add_relaxed(&c->p_admitted, cnt);
           max_relaxed(&c->p_hi, mx + 1);
         }
-        if (t == n_tiles - 1) {  // the round ends without a break
-          const int64_t sum = E + A;
-          add_relaxed(&c->p_admitted_bytes, sum);
-          add_relaxed(&c->p_rounds, (int64_t)1);
-          c->rec[nx].R = R - sum;
-          c->rec[nx].start = end;
-          c->rec[nx].done = 1;
-        }
+        tile_done(c, s, nx, A, R, end, n_tiles);  // A is exact here: E + A <= R
       }
       continue;
     }
