@@ -130,6 +130,94 @@ def c2_step_synchronous(cs, ctx, d_job, d_dem, coins):
     return admitted
 
 
+def tenant_measure(cs, torch, dev):
+    """Event-timed tenant kernels against their roofline: triad and histogram
+    against HBM, GEMM against dense bf16 MFMA."""
+    out = {}
+    n = 1 << 28                                    # 1 GiB per fp32 array
+    b = torch.empty(n, dtype=torch.float32, device=dev)
+    c = torch.empty_like(b)
+    a = torch.empty_like(b)
+    assert cs.sched_triad_fill(b, c, 1) == 0
+    assert cs.sched_triad(a, b, c, 3.0, 2) == 0
+    cs.sched_profile(True)
+    assert cs.sched_triad(a, b, c, 3.0, 10) == 0
+    torch.cuda.synchronize()
+    rc, ms, launches = cs.sched_profile_read("k_triad")
+    cs.sched_profile(False)
+    gbs = 12.0 * n * launches / (ms * 1e-3) / 1e9
+    out["triad"] = {"elements": n, "sweeps": launches, "avg_sweep_us": 1e3 * ms / launches,
+                    "GBps": gbs, "frac_of_peak": gbs / HBM_PEAK_GBS,
+                    "bytes_per_sweep": 12 * n}
+    del a, b, c
+    keys = torch.empty(n, dtype=torch.int32, device=dev)
+    bins = torch.empty(4096, dtype=torch.int32, device=dev)
+    assert cs.sched_hist_fill(keys, 1) == 0
+    assert cs.sched_hist(keys, bins) == 0
+    cs.sched_profile(True)
+    for _ in range(5):
+        assert cs.sched_hist(keys, bins) == 0
+    torch.cuda.synchronize()
+    rc, ms, launches = cs.sched_profile_read("k_hist")
+    cs.sched_profile(False)
+    gbs = 4.0 * n * launches / (ms * 1e-3) / 1e9
+    out["hist"] = {"keys": n, "avg_us": 1e3 * ms / launches, "GBps": gbs,
+                   "frac_of_peak": gbs / HBM_PEAK_GBS}
+    del keys, bins
+    N = 8192
+    A = torch.empty(N * N, dtype=torch.int16, device=dev)
+    B = torch.empty(N * N, dtype=torch.int16, device=dev)
+    C = torch.empty(N * N, dtype=torch.float32, device=dev)
+    assert cs.sched_gemm_fill(A, N, N, 1) == 0
+    assert cs.sched_gemm_fill(B, N, N, 2) == 0
+    assert cs.sched_gemm_bf16(A, B, C, N, N, N) == 0
+    cs.sched_profile(True)
+    for _ in range(5):
+        assert cs.sched_gemm_bf16(A, B, C, N, N, N) == 0
+    torch.cuda.synchronize()
+    rc, ms, launches = cs.sched_profile_read("k_gemm_bf16")
+    cs.sched_profile(False)
+    tf = 2.0 * N ** 3 * launches / (ms * 1e-3) / 1e12
+    out["gemm_bf16"] = {"N": N, "avg_ms": ms / launches, "TFLOPs": tf,
+                        "frac_of_peak": tf / 2500.0, "peak_TFLOPs": 2500.0}
+    del A, B, C
+    torch.cuda.empty_cache()
+    return out
+
+
+def slab_measure(cs, torch, dev):
+    """C3: 2^22 allocator ops in 64 concurrent phases; ops/s over the phases."""
+    from workloads import c3_ops
+    ops = c3_ops(seed=3)
+    rc, ctx = cs.sched_create(capacity_bytes=1 << 40, max_jobs=16, max_tenants=ops.quotas.size,
+                              slab_pool_bytes=ops.pool, queue_capacity=4096)
+    assert rc == 0
+    try:
+        assert cs.sched_slab_set_quotas(ctx, ops.quotas) == 0
+        kind = torch.from_numpy(ops.kind).to(dev)
+        ten = torch.from_numpy(ops.tenant).to(dev)
+        size = torch.from_numpy(ops.size).to(dev)
+        ref = torch.from_numpy(ops.ref).to(dev)
+        ptr = torch.zeros(ops.n, dtype=torch.int64, device=dev)
+        st = torch.zeros(ops.n, dtype=torch.int8, device=dev)
+        torch.cuda.synchronize()
+        cs.sched_profile(True)
+        t0 = time.perf_counter()
+        for p0 in range(0, ops.n, ops.phase_len):
+            assert cs.sched_slab_ops(ctx, p0, min(p0 + ops.phase_len, ops.n), kind, ten, size,
+                                     ref, ptr, st) == 0
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        rc, ms, launches = cs.sched_profile_read("k_slab_phase")
+        cs.sched_profile(False)
+        ok = int((st == 0).sum().item())
+    finally:
+        cs.sched_destroy(ctx)
+    return {"ops": ops.n, "phases": launches, "ops_per_s": ops.n / dt,
+            "ops_per_s_kernels": ops.n / (ms * 1e-3), "avg_phase_us": 1e3 * ms / launches,
+            "ok": ok, "bound": "device atomics (no HBM or MFMA roofline applies)"}
+
+
 def cpu_baseline_c2(q, seconds):
     """The oracle as it stands, on host cores, on whole C2 steps."""
     from oracle import sched as S
@@ -284,7 +372,13 @@ def main():
             "frac_of_peak": bytes_pass / kern_s / 1e9 / HBM_PEAK_GBS, "fixed_point_ok": bool(ok)}
         del dd, dec
 
+    out["tenants"] = tenant_measure(cs, torch, dev)
+    print(f"[bench] tenants: {json.dumps(out['tenants'])}", file=sys.stderr, flush=True)
+    out["slab"] = slab_measure(cs, torch, dev)
+    print(f"[bench] slab: {json.dumps(out['slab'])}", file=sys.stderr, flush=True)
+
     if args.cosched:
+        torch.cuda.empty_cache()
         free, _ = torch.cuda.mem_get_info()
         out["coschedule"] = {}
         for name in [x for x in args.cosched.split(",") if x]:
