@@ -349,7 +349,7 @@ int sched_gemm_bf16(const uint16_t *A, const uint16_t *Bt, float *C, int64_t M, 
 /* ======================================================================== */
 /* The life cycle of Sec. II for every job of a mix: a job arrives, declares
  * its demand (pre-allocation, Sec. IV), waits in the queue until the policy
- * of the context (SCHED_POLICY_FIFO or SCHED_POLICY_MMU, Sec. V) admits it,
+ * of the context (any of the four of Sec. V) admits it,
  * runs concurrently with the other admitted jobs, and returns its
  * reservation when it ends (post-free).  Jobs run on a pool of streams; with
  * batch_small, admitted triads under small_bytes are packed into one
@@ -414,7 +414,7 @@ typedef struct {
 /* Runs n jobs (jobs[i] is job handle i; the context needs max_jobs >= n and
  * is reset first) and fills results[n] and *summary (host pointers).
  * Synchronises; the context mutex is held for the whole run.  Errors:
- * SCHED_E_INVALID for bad descriptors or a priority policy. */
+ * SCHED_E_INVALID for bad descriptors. */
 int sched_serve(sched_ctx_t *ctx, int64_t n, const sched_job_desc_t *jobs,
                 const sched_serve_opts_t *opts, sched_job_result_t *results,
                 sched_serve_summary_t *summary);

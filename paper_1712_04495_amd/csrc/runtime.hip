@@ -112,7 +112,7 @@ static int ctx_alloc(sched_ctx *c) {
 static void ctx_free(sched_ctx *c) {
   void *dev[] = {c->q.demand, c->q.job, c->q.prio, c->q.seq, c->q.decision, c->q.adm_job,
                  c->q.adm_demand, c->q.adm_seq, c->jb.res, c->jb.state, c->d_prio_of_job,
-                 c->d_scratch};
+                 c->d_scratch, c->prio_tmp};
   for (void *p : dev)
     if (p) (void)hipFree(p);
   void *host[] = {c->h_stage, c->h_adm_job, c->h_adm_seq};

@@ -528,7 +528,6 @@ extern "C" int sched_serve(sched_ctx_t *c, int64_t n, const sched_job_desc_t *jo
   if (!c || n < 0 || (n > 0 && (!jobs || !results)) || !opts) return SCHED_E_INVALID;
   std::unique_lock<std::mutex> lk(c->mu);
   if (n > c->jb.max_jobs) return SCHED_E_INVALID;
-  if (c->policy != SCHED_POLICY_FIFO && c->policy != SCHED_POLICY_MMU) return SCHED_E_INVALID;
   for (int64_t i = 0; i < n; ++i)
     if (jobs[i].demand <= 0 || jobs[i].kind < 0 || jobs[i].kind > SCHED_JOB_HIST ||
         (i > 0 && jobs[i].arrival_s < jobs[i - 1].arrival_s))

@@ -463,4 +463,3 @@ extern "C" int sched_slab_reset(sched_ctx_t *c) {
   return SCHED_OK;
 }
 
-int sched_priority_reorder_locked(sched_ctx *, hipStream_t) { return SCHED_E_INVALID; }

@@ -196,7 +196,7 @@ def test_ctx_chain_equals_oracle(cs, policy, seed, n):
 # --------------------------------------------------------------------------
 # Life-cycle API vs the oracle state machine
 # --------------------------------------------------------------------------
-@pytest.mark.parametrize("policy", [0, 1])
+@pytest.mark.parametrize("policy", [0, 1, 2, 3])
 def test_lifecycle_random_vs_oracle(cs, policy):
     C = 10_000
     rc, ctx = cs.sched_create(policy=policy, capacity_bytes=C, max_jobs=64, queue_capacity=4096)
@@ -206,10 +206,11 @@ def test_lifecycle_random_vs_oracle(cs, policy):
     try:
         jobs = []
         for _ in range(24):
-            rc, j = cs.sched_register(ctx, 0, 10)
+            pr = int(rng.integers(0, 3)) if policy >= 2 else 0
+            rc, j = cs.sched_register(ctx, pr, 10)
             assert rc == 0
             jobs.append(j)
-            ref.register(0, 10)
+            ref.register(pr, 10)
         for step in range(300):
             j = jobs[int(rng.integers(len(jobs)))]
             if rng.random() < 0.55:

@@ -30,16 +30,18 @@ def _ctx(cs, policy, capacity, n):
     return ctx
 
 
-def _virtual(cs, mix, policy):
+def _virtual(cs, mix, policy, prio=None):
     jt = job_table(mix)
+    if prio is not None:
+        jt["priority"] = prio
     ctx = _ctx(cs, policy, mix.capacity, mix.n)
     try:
         rc, res, sm = cs.sched_serve(ctx, jt, mode=cs.SCHED_SERVE_VIRTUAL)
         assert rc == 0
     finally:
         cs.sched_destroy(ctx)
-    ref = V.simulate(jt["arrival_s"], jt["demand"], jt["vdur_s"], mix.capacity,
-                     S.FIFO if policy == 0 else S.MMU)
+    ref = V.simulate(jt["arrival_s"], jt["demand"], jt["vdur_s"], mix.capacity, policy,
+                     prio=jt["priority"])
     return res, sm, ref
 
 
@@ -61,6 +63,19 @@ def test_virtual_c4_prefix_equals_oracle(cs, policy):
     assert np.array_equal(res["t_admit"][ok], ref["t_admit"][ok])
     assert np.array_equal(res["t_end"][ok], ref["t_end"][ok])
     print(f"  passes={sm['passes']} p99 wait={sm['p99_wait_s']:.3f}", flush=True)
+
+
+@pytest.mark.parametrize("policy", [2, 3])
+def test_virtual_priority_equals_oracle(cs, policy):
+    """Policies 3/4: (priority, arrival) order; a third of the jobs get a
+    higher priority (value 0), the rest value 1 or 2."""
+    mix = c4_jobs(6, n=800)
+    mix.capacity = 48 * GiB
+    prio = np.random.default_rng(9).integers(0, 3, mix.n).astype(np.int32)
+    res, sm, ref = _virtual(cs, mix, policy, prio)
+    ok = ~np.isnan(ref["t_admit"])
+    assert np.array_equal(res["t_admit"][ok], ref["t_admit"][ok])
+    assert np.array_equal(res["t_end"][ok], ref["t_end"][ok])
 
 
 def test_virtual_c5_prefix_equals_oracle(cs):
