@@ -186,10 +186,9 @@ __global__ __launch_bounds__(WIN_THREADS) void k_window(DevCtl *c, const int64_t
         run = sat_add(run, cd ? x[k] : 0, cap);
         incl[k] = cd ? run : -1;  // -1 marks a non-candidate
       }
-      const int64_t wincl = wave_incl_scan_sat(run, cap);
-      int64_t ex = __shfl_up(wincl, 1, WAVE);
-      if (lane == 0) ex = 0;
-      const int64_t total = __shfl(wincl, WAVE - 1, WAVE);
+      const int64_t wincl = wave_incl_scan_sat_dpp(run, cap);
+      const int64_t ex = wave_prev_lane64(wincl);
+      const int64_t total = read_lane64(wincl, WAVE - 1);
       int my_first = WIN_ITEMS;
       int64_t my_before = ex;
 #pragma unroll
@@ -204,26 +203,29 @@ __global__ __launch_bounds__(WIN_THREADS) void k_window(DevCtl *c, const int64_t
       int64_t first = WIN, sum = total;
       if (ball) {
         const int fl = __builtin_ctzll(ball);
-        first = int64_t(fl) * WIN_ITEMS + __shfl(my_first, fl, WAVE);
-        sum = __shfl(my_before, fl, WAVE);
+        first = int64_t(fl) * WIN_ITEMS + __builtin_amdgcn_readlane(my_first, fl);
+        sum = read_lane64(my_before, fl);
       }
       const int64_t lim = (first < WIN) ? first + 1 : WIN;
-      int64_t my_cnt = 0, my_max = -1;
+      int my_last = -1;  // last admitted item of this lane
+      int64_t cnt = 0;
 #pragma unroll
       for (int k = 0; k < WIN_ITEMS; ++k) {
         const int off = lane * WIN_ITEMS + k;
         const int64_t p = p0 + k;
-        if (off >= s_loc && off < lim && p < end) {
-          const bool a = incl[k] >= 0 && off < first;
-          decision[p & mask] = a ? 1 : 0;
-          if (a) {
-            ++my_cnt;
-            my_max = p;
-          }
-        }
+        const bool in = off >= s_loc && off < lim && p < end;
+        const bool a = in && incl[k] >= 0 && off < first;
+        if (in) decision[p & mask] = a ? 1 : 0;
+        if (a) my_last = k;
+        cnt += __builtin_popcountll(__ballot(a));
       }
-      adm_cnt += wave_sum(my_cnt);
-      const int64_t mx = wave_max(my_max);
+      adm_cnt += cnt;
+      int64_t mx = -1;
+      const uint64_t lb = __ballot(my_last >= 0);
+      if (lb) {
+        const int hl = 63 - __builtin_clzll(lb);
+        mx = pos + int64_t(hl) * WIN_ITEMS + __builtin_amdgcn_readlane(my_last, hl);
+      }
       adm_bytes += sum;
       if (mx + 1 > hi) hi = mx + 1;
       R -= sum;

@@ -83,6 +83,36 @@ __device__ __forceinline__ int64_t wave_incl_scan_sat(int64_t v, int64_t cap) {
   }
   return v;
 }
+// DPP lane moves of a 64-bit value (both halves moved with the same control);
+// lanes without a source, or outside row_mask, receive 0.
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ int64_t dpp_move64(int64_t v) {
+  const int lo = __builtin_amdgcn_update_dpp(0, int(uint32_t(v)), CTRL, ROW_MASK, 0xF, true);
+  const int hi = __builtin_amdgcn_update_dpp(0, int(uint32_t(uint64_t(v) >> 32)), CTRL, ROW_MASK,
+                                             0xF, true);
+  return int64_t((uint64_t(uint32_t(hi)) << 32) | uint32_t(lo));
+}
+// Inclusive saturating prefix with DPP: shifts by 1, 2, 4, 8 inside each row
+// of 16 lanes, then lane 15 of rows 0/2 is broadcast into rows 1/3 and lane 31
+// into rows 2/3 (the GFX9 row broadcasts).  All operands stay in VGPRs.
+__device__ __forceinline__ int64_t wave_incl_scan_sat_dpp(int64_t v, int64_t cap) {
+  v = sat_add(v, dpp_move64<0x111, 0xF>(v), cap);  // row_shr:1
+  v = sat_add(v, dpp_move64<0x112, 0xF>(v), cap);  // row_shr:2
+  v = sat_add(v, dpp_move64<0x114, 0xF>(v), cap);  // row_shr:4
+  v = sat_add(v, dpp_move64<0x118, 0xF>(v), cap);  // row_shr:8
+  v = sat_add(v, dpp_move64<0x142, 0xA>(v), cap);  // row_bcast:15 into rows 1, 3
+  v = sat_add(v, dpp_move64<0x143, 0xC>(v), cap);  // row_bcast:31 into rows 2, 3
+  return v;
+}
+// Value of the previous lane (0 for lane 0): wave_shr:1.
+__device__ __forceinline__ int64_t wave_prev_lane64(int64_t v) { return dpp_move64<0x138, 0xF>(v); }
+// Value of a uniform lane, read into scalar registers.
+__device__ __forceinline__ int64_t read_lane64(int64_t v, int lane) {
+  const uint32_t lo = __builtin_amdgcn_readlane(int(uint32_t(v)), lane);
+  const uint32_t hi = __builtin_amdgcn_readlane(int(uint32_t(uint64_t(v) >> 32)), lane);
+  return int64_t((uint64_t(hi) << 32) | lo);
+}
+
 // Inclusive plain prefix over lanes (no saturation).
 __device__ __forceinline__ int64_t wave_incl_scan(int64_t v) {
   const int lane = lane_id();
