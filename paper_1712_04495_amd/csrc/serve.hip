@@ -20,6 +20,7 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <deque>
 #include <queue>
 #include <thread>
 #include <tuple>
@@ -111,7 +112,9 @@ struct Serve {
   std::chrono::steady_clock::time_point h0;
   unsigned long long *d_digest = nullptr;
   std::vector<hipEvent_t> ev_free;
-  std::vector<Running> running;
+  // in-flight work per stream, oldest first (one extra queue for batches):
+  // work on one stream completes in order, so only heads are polled
+  std::vector<std::deque<Running>> inflight;
   std::vector<std::vector<int32_t>> batch_jobs;
   int32_t *h_job = nullptr, *d_job = nullptr;   // arrival staging
   int64_t *h_dem = nullptr, *d_dem = nullptr;
@@ -149,6 +152,7 @@ struct Serve {
     streams.resize(ns);
     for (auto &s : streams) SCHED_HIP_TRY(hipStreamCreate(&s));
     SCHED_HIP_TRY(hipStreamCreate(&bstream));
+    inflight.resize(ns + 1);
     SCHED_HIP_TRY(hipDeviceGetDefaultMemPool(&pool, c->device));
     uint64_t thr = UINT64_MAX;
     SCHED_HIP_TRY(hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &thr));
@@ -185,10 +189,11 @@ struct Serve {
 
   void fini() {
     (void)hipDeviceSynchronize();
-    for (auto &r : running) {
-      if (r.ev_start) ev_free.push_back(r.ev_start);
-      if (r.ev_end) ev_free.push_back(r.ev_end);
-    }
+    for (auto &q : inflight)
+      for (auto &r : q) {
+        if (r.ev_start) ev_free.push_back(r.ev_start);
+        if (r.ev_end) ev_free.push_back(r.ev_end);
+      }
     for (auto e : ev_free) (void)hipEventDestroy(e);
     for (auto s : streams) (void)hipStreamDestroy(s);
     if (bstream) (void)hipStreamDestroy(bstream);
@@ -352,9 +357,9 @@ struct Serve {
         continue;
       }
       Running r{};
-      hipStream_t s = streams[next_stream++ % streams.size()];
-      if (int rc = launch_single(j, s, &r)) return rc;
-      running.push_back(r);
+      const size_t si = next_stream++ % streams.size();
+      if (int rc = launch_single(j, streams[si], &r)) return rc;
+      inflight[si].push_back(r);
       cur_running += 1;
     }
     if (int rc = maybe_launch_batch()) return rc;
@@ -369,7 +374,7 @@ struct Serve {
     pending_small.erase(pending_small.begin(), pending_small.begin() + k);
     Running r{};
     if (int rc = launch_batch(take, &r)) return rc;
-    running.push_back(r);
+    inflight.back().push_back(r);
     cur_running += int64_t(take.size());
     sum.max_running = std::max<int64_t>(sum.max_running, cur_running);
     return SCHED_OK;
@@ -378,31 +383,29 @@ struct Serve {
   // Completed jobs -> results + staged releases; returns how many staged.
   int64_t poll_completions() {
     int64_t k = 0;
-    for (size_t i = 0; i < running.size();) {
-      Running &r = running[i];
-      if (hipEventQuery(r.ev_end) != hipSuccess) {
-        ++i;
-        continue;
+    for (auto &q : inflight) {
+      while (!q.empty()) {
+        Running &r = q.front();
+        if (hipEventQuery(r.ev_end) != hipSuccess) break;
+        const double ts = dev_time(r.ev_start), te = dev_time(r.ev_end);
+        auto done_one = [&](int32_t j) {
+          res[j].t_start = ts;
+          res[j].t_end = te;
+          h_rel[k++] = j;
+          finished += 1;
+          cur_running -= 1;
+          if (res[j].status == SCHED_OK) sum.completed += 1;
+        };
+        if (r.batch >= 0) {
+          for (int32_t j : batch_jobs[r.batch]) done_one(j);
+          batch_running = false;
+        } else {
+          done_one(r.job);
+        }
+        ev_free.push_back(r.ev_start);
+        ev_free.push_back(r.ev_end);
+        q.pop_front();
       }
-      const double ts = dev_time(r.ev_start), te = dev_time(r.ev_end);
-      auto done_one = [&](int32_t j) {
-        res[j].t_start = ts;
-        res[j].t_end = te;
-        h_rel[k++] = j;
-        finished += 1;
-        cur_running -= 1;
-        if (res[j].status == SCHED_OK) sum.completed += 1;
-      };
-      if (r.batch >= 0) {
-        for (int32_t j : batch_jobs[r.batch]) done_one(j);
-        batch_running = false;
-      } else {
-        done_one(r.job);
-      }
-      ev_free.push_back(r.ev_start);
-      ev_free.push_back(r.ev_end);
-      running[i] = running.back();
-      running.pop_back();
     }
     return k;
   }
