@@ -10,11 +10,19 @@
 //     MiB each), region c holding blocks of class c: capacity_c =
 //     region_bytes / class_bytes(c) blocks, one bit each in a bitmap;
 //   * an allocation charges its tenant (<= quota) and the pool (<= pool
-//     bytes) with compare-and-swap loops, so a counter never holds a charge
-//     that is not accounted for by an allocation in flight, then claims a
-//     free bit with an atomic OR; a failure returns every charge it took;
+//     bytes), then claims a free bit with an atomic OR; a failure returns
+//     every charge it took, so a counter never holds more than its value at
+//     the start of a phase plus the charges of allocations that got past it;
 //   * a free checks that the block lies in the pool, is aligned, belongs to
 //     the freeing tenant and is live, clears its bit and returns the charges.
+// A batch of concurrent ops (a phase) first sums, per tenant and for the
+// pool, the class bytes its allocations could take.  A counter that cannot
+// reach its limit even if all of them succeed needs no compare-and-swap: its
+// charges are added after the fact, aggregated per workgroup in LDS.  A
+// counter that may bind is charged before the claim: per lane with a
+// compare-and-swap loop for a tenant, and for the single pool counter by a
+// wave-wide first-fit that reserves the run of lanes that fits with one
+// compare-and-swap.
 // Quotas come either from an explicit table (standalone use) or from the
 // jobs' admitted reservations (tenant = job).
 #include <algorithm>
@@ -56,8 +64,13 @@ struct SlabDev {
   int64_t *charged;              // per tenant
   int64_t *pool_used;            // one counter
   const int64_t *quota;          // per tenant
+  int64_t *phase_sum;            // per tenant, then the pool: class bytes a phase may charge
+  uint8_t *unbounded;            // per tenant, then the pool: 1 = cannot bind this phase
   int32_t n_tenants;
 };
+
+constexpr int PH_THREADS = 256;
+constexpr int PH_LDS_TENANTS = 1024;  // tenants aggregated in LDS; beyond: direct atomics
 
 __device__ __forceinline__ int size_class(int64_t size) {
   if (size < 1 || size > (int64_t(1) << (MIN_LOG2 + N_CLASSES - 1))) return -1;
@@ -85,6 +98,10 @@ __device__ __forceinline__ bool charge(int64_t *ctr, int64_t v, int64_t limit) {
   }
 }
 
+__device__ bool slab_claim(const SlabDev &s, int c, int32_t t, uint64_t hint, uint64_t *out_ptr);
+
+// One allocation with every counter charged by compare-and-swap (the
+// single-op entry point).
 __device__ int8_t slab_alloc_one(const SlabDev &s, int32_t t, int64_t size, uint64_t hint,
                                  uint64_t *out_ptr) {
   const int c = size_class(size);
@@ -95,6 +112,47 @@ __device__ int8_t slab_alloc_one(const SlabDev &s, int32_t t, int64_t size, uint
     add_relaxed(&s.charged[t], -cs);
     return ST_NOMEM_POOL;
   }
+  if (slab_claim(s, c, t, hint, out_ptr)) return ST_OK;
+  add_relaxed(s.pool_used, -cs);
+  add_relaxed(&s.charged[t], -cs);
+  return ST_NOMEM_CLASS;
+}
+
+// Clears the block's bit if the free is valid; the caller returns the
+// charges (*cs = class bytes on ST_OK).
+__device__ int8_t slab_free_claim(const SlabDev &s, int32_t t, uint64_t ptr, int64_t *cs_out) {
+  if (t < 0 || t >= s.n_tenants) return ST_INVALID;
+  const uint64_t b0 = uint64_t(s.base);
+  if (ptr < b0 || ptr >= b0 + uint64_t(N_CLASSES) * uint64_t(s.region_bytes)) return ST_INVALID;
+  const int64_t off = int64_t(ptr - b0);
+  const int c = int(off / s.region_bytes);
+  const int64_t roff = off - int64_t(c) * s.region_bytes;
+  const int64_t cs = int64_t(1) << (MIN_LOG2 + c);
+  if (roff % cs) return ST_INVALID;
+  const int64_t blk = roff / cs;
+  if (blk >= s.cap[c]) return ST_INVALID;
+  if (s.owner[s.owner_off[c] + blk] != t) return ST_INVALID;
+  const unsigned long long bit = 1ULL << (blk & 63);
+  const unsigned long long old = __hip_atomic_fetch_and(s.bits + s.words_off[c] + (blk >> 6), ~bit,
+                                                        __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  if (!(old & bit)) return ST_INVALID;  // not live: double free
+  *cs_out = cs;
+  return ST_OK;
+}
+
+__device__ int8_t slab_free_one(const SlabDev &s, int32_t t, uint64_t ptr) {
+  int64_t cs = 0;
+  const int8_t st = slab_free_claim(s, t, ptr, &cs);
+  if (st == ST_OK) {
+    add_relaxed(s.pool_used, -cs);
+    add_relaxed(&s.charged[t], -cs);
+  }
+  return st;
+}
+
+// Claims a free block of class c (charges already settled by the caller).
+__device__ bool slab_claim(const SlabDev &s, int c, int32_t t, uint64_t hint, uint64_t *out_ptr) {
+  const int64_t cs = int64_t(1) << (MIN_LOG2 + c);
   const int64_t nw = s.n_words[c];
   unsigned long long *bits = s.bits + s.words_off[c];
   const int64_t w0 = nw > 0 ? int64_t(mix32(hint) % uint64_t(nw)) : 0;
@@ -111,61 +169,184 @@ __device__ int8_t slab_alloc_one(const SlabDev &s, int32_t t, int64_t size, uint
         const int64_t blk = w * 64 + b;
         s.owner[s.owner_off[c] + blk] = t;
         *out_ptr = uint64_t(s.base + int64_t(c) * s.region_bytes + blk * cs);
-        return ST_OK;
+        return true;
       }
       cur = old | bit;
     }
   }
-  add_relaxed(s.pool_used, -cs);
-  add_relaxed(&s.charged[t], -cs);
-  return ST_NOMEM_CLASS;
+  return false;
 }
 
-__device__ int8_t slab_free_one(const SlabDev &s, int32_t t, uint64_t ptr) {
-  if (t < 0 || t >= s.n_tenants) return ST_INVALID;
-  const uint64_t b0 = uint64_t(s.base);
-  if (ptr < b0 || ptr >= b0 + uint64_t(N_CLASSES) * uint64_t(s.region_bytes)) return ST_INVALID;
-  const int64_t off = int64_t(ptr - b0);
-  const int c = int(off / s.region_bytes);
-  const int64_t roff = off - int64_t(c) * s.region_bytes;
-  const int64_t cs = int64_t(1) << (MIN_LOG2 + c);
-  if (roff % cs) return ST_INVALID;
-  const int64_t blk = roff / cs;
-  if (blk >= s.cap[c]) return ST_INVALID;
-  if (s.owner[s.owner_off[c] + blk] != t) return ST_INVALID;
-  const unsigned long long bit = 1ULL << (blk & 63);
-  const unsigned long long old = __hip_atomic_fetch_and(s.bits + s.words_off[c] + (blk >> 6), ~bit,
-                                                        __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  if (!(old & bit)) return ST_INVALID;  // not live: double free
-  add_relaxed(s.pool_used, -cs);
-  add_relaxed(&s.charged[t], -cs);
-  return ST_OK;
+// Wave-collective charge of v (> 0) for the lanes with `want` against
+// *ctr <= limit; every lane of the wave calls it.  Lanes go in lane order,
+// first fit: the run of pending lanes whose running sum fits above the last
+// counter value read is reserved with one compare-and-swap; the lane that
+// breaks the run is refused (that value plus the run plus its own v exceeds
+// the limit) and the rest are tried again.  Returns whether this lane's
+// charge went in.
+__device__ bool charge_wave_first_fit(int64_t *ctr, int64_t v, bool want, int64_t limit) {
+  const int lane = lane_id();
+  uint64_t pending = __ballot(want);
+  if (!pending) return false;
+  bool got = false;
+  int64_t cur = read_lane64(ld_relaxed(ctr), __builtin_ctzll(pending));
+  while (pending) {
+    const bool mine = (pending >> lane) & 1;
+    const int64_t pre = wave_incl_scan(mine ? v : 0);
+    const uint64_t fit = __ballot(mine && pre <= limit - cur);
+    if (fit) {
+      const int last = 63 - __builtin_clzll(fit);
+      const int leader = __builtin_ctzll(fit);
+      const int64_t tot = read_lane64(pre, last);
+      int64_t seen = cur;
+      int ok = 0;
+      if (lane == leader)
+        ok = __hip_atomic_compare_exchange_strong(ctr, &seen, cur + tot, __ATOMIC_RELAXED,
+                                                  __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      ok = __builtin_amdgcn_readlane(ok, leader);
+      seen = read_lane64(seen, leader);
+      if (!ok) {
+        cur = seen;
+        continue;
+      }
+      cur += tot;
+      got = got || ((fit >> lane) & 1);
+      pending &= ~fit;
+    }
+    pending &= pending - 1;  // the lane that breaks the run does not fit
+  }
+  return got;
+}
+
+// Class bytes each tenant's allocations in ops [begin, end) could charge,
+// and their total (slot n_tenants); added into phase_sum, which is zero
+// before the phase.
+__global__ __launch_bounds__(PH_THREADS) void k_slab_sum(SlabDev s, int64_t begin, int64_t end,
+                                                         const uint8_t *__restrict__ kind,
+                                                         const int32_t *__restrict__ tenant,
+                                                         const int64_t *__restrict__ size) {
+  __shared__ int64_t agg[PH_LDS_TENANTS];
+  __shared__ int64_t red[PH_THREADS / WAVE];
+  const bool lds = s.n_tenants <= PH_LDS_TENANTS;
+  if (lds)
+    for (int i = threadIdx.x; i < s.n_tenants; i += PH_THREADS) agg[i] = 0;
+  __syncthreads();
+  int64_t total = 0;
+  for (int64_t i = begin + blockIdx.x * int64_t(PH_THREADS) + threadIdx.x; i < end;
+       i += int64_t(gridDim.x) * PH_THREADS) {
+    if (kind[i] != OPK_ALLOC) continue;
+    const int32_t t = tenant[i];
+    const int c = size_class(size[i]);
+    if (c < 0 || t < 0 || t >= s.n_tenants) continue;
+    const int64_t cs = int64_t(1) << (MIN_LOG2 + c);
+    total += cs;
+    if (lds)
+      atomicAdd((unsigned long long *)&agg[t], (unsigned long long)cs);
+    else
+      add_relaxed(&s.phase_sum[t], cs);
+  }
+  total = block_sum<PH_THREADS>(total, red);  // ends with a barrier after the LDS adds
+  if (lds)
+    for (int i = threadIdx.x; i < s.n_tenants; i += PH_THREADS)
+      if (agg[i]) add_relaxed(&s.phase_sum[i], agg[i]);
+  if (threadIdx.x == 0 && total) add_relaxed(&s.phase_sum[s.n_tenants], total);
+}
+
+// Per counter: can it reach its limit in this phase?  Clears phase_sum for
+// the next phase.
+__global__ void k_slab_bound(SlabDev s) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i <= s.n_tenants; i += gridDim.x * blockDim.x) {
+    const int64_t sum = s.phase_sum[i];
+    const bool free_run = i < s.n_tenants ? ld_relaxed(&s.charged[i]) + sum <= s.quota[i]
+                                          : ld_relaxed(s.pool_used) + sum <= s.pool_bytes;
+    s.unbounded[i] = free_run ? 1 : 0;
+    s.phase_sum[i] = 0;
+  }
 }
 
 // One phase of concurrent ops [begin, end).  Arrays are indexed by the global
 // op index; a free names an alloc op of an earlier phase by index.
-__global__ void k_slab_phase(SlabDev s, int64_t begin, int64_t end, const uint8_t *__restrict__ kind,
-                             const int32_t *__restrict__ tenant, const int64_t *__restrict__ size,
-                             const int64_t *__restrict__ ref, uint64_t *__restrict__ ptr,
-                             int8_t *__restrict__ status) {
-  for (int64_t i = begin + blockIdx.x * int64_t(blockDim.x) + threadIdx.x; i < end;
-       i += int64_t(gridDim.x) * blockDim.x) {
-    const int32_t t = tenant[i];
-    int8_t st;
+__global__ __launch_bounds__(PH_THREADS) void k_slab_phase(
+    SlabDev s, int64_t begin, int64_t end, const uint8_t *__restrict__ kind,
+    const int32_t *__restrict__ tenant, const int64_t *__restrict__ size,
+    const int64_t *__restrict__ ref, uint64_t *__restrict__ ptr, int8_t *__restrict__ status) {
+  __shared__ int64_t agg[PH_LDS_TENANTS];  // deferred tenant charges of this workgroup
+  const bool lds = s.n_tenants <= PH_LDS_TENANTS;
+  if (lds)
+    for (int i = threadIdx.x; i < s.n_tenants; i += PH_THREADS) agg[i] = 0;
+  __syncthreads();
+  const bool pool_free_run = s.unbounded[s.n_tenants] != 0;
+  // the loop bound is uniform over the workgroup: every lane reaches the
+  // wave-wide pool charge together
+  for (int64_t base = begin + blockIdx.x * int64_t(PH_THREADS); base < end;
+       base += int64_t(gridDim.x) * PH_THREADS) {
+    const int64_t i = base + threadIdx.x;
+    const bool active = i < end;
+    int8_t st = ST_INVALID;
     uint64_t p = 0;
-    if (kind[i] == OPK_ALLOC) {
-      st = slab_alloc_one(s, t, size[i], uint64_t(i) * 0x9E3779B97F4A7C15ULL, &p);
-    } else {
-      const int64_t r = ref[i];
-      if (kind[i] != OPK_FREE || r < 0 || r >= begin || kind[r] != OPK_ALLOC || status[r] != ST_OK) {
-        st = ST_INVALID;
+    int64_t cs = 0, tenant_delta = 0, pool_delta = 0;
+    int32_t t = -1;
+    int c = -1;
+    bool t_free_run = false, want_pool = false, is_alloc = false;
+    if (active) {
+      t = tenant[i];
+      const uint8_t k = kind[i];
+      is_alloc = k == OPK_ALLOC;
+      if (is_alloc) {
+        c = size_class(size[i]);
+        if (c >= 0 && t >= 0 && t < s.n_tenants) {
+          cs = int64_t(1) << (MIN_LOG2 + c);
+          t_free_run = s.unbounded[t] != 0;
+          if (t_free_run || charge(&s.charged[t], cs, s.quota[t]))
+            want_pool = true;
+          else
+            st = ST_QUOTA;
+        }
       } else {
-        st = slab_free_one(s, t, ptr[r]);
+        const int64_t r = ref[i];
+        if (k == OPK_FREE && r >= 0 && r < begin && kind[r] == OPK_ALLOC && status[r] == ST_OK) {
+          int64_t fcs = 0;
+          st = slab_free_claim(s, t, ptr[r], &fcs);
+          if (st == ST_OK) {
+            tenant_delta = -fcs;
+            pool_delta = -fcs;
+          }
+        }
       }
     }
-    status[i] = st;
-    ptr[i] = st == ST_OK && kind[i] == OPK_ALLOC ? p : 0;
+    bool pooled = want_pool;
+    if (!pool_free_run) pooled = charge_wave_first_fit(s.pool_used, cs, want_pool, s.pool_bytes);
+    if (want_pool) {
+      if (!pooled) {
+        st = ST_NOMEM_POOL;
+        if (!t_free_run) add_relaxed(&s.charged[t], -cs);
+      } else if (slab_claim(s, c, t, uint64_t(i) * 0x9E3779B97F4A7C15ULL, &p)) {
+        st = ST_OK;
+        if (t_free_run) tenant_delta = cs;
+        if (pool_free_run) pool_delta = cs;
+      } else {
+        st = ST_NOMEM_CLASS;
+        if (!pool_free_run) add_relaxed(s.pool_used, -cs);
+        if (!t_free_run) add_relaxed(&s.charged[t], -cs);
+      }
+    }
+    if (tenant_delta) {
+      if (lds)
+        atomicAdd((unsigned long long *)&agg[t], (unsigned long long)tenant_delta);
+      else
+        add_relaxed(&s.charged[t], tenant_delta);
+    }
+    pool_delta = wave_sum(pool_delta);
+    if (lane_id() == 0 && pool_delta) add_relaxed(s.pool_used, pool_delta);
+    if (active) {
+      status[i] = st;
+      ptr[i] = st == ST_OK && is_alloc ? p : 0;
+    }
   }
+  __syncthreads();
+  if (lds)
+    for (int i = threadIdx.x; i < s.n_tenants; i += PH_THREADS)
+      if (agg[i]) add_relaxed(&s.charged[i], agg[i]);
 }
 
 __global__ void k_slab_one(SlabDev s, int32_t t, int64_t size, uint64_t fptr, int is_free,
@@ -217,6 +398,8 @@ struct SlabState {
   int8_t *d_one_st = nullptr;
   void *h_one = nullptr;
   uint64_t hint = 1;
+  hipEvent_t last_phase = nullptr;  // completion of the last batch of ops
+  bool phase_recorded = false;
   std::vector<std::pair<void *, int64_t>> large;  // large-tier blocks: ptr, charged bytes
   std::vector<int32_t> large_owner;
 };
@@ -252,6 +435,10 @@ int sched_slab_init(sched_ctx *c, int64_t pool_bytes, int32_t n_tenants) {
   SCHED_HIP_TRY(hipMemset(d.charged, 0, sizeof(int64_t) * n_tenants));
   SCHED_HIP_TRY(hipMalloc(&d.pool_used, sizeof(int64_t)));
   SCHED_HIP_TRY(hipMemset(d.pool_used, 0, sizeof(int64_t)));
+  SCHED_HIP_TRY(hipMalloc(&d.phase_sum, sizeof(int64_t) * (n_tenants + 1)));
+  SCHED_HIP_TRY(hipMemset(d.phase_sum, 0, sizeof(int64_t) * (n_tenants + 1)));
+  SCHED_HIP_TRY(hipMalloc(&d.unbounded, n_tenants + 1));
+  SCHED_HIP_TRY(hipEventCreateWithFlags(&s->last_phase, hipEventDisableTiming));
   SCHED_HIP_TRY(hipMalloc(&s->d_quota, sizeof(int64_t) * n_tenants));
   SCHED_HIP_TRY(hipMemset(s->d_quota, 0, sizeof(int64_t) * n_tenants));
   SCHED_HIP_TRY(hipMalloc(&s->d_one_ptr, sizeof(uint64_t)));
@@ -269,11 +456,14 @@ void sched_slab_free(sched_ctx *c) {
   if (!s) return;
   for (auto &b : s->large)
     if (b.first) (void)hipFree(b.first);
-  void *dev[] = {s->dev.base, s->dev.bits, s->dev.owner, s->dev.charged, s->dev.pool_used,
-                 s->d_quota, s->d_one_ptr, s->d_one_st};
+  if (s->last_phase) (void)hipEventSynchronize(s->last_phase);
+  void *dev[] = {s->dev.base,     s->dev.bits,      s->dev.owner,  s->dev.charged,
+                 s->dev.pool_used, s->dev.phase_sum, s->dev.unbounded, s->d_quota,
+                 s->d_one_ptr,    s->d_one_st};
   for (void *p : dev)
     if (p) (void)hipFree(p);
   if (s->h_one) (void)hipHostFree(s->h_one);
+  if (s->last_phase) (void)hipEventDestroy(s->last_phase);
   delete s;
   c->slab = nullptr;
 }
@@ -281,6 +471,7 @@ void sched_slab_free(sched_ctx *c) {
 int64_t sched_slab_pool_used(sched_ctx *c) {
   if (!c->slab) return 0;
   int64_t v = 0;
+  if (c->slab->phase_recorded && hipEventSynchronize(c->slab->last_phase) != hipSuccess) return -1;
   if (hipMemcpy(&v, c->slab->dev.pool_used, sizeof(v), hipMemcpyDeviceToHost) != hipSuccess) return -1;
   return v;
 }
@@ -295,9 +486,19 @@ static int8_t to_status_code(int8_t st) {
   }
 }
 
+// Work on the context stream starts after the last batch of ops, which may
+// run on another stream: a batch decides before it starts which counters can
+// bind, and must not see charges from outside it.
+static int slab_after_phase(sched_ctx *c, hipStream_t st) {
+  SlabState *s = c->slab;
+  if (s->phase_recorded) SCHED_HIP_TRY(hipStreamWaitEvent(st, s->last_phase, 0));
+  return SCHED_OK;
+}
+
 static int slab_one_locked(sched_ctx *c, int32_t t, int64_t size, uint64_t fptr, int is_free,
                            uint64_t *out_ptr, int8_t *out_st) {
   SlabState *s = c->slab;
+  if (int rc = slab_after_phase(c, c->stream)) return rc;
   k_slab_one<<<1, 64, 0, c->stream>>>(s->dev, t, size, fptr, is_free, s->hint++ * 0x9E3779B97F4A7C15ULL,
                                       s->d_one_ptr, s->d_one_st);
   SCHED_HIP_TRY(hipGetLastError());
@@ -311,6 +512,7 @@ static int slab_one_locked(sched_ctx *c, int32_t t, int64_t size, uint64_t fptr,
 
 static int slab_charge_locked(sched_ctx *c, int32_t t, int64_t v, int8_t *st) {
   SlabState *s = c->slab;
+  if (int rc = slab_after_phase(c, c->stream)) return rc;
   k_slab_charge<<<1, 64, 0, c->stream>>>(s->dev, t, v, s->d_one_st);
   SCHED_HIP_TRY(hipGetLastError());
   SCHED_HIP_TRY(hipMemcpyAsync((char *)s->h_one + 8, s->d_one_st, 1, hipMemcpyDeviceToHost, c->stream));
@@ -388,6 +590,7 @@ extern "C" int sched_slab_set_quotas(sched_ctx_t *c, int32_t n, const int64_t *h
     if (h_quotas[i] < 0) return SCHED_E_INVALID;
   SCHED_HIP_TRY(hipSetDevice(c->device));
   SlabState *s = c->slab;
+  if (int rc = slab_after_phase(c, c->stream)) return rc;
   std::vector<int64_t> q(s->dev.n_tenants, 0);
   std::copy(h_quotas, h_quotas + n, q.begin());
   SCHED_HIP_TRY(hipMemcpyAsync(s->d_quota, q.data(), sizeof(int64_t) * q.size(), hipMemcpyHostToDevice,
@@ -408,12 +611,21 @@ extern "C" int sched_slab_ops(sched_ctx_t *c, int64_t begin, int64_t end, const 
   if (end == begin) return SCHED_OK;
   SCHED_HIP_TRY(hipSetDevice(c->device));
   hipStream_t s = stream ? (hipStream_t)stream : c->stream;
+  SlabState *st = c->slab;
+  const SlabDev &d = st->dev;
+  if (int rc = slab_after_phase(c, s)) return rc;
   const int64_t n = end - begin;
-  const int grid = int(std::min<int64_t>((n + 255) / 256, 8192));
-  SCHED_PROF_LAUNCH("k_slab_phase", s,
-                    (k_slab_phase<<<grid, 256, 0, s>>>(c->slab->dev, begin, end, d_kind, d_tenant,
-                                                       d_size, d_ref, d_ptr, d_status)));
+  const int grid = int(std::min<int64_t>((n + PH_THREADS - 1) / PH_THREADS, 1024));
+  k_slab_sum<<<grid, PH_THREADS, 0, s>>>(d, begin, end, d_kind, d_tenant, d_size);
   SCHED_HIP_TRY(hipGetLastError());
+  k_slab_bound<<<(d.n_tenants + 1 + 255) / 256, 256, 0, s>>>(d);
+  SCHED_HIP_TRY(hipGetLastError());
+  SCHED_PROF_LAUNCH("k_slab_phase", s,
+                    (k_slab_phase<<<grid, PH_THREADS, 0, s>>>(d, begin, end, d_kind, d_tenant, d_size,
+                                                              d_ref, d_ptr, d_status)));
+  SCHED_HIP_TRY(hipGetLastError());
+  SCHED_HIP_TRY(hipEventRecord(st->last_phase, s));
+  st->phase_recorded = true;
   return SCHED_OK;
 }
 
@@ -439,6 +651,7 @@ extern "C" int sched_slab_counters(sched_ctx_t *c, int32_t n, int64_t *h_charged
   std::lock_guard<std::mutex> g(c->mu);
   if (!c->slab || n > c->slab->dev.n_tenants) return SCHED_E_INVALID;
   SCHED_HIP_TRY(hipSetDevice(c->device));
+  if (c->slab->phase_recorded) SCHED_HIP_TRY(hipEventSynchronize(c->slab->last_phase));
   SCHED_HIP_TRY(hipStreamSynchronize(c->stream));
   if (n) SCHED_HIP_TRY(hipMemcpy(h_charged, c->slab->dev.charged, sizeof(int64_t) * n, hipMemcpyDeviceToHost));
   SCHED_HIP_TRY(hipMemcpy(h_pool_used, c->slab->dev.pool_used, sizeof(int64_t), hipMemcpyDeviceToHost));
@@ -451,6 +664,7 @@ extern "C" int sched_slab_reset(sched_ctx_t *c) {
   if (!c->slab) return SCHED_E_INVALID;
   SCHED_HIP_TRY(hipSetDevice(c->device));
   SlabState *s = c->slab;
+  if (s->phase_recorded) SCHED_HIP_TRY(hipEventSynchronize(s->last_phase));
   for (auto &b : s->large)
     if (b.first) (void)hipFree(b.first);
   s->large.clear();
@@ -459,6 +673,7 @@ extern "C" int sched_slab_reset(sched_ctx_t *c) {
   SCHED_HIP_TRY(hipGetLastError());
   SCHED_HIP_TRY(hipMemsetAsync(s->dev.charged, 0, sizeof(int64_t) * s->dev.n_tenants, c->stream));
   SCHED_HIP_TRY(hipMemsetAsync(s->dev.pool_used, 0, sizeof(int64_t), c->stream));
+  SCHED_HIP_TRY(hipMemsetAsync(s->dev.phase_sum, 0, sizeof(int64_t) * (s->dev.n_tenants + 1), c->stream));
   SCHED_HIP_TRY(hipStreamSynchronize(c->stream));
   return SCHED_OK;
 }
