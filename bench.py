@@ -46,6 +46,20 @@ def parse():
                     help="bound on the oracle's CPU time for cpu_baseline (0 = skip)")
     ap.add_argument("--no-profile", action="store_true",
                     help="time the steps without kernel events (no roofline)")
+    ap.add_argument("--profile-every", type=int, default=5,
+                    help="bracket the kernels of every n-th timed step with HIP events "
+                         "(events cost time of their own; 1 = every step)")
+    ap.add_argument("--copy-calib-mib", type=int, default=0,
+                    help="run a plain device-to-device copy of this many MiB first (the "
+                         "known-size reference for hardware byte counters)")
+    ap.add_argument("--traffic-from", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
+                    help="no GPU run: turn two rocprofv3 --pmc counter CSVs (FETCH_SIZE, then "
+                         "WRITE_SIZE) of a run with --copy-calib-mib into the traffic record "
+                         "of --traffic-kernel under profiles/")
+    ap.add_argument("--traffic-kernel", default="k_chain")
+    ap.add_argument("--extras", default="dense,tenants,slab",
+                    help="measurements to add after the admission steps (dense, tenants, "
+                         "slab; empty = none)")
     ap.add_argument("--cosched", default="c1,c5",
                     help="co-scheduled vs serial runs to add (c1, c4, c5; empty = none)")
     ap.add_argument("--c5-jobs", type=int, default=50_000)
@@ -108,11 +122,16 @@ def c2_step(cs, ctx, d_job, d_dem, coins):
     assert cs.sched_enqueue_batch(ctx, d_job, d_dem) == 0
     rc, res = cs.sched_pass_chain(ctx, coins.shape[0] + 1, coins)
     assert rc == 0
-    admitted = sum(r["admitted"] for r in res)
-    scanned = sum(r["scanned"] for r in res)
-    compacted = sum(r["compacted"] for r in res)
+    tot = {k: sum(r[k] for r in res) for k in ("admitted", "scanned", "compacted", "released")}
+    # running jobs each round's release step looks at
+    running, considered = 0, 0
+    for i, r in enumerate(res):
+        if i > 0:
+            considered += running
+        running += r["admitted"] - r["released"]
+    tot["considered"] = considered
     per_pass = [(r["admitted"], r["free_after"]) for r in res]
-    return admitted, scanned, compacted, per_pass
+    return tot, per_pass
 
 
 def c2_step_synchronous(cs, ctx, d_job, d_dem, coins):
@@ -238,8 +257,74 @@ def cpu_baseline_c2(q, seconds):
                       f"requests) in {dt:.1f} s, pure numpy/Python, one thread"}, per_pass
 
 
+ROOT = os.path.dirname(os.path.abspath(__file__))
+KERNEL_SOURCE = {"k_chain": "paper_1712_04495_amd/csrc/admission.hip",
+                 "k_window": "paper_1712_04495_amd/csrc/admission.hip",
+                 "k_round": "paper_1712_04495_amd/csrc/admission.hip"}
+
+
+def _sha256(rel):
+    import hashlib
+    with open(os.path.join(ROOT, rel), "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()
+
+
+def _counter_rows(path, counter):
+    """(kernel name, value) per dispatch from a rocprofv3 counter CSV."""
+    import csv
+    out = []
+    with open(path, newline="") as f:
+        for r in csv.DictReader(f):
+            if r.get("Counter_Name", "").strip() != counter:
+                continue
+            out.append((r.get("Kernel_Name", ""), float(r["Counter_Value"])))
+    return out
+
+
+def traffic_record(fetch_csv, write_csv, copy_mib, kernel):
+    """HBM bytes per launch of `kernel`: FETCH_SIZE and WRITE_SIZE (KiB per
+    dispatch) scaled by what the same counters read for a device-to-device
+    copy of copy_mib MiB (which reads and writes exactly that many bytes)."""
+    copy_bytes = float(copy_mib) * (1 << 20)
+    rec = {"kernel": kernel, "source": KERNEL_SOURCE[kernel],
+           "source_sha256": _sha256(KERNEL_SOURCE[kernel]), "copy_bytes": copy_bytes}
+    for name, path, key in (("FETCH_SIZE", fetch_csv, "fetch"), ("WRITE_SIZE", write_csv, "write")):
+        rows = _counter_rows(path, name)
+        mine = [v for k, v in rows if k.split("(")[0].strip().endswith(kernel)]
+        copies = [v for k, v in rows if "copy" in k.lower() and kernel not in k]
+        assert mine and copies, f"no {kernel} or copy dispatches with {name} in {path}"
+        copy_kib = max(copies)       # the calibration copy is the largest copy
+        factor = copy_bytes / (copy_kib * 1024.0)
+        per = sum(mine) / len(mine) * 1024.0 * factor
+        rec[key] = {"counter_kib_per_dispatch": sum(mine) / len(mine), "dispatches": len(mine),
+                    "copy_counter_kib": copy_kib, "scale": factor, "bytes_per_launch": per}
+    rec["bytes_per_launch"] = rec["fetch"]["bytes_per_launch"] + rec["write"]["bytes_per_launch"]
+    return rec
+
+
+def traffic_for(kernel):
+    """The committed traffic record of `kernel`, or None if there is none or
+    its source changed since the counters were taken."""
+    path = os.path.join(ROOT, "profiles", f"{kernel}_c2_traffic.json")
+    if kernel not in KERNEL_SOURCE or not os.path.exists(path):
+        return None
+    with open(path) as f:
+        rec = json.load(f)
+    if rec.get("source_sha256") != _sha256(KERNEL_SOURCE[kernel]):
+        return None
+    return rec["bytes_per_launch"]
+
+
 def main():
     args = parse()
+    if args.traffic_from:
+        rec = traffic_record(args.traffic_from[0], args.traffic_from[1], args.copy_calib_mib,
+                             args.traffic_kernel)
+        path = os.path.join(ROOT, "profiles", f"{args.traffic_kernel}_c2_traffic.json")
+        with open(path, "w") as f:
+            json.dump(rec, f, indent=1)
+        print(json.dumps(rec))
+        return 0
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print(json.dumps({"error": "this build runs on one GPU only; the admission state is "
@@ -267,27 +352,46 @@ def main():
     coins = torch.from_numpy(q.coins).to(dev)
     torch.cuda.synchronize()
 
+    if args.copy_calib_mib > 0:
+        src = torch.ones(args.copy_calib_mib << 18, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     for _ in range(args.warmup):
         c2_step(cs, ctx, d_job, d_dem, coins)
     profile = not args.no_profile
-    cs.sched_profile(profile)
+    every = max(1, args.profile_every)
+    cs.sched_profile(1)
+    cs.sched_profile(0)
+    print(f"[bench] c2: {args.steps} timed steps", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    tot_adm = tot_scan = tot_comp = 0
+    tot_adm = 0
+    prof = {"scanned": 0, "compacted": 0, "released": 0, "considered": 0}
+    prof_steps = 0
     last = None
-    for _ in range(args.steps):
-        a, s_, c_, last = c2_step(cs, ctx, d_job, d_dem, coins)
-        tot_adm += a
-        tot_scan += s_
-        tot_comp += c_
+    for i in range(args.steps):
+        sampled = profile and i % every == every - 1
+        if sampled:
+            cs.sched_profile(2)
+        tot, last = c2_step(cs, ctx, d_job, d_dem, coins)
+        if sampled:
+            cs.sched_profile(0)
+            for k in prof:
+                prof[k] += tot[k]
+            prof_steps += 1
+        tot_adm += tot["admitted"]
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
+    profile = profile and prof_steps > 0
     kern = {}
     if profile:
-        for k in ("k_window", "k_round", "k_compact", "k_release_masked"):
+        for k in ("k_chain", "k_run_list", "k_window", "k_round", "k_compact", "k_release_masked"):
             rc, ms, launches = cs.sched_profile_read(k)
-            kern[k] = (ms, launches)
-        cs.sched_profile(0)
+            if launches:
+                kern[k] = (ms, launches)
     # the per-pass host API on the same rounds, for comparison
     t1 = time.perf_counter()
     sync_adm = 0
@@ -323,29 +427,31 @@ def main():
                                          "us_per_pass": 1e6 * sync_dt / args.steps / q.rounds}},
     }
     if profile:
-        # algorithmic bytes: 8 B demand read + 1 B decision per decided entry
-        # (scan kernels); 25 B read + 24 B written per entry of the compacted
-        # window (compaction); 17 B per job slot for the masked release
-        alg = {"k_window": 9 * tot_scan, "k_round": 0, "k_compact": 49 * tot_comp,
-               "k_release_masked": 17 * n * (q.rounds - 1) * args.steps}
-        if kern["k_round"][1]:
-            alg["k_window"], alg["k_round"] = 0, 9 * tot_scan  # attributed below if both ran
-            if kern["k_window"][1]:
-                alg["k_window"] = 9 * tot_scan * kern["k_window"][0] / (
-                    kern["k_window"][0] + kern["k_round"][0])
-                alg["k_round"] = 9 * tot_scan - alg["k_window"]
+        # algorithmic bytes of a chain (one k_chain launch, all rounds):
+        #   release step: 4 B id + 4 B state + 1 B mask per running job it
+        #            looks at, 8 B reservation read + 12 B written per
+        #            released job;
+        #   pass:    8 B demand read + 1 B decision written per decided entry;
+        #   compaction: 25 B read + 24 B written per entry of [head, last
+        #            admitted].
+        # The running list is built once per chain (4 B state per job slot).
+        alg = {"k_chain": 9 * prof["considered"] + 20 * prof["released"] + 9 * prof["scanned"]
+                          + 49 * prof["compacted"],
+               "k_run_list": 4 * n * prof_steps}
         dom = max(kern, key=lambda k: kern[k][0])
         ms, launches = kern[dom]
         avg_s = ms * 1e-3 / max(launches, 1)
-        bytes_per_launch = alg[dom] / max(launches, 1)
+        bytes_per_launch = alg.get(dom, 0) / max(launches, 1)
         ach = bytes_per_launch / avg_s / 1e9 if avg_s > 0 else 0.0
         out["roofline"] = {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                           "frac": ach / HBM_PEAK_GBS, "traffic": None, "kernel": dom,
+                           "frac": ach / HBM_PEAK_GBS, "traffic": traffic_for(dom), "kernel": dom,
                            "avg_launch_us": avg_s * 1e6, "bytes_per_launch": bytes_per_launch,
-                           "kernels_ms_per_step": {k: v[0] / args.steps for k, v in kern.items()}}
+                           "profiled_steps": prof_steps,
+                           "kernels_ms_per_step": {k: v[0] / prof_steps for k, v in kern.items()}}
 
+    extras = {x for x in args.extras.split(",") if x}
     # ---- dense first-fit pass: every entry must be read (HBM-bound) -------
-    if args.dense_log2 > 0:
+    if args.dense_log2 > 0 and "dense" in extras:
         qd = c2d_queue(seed=args.seed, n=1 << args.dense_log2)
         dd = torch.from_numpy(qd.demand).to(dev)
         dec = torch.zeros(qd.n, dtype=torch.uint8, device=dev)
@@ -372,10 +478,12 @@ def main():
             "frac_of_peak": bytes_pass / kern_s / 1e9 / HBM_PEAK_GBS, "fixed_point_ok": bool(ok)}
         del dd, dec
 
-    out["tenants"] = tenant_measure(cs, torch, dev)
-    print(f"[bench] tenants: {json.dumps(out['tenants'])}", file=sys.stderr, flush=True)
-    out["slab"] = slab_measure(cs, torch, dev)
-    print(f"[bench] slab: {json.dumps(out['slab'])}", file=sys.stderr, flush=True)
+    if "tenants" in extras:
+        out["tenants"] = tenant_measure(cs, torch, dev)
+        print(f"[bench] tenants: {json.dumps(out['tenants'])}", file=sys.stderr, flush=True)
+    if "slab" in extras:
+        out["slab"] = slab_measure(cs, torch, dev)
+        print(f"[bench] slab: {json.dumps(out['slab'])}", file=sys.stderr, flush=True)
 
     if args.cosched:
         torch.cuda.empty_cache()

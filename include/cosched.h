@@ -75,9 +75,9 @@ typedef struct {
   int32_t max_jobs;        /* job handles [0, max_jobs)                        */
   int32_t max_tenants;     /* slab tenants with their own quota; 0 = max_jobs */
   int64_t queue_capacity;  /* pending requests the device queue holds         */
-  int32_t window_limit;    /* windows of 4096 entries the single-workgroup
+  int32_t window_limit;    /* windows of 256 entries the single-wave
                               admission kernel scans before the grid-wide
-                              round kernel takes over; 0 = 16                  */
+                              round kernel takes over; 0 = 64                  */
   int32_t flags;           /* reserved, 0                                      */
 } sched_config_t;
 
@@ -106,6 +106,11 @@ typedef struct {
   int64_t scanned;         /* queue entries the pass decided                   */
   int64_t pending_after;   /* requests still waiting                           */
   int64_t compacted;       /* queue entries the compaction step rewrote        */
+  int64_t released;        /* jobs whose reservation reached 0 through
+                              post-frees since the previous pass result (a
+                              chain round's release step, or calls made
+                              between two passes)                             */
+  int64_t released_bytes;  /* bytes post-freed over the same span              */
 } sched_pass_result_t;
 
 /* ======================================================================== */
@@ -422,13 +427,16 @@ int sched_serve(sched_ctx_t *ctx, int64_t n, const sched_job_desc_t *jobs,
 /* ======================================================================== */
 /* Kernel timing                                                             */
 /* ======================================================================== */
-/* enable != 0 starts bracketing every library kernel launch with a pair of
- * HIP events on the launch's stream and clears the totals; 0 stops it. */
+/* enable == 1 clears the totals and starts bracketing every library kernel
+ * launch with a pair of HIP events on the launch's stream; 2 resumes
+ * bracketing without clearing (to sample some calls of a timed loop); 0
+ * stops it and keeps the totals for sched_profile_read. */
 int sched_profile(int32_t enable);
 
 /* Total device time in ms and launch count of the kernel named `kernel`
  * (k_window, k_round, k_compact, k_release_masked, k_triad, k_hist,
- * k_gemm_bf16, k_slab_phase, ...) since sched_profile(1).  Waits for the
+ * k_gemm_bf16, k_slab_phase, ...) since sched_profile(1), over the bracketed
+ * launches only.  Waits for the
  * recorded events. */
 int sched_profile_read(const char *kernel, double *total_ms, int64_t *launches);
 

@@ -53,7 +53,8 @@ class sched_stats_t(C.Structure):
 
 class sched_pass_result_t(C.Structure):
     _fields_ = [(n, i64) for n in ("admitted", "admitted_bytes", "free_before", "free_after",
-                                   "rounds", "scanned", "pending_after", "compacted")]
+                                   "rounds", "scanned", "pending_after", "compacted",
+                                   "released", "released_bytes")]
 
 
 class sched_scan_result_t(C.Structure):
@@ -343,7 +344,9 @@ def sched_reset(ctx):
 
 
 def sched_profile(enable):
-    return lib().sched_profile(1 if enable else 0)
+    """True/1: clear the totals and start; 2: resume without clearing;
+    False/0: stop (totals kept for sched_profile_read)."""
+    return lib().sched_profile(int(enable) if enable in (0, 1, 2) else 1)
 
 
 def sched_profile_read(kernel):

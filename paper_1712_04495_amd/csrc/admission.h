@@ -8,7 +8,7 @@ namespace schedk {
 
 // Window kernel: one wave, 64 lanes x 16 consecutive entries.
 constexpr int WIN_THREADS = 64;
-constexpr int WIN_ITEMS = 16;
+constexpr int WIN_ITEMS = 4;
 constexpr int WIN = WIN_THREADS * WIN_ITEMS;
 // Compaction: one workgroup, 256 threads x 8 entries per chunk.
 constexpr int CMP_THREADS = 256;
@@ -56,6 +56,8 @@ struct DevCtl {
   long long break_tile[4];
   unsigned long long tiles_done[4];  // tiles finished in the round of a slot
   unsigned long long round_sum[4];   // candidate sums of those tiles
+  int64_t run_n;                     // entries of the running list of a device chain
+  unsigned long long enq_bad;        // invalid requests seen by a checked intake
 };
 
 // What a pass reports to the host; written by the device into host-mapped
@@ -63,6 +65,7 @@ struct DevCtl {
 struct PassSummary {
   int64_t admitted, admitted_bytes, R0, R_after, rounds, start_final, hi;
   int64_t head, tail, used, adm_base;
+  int64_t released_jobs, released_bytes;  // totals since the last reset
   int32_t done, pad;
 };
 constexpr int MAX_CHAIN = 256;
@@ -72,6 +75,8 @@ struct AdmEngine {
   DevCtl *h_ctl = nullptr;          // pinned host mirror
   PassSummary *h_sum = nullptr;     // host-mapped summaries, host view
   PassSummary *d_sum = nullptr;     // same memory, device view
+  int64_t *h_flag = nullptr;        // host-mapped verdict of a checked intake
+  int64_t *d_flag = nullptr;
   unsigned long long *d_flags = nullptr;
   int64_t max_tiles = 0;
   uint64_t launch = 1;              // launch counter of the pass chain
@@ -87,6 +92,7 @@ void adm_engine_free(AdmEngine &e);
 struct PassOut {
   int64_t admitted, admitted_bytes, R0, R_after, rounds, start_final, hi;
   int64_t head, tail, used;
+  int64_t released_jobs, released_bytes;  // totals since the last reset
 };
 
 // One pass over demand[start, end) with free memory R0 (stateless form: the
@@ -131,11 +137,22 @@ int adm_compact(AdmEngine &e, const QueueArrays &q, const JobArrays &j, hipStrea
 // `rounds` release+admit rounds chained on the device (one host sync): round
 // r > 0 first releases every running job j < n_mask with masks[(r-1) * n_mask
 // + j] != 0, then runs a full pass (windows until done) and compaction.  The
-// admitted lists of the rounds are appended one after the other.
+// admitted lists of the rounds are appended one after the other.  run_list
+// is device scratch of jb.max_jobs + q.capacity int32 entries (the running
+// jobs a mask can name, plus every admission of the chain).
 int adm_chain(AdmEngine &e, int policy, const QueueArrays &q, const JobArrays &jb, int rounds,
-              const uint8_t *masks, int64_t n_mask, hipStream_t s);
+              const uint8_t *masks, int64_t n_mask, int32_t *run_list, hipStream_t s);
 
 int adm_zero_decisions(uint8_t *decision, int64_t n, hipStream_t s);
+
+// Intake of n requests at queue position `at` with validation in the same
+// launch: every request needs a job in [0, n_jobs) and a demand in
+// [1, capacity].  The entries are written past the tail either way; the tail
+// only moves when the whole batch is valid.  Synchronises the stream;
+// *n_bad receives the number of invalid requests (0: appended).
+int adm_enqueue_checked(AdmEngine &e, const QueueArrays &q, int64_t at, int64_t n, const int32_t *job,
+                        const int64_t *demand, const int32_t *prio_of_job, int64_t seq0,
+                        int32_t n_jobs, int64_t capacity, hipStream_t s, int64_t *n_bad);
 int adm_release_masked(AdmEngine &e, const JobArrays &j, const uint8_t *mask, int64_t n,
                        hipStream_t s);
 int adm_enqueue(AdmEngine &e, const QueueArrays &q, int64_t at, int64_t n, const int32_t *job,

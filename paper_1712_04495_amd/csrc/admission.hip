@@ -12,10 +12,10 @@
 // sequential first-fit exactly; all arithmetic is exact int64.
 //
 // Two kernels compute rounds:
-//  * k_window: one workgroup of 1024 threads walks the queue in windows of
-//    4096 entries and runs all rounds of a window in LDS.  This is the
-//    latency regime: when free memory runs out after a few thousand entries
-//    the whole pass is one launch.
+//  * k_window: one wave walks the queue in windows of 256 entries and runs
+//    all rounds of a window in registers.  This is the latency regime: when
+//    free memory runs out after a few thousand entries the whole pass is one
+//    launch.
 //  * k_round: a persistent grid that computes one round over the whole
 //    remaining queue with a single-pass decoupled look-back scan.  Tiles are
 //    taken from an atomic ticket in queue order; each tile publishes its
@@ -51,18 +51,26 @@ __device__ __forceinline__ void reset_next_slot(DevCtl *c, uint32_t L) {
   c->round_sum[nx] = 0;
 }
 
-// Called once per tile that decided its entries.  In a round without a break
-// every such tile admitted all of its candidates, so the round's admitted sum
-// is the sum of the tiles' candidate sums; the tile that finishes last
-// closes the round.  (With a break, the break tile closes it instead.)
-__device__ __forceinline__ void tile_done(DevCtl *c, int s, int nx, int64_t a, int64_t R,
-                                          int64_t end, long long n_tiles) {
-  add_relaxed(&c->round_sum[s], (unsigned long long)a);
-  const unsigned long long prev =
-      __hip_atomic_fetch_add(&c->tiles_done[s], 1ULL, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-  if (prev + 1 != (unsigned long long)n_tiles) return;
-  if (__hip_atomic_load(&c->break_tile[s], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) != LLONG_MAX)
-    return;
+// Called once per workgroup when it leaves a round, with the candidate sum of
+// the tiles it decided.  In a round without a break every decided tile
+// admitted all of its candidates, so the round's admitted sum is the sum of
+// those candidate sums; the workgroup that leaves last closes the round.
+// (With a break, the break tile closes it instead.)  Workgroups accumulate
+// over all their tiles so that these counters see one update per workgroup,
+// not one per tile.
+// The last workgroup only reads values other workgroups changed with device
+// atomics (round_sum, break_tile); each workgroup waits for its own atomics
+// to complete before it counts itself out, so those values are final when
+// the count is.  No release/acquire is needed (at device scope that would
+// write back the whole L2 of the workgroup's XCD once per workgroup); plain
+// stores (decisions, records) are only read after the kernel ends.
+__device__ __forceinline__ void block_done(DevCtl *c, int s, int nx, int64_t a, int64_t R,
+                                           int64_t end, unsigned n_blocks) {
+  if (a) add_relaxed(&c->round_sum[s], (unsigned long long)a);
+  asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+  const unsigned long long prev = add_relaxed(&c->tiles_done[s], 1ULL);
+  if (prev + 1 != (unsigned long long)n_blocks) return;
+  if (ld_relaxed(&c->break_tile[s]) != LLONG_MAX) return;
   const int64_t sum = int64_t(ld_relaxed(&c->round_sum[s]));
   add_relaxed(&c->p_admitted_bytes, sum);
   add_relaxed(&c->p_rounds, (int64_t)1);
@@ -127,15 +135,34 @@ __global__ void k_summary(DevCtl *c, uint32_t L, PassSummary *out) {
 // consecutive entries starting at l * WIN_ITEMS, so a lane-local running sum
 // plus one wave-wide exclusive scan gives every entry its prefix in queue
 // order.  The break of a round is the lowest set bit of a ballot.  No LDS and
-// no barriers: every round costs a few dozen wave instructions.
+// no barriers.
+// Sums need no saturation: a candidate's demand is clamped to R + 1 (only
+// FIFO, which does not filter, sees larger ones), so a window's sum stays
+// below 2^54, and a prefix exceeds R exactly when the unclamped one does.
+// A round only updates a per-lane bit mask of admitted items; decisions,
+// counts and the highest admitted position are written once per window, and
+// the next window's demands are loaded while the current one is decided.
 // init != 0: the kernel also does the prologue (pass start state from the
 // arguments or, with from_state, from the control block).
-__global__ __launch_bounds__(WIN_THREADS) void k_window(DevCtl *c, const int64_t *__restrict__ demand,
-                                                        uint8_t *__restrict__ decision, int64_t mask,
-                                                        uint32_t L, int max_windows, int init,
-                                                        int filter_arg, int from_state, int64_t R0,
-                                                        int64_t start0, int64_t end0, int append) {
-  const int lane = threadIdx.x;
+__device__ __forceinline__ void window_load(const int64_t *__restrict__ demand, int64_t mask,
+                                            int64_t p0, int64_t end, int64_t (&x)[WIN_ITEMS]) {
+#pragma unroll
+  for (int k = 0; k < WIN_ITEMS; ++k) x[k] = (p0 + k < end) ? demand[(p0 + k) & mask] : -1;
+}
+
+// The window walk, run by one whole wave (lane = its lane index).
+// Results of a window walk, handed to the rest of a workgroup through LDS.
+struct WinResult {
+  int64_t R, start, admitted, admitted_bytes, hi, rounds;
+  int32_t done, pad;
+};
+
+__device__ __forceinline__ void window_pass(DevCtl *c, const int64_t *__restrict__ demand,
+                                            uint8_t *__restrict__ decision, int64_t mask, uint32_t L,
+                                            int max_windows, int init, int filter_arg,
+                                            int from_state, int64_t R0, int64_t start0,
+                                            int64_t end0, int append, int lane,
+                                            WinResult *wr = nullptr) {
   const int s = L & 3, nx = (L + 1) & 3;
   // pass state in registers: every lane derives it from the same inputs
   int64_t R, pos, end, hi;
@@ -164,86 +191,86 @@ __global__ __launch_bounds__(WIN_THREADS) void k_window(DevCtl *c, const int64_t
   }
   if (lane == 0) reset_next_slot(c, L);
   int64_t adm_cnt = 0, adm_bytes = 0, rounds = 0;
+  const int base = lane * WIN_ITEMS;
+  int64_t x[WIN_ITEMS];
+  if (!done) window_load(demand, mask, pos + base, end, x);
 
   for (int w = 0; w < max_windows && !done; ++w) {
     if (pos >= end || R == 0) {
       done = 1;
       break;
     }
-    const int64_t p0 = pos + int64_t(lane) * WIN_ITEMS;
-    int64_t x[WIN_ITEMS];
-#pragma unroll
-    for (int k = 0; k < WIN_ITEMS; ++k) x[k] = (p0 + k < end) ? demand[(p0 + k) & mask] : -1;
-    int s_loc = 0;
+    const int64_t wpos = pos;
+    int64_t xn[WIN_ITEMS];
+    const bool more = w + 1 < max_windows && wpos + WIN < end;
+    if (more) window_load(demand, mask, wpos + WIN + base, end, xn);
+    uint32_t abits = 0;
+    int s_loc = 0, lim = WIN;
     for (;;) {
       const int64_t cap = R + 1;
-      int64_t incl[WIN_ITEMS];
+      int64_t v[WIN_ITEMS], r[WIN_ITEMS];
       int64_t run = 0;
 #pragma unroll
       for (int k = 0; k < WIN_ITEMS; ++k) {
-        const int off = lane * WIN_ITEMS + k;
-        const bool cd = x[k] >= 0 && off >= s_loc && (!filter || x[k] <= R);
-        run = sat_add(run, cd ? x[k] : 0, cap);
-        incl[k] = cd ? run : -1;  // -1 marks a non-candidate
+        const bool cd = x[k] >= 0 && base + k >= s_loc && (!filter || x[k] <= R);
+        v[k] = cd ? (x[k] < cap ? x[k] : cap) : 0;
+        run += v[k];
+        r[k] = cd ? run : -1;  // -1 marks a non-candidate
       }
-      const int64_t wincl = wave_incl_scan_sat_dpp(run, cap);
+      const int64_t wincl = wave_incl_scan_dpp(run);
       const int64_t ex = wave_prev_lane64(wincl);
       const int64_t total = read_lane64(wincl, WAVE - 1);
-      int my_first = WIN_ITEMS;
-      int64_t my_before = ex;
+      int kb = WIN_ITEMS;      // this lane's break item
+      int64_t before = 0;      // prefix just before it
+      uint32_t a = 0;
 #pragma unroll
       for (int k = WIN_ITEMS - 1; k >= 0; --k) {
-        if (incl[k] >= 0 && sat_add(ex, incl[k], cap) > R) my_first = k;
+        const int64_t inc = ex + r[k];
+        if (r[k] >= 0 && inc > R) {
+          kb = k;
+          before = inc - v[k];
+        }
+        if (r[k] >= 0 && inc <= R) a |= 1u << k;
       }
-      // prefix just before my_first: the last candidate before it, else ex
-#pragma unroll
-      for (int k = 0; k < WIN_ITEMS; ++k)
-        if (k < my_first && incl[k] >= 0) my_before = sat_add(ex, incl[k], cap);
-      const uint64_t ball = __ballot(my_first < WIN_ITEMS);
-      int64_t first = WIN, sum = total;
+      abits |= a;
+      const uint64_t ball = __ballot(kb < WIN_ITEMS);
+      int first = WIN;
+      int64_t sum = total;
       if (ball) {
         const int fl = __builtin_ctzll(ball);
-        first = int64_t(fl) * WIN_ITEMS + __builtin_amdgcn_readlane(my_first, fl);
-        sum = read_lane64(my_before, fl);
+        first = fl * WIN_ITEMS + __builtin_amdgcn_readlane(kb, fl);
+        sum = read_lane64(before, fl);
       }
-      const int64_t lim = (first < WIN) ? first + 1 : WIN;
-      int my_last = -1;  // last admitted item of this lane
-      int64_t cnt = 0;
-#pragma unroll
-      for (int k = 0; k < WIN_ITEMS; ++k) {
-        const int off = lane * WIN_ITEMS + k;
-        const int64_t p = p0 + k;
-        const bool in = off >= s_loc && off < lim && p < end;
-        const bool a = in && incl[k] >= 0 && off < first;
-        if (in) decision[p & mask] = a ? 1 : 0;
-        if (a) my_last = k;
-        cnt += __builtin_popcountll(__ballot(a));
-      }
-      adm_cnt += cnt;
-      int64_t mx = -1;
-      const uint64_t lb = __ballot(my_last >= 0);
-      if (lb) {
-        const int hl = 63 - __builtin_clzll(lb);
-        mx = pos + int64_t(hl) * WIN_ITEMS + __builtin_amdgcn_readlane(my_last, hl);
-      }
-      adm_bytes += sum;
-      if (mx + 1 > hi) hi = mx + 1;
       R -= sum;
+      adm_bytes += sum;
       ++rounds;
-      if (first >= WIN) {
-        pos += WIN;
-        break;
-      }
+      if (first >= WIN) break;
       if (!filter || R == 0) {
         done = 1;
-        pos += first + 1;
+        lim = first + 1;
         break;
       }
-      s_loc = int(first) + 1;
-      if (s_loc >= WIN) {
-        pos += WIN;
-        break;
-      }
+      s_loc = first + 1;
+      if (s_loc >= WIN) break;
+    }
+    // the window's decided entries [0, lim)
+#pragma unroll
+    for (int k = 0; k < WIN_ITEMS; ++k) {
+      const int64_t p = wpos + base + k;
+      if (base + k < lim && p < end) decision[p & mask] = uint8_t((abits >> k) & 1u);
+      adm_cnt += __builtin_popcountll(__ballot((abits >> k) & 1u));
+    }
+    const uint64_t lb = __ballot(abits != 0);
+    if (lb) {
+      const int hl = 63 - __builtin_clzll(lb);
+      const uint32_t hb = uint32_t(__builtin_amdgcn_readlane(int(abits), hl));
+      const int64_t mx = wpos + int64_t(hl) * WIN_ITEMS + (31 - __builtin_clz(hb));
+      if (mx + 1 > hi) hi = mx + 1;
+    }
+    pos = done ? wpos + lim : wpos + WIN;
+    if (more) {
+#pragma unroll
+      for (int k = 0; k < WIN_ITEMS; ++k) x[k] = xn[k];
     }
   }
   if (!done && (pos >= end || R == 0)) done = 1;
@@ -266,7 +293,25 @@ __global__ __launch_bounds__(WIN_THREADS) void k_window(DevCtl *c, const int64_t
       c->p_hi = hi;
       c->p_rounds += rounds;
     }
+    if (wr) {
+      wr->R = R;
+      wr->start = pos < end ? pos : end;
+      wr->done = done;
+      wr->admitted = adm_cnt;
+      wr->admitted_bytes = adm_bytes;
+      wr->hi = hi;
+      wr->rounds = rounds;
+    }
   }
+}
+
+__global__ __launch_bounds__(WIN_THREADS) void k_window(DevCtl *c, const int64_t *__restrict__ demand,
+                                                        uint8_t *__restrict__ decision, int64_t mask,
+                                                        uint32_t L, int max_windows, int init,
+                                                        int filter_arg, int from_state, int64_t R0,
+                                                        int64_t start0, int64_t end0, int append) {
+  window_pass(c, demand, decision, mask, L, max_windows, init, filter_arg, from_state, R0, start0,
+              end0, append, threadIdx.x);
 }
 
 // ---------------------------------------------------------------------------
@@ -292,6 +337,8 @@ __global__ __launch_bounds__(RND_THREADS) void k_round(DevCtl *c, const int64_t 
   const int64_t cap = R + 1;
   const bool filter = c->filter != 0;
   const long long n_tiles = (end - start + TILE - 1) / TILE;
+  // thread 0's totals over the whole tiles this workgroup decided
+  int64_t acc_sum = 0, acc_cnt = 0, acc_hi = -1;
 
   for (;;) {
     if (tid == 0) {
@@ -301,7 +348,16 @@ __global__ __launch_bounds__(RND_THREADS) void k_round(DevCtl *c, const int64_t 
     }
     __syncthreads();
     const long long t = s_t;
-    if (t < 0) break;
+    if (t < 0) {
+      if (tid == 0) {
+        if (acc_cnt) {
+          add_relaxed(&c->p_admitted, acc_cnt);
+          max_relaxed(&c->p_hi, acc_hi);
+        }
+        block_done(c, s, nx, acc_sum, R, end, gridDim.x);
+      }
+      break;
+    }
     const int64_t base = start + int64_t(t) * TILE;
 
     int64_t x[RND_ITEMS];
@@ -327,7 +383,6 @@ __global__ __launch_bounds__(RND_THREADS) void k_round(DevCtl *c, const int64_t 
         const int64_t p = base + int64_t(j) * RND_THREADS + tid;
         if (p < end) decision[p & mask] = 0;
       }
-      if (tid == 0) tile_done(c, s, nx, 0, R, end, n_tiles);
       continue;
     }
 
@@ -396,11 +451,9 @@ __global__ __launch_bounds__(RND_THREADS) void k_round(DevCtl *c, const int64_t 
       const int64_t cnt = block_sum<RND_THREADS>(tcnt, red);
       const int64_t mx = block_max<RND_THREADS>(tmax, red);
       if (tid == 0) {
-        if (cnt) {
-          add_relaxed(&c->p_admitted, cnt);
-          max_relaxed(&c->p_hi, mx + 1);
-        }
-        tile_done(c, s, nx, A, R, end, n_tiles);  // A is exact here: E + A <= R
+        acc_cnt += cnt;
+        if (mx + 1 > acc_hi) acc_hi = mx + 1;
+        acc_sum += A;  // exact here: E + A <= R
       }
       continue;
     }
@@ -487,17 +540,19 @@ __device__ void write_summary(DevCtl *c, const RoundRec &r, int done, PassSummar
   out->tail = c->tail;
   out->used = c->used;
   out->adm_base = c->adm_base;
+  out->released_jobs = ld_relaxed(&c->released_jobs);
+  out->released_bytes = ld_relaxed(&c->released_bytes);
   out->done = done;
 }
 
-__global__ __launch_bounds__(CMP_THREADS) void k_compact(DevCtl *c, QueueArrays q, JobArrays jb,
-                                                         int slot, PassSummary *out, int append) {
+// Run by a whole workgroup of CMP_THREADS; `red` is LDS for block scans.
+__device__ void compact_pass(DevCtl *c, const QueueArrays &q, const JobArrays &jb, int slot,
+                             PassSummary *out, int append, int64_t *red) {
   if (slot >= 0 && !c->rec[slot].done) {
     if (threadIdx.x == 0 && out) write_summary(c, c->rec[slot], 0, out);
     return;
   }
   const int64_t mask = q.capacity - 1;
-  __shared__ int64_t red[CMP_THREADS / WAVE];
   const int tid = threadIdx.x;
   const int64_t head = c->head, hi = c->p_hi;
   int64_t surv_hi = hi;
@@ -568,9 +623,17 @@ __global__ __launch_bounds__(CMP_THREADS) void k_compact(DevCtl *c, QueueArrays 
   }
 }
 
-__global__ void k_release_masked(DevCtl *c, JobArrays jb, const uint8_t *__restrict__ mask,
-                                 int64_t n) {
-  __shared__ int64_t red[256 / WAVE];
+__global__ __launch_bounds__(CMP_THREADS) void k_compact(DevCtl *c, QueueArrays q, JobArrays jb,
+                                                         int slot, PassSummary *out, int append) {
+  __shared__ int64_t red[CMP_THREADS / WAVE];
+  compact_pass(c, q, jb, slot, out, append, red);
+}
+
+// Grid-stride part of a masked release; run by every thread of a grid of
+// 256-thread workgroups.
+__device__ __forceinline__ void release_masked_part(DevCtl *c, const JobArrays &jb,
+                                                    const uint8_t *__restrict__ mask, int64_t n,
+                                                    int64_t *red) {
   int64_t bytes = 0, cnt = 0;
   for (int64_t j = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; j < n;
        j += int64_t(gridDim.x) * blockDim.x) {
@@ -588,6 +651,281 @@ __global__ void k_release_masked(DevCtl *c, JobArrays jb, const uint8_t *__restr
     add_relaxed(&c->released_bytes, bytes);
     add_relaxed(&c->released_jobs, cnt);
   }
+}
+
+__global__ __launch_bounds__(256) void k_release_masked(DevCtl *c, JobArrays jb,
+                                                        const uint8_t *__restrict__ mask, int64_t n) {
+  __shared__ int64_t red[256 / WAVE];
+  release_masked_part(c, jb, mask, n, red);
+}
+
+// ---------------------------------------------------------------------------
+// Device chain: all release/admit rounds in one single-workgroup launch
+// ---------------------------------------------------------------------------
+// The running jobs a release mask can name (ids < n), listed in any order.
+// run_n is 0 before the launch.
+__global__ __launch_bounds__(256) void k_run_list(DevCtl *c, const int32_t *__restrict__ state,
+                                                  int64_t n, int32_t *__restrict__ run_list) {
+  const int lane = lane_id();
+  for (int64_t base = blockIdx.x * int64_t(blockDim.x); base < n;
+       base += int64_t(gridDim.x) * blockDim.x) {
+    const int64_t j = base + threadIdx.x;
+    const bool run = j < n && state[j] == 1;
+    const uint64_t b = __ballot(run);
+    if (!b) continue;
+    const int leader = __builtin_ctzll(b);
+    int64_t at = 0;
+    if (lane == leader) at = add_relaxed(&c->run_n, int64_t(__builtin_popcountll(b)));
+    at = __shfl(at, leader, WAVE);
+    if (run) run_list[at + __builtin_popcountll(b & ((1ULL << lane) - 1))] = int32_t(j);
+  }
+}
+
+// ---- the device chain's own steps (one workgroup of CMP_THREADS) ----------
+// Scheduler scalars the chain keeps in LDS between its steps.
+struct ChainState {
+  int64_t capacity, used, head, tail, adm_base, run_n, rel_jobs, rel_bytes, R0;
+  WinResult w;
+};
+
+// Releases every listed job whose mask byte is set and still holds a
+// reservation (Sec. IV post-free with bytes == 0) and keeps the entries whose
+// mask byte is clear.  A job holds a reservation exactly when it is
+// positive, so exchanging it with 0 both claims and reads it: when the list
+// names a job twice (each admission appends its job) or names a job that is
+// no longer running, the extra entries get 0 back and drop out.  Three
+// memory round trips per chunk: ids, mask bytes, exchanges.
+constexpr int REL_ITEMS = 8;
+constexpr int REL_CHUNK = CMP_THREADS * REL_ITEMS;
+__device__ void chain_release(ChainState &L, const JobArrays &jb, const uint8_t *__restrict__ mask,
+                              int64_t n_mask, int32_t *run_list, int64_t *red) {
+  const int tid = threadIdx.x;
+  const int64_t n = L.run_n;
+  int64_t kept = 0, bytes = 0, cnt = 0;
+  for (int64_t c0 = 0; c0 < n; c0 += REL_CHUNK) {
+    int32_t j[REL_ITEMS];
+#pragma unroll
+    for (int k = 0; k < REL_ITEMS; ++k) {
+      const int64_t i = c0 + int64_t(tid) * REL_ITEMS + k;
+      j[k] = i < n ? run_list[i] : -1;
+      if (j[k] >= n_mask) j[k] = -1;
+    }
+    uint8_t m[REL_ITEMS];
+#pragma unroll
+    for (int k = 0; k < REL_ITEMS; ++k) m[k] = j[k] >= 0 ? mask[j[k]] : 0;
+    int64_t got[REL_ITEMS];
+#pragma unroll
+    for (int k = 0; k < REL_ITEMS; ++k)
+      got[k] = (j[k] >= 0 && m[k]) ? __hip_atomic_exchange(&jb.res[j[k]], int64_t(0), __ATOMIC_RELAXED,
+                                                           __HIP_MEMORY_SCOPE_AGENT)
+                                   : 0;
+    int64_t k_loc = 0;
+#pragma unroll
+    for (int k = 0; k < REL_ITEMS; ++k) {
+      if (got[k] > 0) {
+        bytes += got[k];
+        ++cnt;
+        jb.state[j[k]] = 0;
+      }
+      k_loc += (j[k] >= 0 && !m[k]) ? 1 : 0;
+    }
+    // every entry of the chunk is in registers before the first write below
+    int64_t tot;
+    int64_t at = kept + block_excl_scan<CMP_THREADS>(k_loc, red, &tot);
+#pragma unroll
+    for (int k = 0; k < REL_ITEMS; ++k)
+      if (j[k] >= 0 && !m[k]) run_list[at++] = j[k];
+    kept += tot;
+  }
+  bytes = block_sum<CMP_THREADS>(bytes, red);
+  cnt = block_sum<CMP_THREADS>(cnt, red);
+  if (tid == 0) {
+    L.run_n = kept;
+    L.used -= bytes;
+    L.rel_bytes += bytes;
+    L.rel_jobs += cnt;
+  }
+  __syncthreads();
+}
+
+// Queue compaction after a chain round's pass (the stable right-aligned
+// compaction of compact_pass, reading the pass result from LDS); admitted
+// jobs also go to the running list, at run_n + their admitted-list offset.
+__device__ void chain_compact(DevCtl *c, ChainState &L, const QueueArrays &q, const JobArrays &jb,
+                              int32_t *run_list, int64_t n_mask, int64_t run_cap, PassSummary *out,
+                              int64_t *red) {
+  const int64_t mask = q.capacity - 1;
+  const int tid = threadIdx.x;
+  const int64_t head = L.head, hi = L.w.hi, adm_base = L.adm_base, A = L.w.admitted;
+  const int64_t run_n = L.run_n;
+  int64_t surv_hi = hi;
+  int64_t adm_hi = adm_base + A;
+  for (int64_t chunk_hi = hi; chunk_hi > head; chunk_hi -= CMP_CHUNK) {
+    const int64_t chunk_lo = chunk_hi - CMP_CHUNK > head ? chunk_hi - CMP_CHUNK : head;
+    const int64_t p0 = chunk_lo + int64_t(tid) * CMP_ITEMS;
+    int64_t d[CMP_ITEMS], sq[CMP_ITEMS];
+    int32_t jo[CMP_ITEMS], pr[CMP_ITEMS];
+    uint8_t adm[CMP_ITEMS], sur[CMP_ITEMS];
+    int64_t a_loc = 0, s_loc = 0;
+#pragma unroll
+    for (int k = 0; k < CMP_ITEMS; ++k) {
+      const int64_t p = p0 + k;
+      const bool valid = p < chunk_hi;
+      const int64_t pm = p & mask;
+      d[k] = valid ? q.demand[pm] : -1;
+      jo[k] = valid ? q.job[pm] : 0;
+      pr[k] = valid ? q.prio[pm] : 0;
+      sq[k] = valid ? q.seq[pm] : 0;
+      const uint8_t de = valid ? q.decision[pm] : 0;
+      adm[k] = valid && de == 1;
+      sur[k] = valid && de != 1 && d[k] >= 0;
+      a_loc += adm[k];
+      s_loc += sur[k];
+    }
+    int64_t total;
+    const int64_t ex = block_excl_scan<CMP_THREADS>((a_loc << 32) | s_loc, red, &total);
+    const int64_t a_tot = total >> 32, s_tot = total & 0xffffffffLL;
+    int64_t a_pos = adm_hi - a_tot + (ex >> 32);
+    int64_t s_pos = surv_hi - s_tot + (ex & 0xffffffffLL);
+#pragma unroll
+    for (int k = 0; k < CMP_ITEMS; ++k) {
+      const int64_t p = p0 + k;
+      if (p >= chunk_hi) continue;
+      q.decision[p & mask] = 0;
+      if (adm[k]) {
+        if (a_pos >= 0 && a_pos < q.capacity) {
+          q.adm_job[a_pos] = jo[k];
+          q.adm_demand[a_pos] = d[k];
+          q.adm_seq[a_pos] = sq[k];
+        }
+        if (run_list) {
+          const int64_t at = run_n + (a_pos - adm_base);
+          if (at < run_cap) run_list[at] = jo[k] < n_mask ? jo[k] : -1;
+        }
+        ++a_pos;
+        add_relaxed(&jb.res[jo[k]], d[k]);
+        jb.state[jo[k]] = 1;
+      } else if (sur[k]) {
+        const int64_t sm = s_pos & mask;
+        q.demand[sm] = d[k];
+        q.job[sm] = jo[k];
+        q.prio[sm] = pr[k];
+        q.seq[sm] = sq[k];
+        ++s_pos;
+      }
+    }
+    surv_hi -= s_tot;
+    adm_hi -= a_tot;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    L.head = surv_hi;
+    L.used += L.w.admitted_bytes;
+    L.adm_base = adm_base + A;
+    if (run_list) L.run_n = run_n + A < run_cap ? run_n + A : run_cap;
+    c->head = L.head;
+    c->used = L.used;
+    c->adm_base = L.adm_base;
+    out->admitted = A;
+    out->admitted_bytes = L.w.admitted_bytes;
+    out->R0 = L.R0;
+    out->R_after = L.w.R;
+    out->rounds = L.w.rounds;
+    out->start_final = L.w.start;
+    out->hi = hi;
+    out->head = L.head;
+    out->tail = L.tail;
+    out->used = L.used;
+    out->adm_base = L.adm_base;
+    out->released_jobs = L.rel_jobs;
+    out->released_bytes = L.rel_bytes;
+    out->done = 1;
+  }
+  __syncthreads();
+}
+
+// rounds release/admit rounds; round r > 0 first releases the listed jobs
+// named by masks[(r - 1) * n_mask + j] (run_list == nullptr: no releases).
+// Each round's pass runs in the first wave (window walk without a window
+// limit, so it always completes), then the whole workgroup compacts the queue,
+// appends the admitted jobs to the running list and writes the round's
+// summary to out[r].  One workgroup: every step sees the previous one through
+// workgroup barriers, and the scheduler scalars stay in LDS; reservations,
+// which the release step exchanges atomically, are only touched by atomics
+// inside the chain.  run_cap: entries run_list can hold (jobs running at the
+// start plus every admission of the chain fit).
+__global__ __launch_bounds__(CMP_THREADS) void k_chain(DevCtl *c, QueueArrays q, JobArrays jb,
+                                                       const uint8_t *__restrict__ masks,
+                                                       int64_t n_mask, int rounds, uint32_t L0,
+                                                       int filter, PassSummary *out,
+                                                       int32_t *run_list, int64_t run_cap) {
+  __shared__ int64_t red[CMP_THREADS / WAVE];
+  __shared__ ChainState L;
+  if (threadIdx.x == 0) {
+    L.capacity = c->capacity;
+    L.used = c->used;
+    L.head = c->head;
+    L.tail = c->tail;
+    L.adm_base = 0;
+    L.rel_jobs = c->released_jobs;
+    L.rel_bytes = c->released_bytes;
+    const int64_t rn = run_list ? ld_relaxed(&c->run_n) : 0;
+    L.run_n = rn < run_cap ? rn : run_cap;
+  }
+  __syncthreads();
+  for (int r = 0; r < rounds; ++r) {
+    if (r > 0 && run_list)
+      chain_release(L, jb, masks + int64_t(r - 1) * n_mask, n_mask, run_list, red);
+    if (threadIdx.x < WAVE) {
+      const int64_t R0 = L.capacity - L.used;
+      if (threadIdx.x == 0) L.R0 = R0;
+      window_pass(c, q.demand, q.decision, q.capacity - 1, L0 + uint32_t(r), 1 << 30, 1, filter, 0,
+                  R0, L.head, L.tail, r > 0 ? 1 : 0, threadIdx.x, &L.w);
+    }
+    __syncthreads();
+    chain_compact(c, L, q, jb, run_list, n_mask, run_cap, out + r, red);
+  }
+  if (threadIdx.x == 0) {
+    c->released_jobs = L.rel_jobs;
+    c->released_bytes = L.rel_bytes;
+    if (run_list) st_relaxed(&c->run_n, int64_t(0));
+  }
+}
+
+// Checked intake: every workgroup validates and writes its share of the
+// batch past the tail and adds its count of invalid requests (rare, so the
+// counter sees almost no traffic); k_enqueue_commit then moves the tail only
+// if the count is zero and reports it through host-mapped memory.
+__global__ __launch_bounds__(256) void k_enqueue_checked(DevCtl *c, QueueArrays q, int64_t at,
+                                                         int64_t n, const int32_t *__restrict__ job,
+                                                         const int64_t *__restrict__ demand,
+                                                         const int32_t *__restrict__ prio_of_job,
+                                                         int64_t seq0, int32_t n_jobs,
+                                                         int64_t capacity) {
+  __shared__ int64_t red[256 / WAVE];
+  int64_t bad = 0;
+  for (int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; i < n;
+       i += int64_t(gridDim.x) * blockDim.x) {
+    const int32_t j = job[i];
+    const int64_t d = demand[i];
+    const bool ok = j >= 0 && j < n_jobs && d >= 1 && d <= capacity;
+    bad += ok ? 0 : 1;
+    const int64_t pm = (at + i) & (q.capacity - 1);
+    q.demand[pm] = d;
+    q.job[pm] = j;
+    q.prio[pm] = ok ? prio_of_job[j] : 0;
+    q.seq[pm] = seq0 + i;
+  }
+  bad = block_sum<256>(bad, red);
+  if (threadIdx.x == 0 && bad) add_relaxed(&c->enq_bad, (unsigned long long)bad);
+}
+
+__global__ void k_enqueue_commit(DevCtl *c, int64_t new_tail, int64_t *verdict) {
+  if (threadIdx.x || blockIdx.x) return;
+  const unsigned long long b = c->enq_bad;
+  if (!b) c->tail = new_tail;
+  c->enq_bad = 0;
+  *verdict = int64_t(b);
 }
 
 __global__ void k_enqueue(DevCtl *c, QueueArrays q, int64_t at, int64_t n, const int32_t *__restrict__ job,
@@ -624,6 +962,9 @@ int adm_engine_init(AdmEngine &e, int device, int64_t max_entries) {
   SCHED_HIP_TRY(hipHostMalloc(&e.h_sum, sizeof(PassSummary) * MAX_CHAIN, hipHostMallocMapped));
   memset(e.h_sum, 0, sizeof(PassSummary) * MAX_CHAIN);
   SCHED_HIP_TRY(hipHostGetDevicePointer((void **)&e.d_sum, e.h_sum, 0));
+  SCHED_HIP_TRY(hipHostMalloc(&e.h_flag, 64, hipHostMallocMapped));
+  memset(e.h_flag, 0, 64);
+  SCHED_HIP_TRY(hipHostGetDevicePointer((void **)&e.d_flag, e.h_flag, 0));
   SCHED_HIP_TRY(hipMalloc(&e.d_flags, sizeof(unsigned long long) * e.max_tiles));
   SCHED_HIP_TRY(hipMemset(e.d_flags, 0, sizeof(unsigned long long) * e.max_tiles));
   int cus = 0;
@@ -639,8 +980,11 @@ void adm_engine_free(AdmEngine &e) {
   if (e.h_ctl) (void)hipHostFree(e.h_ctl);
   if (e.d_flags) (void)hipFree(e.d_flags);
   if (e.h_sum) (void)hipHostFree(e.h_sum);
+  if (e.h_flag) (void)hipHostFree(e.h_flag);
   e.h_sum = nullptr;
   e.d_sum = nullptr;
+  e.h_flag = nullptr;
+  e.d_flag = nullptr;
   e.d_ctl = nullptr;
   e.h_ctl = nullptr;
   e.d_flags = nullptr;
@@ -683,6 +1027,8 @@ static void fill_out(const PassSummary &h, PassOut *out) {
   out->head = h.head;
   out->tail = h.tail;
   out->used = h.used;
+  out->released_jobs = h.released_jobs;
+  out->released_bytes = h.released_bytes;
 }
 
 // Round kernels until the pass recorded in slot L & 3 is done; returns the
@@ -776,20 +1122,25 @@ int adm_pass_ctx(AdmEngine &e, int policy, const QueueArrays &q, const JobArrays
 }
 
 int adm_chain(AdmEngine &e, int policy, const QueueArrays &q, const JobArrays &jb, int rounds,
-              const uint8_t *masks, int64_t n_mask, hipStream_t s) {
+              const uint8_t *masks, int64_t n_mask, int32_t *run_list, hipStream_t s) {
   if (rounds <= 0 || rounds > MAX_CHAIN) return SCHED_E_INVALID;
   const int filter = policy == SCHED_POLICY_MMU ? 1 : 0;
-  const int64_t mask = q.capacity - 1;
-  uint32_t L = uint32_t(e.launch);
-  for (int r = 0; r < rounds; ++r) {
-    if (r > 0 && masks && n_mask > 0)
-      if (int rc = adm_release_masked(e, jb, masks + int64_t(r - 1) * n_mask, n_mask, s)) return rc;
-    // windows until the pass is done: one launch decides the whole pass
-    if (int rc = launch_window(e, q.demand, q.decision, mask, 1 << 30, filter, 1, 0, 0, 0,
-                               r > 0 ? 1 : 0, s, &L))
-      return rc;
-    if (int rc = adm_compact(e, q, jb, s, int(L & 3), e.d_sum + r, 1)) return rc;
+  const bool listed = rounds > 1 && masks && n_mask > 0;
+  if (listed && (!run_list || n_mask > jb.max_jobs)) return SCHED_E_INVALID;
+  if (listed) {
+    SCHED_PROF_LAUNCH("k_run_list", s,
+                      (k_run_list<<<grid_for(n_mask, 256, 1024), 256, 0, s>>>(e.d_ctl, jb.state,
+                                                                              n_mask, run_list)));
+    SCHED_HIP_TRY(hipGetLastError());
   }
+  const uint32_t L0 = uint32_t(e.launch);
+  SCHED_PROF_LAUNCH("k_chain", s,
+                    (k_chain<<<1, CMP_THREADS, 0, s>>>(e.d_ctl, q, jb, masks, listed ? n_mask : 0,
+                                                       rounds, L0, filter, e.d_sum,
+                                                       listed ? run_list : nullptr,
+                                                       int64_t(jb.max_jobs) + q.capacity)));
+  SCHED_HIP_TRY(hipGetLastError());
+  e.launch += rounds;
   SCHED_HIP_TRY(hipStreamSynchronize(s));
   return SCHED_OK;
 }
@@ -815,6 +1166,23 @@ int adm_enqueue(AdmEngine &e, const QueueArrays &q, int64_t at, int64_t n, const
                 const int64_t *demand, const int32_t *prio_of_job, int64_t seq0, hipStream_t s) {
   k_enqueue<<<grid_for(n, 256, 4096), 256, 0, s>>>(e.d_ctl, q, at, n, job, demand, prio_of_job, seq0);
   SCHED_HIP_TRY(hipGetLastError());
+  return SCHED_OK;
+}
+
+int adm_enqueue_checked(AdmEngine &e, const QueueArrays &q, int64_t at, int64_t n, const int32_t *job,
+                        const int64_t *demand, const int32_t *prio_of_job, int64_t seq0,
+                        int32_t n_jobs, int64_t capacity, hipStream_t s, int64_t *n_bad) {
+  volatile int64_t *v = e.h_flag;
+  *v = -1;
+  k_enqueue_checked<<<grid_for(n, 256, 4096), 256, 0, s>>>(e.d_ctl, q, at, n, job, demand,
+                                                           prio_of_job, seq0, n_jobs, capacity);
+  SCHED_HIP_TRY(hipGetLastError());
+  k_enqueue_commit<<<1, 64, 0, s>>>(e.d_ctl, at + n, e.d_flag);
+  SCHED_HIP_TRY(hipGetLastError());
+  SCHED_HIP_TRY(hipStreamSynchronize(s));
+  const int64_t b = *v;
+  if (b < 0) return SCHED_E_INTERNAL;
+  *n_bad = b;
   return SCHED_OK;
 }
 

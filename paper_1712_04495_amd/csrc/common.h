@@ -104,6 +104,17 @@ __device__ __forceinline__ int64_t wave_incl_scan_sat_dpp(int64_t v, int64_t cap
   v = sat_add(v, dpp_move64<0x143, 0xC>(v), cap);  // row_bcast:31 into rows 2, 3
   return v;
 }
+// Inclusive plain prefix with the same DPP steps, for values small enough
+// that the 64-lane total cannot overflow.
+__device__ __forceinline__ int64_t wave_incl_scan_dpp(int64_t v) {
+  v += dpp_move64<0x111, 0xF>(v);  // row_shr:1
+  v += dpp_move64<0x112, 0xF>(v);  // row_shr:2
+  v += dpp_move64<0x114, 0xF>(v);  // row_shr:4
+  v += dpp_move64<0x118, 0xF>(v);  // row_shr:8
+  v += dpp_move64<0x142, 0xA>(v);  // row_bcast:15 into rows 1, 3
+  v += dpp_move64<0x143, 0xC>(v);  // row_bcast:31 into rows 2, 3
+  return v;
+}
 // Value of the previous lane (0 for lane 0): wave_shr:1.
 __device__ __forceinline__ int64_t wave_prev_lane64(int64_t v) { return dpp_move64<0x138, 0xF>(v); }
 // Value of a uniform lane, read into scalar registers.

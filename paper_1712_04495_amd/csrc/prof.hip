@@ -81,9 +81,10 @@ void prof_end(const char *name, hipStream_t s) {
 }  // namespace schedk
 
 extern "C" int sched_profile(int32_t enable) {
+  if (enable < 0 || enable > 2) return SCHED_E_INVALID;
   std::lock_guard<std::mutex> g(g_mu);
   drain_locked();
-  g_acc.clear();
+  if (enable == 1) g_acc.clear();
   g_on.store(enable != 0);
   return SCHED_OK;
 }

@@ -25,6 +25,7 @@ struct sched_ctx {
   schedk::QueueArrays q{};
   schedk::JobArrays jb{};
   int32_t *d_prio_of_job = nullptr;
+  int32_t *d_run_list = nullptr;  // running jobs a chain's release masks can name
   void *d_scratch = nullptr;   // 4 KiB of small device staging
   void *h_stage = nullptr;     // 4 KiB of pinned host staging
 
@@ -36,6 +37,7 @@ struct sched_ctx {
   int64_t seq_next = 0;
   int64_t head_h = 0, tail_h = 0, used_h = 0;
   int64_t last_A = 0;
+  int64_t rel_jobs_seen = 0, rel_bytes_seen = 0;  // release totals at the last pass result
   int64_t last_adm_off = 0;
   int32_t *h_adm_job = nullptr;
   int64_t *h_adm_seq = nullptr;

@@ -52,20 +52,6 @@ __global__ void k_withdraw(DevCtl *c, QueueArrays q, int32_t job, int64_t *count
   }
 }
 
-// Batch validation: counts requests with an unknown job or a demand outside
-// [1, capacity].
-__global__ void k_validate(int64_t n, const int32_t *job, const int64_t *demand, int32_t n_jobs,
-                           int64_t capacity, unsigned long long *bad) {
-  unsigned long long b = 0;
-  for (int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; i < n;
-       i += int64_t(gridDim.x) * blockDim.x) {
-    const int32_t j = job[i];
-    const int64_t d = demand[i];
-    b += (j < 0 || j >= n_jobs || d < 1 || d > capacity) ? 1 : 0;
-  }
-  if (b) atomicAdd(bad, b);
-}
-
 __global__ void k_set_capacity(DevCtl *c, int64_t capacity) {
   c->capacity = capacity;
   c->used = 0;
@@ -101,6 +87,8 @@ static int ctx_alloc(sched_ctx *c) {
   SCHED_HIP_TRY(hipMemset(c->jb.state, 0, sizeof(int32_t) * J));
   SCHED_HIP_TRY(hipMalloc(&c->d_prio_of_job, sizeof(int32_t) * J));
   SCHED_HIP_TRY(hipMemset(c->d_prio_of_job, 0, sizeof(int32_t) * J));
+  // running jobs at the start of a chain (<= J) plus its admissions (<= Q)
+  SCHED_HIP_TRY(hipMalloc(&c->d_run_list, sizeof(int32_t) * (int64_t(J) + Q)));
   SCHED_HIP_TRY(hipMalloc(&c->d_scratch, 4096));
   SCHED_HIP_TRY(hipHostMalloc(&c->h_stage, 4096, hipHostMallocDefault));
   c->h_adm_cap = 1 << 16;
@@ -112,7 +100,7 @@ static int ctx_alloc(sched_ctx *c) {
 static void ctx_free(sched_ctx *c) {
   void *dev[] = {c->q.demand, c->q.job, c->q.prio, c->q.seq, c->q.decision, c->q.adm_job,
                  c->q.adm_demand, c->q.adm_seq, c->jb.res, c->jb.state, c->d_prio_of_job,
-                 c->d_scratch, c->prio_tmp};
+                 c->d_scratch, c->prio_tmp, c->d_run_list};
   for (void *p : dev)
     if (p) (void)hipFree(p);
   void *host[] = {c->h_stage, c->h_adm_job, c->h_adm_seq};
@@ -146,7 +134,7 @@ extern "C" int sched_create(const sched_config_t *cfg, sched_ctx_t **out) {
   c->device = cfg->device;
   c->capacity = capacity;
   c->policy = cfg->policy;
-  c->window_limit = cfg->window_limit > 0 ? cfg->window_limit : 16;
+  c->window_limit = cfg->window_limit > 0 ? cfg->window_limit : 64;
   c->q.capacity = pow2_at_least(std::max<int64_t>(cfg->queue_capacity, WIN));
   c->jb.max_jobs = cfg->max_jobs;
   c->prio.assign(cfg->max_jobs, 0);
@@ -276,7 +264,11 @@ int sched_run_pass_locked(sched_ctx *c, hipStream_t s, sched_pass_result_t *res)
     res->scanned = po.start_final - head_before;
     res->pending_after = po.tail - po.head;
     res->compacted = po.hi - head_before;
+    res->released = po.released_jobs - c->rel_jobs_seen;
+    res->released_bytes = po.released_bytes - c->rel_bytes_seen;
   }
+  c->rel_jobs_seen = po.released_jobs;
+  c->rel_bytes_seen = po.released_bytes;
   c->cv.notify_all();
   return SCHED_OK;
 }
@@ -441,18 +433,11 @@ extern "C" int sched_enqueue_batch(sched_ctx_t *c, int64_t n, const int32_t *d_j
   if (c->tail_h - c->head_h + n > c->q.capacity) return SCHED_E_INVALID;
   SCHED_HIP_TRY(hipSetDevice(c->device));
   hipStream_t s = pick(c, stream);
-  unsigned long long *bad = (unsigned long long *)c->d_scratch;
-  SCHED_HIP_TRY(hipMemsetAsync(bad, 0, sizeof(unsigned long long), s));
-  const int grid = int(std::min<int64_t>((n + 255) / 256, 2048));
-  k_validate<<<grid, 256, 0, s>>>(n, d_job, d_demand, c->n_jobs, c->capacity, bad);
-  SCHED_HIP_TRY(hipGetLastError());
-  unsigned long long *hb = (unsigned long long *)c->h_stage;
-  SCHED_HIP_TRY(hipMemcpyAsync(hb, bad, sizeof(*hb), hipMemcpyDeviceToHost, s));
-  SCHED_HIP_TRY(hipStreamSynchronize(s));
-  if (*hb) return SCHED_E_INVALID;
-  if (int rc = adm_enqueue(c->eng, c->q, c->tail_h, n, d_job, d_demand, c->d_prio_of_job,
-                           c->seq_next, s))
+  int64_t n_bad = 0;
+  if (int rc = adm_enqueue_checked(c->eng, c->q, c->tail_h, n, d_job, d_demand, c->d_prio_of_job,
+                                   c->seq_next, c->n_jobs, c->capacity, s, &n_bad))
     return rc;
+  if (n_bad) return SCHED_E_INVALID;
   c->seq_next += n;
   c->tail_h += n;
   return SCHED_OK;
@@ -492,7 +477,8 @@ extern "C" int sched_pass_chain(sched_ctx_t *c, int32_t rounds, const uint8_t *d
   if (c->policy != SCHED_POLICY_FIFO && c->policy != SCHED_POLICY_MMU) return SCHED_E_INVALID;
   SCHED_HIP_TRY(hipSetDevice(c->device));
   hipStream_t s = pick(c, stream);
-  if (int rc = adm_chain(c->eng, c->policy, c->q, c->jb, rounds, d_masks, n_mask, s)) return rc;
+  if (int rc = adm_chain(c->eng, c->policy, c->q, c->jb, rounds, d_masks, n_mask, c->d_run_list, s))
+    return rc;
   int64_t head_before = c->head_h, total = 0;
   for (int r = 0; r < rounds; ++r) {
     const PassSummary &h = c->eng.h_sum[r];
@@ -506,7 +492,11 @@ extern "C" int sched_pass_chain(sched_ctx_t *c, int32_t rounds, const uint8_t *d
       o.scanned = h.start_final - head_before;
       o.pending_after = h.tail - h.head;
       o.compacted = h.hi - head_before;
+      o.released = h.released_jobs - c->rel_jobs_seen;
+      o.released_bytes = h.released_bytes - c->rel_bytes_seen;
     }
+    c->rel_jobs_seen = h.released_jobs;
+    c->rel_bytes_seen = h.released_bytes;
     head_before = h.head;
     total += h.admitted;
     c->stats.passes += 1;
@@ -596,6 +586,8 @@ __global__ void k_reset_jobs(DevCtl *c, JobArrays jb) {
     c->tail = 0;
     c->released_bytes = 0;
     c->released_jobs = 0;
+    c->run_n = 0;
+    c->enq_bad = 0;
   }
 }
 
@@ -607,10 +599,13 @@ extern "C" int sched_reset(sched_ctx_t *c) {
   SCHED_HIP_TRY(hipGetLastError());
   if (int rc = adm_zero_decisions(c->q.decision, c->q.capacity, c->stream)) return rc;
   SCHED_HIP_TRY(hipStreamSynchronize(c->stream));
+  // pending[j] counts the host-side waiting requests of job j, which are
+  // exactly the entries of host_seq naming j
+  for (const auto &kv : c->host_seq) c->pending[kv.second] = 0;
   c->host_seq.clear();
-  std::fill(c->pending.begin(), c->pending.end(), 0);
   c->head_h = c->tail_h = c->used_h = 0;
   c->last_A = 0;
+  c->rel_jobs_seen = c->rel_bytes_seen = 0;
   c->cv.notify_all();
   return SCHED_OK;
 }

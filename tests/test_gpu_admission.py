@@ -186,9 +186,123 @@ def test_ctx_chain_equals_oracle(cs, policy, seed, n):
                 assert pr["admitted"] == k, f"round {r}"
                 assert np.array_equal(got[off:off + k], rr.admitted), f"round {r}"
                 assert pr["free_after"] == rr.R_after
+                # the round's release step (Sec. IV post-free of whole jobs)
+                assert pr["released"] == rr.released.size, f"round {r}"
+                assert pr["released_bytes"] == int(q.demand[rr.released].sum()), f"round {r}"
                 off += k
             rc, st = cs.sched_stats(ctx)
             assert st["used"] == ref[-1].used_after
+    finally:
+        cs.sched_destroy(ctx)
+
+
+@pytest.mark.parametrize("policy", [0, 1])
+@pytest.mark.parametrize("seed", [11, 12])
+def test_ctx_chain_repeated_jobs(cs, policy, seed):
+    """Chain rounds where jobs have several requests in the queue: a job can be
+    released and admitted again within one chain, and several of its requests
+    can be admitted by one pass.  Reference: per round, every masked job that
+    holds a reservation releases all of it (Sec. IV post-free, 0 bytes), then
+    one oracle pass (Sec. V) runs over the waiting requests in order."""
+    rng = np.random.default_rng(seed)
+    n_jobs, n_req, rounds, C = 300, 2000, 12, 10**6
+    job = rng.integers(0, n_jobs, n_req).astype(np.int32)
+    dem = rng.integers(1, C // 40, n_req).astype(np.int64)
+    masks = (rng.random((rounds - 1, n_jobs)) < 0.4).astype(np.uint8)
+    # reference
+    res = np.zeros(n_jobs, np.int64)
+    pend = np.arange(n_req)
+    used = 0
+    ref = []
+    for r in range(rounds):
+        rel_jobs = 0
+        rel_bytes = 0
+        if r > 0:
+            hit = (masks[r - 1] != 0) & (res > 0)
+            rel_jobs = int(hit.sum())
+            rel_bytes = int(res[hit].sum())
+            used -= rel_bytes
+            res[hit] = 0
+        R = C - used
+        if policy == S.FIFO:
+            adm, R2 = S.fifo_pass(dem[pend], R)
+        else:
+            adm, R2 = S.mmu_pass(dem[pend], R)
+        got = pend[adm]
+        np.add.at(res, job[got], dem[got])
+        used = C - R2
+        pend = pend[~adm]
+        ref.append((job[got].astype(np.int64), R2, rel_jobs, rel_bytes))
+    rc, ctx = cs.sched_create(policy=policy, capacity_bytes=C, max_jobs=n_jobs, queue_capacity=4096)
+    assert rc == 0
+    try:
+        assert cs.sched_register_batch(ctx, n_jobs)[0] == 0
+        d_job = torch.from_numpy(job).to(DEV)
+        d_dem = torch.from_numpy(dem).to(DEV)
+        d_masks = torch.from_numpy(masks).to(DEV)
+        adm = torch.full((n_req,), -1, dtype=torch.int32, device=DEV)
+        assert cs.sched_enqueue_batch(ctx, d_job, d_dem) == 0
+        rc, out = cs.sched_pass_chain(ctx, rounds, d_masks, adm)
+        assert rc == 0
+        torch.cuda.synchronize()
+        got = adm.cpu().numpy().astype(np.int64)
+        off = 0
+        for r, ((jobs_r, R2, rj, rb), o) in enumerate(zip(ref, out)):
+            k = jobs_r.size
+            assert o["admitted"] == k, f"round {r}"
+            assert np.array_equal(got[off:off + k], jobs_r), f"round {r}"
+            assert o["free_after"] == R2, f"round {r}"
+            assert o["released"] == rj and o["released_bytes"] == rb, f"round {r}"
+            off += k
+        rc, st = cs.sched_stats(ctx)
+        assert st["used"] == C - ref[-1][1]
+    finally:
+        cs.sched_destroy(ctx)
+
+
+def test_enqueue_batch_rejects_invalid(cs):
+    """A batch with any invalid request (unknown job, demand < 1 or above the
+    capacity) is refused as a whole and leaves the queue as it was; valid
+    batches before and after it are admitted exactly as the oracle says."""
+    C, n_jobs = 10_000, 16
+    rng = np.random.default_rng(5)
+    rc, ctx = cs.sched_create(policy=cs.SCHED_POLICY_MMU, capacity_bytes=C, max_jobs=n_jobs,
+                              queue_capacity=4096)
+    assert rc == 0
+    try:
+        assert cs.sched_register_batch(ctx, n_jobs)[0] == 0
+        def batch(k):
+            j = rng.integers(0, n_jobs, k).astype(np.int32)
+            d = rng.integers(1, C // 20, k).astype(np.int64)
+            return j, d
+        j1, d1 = batch(300)
+        assert cs.sched_enqueue_batch(ctx, torch.from_numpy(j1).to(DEV),
+                                      torch.from_numpy(d1).to(DEV)) == 0
+        for bad in ("demand0", "job", "toobig"):
+            jb, db = batch(500)
+            if bad == "demand0":
+                db[250] = 0
+            elif bad == "job":
+                jb[499] = n_jobs
+            else:
+                db[0] = C + 1
+            assert cs.sched_enqueue_batch(ctx, torch.from_numpy(jb).to(DEV),
+                                          torch.from_numpy(db).to(DEV)) == cs.SCHED_E_INVALID
+        j2, d2 = batch(200)
+        assert cs.sched_enqueue_batch(ctx, torch.from_numpy(j2).to(DEV),
+                                      torch.from_numpy(d2).to(DEV)) == 0
+        rc, st = cs.sched_stats(ctx)
+        assert st["pending"] == 500
+        rc, res = cs.sched_pass(ctx)
+        assert rc == 0
+        d = np.concatenate([d1, d2])
+        admit, R2 = S.mmu_pass(d, C)
+        assert res["admitted"] == int(admit.sum()) and res["free_after"] == R2
+        out = torch.full((600,), -1, dtype=torch.int32, device=DEV)
+        rc, n = cs.sched_last_admitted(ctx, out)
+        assert rc == 0 and n == int(admit.sum())
+        jobs = np.concatenate([j1, j2])
+        assert np.array_equal(out[:n].cpu().numpy(), jobs[admit])
     finally:
         cs.sched_destroy(ctx)
 

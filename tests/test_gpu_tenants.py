@@ -79,7 +79,11 @@ def test_gemm_operands_exact(cs):
     assert np.array_equal(got, T.gemm_operand(9, np.arange(4), 64))
 
 
-@pytest.mark.parametrize("M,N,K", [(128, 128, 64), (256, 384, 192), (1024, 1024, 1024)])
+# 128-tile kernel: (128, 128, 64), (256, 384, 192); 256-tile kernel: the
+# others, (512, 768, 320) with the plain tile order and (2048, 2048, 128)
+# with the XCD-grouped one.
+@pytest.mark.parametrize("M,N,K", [(128, 128, 64), (256, 384, 192), (512, 768, 320),
+                                   (1024, 1024, 1024), (2048, 2048, 128)])
 def test_gemm_full(cs, M, N, K):
     _, _, C = _gemm(cs, M, N, K)
     ref = T.gemm_ref_full(1, 2, M, N, K)
