@@ -9,6 +9,7 @@ namespace schedk {
 // Window kernel: one wave, 64 lanes x 16 consecutive entries.
 constexpr int WIN_THREADS = 64;
 constexpr int WIN_ITEMS = 4;
+constexpr int WIN_PF = 4;       // windows the single-wave walk keeps loaded
 constexpr int WIN = WIN_THREADS * WIN_ITEMS;
 // Compaction: one workgroup, 256 threads x 8 entries per chunk.
 constexpr int CMP_THREADS = 256;

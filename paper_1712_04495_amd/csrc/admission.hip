@@ -150,19 +150,94 @@ __device__ __forceinline__ void window_load(const int64_t *__restrict__ demand, 
   for (int k = 0; k < WIN_ITEMS; ++k) x[k] = (p0 + k < end) ? demand[(p0 + k) & mask] : -1;
 }
 
-// The window walk, run by one whole wave (lane = its lane index).
+// Decides one window [wpos, wpos + WIN) of a pass: first-fit rounds until the
+// window is exhausted or the pass ends inside it; updates the pass state.
+__device__ __forceinline__ void decide_window(const int64_t (&x)[WIN_ITEMS], const int64_t wpos,
+                                              const int base, const int64_t end,
+                                              const int64_t mask, const bool filter,
+                                              uint8_t *__restrict__ decision, int64_t &R,
+                                              int &done, int64_t &hi, int64_t &adm_cnt,
+                                              int64_t &adm_bytes, int64_t &rounds, int64_t &pos) {
+  uint32_t abits = 0;
+  int s_loc = 0, lim = WIN;
+  for (;;) {
+    const int64_t cap = R + 1;
+    int64_t v[WIN_ITEMS], r[WIN_ITEMS];
+    int64_t run = 0;
+#pragma unroll
+    for (int k = 0; k < WIN_ITEMS; ++k) {
+      const bool cd = x[k] >= 0 && base + k >= s_loc && (!filter || x[k] <= R);
+      v[k] = cd ? (x[k] < cap ? x[k] : cap) : 0;
+      run += v[k];
+      r[k] = cd ? run : -1;  // -1 marks a non-candidate
+    }
+    const int64_t wincl = wave_incl_scan_dpp(run);
+    const int64_t ex = wave_prev_lane64(wincl);
+    const int64_t total = read_lane64(wincl, WAVE - 1);
+    int kb = WIN_ITEMS;      // this lane's break item
+    int64_t before = 0;      // prefix just before it
+    uint32_t a = 0;
+#pragma unroll
+    for (int k = WIN_ITEMS - 1; k >= 0; --k) {
+      const int64_t inc = ex + r[k];
+      if (r[k] >= 0 && inc > R) {
+        kb = k;
+        before = inc - v[k];
+      }
+      if (r[k] >= 0 && inc <= R) a |= 1u << k;
+    }
+    abits |= a;
+    const uint64_t ball = __ballot(kb < WIN_ITEMS);
+    int first = WIN;
+    int64_t sum = total;
+    if (ball) {
+      const int fl = __builtin_ctzll(ball);
+      first = fl * WIN_ITEMS + __builtin_amdgcn_readlane(kb, fl);
+      sum = read_lane64(before, fl);
+    }
+    R -= sum;
+    adm_bytes += sum;
+    ++rounds;
+    if (first >= WIN) break;
+    if (!filter || R == 0) {
+      done = 1;
+      lim = first + 1;
+      break;
+    }
+    s_loc = first + 1;
+    if (s_loc >= WIN) break;
+  }
+  // the window's decided entries [0, lim)
+#pragma unroll
+  for (int k = 0; k < WIN_ITEMS; ++k) {
+    const int64_t p = wpos + base + k;
+    if (base + k < lim && p < end) decision[p & mask] = uint8_t((abits >> k) & 1u);
+    adm_cnt += __builtin_popcountll(__ballot((abits >> k) & 1u));
+  }
+  const uint64_t lb = __ballot(abits != 0);
+  if (lb) {
+    const int hl = 63 - __builtin_clzll(lb);
+    const uint32_t hb = uint32_t(__builtin_amdgcn_readlane(int(abits), hl));
+    const int64_t mx = wpos + int64_t(hl) * WIN_ITEMS + (31 - __builtin_clz(hb));
+    if (mx + 1 > hi) hi = mx + 1;
+  }
+  pos = done ? wpos + lim : wpos + WIN;
+}
+
 // Results of a window walk, handed to the rest of a workgroup through LDS.
 struct WinResult {
   int64_t R, start, admitted, admitted_bytes, hi, rounds;
   int32_t done, pad;
 };
 
+// The window walk, run by one whole wave (lane = its lane index).
 __device__ __forceinline__ void window_pass(DevCtl *c, const int64_t *__restrict__ demand,
                                             uint8_t *__restrict__ decision, int64_t mask, uint32_t L,
                                             int max_windows, int init, int filter_arg,
                                             int from_state, int64_t R0, int64_t start0,
                                             int64_t end0, int append, int lane,
-                                            WinResult *wr = nullptr) {
+                                            WinResult *wr = nullptr,
+                                            const int64_t *pre = nullptr) {
   const int s = L & 3, nx = (L + 1) & 3;
   // pass state in registers: every lane derives it from the same inputs
   int64_t R, pos, end, hi;
@@ -189,92 +264,42 @@ __device__ __forceinline__ void window_pass(DevCtl *c, const int64_t *__restrict
     filter = c->filter != 0;
     hi = c->p_hi;
   }
-  if (lane == 0) reset_next_slot(c, L);
+  if (lane == 0 && !wr) reset_next_slot(c, L);
   int64_t adm_cnt = 0, adm_bytes = 0, rounds = 0;
   const int base = lane * WIN_ITEMS;
-  int64_t x[WIN_ITEMS];
-  if (!done) window_load(demand, mask, pos + base, end, x);
-
-  for (int w = 0; w < max_windows && !done; ++w) {
-    if (pos >= end || R == 0) {
-      done = 1;
-      break;
-    }
-    const int64_t wpos = pos;
-    int64_t xn[WIN_ITEMS];
-    const bool more = w + 1 < max_windows && wpos + WIN < end;
-    if (more) window_load(demand, mask, wpos + WIN + base, end, xn);
-    uint32_t abits = 0;
-    int s_loc = 0, lim = WIN;
-    for (;;) {
-      const int64_t cap = R + 1;
-      int64_t v[WIN_ITEMS], r[WIN_ITEMS];
-      int64_t run = 0;
+  // windows are contiguous (a window either completes, and the next one
+  // starts WIN entries later, or ends the pass), so window w + WIN_PF can be
+  // loaded as soon as window w is decided: WIN_PF - 1 windows stay in flight
+  int64_t x[WIN_PF][WIN_ITEMS];
+  if (pre) {
+    // the caller loaded this lane's entries of the first WIN_PF windows
 #pragma unroll
-      for (int k = 0; k < WIN_ITEMS; ++k) {
-        const bool cd = x[k] >= 0 && base + k >= s_loc && (!filter || x[k] <= R);
-        v[k] = cd ? (x[k] < cap ? x[k] : cap) : 0;
-        run += v[k];
-        r[k] = cd ? run : -1;  // -1 marks a non-candidate
-      }
-      const int64_t wincl = wave_incl_scan_dpp(run);
-      const int64_t ex = wave_prev_lane64(wincl);
-      const int64_t total = read_lane64(wincl, WAVE - 1);
-      int kb = WIN_ITEMS;      // this lane's break item
-      int64_t before = 0;      // prefix just before it
-      uint32_t a = 0;
+    for (int u = 0; u < WIN_PF; ++u)
 #pragma unroll
-      for (int k = WIN_ITEMS - 1; k >= 0; --k) {
-        const int64_t inc = ex + r[k];
-        if (r[k] >= 0 && inc > R) {
-          kb = k;
-          before = inc - v[k];
-        }
-        if (r[k] >= 0 && inc <= R) a |= 1u << k;
-      }
-      abits |= a;
-      const uint64_t ball = __ballot(kb < WIN_ITEMS);
-      int first = WIN;
-      int64_t sum = total;
-      if (ball) {
-        const int fl = __builtin_ctzll(ball);
-        first = fl * WIN_ITEMS + __builtin_amdgcn_readlane(kb, fl);
-        sum = read_lane64(before, fl);
-      }
-      R -= sum;
-      adm_bytes += sum;
-      ++rounds;
-      if (first >= WIN) break;
-      if (!filter || R == 0) {
+      for (int k = 0; k < WIN_ITEMS; ++k) x[u][k] = pre[u * WIN_ITEMS + k];
+  } else if (!done) {
+#pragma unroll
+    for (int u = 0; u < WIN_PF; ++u) window_load(demand, mask, pos + u * WIN + base, end, x[u]);
+  }
+  int w = 0;
+  while (w < max_windows && !done) {
+#pragma unroll
+    for (int u = 0; u < WIN_PF; ++u) {
+      if (w >= max_windows || done) break;
+      if (pos >= end || R == 0) {
         done = 1;
-        lim = first + 1;
         break;
       }
-      s_loc = first + 1;
-      if (s_loc >= WIN) break;
-    }
-    // the window's decided entries [0, lim)
-#pragma unroll
-    for (int k = 0; k < WIN_ITEMS; ++k) {
-      const int64_t p = wpos + base + k;
-      if (base + k < lim && p < end) decision[p & mask] = uint8_t((abits >> k) & 1u);
-      adm_cnt += __builtin_popcountll(__ballot((abits >> k) & 1u));
-    }
-    const uint64_t lb = __ballot(abits != 0);
-    if (lb) {
-      const int hl = 63 - __builtin_clzll(lb);
-      const uint32_t hb = uint32_t(__builtin_amdgcn_readlane(int(abits), hl));
-      const int64_t mx = wpos + int64_t(hl) * WIN_ITEMS + (31 - __builtin_clz(hb));
-      if (mx + 1 > hi) hi = mx + 1;
-    }
-    pos = done ? wpos + lim : wpos + WIN;
-    if (more) {
-#pragma unroll
-      for (int k = 0; k < WIN_ITEMS; ++k) x[k] = xn[k];
+      const int64_t wpos = pos;
+      decide_window(x[u], wpos, base, end, mask, filter, decision, R, done, hi, adm_cnt, adm_bytes,
+                    rounds, pos);
+      if (!done && w + WIN_PF < max_windows)
+        window_load(demand, mask, wpos + WIN_PF * WIN + base, end, x[u]);
+      ++w;
     }
   }
   if (!done && (pos >= end || R == 0)) done = 1;
-  if (lane == 0) {
+  if (lane == 0 && !wr) {
     c->rec[nx].R = R;
     c->rec[nx].start = pos < end ? pos : end;
     c->rec[nx].done = done;
@@ -293,15 +318,15 @@ __device__ __forceinline__ void window_pass(DevCtl *c, const int64_t *__restrict
       c->p_hi = hi;
       c->p_rounds += rounds;
     }
-    if (wr) {
-      wr->R = R;
-      wr->start = pos < end ? pos : end;
-      wr->done = done;
-      wr->admitted = adm_cnt;
-      wr->admitted_bytes = adm_bytes;
-      wr->hi = hi;
-      wr->rounds = rounds;
-    }
+  }
+  if (lane == 0 && wr) {
+    wr->R = R;
+    wr->start = pos < end ? pos : end;
+    wr->done = done;
+    wr->admitted = adm_cnt;
+    wr->admitted_bytes = adm_bytes;
+    wr->hi = hi;
+    wr->rounds = rounds;
   }
 }
 
@@ -737,9 +762,22 @@ __device__ void chain_release(ChainState &L, const JobArrays &jb, const uint8_t 
       if (j[k] >= 0 && !m[k]) run_list[at++] = j[k];
     kept += tot;
   }
-  bytes = block_sum<CMP_THREADS>(bytes, red);
-  cnt = block_sum<CMP_THREADS>(cnt, red);
+  // one reduction for both totals (red holds 2 values per wave)
+  bytes = wave_sum(bytes);
+  cnt = wave_sum(cnt);
+  __syncthreads();
+  if (lane_id() == 0) {
+    red[2 * (tid / WAVE)] = bytes;
+    red[2 * (tid / WAVE) + 1] = cnt;
+  }
+  __syncthreads();
   if (tid == 0) {
+    bytes = cnt = 0;
+#pragma unroll
+    for (int w = 0; w < CMP_THREADS / WAVE; ++w) {
+      bytes += red[2 * w];
+      cnt += red[2 * w + 1];
+    }
     L.run_n = kept;
     L.used -= bytes;
     L.rel_bytes += bytes;
@@ -751,7 +789,7 @@ __device__ void chain_release(ChainState &L, const JobArrays &jb, const uint8_t 
 // Queue compaction after a chain round's pass (the stable right-aligned
 // compaction of compact_pass, reading the pass result from LDS); admitted
 // jobs also go to the running list, at run_n + their admitted-list offset.
-__device__ void chain_compact(DevCtl *c, ChainState &L, const QueueArrays &q, const JobArrays &jb,
+__device__ void chain_compact(ChainState &L, const QueueArrays &q, const JobArrays &jb,
                               int32_t *run_list, int64_t n_mask, int64_t run_cap, PassSummary *out,
                               int64_t *red) {
   const int64_t mask = q.capacity - 1;
@@ -823,9 +861,6 @@ __device__ void chain_compact(DevCtl *c, ChainState &L, const QueueArrays &q, co
     L.used += L.w.admitted_bytes;
     L.adm_base = adm_base + A;
     if (run_list) L.run_n = run_n + A < run_cap ? run_n + A : run_cap;
-    c->head = L.head;
-    c->used = L.used;
-    c->adm_base = L.adm_base;
     out->admitted = A;
     out->admitted_bytes = L.w.admitted_bytes;
     out->R0 = L.R0;
@@ -859,8 +894,11 @@ __global__ __launch_bounds__(CMP_THREADS) void k_chain(DevCtl *c, QueueArrays q,
                                                        int64_t n_mask, int rounds, uint32_t L0,
                                                        int filter, PassSummary *out,
                                                        int32_t *run_list, int64_t run_cap) {
-  __shared__ int64_t red[CMP_THREADS / WAVE];
+  __shared__ int64_t red[2 * CMP_THREADS / WAVE];
   __shared__ ChainState L;
+  // round summaries stay in LDS until the end: stores to host memory inside
+  // the loop would be waited for at every barrier
+  __shared__ PassSummary sums[MAX_CHAIN];
   if (threadIdx.x == 0) {
     L.capacity = c->capacity;
     L.used = c->used;
@@ -873,23 +911,41 @@ __global__ __launch_bounds__(CMP_THREADS) void k_chain(DevCtl *c, QueueArrays q,
     L.run_n = rn < run_cap ? rn : run_cap;
   }
   __syncthreads();
+  const int64_t qmask = q.capacity - 1;
   for (int r = 0; r < rounds; ++r) {
+    // the first wave loads the pass's first windows now: the queue does not
+    // change during the release step, so the loads overlap it
+    int64_t pre[WIN_PF * WIN_ITEMS];
+    if (threadIdx.x < WAVE) {
+#pragma unroll
+      for (int u = 0; u < WIN_PF; ++u)
+        window_load(q.demand, qmask, L.head + u * WIN + threadIdx.x * WIN_ITEMS, L.tail,
+                    *reinterpret_cast<int64_t(*)[WIN_ITEMS]>(pre + u * WIN_ITEMS));
+    }
     if (r > 0 && run_list)
       chain_release(L, jb, masks + int64_t(r - 1) * n_mask, n_mask, run_list, red);
     if (threadIdx.x < WAVE) {
       const int64_t R0 = L.capacity - L.used;
       if (threadIdx.x == 0) L.R0 = R0;
-      window_pass(c, q.demand, q.decision, q.capacity - 1, L0 + uint32_t(r), 1 << 30, 1, filter, 0,
-                  R0, L.head, L.tail, r > 0 ? 1 : 0, threadIdx.x, &L.w);
+      window_pass(c, q.demand, q.decision, qmask, L0 + uint32_t(r), 1 << 30, 1, filter, 0, R0,
+                  L.head, L.tail, r > 0 ? 1 : 0, threadIdx.x, &L.w, pre);
     }
     __syncthreads();
-    chain_compact(c, L, q, jb, run_list, n_mask, run_cap, out + r, red);
+    chain_compact(L, q, jb, run_list, n_mask, run_cap, sums + r, red);
   }
   if (threadIdx.x == 0) {
+    c->head = L.head;
+    c->used = L.used;
+    c->adm_base = L.adm_base;
     c->released_jobs = L.rel_jobs;
     c->released_bytes = L.rel_bytes;
     if (run_list) st_relaxed(&c->run_n, int64_t(0));
   }
+  // summaries to host-mapped memory, 8-byte words spread over the workgroup
+  const int64_t words = int64_t(rounds) * int64_t(sizeof(PassSummary) / 8);
+  const int64_t *src = reinterpret_cast<const int64_t *>(sums);
+  int64_t *dst = reinterpret_cast<int64_t *>(out);
+  for (int64_t i = threadIdx.x; i < words; i += CMP_THREADS) dst[i] = src[i];
 }
 
 // Checked intake: every workgroup validates and writes its share of the
