@@ -40,7 +40,7 @@ def parse():
     ap.add_argument("--queue-log2", type=int, default=20)
     ap.add_argument("--dense-log2", type=int, default=26)
     ap.add_argument("--dense-reps", type=int, default=10)
-    ap.add_argument("--dense-window", type=int, default=1,
+    ap.add_argument("--dense-window", type=int, default=64,
                     help="single-wave windows before the grid rounds take over")
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
                     help="bound on the oracle's CPU time for cpu_baseline (0 = skip)")
@@ -103,7 +103,11 @@ def cosched_run(cs, name, n_jobs, dev_free):
                           "completed": sm["completed"], "rejected": sm["rejected"],
                           "violations": sm["violations"], "passes": sm["passes"],
                           "max_running": sm["max_running"], "batches": sm["batches"],
-                          "batched_jobs": sm["batched_jobs"]}
+                          "batched_jobs": sm["batched_jobs"], "wall_s": sm["wall_s"],
+                          "host_s": {k: sm["host_" + k + "_s"] for k in ("pass", "launch", "poll",
+                                                                          "idle")},
+                          "dev_busy_s": sm["dev_busy_s"], "host_alloc_s": sm["host_alloc_s"],
+                          "deferred": sm["deferred"]}
             if label == "coscheduled" and batch:
                 out[label]["autotuned"] = {"block": sm["tuned_block"], "chunk": sm["tuned_chunk"],
                                            "per_cu": sm["tuned_per_cu"]}
@@ -466,14 +470,16 @@ def main():
         torch.cuda.synchronize()
         ddt = (time.perf_counter() - t1) / args.dense_reps
         rc, ms, launches = cs.sched_profile_read("k_round")
+        rc, ms_w, launches_w = cs.sched_profile_read("k_window")
         cs.sched_profile(0)
         from oracle import sched as S
         ok = S.first_fit_fixed_point(qd.demand, qd.capacity, dec.cpu().numpy().astype(bool))
         bytes_pass = 9 * qd.n     # each entry read once (8 B) + its decision (1 B)
-        kern_s = ms * 1e-3 / args.dense_reps
+        kern_s = (ms + ms_w) * 1e-3 / args.dense_reps
         out["dense_scan"] = {
             "entries": qd.n, "rounds": r["rounds"], "pass_ms": ddt * 1e3,
-            "round_kernels_ms": kern_s * 1e3, "round_launches_per_pass": launches / args.dense_reps,
+            "kernels_ms": kern_s * 1e3, "round_launches_per_pass": launches / args.dense_reps,
+            "window_launches_per_pass": launches_w / args.dense_reps, "window_limit": args.dense_window,
             "GBps_pass": bytes_pass / ddt / 1e9, "GBps_kernels": bytes_pass / kern_s / 1e9,
             "frac_of_peak": bytes_pass / kern_s / 1e9 / HBM_PEAK_GBS, "fixed_point_ok": bool(ok)}
         del dd, dec

@@ -414,6 +414,13 @@ typedef struct {
   int64_t completed, rejected, violations, passes, batches, batched_jobs;
   int64_t peak_used, max_running;
   int64_t tuned_block, tuned_chunk, tuned_per_cu;
+  /* where the controller's host time went (real-time mode), in seconds:
+   * admission passes, launches of admitted work, completion polling and
+   * releases, and idle waits; dev_busy_s is the time at least one job was
+   * running on the device (union of the jobs' [start, end] intervals) */
+  double host_pass_s, host_launch_s, host_poll_s, host_idle_s, dev_busy_s;
+  double host_alloc_s; /* part of host_launch_s spent allocating job memory     */
+  int64_t deferred;    /* launches that waited for a contiguous device range    */
 } sched_serve_summary_t;
 
 /* Runs n jobs (jobs[i] is job handle i; the context needs max_jobs >= n and

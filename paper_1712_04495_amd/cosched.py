@@ -78,7 +78,10 @@ class sched_serve_summary_t(C.Structure):
                                              "p99_wait_s", "p50_turn_s", "p99_turn_s")]
                 + [(n, i64) for n in ("completed", "rejected", "violations", "passes", "batches",
                                       "batched_jobs", "peak_used", "max_running", "tuned_block",
-                                      "tuned_chunk", "tuned_per_cu")])
+                                      "tuned_chunk", "tuned_per_cu")]
+                + [(n, C.c_double) for n in ("host_pass_s", "host_launch_s", "host_poll_s",
+                                             "host_idle_s", "dev_busy_s", "host_alloc_s")]
+                + [("deferred", i64)])
 
 
 SCHED_JOB_TRIAD = 0

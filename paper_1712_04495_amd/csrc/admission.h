@@ -10,6 +10,7 @@ namespace schedk {
 constexpr int WIN_THREADS = 64;
 constexpr int WIN_ITEMS = 4;
 constexpr int WIN_PF = 4;       // windows the single-wave walk keeps loaded
+constexpr int WIN_EMPTY_EXIT = 2;  // candidate-free windows after which a limited walk hands over
 constexpr int WIN = WIN_THREADS * WIN_ITEMS;
 // Compaction: one workgroup, 256 threads x 8 entries per chunk.
 constexpr int CMP_THREADS = 256;
@@ -53,8 +54,13 @@ struct DevCtl {
   int32_t pad;
   int64_t adm_base;        // where the next admitted list starts (chains append)
   RoundRec rec[4];
-  unsigned long long ticket[4];
-  long long break_tile[4];
+  // the ticket counters take a 256-byte line of their own: every workgroup
+  // of a round hits the active one, and any other word on that line (the
+  // break marker above all, read per ticket) would be slowed down with it
+  alignas(256) unsigned long long ticket[4];
+  unsigned long long ticket_pad[28];
+  long long break_tile[4];           // read per ticket: kept off the counters' lines too
+  long long break_pad[28];
   unsigned long long tiles_done[4];  // tiles finished in the round of a slot
   unsigned long long round_sum[4];   // candidate sums of those tiles
   int64_t run_n;                     // entries of the running list of a device chain
@@ -83,7 +89,7 @@ struct AdmEngine {
   uint64_t launch = 1;              // launch counter of the pass chain
   uint32_t epoch = 0;               // last look-back epoch handed out
   int round_grid = 0;               // persistent grid of the round kernel
-  int rounds_per_check = 4;         // round launches between host checks
+  int rounds_per_check = 2;         // round launches between host checks
   int device = 0;
 };
 

@@ -152,7 +152,8 @@ __device__ __forceinline__ void window_load(const int64_t *__restrict__ demand, 
 
 // Decides one window [wpos, wpos + WIN) of a pass: first-fit rounds until the
 // window is exhausted or the pass ends inside it; updates the pass state.
-__device__ __forceinline__ void decide_window(const int64_t (&x)[WIN_ITEMS], const int64_t wpos,
+// Returns whether the window held any candidate.
+__device__ __forceinline__ bool decide_window(const int64_t (&x)[WIN_ITEMS], const int64_t wpos,
                                               const int base, const int64_t end,
                                               const int64_t mask, const bool filter,
                                               uint8_t *__restrict__ decision, int64_t &R,
@@ -160,6 +161,7 @@ __device__ __forceinline__ void decide_window(const int64_t (&x)[WIN_ITEMS], con
                                               int64_t &adm_bytes, int64_t &rounds, int64_t &pos) {
   uint32_t abits = 0;
   int s_loc = 0, lim = WIN;
+  bool any_cand = false;
   for (;;) {
     const int64_t cap = R + 1;
     int64_t v[WIN_ITEMS], r[WIN_ITEMS];
@@ -174,6 +176,12 @@ __device__ __forceinline__ void decide_window(const int64_t (&x)[WIN_ITEMS], con
     const int64_t wincl = wave_incl_scan_dpp(run);
     const int64_t ex = wave_prev_lane64(wincl);
     const int64_t total = read_lane64(wincl, WAVE - 1);
+    if (!any_cand) {
+      bool mine = false;
+#pragma unroll
+      for (int k = 0; k < WIN_ITEMS; ++k) mine = mine || r[k] >= 0;
+      any_cand = __ballot(mine) != 0;
+    }
     int kb = WIN_ITEMS;      // this lane's break item
     int64_t before = 0;      // prefix just before it
     uint32_t a = 0;
@@ -222,6 +230,7 @@ __device__ __forceinline__ void decide_window(const int64_t (&x)[WIN_ITEMS], con
     if (mx + 1 > hi) hi = mx + 1;
   }
   pos = done ? wpos + lim : wpos + WIN;
+  return any_cand;
 }
 
 // Results of a window walk, handed to the rest of a workgroup through LDS.
@@ -237,7 +246,7 @@ __device__ __forceinline__ void window_pass(DevCtl *c, const int64_t *__restrict
                                             int from_state, int64_t R0, int64_t start0,
                                             int64_t end0, int append, int lane,
                                             WinResult *wr = nullptr,
-                                            const int64_t *pre = nullptr) {
+                                            const int64_t *pre = nullptr, int empty_exit = 0) {
   const int s = L & 3, nx = (L + 1) & 3;
   // pass state in registers: every lane derives it from the same inputs
   int64_t R, pos, end, hi;
@@ -281,7 +290,11 @@ __device__ __forceinline__ void window_pass(DevCtl *c, const int64_t *__restrict
 #pragma unroll
     for (int u = 0; u < WIN_PF; ++u) window_load(demand, mask, pos + u * WIN + base, end, x[u]);
   }
-  int w = 0;
+  // empty_exit > 0: stop (leaving the rest to the grid rounds) after that
+  // many consecutive windows without a single candidate; free memory is then
+  // below every demand seen, and a candidate-free stretch is the grid
+  // kernel's streaming case
+  int w = 0, empty_run = 0;
   while (w < max_windows && !done) {
 #pragma unroll
     for (int u = 0; u < WIN_PF; ++u) {
@@ -291,8 +304,10 @@ __device__ __forceinline__ void window_pass(DevCtl *c, const int64_t *__restrict
         break;
       }
       const int64_t wpos = pos;
-      decide_window(x[u], wpos, base, end, mask, filter, decision, R, done, hi, adm_cnt, adm_bytes,
-                    rounds, pos);
+      const bool cand = decide_window(x[u], wpos, base, end, mask, filter, decision, R, done, hi,
+                                      adm_cnt, adm_bytes, rounds, pos);
+      empty_run = cand ? 0 : empty_run + 1;
+      if (empty_exit > 0 && empty_run >= empty_exit) max_windows = w + 1;
       if (!done && w + WIN_PF < max_windows)
         window_load(demand, mask, wpos + WIN_PF * WIN + base, end, x[u]);
       ++w;
@@ -334,20 +349,208 @@ __global__ __launch_bounds__(WIN_THREADS) void k_window(DevCtl *c, const int64_t
                                                         uint8_t *__restrict__ decision, int64_t mask,
                                                         uint32_t L, int max_windows, int init,
                                                         int filter_arg, int from_state, int64_t R0,
-                                                        int64_t start0, int64_t end0, int append) {
+                                                        int64_t start0, int64_t end0, int append,
+                                                        int empty_exit) {
   window_pass(c, demand, decision, mask, L, max_windows, init, filter_arg, from_state, R0, start0,
-              end0, append, threadIdx.x);
+              end0, append, threadIdx.x, nullptr, nullptr, empty_exit);
 }
 
 // ---------------------------------------------------------------------------
 // Grid-wide round with decoupled look-back
 // ---------------------------------------------------------------------------
+// Loads tile t's demands (raw; -1 past the end) without using them, so a
+// prefetch does not wait for the data.
+__device__ __forceinline__ void round_load(const int64_t *__restrict__ demand, int64_t mask,
+                                           int64_t base, int64_t end, int64_t (&x)[RND_ITEMS]) {
+#pragma unroll
+  for (int j = 0; j < RND_ITEMS; ++j) {
+    const int64_t p = base + int64_t(j) * RND_THREADS + threadIdx.x;
+    x[j] = p < end ? __builtin_nontemporal_load(demand + (p & mask)) : -1;
+  }
+}
+
+// One tile of a round (whole workgroup).  raw: the tile's demands from
+// round_load.  Returns true when the tile lies past the round's break (so
+// does every later tile).
+__device__ __forceinline__ bool round_tile(DevCtl *c, uint8_t *__restrict__ decision, int64_t mask,
+                                           unsigned long long *flags, int s, int nx,
+                                           uint32_t epoch, int64_t R, int64_t cap, bool filter,
+                                           int64_t end, long long t, int64_t base,
+                                           const int64_t (&raw)[RND_ITEMS], int64_t *red,
+                                           int64_t &s_E, int64_t &s_brk_sum, int64_t &acc_sum,
+                                           int64_t &acc_cnt, int64_t &acc_hi) {
+  const int tid = threadIdx.x;
+  int64_t x[RND_ITEMS];
+  int64_t tsum = 0;
+#pragma unroll
+  for (int j = 0; j < RND_ITEMS; ++j) {
+    const int64_t v = raw[j];
+    const bool cd = v >= 0 && (!filter || v <= R);
+    x[j] = cd ? v : -1;
+    tsum += cd ? v : 0;
+  }
+  const int64_t Araw = block_sum<RND_THREADS>(tsum, red);
+  const int64_t A = Araw < cap ? Araw : cap;
+
+  if (Araw == 0) {
+    // No candidate in this tile: every entry is rejected whatever the
+    // prefix before it is, so the tile needs no look-back.  It publishes
+    // its zero sum for the tiles after it (tile 0 knows its prefix is 0).
+    if (tid == 0) st_relaxed(&flags[t], pack_flag(epoch, t == 0 ? FL_INC : FL_AGG, 0));
+#pragma unroll
+    for (int j = 0; j < RND_ITEMS; ++j) {
+      const int64_t p = base + int64_t(j) * RND_THREADS + tid;
+      if (p < end) decision[p & mask] = 0;
+    }
+    return false;
+  }
+
+  if (tid < WAVE) {
+    // Wave 0 looks back 64 predecessors at a time: lane l reads the flag of
+    // tile p - l.  The nearest inclusive flag ends the walk once every
+    // nearer predecessor has published its aggregate.
+    const int lane = tid;
+    int64_t E = 0;
+    if (t == 0) {
+      if (lane == 0) st_relaxed(&flags[t], pack_flag(epoch, FL_INC, A));
+    } else {
+      if (lane == 0) st_relaxed(&flags[t], pack_flag(epoch, FL_AGG, A));
+      long long p = t - 1;
+      for (;;) {
+        const long long qq = p - lane;
+        const unsigned long long f =
+            qq >= 0 ? ld_relaxed(&flags[qq]) : pack_flag(epoch, FL_INC, 0);
+        const uint64_t st = (f >> 46) & 3;
+        const bool valid = uint32_t(f >> 48) == epoch && st != 0;
+        const uint64_t inc_b = __ballot(valid && st == FL_INC);
+        const uint64_t bad_b = __ballot(!valid);
+        const int fi = inc_b ? __builtin_ctzll(inc_b) : WAVE;
+        const uint64_t need = fi >= WAVE - 1 ? ~0ULL : ((2ULL << fi) - 1);
+        if (bad_b & need) {
+          // a predecessor that saw the break marker first may never publish
+          if (ld_relaxed(&c->break_tile[s]) < t) {
+            E = cap;
+            break;
+          }
+          __builtin_amdgcn_s_sleep(1);
+          continue;
+        }
+        const int64_t v = lane <= fi ? int64_t(f & VMASK) : 0;
+        const int64_t w = wave_sum(v);  // <= 64 * cap, no overflow
+        E = sat_add(E, w < cap ? w : cap, cap);
+        if (fi < WAVE || E >= cap) break;
+        p -= WAVE;
+      }
+      if (lane == 0) st_relaxed(&flags[t], pack_flag(epoch, FL_INC, sat_add(E, A, cap)));
+    }
+    if (lane == 0) {
+      if (E <= R && sat_add(E, A, cap) > R) min_relaxed(&c->break_tile[s], (long long)t);
+      s_E = E;
+    }
+  }
+  __syncthreads();
+  const int64_t E = s_E;
+  if (E > R) return true;  // the break lies in an earlier tile, which closes the round
+
+  int64_t tcnt = 0, tmax = -1;
+  if (sat_add(E, A, cap) <= R) {
+    // every candidate of this tile is admitted
+#pragma unroll
+    for (int j = 0; j < RND_ITEMS; ++j) {
+      const int64_t p = base + int64_t(j) * RND_THREADS + tid;
+      if (p < end) {
+        const bool a = x[j] >= 0;
+        decision[p & mask] = a ? 1 : 0;
+        if (a) {
+          ++tcnt;
+          tmax = p;
+        }
+      }
+    }
+    const int64_t cnt = block_sum<RND_THREADS>(tcnt, red);
+    const int64_t mx = block_max<RND_THREADS>(tmax, red);
+    if (tid == 0) {
+      acc_cnt += cnt;
+      if (mx + 1 > acc_hi) acc_hi = mx + 1;
+      acc_sum += A;  // exact here: E + A <= R
+    }
+    return false;
+  }
+
+  // This tile holds the break: scan it row by row in queue order.
+  int64_t carry = E, brk = -1, brk_sum = 0;
+  for (int j = 0; j < RND_ITEMS; ++j) {
+    const int64_t p = base + int64_t(j) * RND_THREADS + tid;
+    const int64_t v = x[j] >= 0 ? x[j] : 0;
+    int64_t rowtot;
+    const int64_t ex = block_excl_scan_sat<RND_THREADS>(v, cap, red, &rowtot);
+    const int64_t P = sat_add(carry, sat_add(ex, v, cap), cap);
+    const bool over = x[j] >= 0 && P > R;
+    const int64_t f = block_min<RND_THREADS>(over ? tid : RND_THREADS, red);
+    if (f < RND_THREADS) {
+      if (tid == f) s_brk_sum = sat_add(carry, ex, cap);
+      if (tid <= f && p < end) {
+        const bool a = x[j] >= 0 && tid < f;
+        decision[p & mask] = a ? 1 : 0;
+        if (a) {
+          ++tcnt;
+          tmax = p;
+        }
+      }
+      __syncthreads();
+      brk = base + int64_t(j) * RND_THREADS + f;
+      brk_sum = s_brk_sum;
+      break;
+    }
+    if (p < end) {
+      const bool a = x[j] >= 0;
+      decision[p & mask] = a ? 1 : 0;
+      if (a) {
+        ++tcnt;
+        tmax = p;
+      }
+    }
+    carry = sat_add(carry, rowtot, cap);
+  }
+  const int64_t cnt = block_sum<RND_THREADS>(tcnt, red);
+  const int64_t mx = block_max<RND_THREADS>(tmax, red);
+  if (tid == 0) {
+    if (cnt) {
+      add_relaxed(&c->p_admitted, cnt);
+      max_relaxed(&c->p_hi, mx + 1);
+    }
+    add_relaxed(&c->p_admitted_bytes, brk_sum);
+    add_relaxed(&c->p_rounds, (int64_t)1);
+    const int64_t R2 = R - brk_sum;
+    c->rec[nx].R = R2;
+    c->rec[nx].start = brk + 1;
+    c->rec[nx].done = (!filter || R2 == 0 || brk + 1 >= end) ? 1 : 0;
+  }
+  return false;
+}
+
+// Tiles are handed out in tickets of TILES_PER_TICKET consecutive tiles: a
+// quarter of the ticket atomics (one counter serves the whole grid).  A
+// workgroup takes its next ticket while it decides the current one and loads
+// each tile while the one before it is decided (the first tile of the next
+// ticket during the last tile of this one).  A tile's look-back only waits
+// for lower tiles, which belong to earlier tickets (held by running
+// workgroups, which never wait for a higher tile) or come earlier in the same
+// ticket.
+constexpr int TILES_PER_TICKET = 4;
+__device__ __forceinline__ long long take_ticket(DevCtl *c, int s, long long n_tiles) {
+  const long long k = (long long)add_relaxed(&c->ticket[s], 1ULL);
+  const long long t0 = k * TILES_PER_TICKET;
+  const long long bt = ld_relaxed(&c->break_tile[s]);
+  return (t0 < n_tiles && t0 <= bt) ? t0 : -1;
+}
+
 __global__ __launch_bounds__(RND_THREADS) void k_round(DevCtl *c, const int64_t *__restrict__ demand,
                                                        uint8_t *__restrict__ decision, int64_t mask,
                                                        unsigned long long *flags, uint32_t L,
                                                        uint32_t epoch) {
   __shared__ int64_t red[RND_THREADS / WAVE];
-  __shared__ long long s_t;
+  __shared__ long long s_tk[2];  // next ticket, by iteration parity
   __shared__ int64_t s_E;
   __shared__ int64_t s_brk_sum;
   const int tid = threadIdx.x;
@@ -365,15 +568,13 @@ __global__ __launch_bounds__(RND_THREADS) void k_round(DevCtl *c, const int64_t 
   // thread 0's totals over the whole tiles this workgroup decided
   int64_t acc_sum = 0, acc_cnt = 0, acc_hi = -1;
 
-  for (;;) {
-    if (tid == 0) {
-      const long long t = (long long)add_relaxed(&c->ticket[s], 1ULL);
-      const long long bt = ld_relaxed(&c->break_tile[s]);
-      s_t = (t < n_tiles && t <= bt) ? t : -1;
-    }
-    __syncthreads();
-    const long long t = s_t;
-    if (t < 0) {
+  if (tid == 0) s_tk[1] = take_ticket(c, s, n_tiles);
+  __syncthreads();
+  long long t0 = s_tk[1];
+  int64_t xa[RND_ITEMS], xb[RND_ITEMS];
+  if (t0 >= 0) round_load(demand, mask, start + int64_t(t0) * TILE, end, xa);
+  for (int it = 0;; ++it) {
+    if (t0 < 0) {
       if (tid == 0) {
         if (acc_cnt) {
           add_relaxed(&c->p_admitted, acc_cnt);
@@ -383,155 +584,35 @@ __global__ __launch_bounds__(RND_THREADS) void k_round(DevCtl *c, const int64_t 
       }
       break;
     }
-    const int64_t base = start + int64_t(t) * TILE;
-
-    int64_t x[RND_ITEMS];
-    int64_t tsum = 0;
+    const int par = it & 1;
+    // read by the other threads only after the first tile's barriers
+    if (tid == 0) s_tk[par] = take_ticket(c, s, n_tiles);
+    bool next_loaded = false, past = false;
 #pragma unroll
-    for (int j = 0; j < RND_ITEMS; ++j) {
-      const int64_t p = base + int64_t(j) * RND_THREADS + tid;
-      const int64_t v = p < end ? __builtin_nontemporal_load(demand + (p & mask)) : -1;
-      const bool cd = v >= 0 && (!filter || v <= R);
-      x[j] = cd ? v : -1;
-      tsum += cd ? v : 0;
-    }
-    const int64_t Araw = block_sum<RND_THREADS>(tsum, red);
-    const int64_t A = Araw < cap ? Araw : cap;
-
-    if (Araw == 0) {
-      // No candidate in this tile: every entry is rejected whatever the
-      // prefix before it is, so the tile needs no look-back.  It publishes
-      // its zero sum for the tiles after it (tile 0 knows its prefix is 0).
-      if (tid == 0) st_relaxed(&flags[t], pack_flag(epoch, t == 0 ? FL_INC : FL_AGG, 0));
-#pragma unroll
-      for (int j = 0; j < RND_ITEMS; ++j) {
-        const int64_t p = base + int64_t(j) * RND_THREADS + tid;
-        if (p < end) decision[p & mask] = 0;
-      }
-      continue;
-    }
-
-    if (tid < WAVE) {
-      // Wave 0 looks back 64 predecessors at a time: lane l reads the flag of
-      // tile p - l.  The nearest inclusive flag ends the walk once every
-      // nearer predecessor has published its aggregate.
-      const int lane = tid;
-      int64_t E = 0;
-      if (t == 0) {
-        if (lane == 0) st_relaxed(&flags[t], pack_flag(epoch, FL_INC, A));
-      } else {
-        if (lane == 0) st_relaxed(&flags[t], pack_flag(epoch, FL_AGG, A));
-        long long p = t - 1;
-        for (;;) {
-          const long long qq = p - lane;
-          const unsigned long long f =
-              qq >= 0 ? ld_relaxed(&flags[qq]) : pack_flag(epoch, FL_INC, 0);
-          const uint64_t st = (f >> 46) & 3;
-          const bool valid = uint32_t(f >> 48) == epoch && st != 0;
-          const uint64_t inc_b = __ballot(valid && st == FL_INC);
-          const uint64_t bad_b = __ballot(!valid);
-          const int fi = inc_b ? __builtin_ctzll(inc_b) : WAVE;
-          const uint64_t need = fi >= WAVE - 1 ? ~0ULL : ((2ULL << fi) - 1);
-          if (bad_b & need) {
-            // a predecessor that saw the break marker first may never publish
-            if (ld_relaxed(&c->break_tile[s]) < t) {
-              E = cap;
-              break;
-            }
-            __builtin_amdgcn_s_sleep(1);
-            continue;
-          }
-          const int64_t v = lane <= fi ? int64_t(f & VMASK) : 0;
-          const int64_t w = wave_sum(v);  // <= 64 * cap, no overflow
-          E = sat_add(E, w < cap ? w : cap, cap);
-          if (fi < WAVE || E >= cap) break;
-          p -= WAVE;
+    for (int u = 0; u < TILES_PER_TICKET; ++u) {
+      const long long t = t0 + u;
+      if (t >= n_tiles) break;
+      if (u + 1 < TILES_PER_TICKET) {
+        if (t + 1 < n_tiles)
+          round_load(demand, mask, start + int64_t(t + 1) * TILE, end, (u & 1) ? xa : xb);
+      } else if (u > 0) {
+        const long long tn = s_tk[par];
+        if (tn >= 0) {
+          round_load(demand, mask, start + int64_t(tn) * TILE, end, xa);
+          next_loaded = true;
         }
-        if (lane == 0) st_relaxed(&flags[t], pack_flag(epoch, FL_INC, sat_add(E, A, cap)));
       }
-      if (lane == 0) {
-        if (E <= R && sat_add(E, A, cap) > R) min_relaxed(&c->break_tile[s], (long long)t);
-        s_E = E;
-      }
+      past = round_tile(c, decision, mask, flags, s, nx, epoch, R, cap, filter, end, t,
+                        start + int64_t(t) * TILE, (u & 1) ? xb : xa, red, s_E, s_brk_sum,
+                        acc_sum, acc_cnt, acc_hi);
+      if (past) break;
     }
     __syncthreads();
-    const int64_t E = s_E;
-    if (E > R) continue;  // the break lies in an earlier tile, which closes the round
-
-    int64_t tcnt = 0, tmax = -1;
-    if (sat_add(E, A, cap) <= R) {
-      // every candidate of this tile is admitted
-#pragma unroll
-      for (int j = 0; j < RND_ITEMS; ++j) {
-        const int64_t p = base + int64_t(j) * RND_THREADS + tid;
-        if (p < end) {
-          const bool a = x[j] >= 0;
-          decision[p & mask] = a ? 1 : 0;
-          if (a) {
-            ++tcnt;
-            tmax = p;
-          }
-        }
-      }
-      const int64_t cnt = block_sum<RND_THREADS>(tcnt, red);
-      const int64_t mx = block_max<RND_THREADS>(tmax, red);
-      if (tid == 0) {
-        acc_cnt += cnt;
-        if (mx + 1 > acc_hi) acc_hi = mx + 1;
-        acc_sum += A;  // exact here: E + A <= R
-      }
-      continue;
-    }
-
-    // This tile holds the break: scan it row by row in queue order.
-    int64_t carry = E, brk = -1, brk_sum = 0;
-    for (int j = 0; j < RND_ITEMS; ++j) {
-      const int64_t p = base + int64_t(j) * RND_THREADS + tid;
-      const int64_t v = x[j] >= 0 ? x[j] : 0;
-      int64_t rowtot;
-      const int64_t ex = block_excl_scan_sat<RND_THREADS>(v, cap, red, &rowtot);
-      const int64_t P = sat_add(carry, sat_add(ex, v, cap), cap);
-      const bool over = x[j] >= 0 && P > R;
-      const int64_t f = block_min<RND_THREADS>(over ? tid : RND_THREADS, red);
-      if (f < RND_THREADS) {
-        if (tid == f) s_brk_sum = sat_add(carry, ex, cap);
-        if (tid <= f && p < end) {
-          const bool a = x[j] >= 0 && tid < f;
-          decision[p & mask] = a ? 1 : 0;
-          if (a) {
-            ++tcnt;
-            tmax = p;
-          }
-        }
-        __syncthreads();
-        brk = base + int64_t(j) * RND_THREADS + f;
-        brk_sum = s_brk_sum;
-        break;
-      }
-      if (p < end) {
-        const bool a = x[j] >= 0;
-        decision[p & mask] = a ? 1 : 0;
-        if (a) {
-          ++tcnt;
-          tmax = p;
-        }
-      }
-      carry = sat_add(carry, rowtot, cap);
-    }
-    const int64_t cnt = block_sum<RND_THREADS>(tcnt, red);
-    const int64_t mx = block_max<RND_THREADS>(tmax, red);
-    if (tid == 0) {
-      if (cnt) {
-        add_relaxed(&c->p_admitted, cnt);
-        max_relaxed(&c->p_hi, mx + 1);
-      }
-      add_relaxed(&c->p_admitted_bytes, brk_sum);
-      add_relaxed(&c->p_rounds, (int64_t)1);
-      const int64_t R2 = R - brk_sum;
-      c->rec[nx].R = R2;
-      c->rec[nx].start = brk + 1;
-      c->rec[nx].done = (!filter || R2 == 0 || brk + 1 >= end) ? 1 : 0;
-    }
+    // past the break, so is every later tile: leave them unpublished (a
+    // later look-back that meets them reads the break marker instead)
+    const long long tn = past ? -1 : s_tk[par];
+    if (!next_loaded && tn >= 0) round_load(demand, mask, start + int64_t(tn) * TILE, end, xa);
+    t0 = tn;
   }
 }
 
@@ -1025,7 +1106,12 @@ int adm_engine_init(AdmEngine &e, int device, int64_t max_entries) {
   SCHED_HIP_TRY(hipMemset(e.d_flags, 0, sizeof(unsigned long long) * e.max_tiles));
   int cus = 0;
   SCHED_HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device));
-  e.round_grid = cus * 8;
+  // the round grid is what the device holds at once: more workgroups only
+  // add ticket traffic (tiles are handed out dynamically anyway)
+  int per_cu = 0;
+  SCHED_HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_round, RND_THREADS, 0));
+  if (per_cu < 1) per_cu = 1;
+  e.round_grid = cus * per_cu;
   e.launch = 1;
   e.epoch = 0;
   return SCHED_OK;
@@ -1121,7 +1207,7 @@ static int launch_window(AdmEngine &e, const int64_t *demand, uint8_t *decision,
   SCHED_PROF_LAUNCH("k_window", s,
                     (k_window<<<1, WIN_THREADS, 0, s>>>(e.d_ctl, demand, decision, mask, L,
                                                         window_limit, 1, filter, from_state, R0,
-                                                        start, end, append)));
+                                                        start, end, append, WIN_EMPTY_EXIT)));
   SCHED_HIP_TRY(hipGetLastError());
   *Lio = advance(e);
   return SCHED_OK;
@@ -1131,19 +1217,18 @@ int adm_scan(AdmEngine &e, int policy, const int64_t *demand, uint8_t *decision,
              int64_t end, int64_t R0, int window_limit, hipStream_t s, PassOut *out) {
   uint32_t L = uint32_t(e.launch);
   const int filter = policy == SCHED_POLICY_MMU ? 1 : 0;
-  bool done = false;
+  // the grid rounds go right behind the window kernel without a host check in
+  // between: when the window walk already finished the pass they return at
+  // once (a few microseconds each, less than a synchronisation)
   if (window_limit > 0) {
     if (int rc = launch_window(e, demand, decision, -1, window_limit, filter, 0, R0, start, end, 0,
                                s, &L))
       return rc;
-    if (int rc = read_summary(e, L, s)) return rc;
-    done = e.h_sum[0].done != 0;
   } else {
     k_prologue<<<1, 64, 0, s>>>(e.d_ctl, L, filter, 0, R0, start, end);
     SCHED_HIP_TRY(hipGetLastError());
   }
-  if (!done)
-    if (int rc = run_rounds(e, demand, decision, -1, end - start, s, &L)) return rc;
+  if (int rc = run_rounds(e, demand, decision, -1, end - start, s, &L)) return rc;
   fill_out(e.h_sum[0], out);
   return SCHED_OK;
 }

@@ -21,6 +21,8 @@
 #include <chrono>
 #include <cmath>
 #include <deque>
+#include <iterator>
+#include <map>
 #include <queue>
 #include <thread>
 #include <tuple>
@@ -91,9 +93,71 @@ int grid_of(int64_t n, int cap) {
 struct Running {
   int32_t job;          // -1 for a batch
   int32_t batch;        // index into batch_jobs, -1 for a single job
-  void *mem;
+  uint64_t off, len;    // arena range (len 0: none)
   hipEvent_t ev_start, ev_end;
   hipStream_t stream;
+};
+
+// Device memory of the admitted jobs: one allocation of the scheduler's
+// capacity, carved on the host best fit with coalescing of free neighbours
+// (4 KiB granules).  Admission keeps the sum of the live demands within the
+// capacity; a job whose demand fits but finds no contiguous range waits
+// until a running job ends (when nothing runs the arena is one free range,
+// so every admitted job eventually gets its memory).  A range returns to the
+// arena only when its job's completion has been observed.
+class Arena {
+ public:
+  char *base = nullptr;
+  uint64_t size = 0;
+  bool alloc(uint64_t len, uint64_t *off) {
+    auto it = by_len.lower_bound(len);
+    if (it == by_len.end()) return false;
+    const uint64_t L = it->first, o = it->second;
+    by_len.erase(it);
+    by_off.erase(o);
+    if (L > len) put(o + len, L - len);
+    *off = o;
+    return true;
+  }
+  void release(uint64_t off, uint64_t len) {
+    auto nx = by_off.lower_bound(off);
+    if (nx != by_off.end() && off + len == nx->first) {
+      drop_len(nx->second, nx->first);
+      len += nx->second;
+      nx = by_off.erase(nx);
+    }
+    if (nx != by_off.begin()) {
+      auto pv = std::prev(nx);
+      if (pv->first + pv->second == off) {
+        drop_len(pv->second, pv->first);
+        off = pv->first;
+        len += pv->second;
+        by_off.erase(pv);
+      }
+    }
+    put(off, len);
+  }
+  void reset() {
+    by_off.clear();
+    by_len.clear();
+    if (size) put(0, size);
+  }
+
+ private:
+  std::map<uint64_t, uint64_t> by_off;       // offset -> length
+  std::multimap<uint64_t, uint64_t> by_len;  // length -> offset
+  void put(uint64_t off, uint64_t len) {
+    by_off.emplace(off, len);
+    by_len.emplace(len, off);
+  }
+  void drop_len(uint64_t len, uint64_t off) {
+    auto r = by_len.equal_range(len);
+    for (auto it = r.first; it != r.second; ++it)
+      if (it->second == off) {
+        by_len.erase(it);
+        return;
+      }
+  }
 };
 
 struct Serve {
@@ -107,7 +171,6 @@ struct Serve {
   std::vector<hipStream_t> streams;
   size_t next_stream = 0;
   hipStream_t bstream = nullptr;
-  hipMemPool_t pool = nullptr;
   hipEvent_t ev0 = nullptr;
   std::chrono::steady_clock::time_point h0;
   unsigned long long *d_digest = nullptr;
@@ -126,6 +189,8 @@ struct Serve {
   BatchEngine *beng = nullptr;
   int64_t finished = 0;
   int64_t cur_running = 0;
+  Arena arena;
+  std::deque<int32_t> deferred;  // admitted, waiting for a contiguous range
 
   double host_now() const {
     return std::chrono::duration<double>(std::chrono::steady_clock::now() - h0).count();
@@ -153,9 +218,11 @@ struct Serve {
     for (auto &s : streams) SCHED_HIP_TRY(hipStreamCreate(&s));
     SCHED_HIP_TRY(hipStreamCreate(&bstream));
     inflight.resize(ns + 1);
-    SCHED_HIP_TRY(hipDeviceGetDefaultMemPool(&pool, c->device));
-    uint64_t thr = UINT64_MAX;
-    SCHED_HIP_TRY(hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &thr));
+    if (o.mode == SCHED_SERVE_REALTIME) {
+      arena.size = uint64_t(rup(c->capacity, 4096));
+      SCHED_HIP_TRY(hipMalloc(&arena.base, arena.size));
+      arena.reset();
+    }
     SCHED_HIP_TRY(hipMalloc(&d_digest, sizeof(unsigned long long) * std::max<int64_t>(n, 1)));
     k_zero_u64<<<grid_of(n, 1024), 256, 0, stream_ctl>>>(d_digest, n);
     SCHED_HIP_TRY(hipGetLastError());
@@ -196,6 +263,8 @@ struct Serve {
       }
     for (auto e : ev_free) (void)hipEventDestroy(e);
     for (auto s : streams) (void)hipStreamDestroy(s);
+    if (arena.base) (void)hipFree(arena.base);
+    arena.base = nullptr;
     if (bstream) (void)hipStreamDestroy(bstream);
     if (ev0) (void)hipEventDestroy(ev0);
     if (d_digest) (void)hipFree(d_digest);
@@ -210,7 +279,6 @@ struct Serve {
       batch_free(*beng);
       delete beng;
     }
-    if (pool) (void)hipMemPoolTrimTo(pool, 0);
   }
 
   int64_t demand_of(int64_t j) const { return o.serial ? c->capacity : J[j].demand; }
@@ -261,22 +329,20 @@ struct Serve {
     r->job = j;
     r->batch = -1;
     r->stream = s;
+    const int64_t bytes = job_bytes(d);
+    if (bytes < 0 || bytes > d.demand) return SCHED_E_INVALID;
+    const uint64_t len = uint64_t(rup(std::max<int64_t>(bytes, 1), 4096));
+    uint64_t off = 0;
+    const double ta = host_now();
+    const bool got = arena.alloc(len, &off);
+    sum.host_alloc_s += host_now() - ta;
+    if (!got) return SCHED_NOT_READY;  // no contiguous range yet: the caller defers
+    r->off = off;
+    r->len = len;
     r->ev_start = take_event();
     r->ev_end = take_event();
     SCHED_HIP_TRY(hipEventRecord(r->ev_start, s));
-    const int64_t bytes = job_bytes(d);
-    if (bytes < 0 || bytes > d.demand) return SCHED_E_INVALID;
-    void *mem = nullptr;
-    if (hipMallocFromPoolAsync(&mem, size_t(bytes), pool, s) != hipSuccess || !mem) {
-      (void)hipGetLastError();
-      res[j].status = SCHED_E_NOMEM;  // inside its reservation: a memory-safety violation
-      sum.violations += 1;
-      SCHED_HIP_TRY(hipEventRecord(r->ev_end, s));
-      r->mem = nullptr;
-      return SCHED_OK;
-    }
-    r->mem = mem;
-    char *p = (char *)mem;
+    char *p = arena.base + off;
     unsigned long long *dg = d_digest + j;
     if (d.kind == SCHED_JOB_TRIAD) {
       const int64_t n4 = rup(4 * d.size, 4096);
@@ -300,7 +366,6 @@ struct Serve {
       if (o.digest) k_digest<<<1, 256, 0, s>>>(bins, SCHED_HIST_BINS, dg);
     }
     SCHED_HIP_TRY(hipGetLastError());
-    SCHED_HIP_TRY(hipFreeAsync(mem, s));
     SCHED_HIP_TRY(hipEventRecord(r->ev_end, s));
     return SCHED_OK;
   }
@@ -310,25 +375,21 @@ struct Serve {
     r->job = -1;
     r->batch = int32_t(batch_jobs.size());
     r->stream = bstream;
+    uint64_t total = 0;
+    for (int32_t j : jobs) total += uint64_t(job_bytes(J[j]));  // whole pages per array
+    uint64_t off = 0;
+    const double ta = host_now();
+    const bool got = arena.alloc(std::max<uint64_t>(total, 4096), &off);
+    sum.host_alloc_s += host_now() - ta;
+    if (!got) return SCHED_NOT_READY;
+    r->off = off;
+    r->len = std::max<uint64_t>(total, 4096);
     r->ev_start = take_event();
     r->ev_end = take_event();
     SCHED_HIP_TRY(hipEventRecord(r->ev_start, bstream));
-    int64_t total = 0;
-    for (int32_t j : jobs) total += job_bytes(J[j]);
-    void *mem = nullptr;
-    if (hipMallocFromPoolAsync(&mem, size_t(total), pool, bstream) != hipSuccess || !mem) {
-      (void)hipGetLastError();
-      for (int32_t j : jobs) res[j].status = SCHED_E_NOMEM;
-      sum.violations += int64_t(jobs.size());
-      SCHED_HIP_TRY(hipEventRecord(r->ev_end, bstream));
-      r->mem = nullptr;
-      batch_jobs.push_back(jobs);
-      return SCHED_OK;
-    }
-    r->mem = mem;
     std::vector<BatchDesc> ds;
     ds.reserve(jobs.size());
-    char *p = (char *)mem;
+    char *p = arena.base + off;
     for (int32_t j : jobs) {
       const int64_t n4 = rup(4 * J[j].size, 4096);
       ds.push_back(BatchDesc{(float *)p, (float *)(p + n4), (float *)(p + 2 * n4), J[j].size,
@@ -339,7 +400,6 @@ struct Serve {
     // the pinned table is rewritten only when no batch is in flight
     if (int rc = batch_fill(*beng, ds, beng->chunk)) return rc;
     if (int rc = batch_launch(*beng, bstream, o.use_graph != 0)) return rc;
-    SCHED_HIP_TRY(hipFreeAsync(mem, bstream));
     SCHED_HIP_TRY(hipEventRecord(r->ev_end, bstream));
     batch_running = true;
     sum.batches += 1;
@@ -356,24 +416,67 @@ struct Serve {
         pending_small.push_back(j);
         continue;
       }
-      Running r{};
-      const size_t si = next_stream++ % streams.size();
-      if (int rc = launch_single(j, streams[si], &r)) return rc;
-      inflight[si].push_back(r);
-      cur_running += 1;
+      if (!deferred.empty()) {  // keep admission order behind jobs already waiting
+        deferred.push_back(j);
+        continue;
+      }
+      if (int rc = start_single(j)) return rc;
     }
     if (int rc = maybe_launch_batch()) return rc;
     sum.max_running = std::max<int64_t>(sum.max_running, cur_running);
     return SCHED_OK;
   }
 
+  // Launches admitted job j, or defers it while no contiguous range fits.
+  int start_single(int32_t j) {
+    Running r{};
+    const size_t si = next_stream % streams.size();
+    const int rc = launch_single(j, streams[si], &r);
+    if (rc == SCHED_NOT_READY) {
+      deferred.push_back(j);
+      sum.deferred += 1;
+      return SCHED_OK;
+    }
+    if (rc) return rc;
+    ++next_stream;
+    inflight[si].push_back(r);
+    cur_running += 1;
+    return SCHED_OK;
+  }
+
+  // Deferred jobs, oldest first, as long as ranges fit.
+  int launch_deferred() {
+    while (!deferred.empty()) {
+      const int32_t j = deferred.front();
+      Running r{};
+      const size_t si = next_stream % streams.size();
+      const int rc = launch_single(j, streams[si], &r);
+      if (rc == SCHED_NOT_READY) break;
+      if (rc) return rc;
+      deferred.pop_front();
+      ++next_stream;
+      inflight[si].push_back(r);
+      cur_running += 1;
+    }
+    sum.max_running = std::max<int64_t>(sum.max_running, cur_running);
+    return SCHED_OK;
+  }
+
   int maybe_launch_batch() {
     if (!beng || batch_running || pending_small.empty()) return SCHED_OK;
-    const size_t k = std::min<size_t>(pending_small.size(), size_t(beng->max_desc));
-    std::vector<int32_t> take(pending_small.begin(), pending_small.begin() + k);
-    pending_small.erase(pending_small.begin(), pending_small.begin() + k);
+    // as many of the waiting small jobs as one contiguous range holds
+    size_t k = std::min<size_t>(pending_small.size(), size_t(beng->max_desc));
     Running r{};
-    if (int rc = launch_batch(take, &r)) return rc;
+    std::vector<int32_t> take;
+    for (;;) {
+      take.assign(pending_small.begin(), pending_small.begin() + k);
+      const int rc = launch_batch(take, &r);
+      if (rc == SCHED_OK) break;
+      if (rc != SCHED_NOT_READY) return rc;
+      if (k == 1) return SCHED_OK;  // retried after the next completion
+      k /= 2;
+    }
+    pending_small.erase(pending_small.begin(), pending_small.begin() + k);
     inflight.back().push_back(r);
     cur_running += int64_t(take.size());
     sum.max_running = std::max<int64_t>(sum.max_running, cur_running);
@@ -402,6 +505,7 @@ struct Serve {
         } else {
           done_one(r.job);
         }
+        if (r.len) arena.release(r.off, r.len);
         ev_free.push_back(r.ev_start);
         ev_free.push_back(r.ev_end);
         q.pop_front();
@@ -435,23 +539,36 @@ struct Serve {
         if (int rc = enqueue(k)) return rc;
         changed = true;
       }
+      double t1 = host_now();
       const int64_t r = poll_completions();
       if (r) {
         if (int rc = release(r)) return rc;
         changed = true;
       }
+      double t2 = host_now();
+      sum.host_poll_s += t2 - t1;
+      if (r)
+        if (int rc = launch_deferred()) return rc;
       if (int rc = maybe_launch_batch()) return rc;
+      t1 = host_now();
+      sum.host_launch_s += t1 - t2;
       if (changed) {
         int64_t A = 0;
         if (int rc = pass(&A)) return rc;
+        t2 = host_now();
+        sum.host_pass_s += t2 - t1;
         if (A)
-          if (int rc = launch_admitted(A, host_now())) return rc;
+          if (int rc = launch_admitted(A, t2)) return rc;
+        sum.host_launch_s += host_now() - t2;
         continue;
       }
-      // idle: wait for the next arrival or a completion
-      double wait = 50e-6;
+      // idle: wait for the next arrival or a completion (short sleeps: a
+      // completion is noticed within a few microseconds, which matters most
+      // for exclusive serial runs, where every job waits for the last one)
+      double wait = 5e-6;
       if (ai < n) wait = std::min(wait, std::max(0.0, J[ai].arrival_s * scale - now));
       if (wait > 2e-6) std::this_thread::sleep_for(std::chrono::duration<double>(wait));
+      sum.host_idle_s += host_now() - t1;
     }
     SCHED_HIP_TRY(hipDeviceSynchronize());
     return SCHED_OK;
@@ -520,6 +637,24 @@ struct Serve {
     sum.p99_turn_s = pct(turns, 99);
     sum.makespan_s = last;
     sum.jobs_per_s = last > 0 ? double(sum.completed) / last : 0.0;
+    // union of the jobs' device intervals
+    std::vector<std::pair<double, double>> iv;
+    for (int64_t j = 0; j < n; ++j)
+      if (res[j].status == SCHED_OK && res[j].t_end > res[j].t_start)
+        iv.emplace_back(res[j].t_start, res[j].t_end);
+    std::sort(iv.begin(), iv.end());
+    double busy = 0.0, a = 0.0, b = -1.0;
+    for (const auto &x : iv) {
+      if (x.first > b) {
+        if (b > a) busy += b - a;
+        a = x.first;
+        b = x.second;
+      } else if (x.second > b) {
+        b = x.second;
+      }
+    }
+    if (b > a) busy += b - a;
+    sum.dev_busy_s = busy;
   }
 };
 
