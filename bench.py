@@ -62,12 +62,17 @@ def parse():
                          "slab; empty = none)")
     ap.add_argument("--cosched", default="c1,c5",
                     help="co-scheduled vs serial runs to add (c1, c4, c5; empty = none)")
+    ap.add_argument("--cosched-streams", type=int, default=3,
+                    help="HIP streams for single-job launches in the co-scheduled runs (with "
+                         "more streams than the process's hardware queues, the scheduler's "
+                         "own stream shares a queue with job kernels and its passes wait "
+                         "behind them)")
     ap.add_argument("--c5-jobs", type=int, default=50_000)
     ap.add_argument("--c4-jobs", type=int, default=10_000)
     return ap.parse_args()
 
 
-def cosched_run(cs, name, n_jobs, dev_free):
+def cosched_run(cs, name, n_jobs, dev_free, n_streams=3):
     """One job mix co-scheduled (MMU, batching of small triads) and exclusive
     serial (every demand := capacity).  Returns a dict of results."""
     import numpy as np
@@ -90,10 +95,11 @@ def cosched_run(cs, name, n_jobs, dev_free):
     out = {"jobs": mix.n, "capacity_bytes": int(mix.capacity),
            "policy": "fifo" if policy == 0 else "mmu"}
     try:
-        for label, kw in (("coscheduled", dict(n_streams=16, batch_small=batch, use_graph=1,
+        for label, kw in (("coscheduled", dict(n_streams=n_streams, batch_small=batch, use_graph=1,
                                                tune_cache=os.path.join(ROOT, "gpurun_out",
                                                                        "batch_tune.json"))),
                           ("serial", dict(n_streams=1, serial=1))):
+            print(f"[bench] {name} {label}: {mix.n} jobs", file=sys.stderr, flush=True)
             rc, res, sm = cs.sched_serve(ctx, jt, **kw)
             assert rc == 0, rc
             ok = res["status"] == 0
@@ -498,7 +504,7 @@ def main():
         for name in [x for x in args.cosched.split(",") if x]:
             out["coschedule"][name] = cosched_run(cs, name,
                                                   args.c5_jobs if name == "c5" else args.c4_jobs,
-                                                  int(free))
+                                                  int(free), args.cosched_streams)
             print(f"[bench] {name}: {json.dumps(out['coschedule'][name])}", file=sys.stderr,
                   flush=True)
 
