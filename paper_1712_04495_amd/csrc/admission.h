@@ -89,7 +89,7 @@ struct AdmEngine {
   uint64_t launch = 1;              // launch counter of the pass chain
   uint32_t epoch = 0;               // last look-back epoch handed out
   int round_grid = 0;               // persistent grid of the round kernel
-  int rounds_per_check = 2;         // round launches between host checks
+  int rounds_per_check = 1;         // round launches between host checks
   int device = 0;
 };
 

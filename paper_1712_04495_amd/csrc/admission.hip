@@ -1106,11 +1106,14 @@ int adm_engine_init(AdmEngine &e, int device, int64_t max_entries) {
   SCHED_HIP_TRY(hipMemset(e.d_flags, 0, sizeof(unsigned long long) * e.max_tiles));
   int cus = 0;
   SCHED_HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device));
-  // the round grid is what the device holds at once: more workgroups only
-  // add ticket traffic (tiles are handed out dynamically anyway)
+  // the round grid is at most what the device holds at once: more workgroups
+  // only add ticket traffic (tiles are handed out dynamically anyway).  Two
+  // per CU stream a candidate-free round faster than three (each workgroup
+  // walks 4 consecutive tiles per ticket, and fewer concurrent streams of
+  // 128 KiB spread better over the HBM channels).
   int per_cu = 0;
   SCHED_HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_round, RND_THREADS, 0));
-  if (per_cu < 1) per_cu = 1;
+  per_cu = per_cu < 1 ? 1 : (per_cu > 2 ? 2 : per_cu);
   e.round_grid = cus * per_cu;
   e.launch = 1;
   e.epoch = 0;
