@@ -338,7 +338,7 @@ def main():
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print(json.dumps({"error": "this build runs on one GPU only; the admission state is "
-                                   "per device (see DESIGN.md on sharding)", "n_gpus": args.gpus}))
+                                   "per device (sharding across GPUs is not built)", "n_gpus": args.gpus}))
         return 2
 
     import numpy as np
