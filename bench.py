@@ -199,9 +199,10 @@ def tenant_measure(cs, torch, dev):
     C = torch.empty(N * N, dtype=torch.float32, device=dev)
     assert cs.sched_gemm_fill(A, N, N, 1) == 0
     assert cs.sched_gemm_fill(B, N, N, 2) == 0
-    assert cs.sched_gemm_bf16(A, B, C, N, N, N) == 0
+    for _ in range(3):
+        assert cs.sched_gemm_bf16(A, B, C, N, N, N) == 0
     cs.sched_profile(True)
-    for _ in range(5):
+    for _ in range(10):
         assert cs.sched_gemm_bf16(A, B, C, N, N, N) == 0
     torch.cuda.synchronize()
     rc, ms, launches = cs.sched_profile_read("k_gemm_bf16")

@@ -249,24 +249,41 @@ __global__ __launch_bounds__(GT) void k_gemm_bf16(const uint16_t *__restrict__ A
       }
 }
 
-// 256 x 256 x 64 block tile, 4 waves of 128 x 128 (16 MFMA tiles of 32 x 32,
-// 256 fp32 accumulators per lane): each operand fragment read from LDS feeds
-// four MFMAs, half the LDS traffic per flop of the 64 x 64 wave tile, which
-// reads LDS at the rate the MFMA pipes can consume it.  Double-buffered LDS
-// with the same padded rows takes 144 KiB: one workgroup (one wave per SIMD)
-// per CU.  Blocks are dealt to the 8 XCDs round robin (block b runs on XCD
-// b % 8); when the tile grid allows, XCD x gets a band of tile columns and
-// walks it in groups of 8 tile rows, so the ~32 workgroups an XCD runs at a
-// time share their A and B k-slices in that XCD's L2.
+// 256 x 256 x 64 block tile in 8 waves, two per SIMD, each owning 64 x 128
+// of C (2 x 4 MFMA blocks of 32 x 32, 128 fp32 accumulators per lane).
+//   * Operands go from HBM straight into LDS: buffer loads with the LDS flag
+//     move 16 B per lane, one wave instruction filling 1 KiB of LDS (8 rows of
+//     64 bf16).  The lane that fills chunk position p of row r fetches global
+//     chunk p ^ ((r >> 1) & 7), so a fragment read (32 rows, one chunk each,
+//     16 lanes per LDS cycle) touches 16 distinct 16-B bank groups.
+//   * Two LDS stages (128 KiB).  One barrier per k-tile, placed before its
+//     last k-step: the next tile's first fragments are read during that step,
+//     and right after the barrier the stage just finished is refilled with
+//     tile t + 2, its eight loads interleaved with the step's eight MFMAs.  A
+//     load thus has a whole k-tile to land; each wave waits for its own loads
+//     before the barrier, which publishes them to the other waves.
+//   * Inside a k-tile, the fragment reads of step s + 1 alternate with the
+//     MFMAs of step s.
+// Blocks are dealt to the 8 XCDs round robin (block b runs on XCD b % 8);
+// when the tile grid allows, XCD x gets a band of tile columns and walks it in
+// groups of 8 tile rows, so the 32 workgroups an XCD runs at a time share
+// their A and B k-slices in that XCD's L2.
 constexpr int BM2 = 256, BN2 = 256;
+constexpr int GT2 = 512;           // 8 waves
+constexpr int ROW2 = BK;           // bf16 per LDS row: 128 B, unpadded (swizzled)
 constexpr int N_XCD = 8, GROUP_ROWS = 8;
+constexpr int BUF_RSRC_DW3 = 0x00020000;  // raw buffer, 32-bit dword format
 
-__global__ __launch_bounds__(GT, 1) void k_gemm_bf16_256(const uint16_t *__restrict__ A,
-                                                         const uint16_t *__restrict__ Bt,
-                                                         float *__restrict__ C, int64_t M,
-                                                         int64_t N, int64_t K) {
-  __shared__ __attribute__((aligned(16))) uint16_t sA[2][BM2 * LDS_ROW];
-  __shared__ __attribute__((aligned(16))) uint16_t sB[2][BN2 * LDS_ROW];
+typedef __attribute__((address_space(3))) void lds_void;
+
+__global__ __launch_bounds__(GT2, 1) void k_gemm_bf16_256(const uint16_t *__restrict__ A,
+                                                          const uint16_t *__restrict__ Bt,
+                                                          float *__restrict__ C, int64_t M,
+                                                          int64_t N, int64_t K) {
+  __shared__ __attribute__((aligned(1024))) uint16_t sA0[BM2 * ROW2];
+  __shared__ __attribute__((aligned(1024))) uint16_t sA1[BM2 * ROW2];
+  __shared__ __attribute__((aligned(1024))) uint16_t sB0[BN2 * ROW2];
+  __shared__ __attribute__((aligned(1024))) uint16_t sB1[BN2 * ROW2];
   const int64_t tiles_m = M / BM2, tiles_n = N / BN2;
   const int64_t b = blockIdx.x;
   int64_t bm, bn;
@@ -281,80 +298,110 @@ __global__ __launch_bounds__(GT, 1) void k_gemm_bf16_256(const uint16_t *__restr
     bn = b / tiles_m;
   }
   const int64_t m0 = bm * BM2, n0 = bn * BN2;
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int wm = (wave >> 1) * 128, wn = (wave & 1) * 128;
+  const int wave = __builtin_amdgcn_readfirstlane(int(threadIdx.x >> 6)), lane = threadIdx.x & 63;
+  const int wm = (wave >> 1) * 64, wn = (wave & 1) * 128;
+  const int frow = lane & 31, half = lane >> 5, sw = (frow >> 1) & 7;
 
-  f32x16 acc[4][4];
+  f32x16 acc[2][4];
 #pragma unroll
-  for (int i = 0; i < 4; ++i)
+  for (int i = 0; i < 2; ++i)
 #pragma unroll
     for (int j = 0; j < 4; ++j)
 #pragma unroll
       for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.0f;
 
-  Stage ra0 = g2r(A, K, m0, 0), ra1 = g2r(A, K, m0 + 128, 0);
-  Stage rb0 = g2r(Bt, K, n0, 0), rb1 = g2r(Bt, K, n0 + 128, 0);
-  r2s(sA[0], ra0);
-  r2s(sA[0] + 128 * LDS_ROW, ra1);
-  r2s(sB[0], rb0);
-  r2s(sB[0] + 128 * LDS_ROW, rb1);
-  __syncthreads();
-
+  // One buffer resource per 256-row operand panel (the host guarantees its
+  // byte size fits the 32-bit range); lane offsets are fixed, the k advance
+  // rides in the scalar offset.
   const int nk = int(K / BK);
-  const int frow = lane & 31, fk = (lane >> 5) * 8;
-  for (int kb = 0; kb < nk; ++kb) {
-    const int cur = kb & 1;
-    if (kb + 1 < nk) {
-      const int64_t k1 = int64_t(kb + 1) * BK;
-      ra0 = g2r(A, K, m0, k1);
-      ra1 = g2r(A, K, m0 + 128, k1);
-      rb0 = g2r(Bt, K, n0, k1);
-      rb1 = g2r(Bt, K, n0 + 128, k1);
-    }
-    const uint16_t *a_s = sA[cur];
-    const uint16_t *b_s = sB[cur];
-    // fragments double-buffered in registers: the eight LDS reads of k step
-    // s + 1 are issued before the sixteen MFMAs of step s, so their latency
-    // hides behind the MFMA pipe instead of stalling it four times a step
-    // (scheduling barriers keep the compiler from sinking the reads back
-    // next to their uses to save registers)
-    bf16x8 fa[2][4], fb[2][4];
+  const __amdgpu_buffer_rsrc_t rsA =
+      __builtin_amdgcn_make_buffer_rsrc((void *)(A + m0 * K), 0, int(BM2 * K * 2), BUF_RSRC_DW3);
+  const __amdgpu_buffer_rsrc_t rsB =
+      __builtin_amdgcn_make_buffer_rsrc((void *)(Bt + n0 * K), 0, int(BN2 * K * 2), BUF_RSRC_DW3);
+  int voff[4];
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      fa[0][i] = *reinterpret_cast<const bf16x8 *>(a_s + (wm + 32 * i + frow) * LDS_ROW + fk);
-      fb[0][i] = *reinterpret_cast<const bf16x8 *>(b_s + (wn + 32 * i + frow) * LDS_ROW + fk);
-    }
-#pragma unroll
-    for (int s = 0; s < BK / 16; ++s) {
-      const int p = s & 1;
-      if (s + 1 < BK / 16) {
-        const int ks = (s + 1) * 16;
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-          fa[p ^ 1][i] =
-              *reinterpret_cast<const bf16x8 *>(a_s + (wm + 32 * i + frow) * LDS_ROW + ks + fk);
-          fb[p ^ 1][i] =
-              *reinterpret_cast<const bf16x8 *>(b_s + (wn + 32 * i + frow) * LDS_ROW + ks + fk);
-        }
-      }
-      __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-      for (int i = 0; i < 4; ++i)
-#pragma unroll
-        for (int j = 0; j < 4; ++j)
-          acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa[p][i], fb[p][j], acc[i][j], 0, 0, 0);
-      __builtin_amdgcn_sched_barrier(0);
-    }
-    if (kb + 1 < nk) {
-      r2s(sA[cur ^ 1], ra0);
-      r2s(sA[cur ^ 1] + 128 * LDS_ROW, ra1);
-      r2s(sB[cur ^ 1], rb0);
-      r2s(sB[cur ^ 1] + 128 * LDS_ROW, rb1);
-    }
-    __syncthreads();
+  for (int j = 0; j < 4; ++j) {
+    const int r = 8 * (wave + 8 * j) + (lane >> 3);  // wave instruction j fills rows 8G .. 8G + 7
+    voff[j] = (r * int(K) + ((lane & 7) ^ ((r >> 1) & 7)) * 8) * 2;
   }
+  auto fill = [&](__amdgpu_buffer_rsrc_t rs, uint16_t *stage, int kbyte) {
 #pragma unroll
-  for (int i = 0; i < 4; ++i)
+    for (int j = 0; j < 4; ++j)
+      __builtin_amdgcn_raw_ptr_buffer_load_lds(rs, (lds_void *)(stage + (wave + 8 * j) * 8 * ROW2),
+                                               16, voff[j], kbyte, 0, 0);
+  };
+  bf16x8 fa[2][2], fb[2][4];
+  auto frag = [&](bf16x8 *xa, bf16x8 *xb, const uint16_t *a_s, const uint16_t *b_s, int step) {
+    const int p = ((2 * step + half) ^ sw) * 8;
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+      xa[i] = *reinterpret_cast<const bf16x8 *>(a_s + (wm + 32 * i + frow) * ROW2 + p);
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+      xb[j] = *reinterpret_cast<const bf16x8 *>(b_s + (wn + 32 * j + frow) * ROW2 + p);
+  };
+
+  fill(rsA, sA0, 0);
+  fill(rsB, sB0, 0);
+  if (nk > 1) {
+    fill(rsA, sA1, BK * 2);
+    fill(rsB, sB1, BK * 2);
+  }
+  asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+  __syncthreads();
+  frag(fa[0], fb[0], sA0, sB0, 0);
+
+  for (int t = 0; t < nk; ++t) {
+    const int cur = t & 1;
+    uint16_t *a_s = cur ? sA1 : sA0, *b_s = cur ? sB1 : sB0;
+    const uint16_t *a_n = cur ? sA0 : sA1, *b_n = cur ? sB0 : sB1;
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      const int p = s & 1;
+      if (s < 3) {
+        frag(fa[p ^ 1], fb[p ^ 1], a_s, b_s, s + 1);
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+          for (int j = 0; j < 4; ++j)
+            acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa[p][i], fb[p][j], acc[i][j], 0, 0, 0);
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+          __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);         // one MFMA
+          if (q < 6) __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);  // one LDS read
+        }
+        __builtin_amdgcn_sched_barrier(0);
+      } else {
+        // this wave's loads of tile t + 1 must have landed before the barrier
+        // publishes them; the memory clobber also keeps every LDS read of
+        // tile t on this side of the barrier
+        asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+        __syncthreads();
+        frag(fa[p ^ 1], fb[p ^ 1], a_n, b_n, 0);  // on the last tile: unused reads of the idle stage
+        // stage `cur` is free now; past the end the loads repeat the last
+        // tile (in bounds) into it, which no one reads, so the block stays
+        // branch free for the interleaving below
+        const int kbyte = (t + 2 < nk ? t + 2 : nk - 1) * BK * 2;
+        fill(rsA, a_s, kbyte);
+        fill(rsB, b_s, kbyte);
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+          for (int j = 0; j < 4; ++j)
+            acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa[p][i], fb[p][j], acc[i][j], 0, 0, 0);
+        __builtin_amdgcn_sched_group_barrier(0x100, 6, 0);  // the six LDS reads first
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+          __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);  // one MFMA
+          __builtin_amdgcn_sched_group_barrier(0x020, 1, 0);  // one buffer load
+        }
+        __builtin_amdgcn_sched_barrier(0);
+      }
+    }
+  }
+  asm volatile("s_waitcnt vmcnt(0)" ::: "memory");  // no load may still target LDS at exit
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
 #pragma unroll
     for (int j = 0; j < 4; ++j)
 #pragma unroll
@@ -424,11 +471,13 @@ extern "C" int sched_gemm_bf16(const uint16_t *A, const uint16_t *Bt, float *C, 
   if (M <= 0 || N <= 0 || K <= 0 || !A || !Bt || !C) return SCHED_E_INVALID;
   if (M % BM || N % BN || K % BK) return SCHED_E_INVALID;
   if ((uintptr_t(A) | uintptr_t(Bt)) & 15) return SCHED_E_INVALID;
-  if (M % BM2 == 0 && N % BN2 == 0) {
+  // the 256-tile kernel addresses a 256-row operand panel with 32-bit buffer
+  // offsets: 256 * K * 2 bytes must stay below 2^31
+  if (M % BM2 == 0 && N % BN2 == 0 && K < (int64_t(1) << 22)) {
     const int64_t blocks = (M / BM2) * (N / BN2);
     if (blocks > 0x7fffffff) return SCHED_E_INVALID;
     SCHED_PROF_LAUNCH("k_gemm_bf16", (hipStream_t)st,
-                      (k_gemm_bf16_256<<<int(blocks), GT, 0, (hipStream_t)st>>>(A, Bt, C, M, N, K)));
+                      (k_gemm_bf16_256<<<int(blocks), GT2, 0, (hipStream_t)st>>>(A, Bt, C, M, N, K)));
     SCHED_HIP_TRY(hipGetLastError());
     return SCHED_OK;
   }

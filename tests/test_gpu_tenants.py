@@ -80,9 +80,11 @@ def test_gemm_operands_exact(cs):
 
 
 # 128-tile kernel: (128, 128, 64), (256, 384, 192); 256-tile kernel: the
-# others, (512, 768, 320) with the plain tile order and (2048, 2048, 128)
-# with the XCD-grouped one.
-@pytest.mark.parametrize("M,N,K", [(128, 128, 64), (256, 384, 192), (512, 768, 320),
+# others -- one k-tile (256, 256, 64), an odd count of k-tiles (512, 768, 320)
+# and (256, 512, 192), a single tile column (4096, 256, 576), all with the
+# plain tile order, and (2048, 2048, 128) with the XCD-grouped one.
+@pytest.mark.parametrize("M,N,K", [(128, 128, 64), (256, 384, 192), (256, 256, 64),
+                                   (256, 512, 192), (512, 768, 320), (4096, 256, 576),
                                    (1024, 1024, 1024), (2048, 2048, 128)])
 def test_gemm_full(cs, M, N, K):
     _, _, C = _gemm(cs, M, N, K)
