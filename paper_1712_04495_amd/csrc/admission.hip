@@ -163,37 +163,68 @@ __device__ __forceinline__ bool decide_window(const int64_t (&x)[WIN_ITEMS], con
   int s_loc = 0, lim = WIN;
   bool any_cand = false;
   for (;;) {
-    const int64_t cap = R + 1;
-    int64_t v[WIN_ITEMS], r[WIN_ITEMS];
-    int64_t run = 0;
-#pragma unroll
-    for (int k = 0; k < WIN_ITEMS; ++k) {
-      const bool cd = x[k] >= 0 && base + k >= s_loc && (!filter || x[k] <= R);
-      v[k] = cd ? (x[k] < cap ? x[k] : cap) : 0;
-      run += v[k];
-      r[k] = cd ? run : -1;  // -1 marks a non-candidate
-    }
-    const int64_t wincl = wave_incl_scan_dpp(run);
-    const int64_t ex = wave_prev_lane64(wincl);
-    const int64_t total = read_lane64(wincl, WAVE - 1);
-    if (!any_cand) {
-      bool mine = false;
-#pragma unroll
-      for (int k = 0; k < WIN_ITEMS; ++k) mine = mine || r[k] >= 0;
-      any_cand = __ballot(mine) != 0;
-    }
     int kb = WIN_ITEMS;      // this lane's break item
     int64_t before = 0;      // prefix just before it
-    uint32_t a = 0;
+    int64_t total;           // the window's candidate total (exact when no lane breaks)
+    uint32_t a = 0;          // this lane's items admitted by the round
+    bool mine = false;       // this lane holds a candidate
+    if (R < int64_t(0xffffffff)) {
+      // R + 1 fits in 32 bits: candidates are clamped to it and prefixes
+      // saturate at 2^32 - 1, which keeps every prefix up to R + 1 exact and
+      // every larger one above R -- all the round's tests need.  After a
+      // pass's first break R is below that break's demand, so this is the
+      // common case.
+      const uint32_t R32 = uint32_t(R), cap32 = R32 + 1;
+      uint32_t v[WIN_ITEMS], rex[WIN_ITEMS];
+      bool cd[WIN_ITEMS];
+      uint32_t run = 0;
 #pragma unroll
-    for (int k = WIN_ITEMS - 1; k >= 0; --k) {
-      const int64_t inc = ex + r[k];
-      if (r[k] >= 0 && inc > R) {
-        kb = k;
-        before = inc - v[k];
+      for (int k = 0; k < WIN_ITEMS; ++k) {
+        cd[k] = x[k] >= 0 && base + k >= s_loc && (!filter || x[k] <= R);
+        v[k] = cd[k] ? (x[k] < int64_t(cap32) ? uint32_t(x[k]) : cap32) : 0u;
+        rex[k] = run;
+        run = add_sat_u32(run, v[k]);
+        mine = mine || cd[k];
       }
-      if (r[k] >= 0 && inc <= R) a |= 1u << k;
+      const uint32_t wincl = wave_incl_scan_sat32_dpp(run);
+      const uint32_t ex = wave_prev_lane32(wincl);
+      total = int64_t(uint32_t(__builtin_amdgcn_readlane(int(wincl), WAVE - 1)));
+#pragma unroll
+      for (int k = WIN_ITEMS - 1; k >= 0; --k) {
+        const uint32_t exk = add_sat_u32(ex, rex[k]);
+        const uint32_t inc = add_sat_u32(exk, v[k]);
+        if (cd[k] && inc > R32) {
+          kb = k;
+          before = int64_t(exk);  // the break's exclusive prefix is <= R, hence exact
+        }
+        if (cd[k] && inc <= R32) a |= 1u << k;
+      }
+    } else {
+      const int64_t cap = R + 1;
+      int64_t v[WIN_ITEMS], r[WIN_ITEMS];
+      int64_t run = 0;
+#pragma unroll
+      for (int k = 0; k < WIN_ITEMS; ++k) {
+        const bool cd = x[k] >= 0 && base + k >= s_loc && (!filter || x[k] <= R);
+        v[k] = cd ? (x[k] < cap ? x[k] : cap) : 0;
+        run += v[k];
+        r[k] = cd ? run : -1;  // -1 marks a non-candidate
+        mine = mine || cd;
+      }
+      const int64_t wincl = wave_incl_scan_dpp(run);
+      const int64_t ex = wave_prev_lane64(wincl);
+      total = read_lane64(wincl, WAVE - 1);
+#pragma unroll
+      for (int k = WIN_ITEMS - 1; k >= 0; --k) {
+        const int64_t inc = ex + r[k];
+        if (r[k] >= 0 && inc > R) {
+          kb = k;
+          before = inc - v[k];
+        }
+        if (r[k] >= 0 && inc <= R) a |= 1u << k;
+      }
     }
+    if (!any_cand) any_cand = __ballot(mine) != 0;
     abits |= a;
     const uint64_t ball = __ballot(kb < WIN_ITEMS);
     int first = WIN;

@@ -115,6 +115,26 @@ __device__ __forceinline__ int64_t wave_incl_scan_dpp(int64_t v) {
   v += dpp_move64<0x143, 0xC>(v);  // row_bcast:31 into rows 2, 3
   return v;
 }
+// 32-bit unsigned variants: saturating add (v_add_u32 with clamp) and the
+// same DPP prefix steps.  A saturated prefix only ever stands for "more than
+// any bound below 2^32 - 1", so comparisons against such a bound stay exact.
+__device__ __forceinline__ uint32_t add_sat_u32(uint32_t a, uint32_t b) {
+  return __builtin_elementwise_add_sat(a, b);
+}
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ uint32_t dpp_move32(uint32_t v) {
+  return uint32_t(__builtin_amdgcn_update_dpp(0, int(v), CTRL, ROW_MASK, 0xF, true));
+}
+__device__ __forceinline__ uint32_t wave_incl_scan_sat32_dpp(uint32_t v) {
+  v = add_sat_u32(v, dpp_move32<0x111, 0xF>(v));  // row_shr:1
+  v = add_sat_u32(v, dpp_move32<0x112, 0xF>(v));  // row_shr:2
+  v = add_sat_u32(v, dpp_move32<0x114, 0xF>(v));  // row_shr:4
+  v = add_sat_u32(v, dpp_move32<0x118, 0xF>(v));  // row_shr:8
+  v = add_sat_u32(v, dpp_move32<0x142, 0xA>(v));  // row_bcast:15 into rows 1, 3
+  v = add_sat_u32(v, dpp_move32<0x143, 0xC>(v));  // row_bcast:31 into rows 2, 3
+  return v;
+}
+__device__ __forceinline__ uint32_t wave_prev_lane32(uint32_t v) { return dpp_move32<0x138, 0xF>(v); }
 // Value of the previous lane (0 for lane 0): wave_shr:1.
 __device__ __forceinline__ int64_t wave_prev_lane64(int64_t v) { return dpp_move64<0x138, 0xF>(v); }
 // Value of a uniform lane, read into scalar registers.
