@@ -488,7 +488,14 @@ def main():
             "kernels_ms": kern_s * 1e3, "round_launches_per_pass": launches / args.dense_reps,
             "window_launches_per_pass": launches_w / args.dense_reps, "window_limit": args.dense_window,
             "GBps_pass": bytes_pass / ddt / 1e9, "GBps_kernels": bytes_pass / kern_s / 1e9,
-            "frac_of_peak": bytes_pass / kern_s / 1e9 / HBM_PEAK_GBS, "fixed_point_ok": bool(ok)}
+            "frac_of_peak": bytes_pass / kern_s / 1e9 / HBM_PEAK_GBS,
+            # the grid round (the streaming scan kernel) alone: the single-wave
+            # window walk in front of it decides the first few thousand entries,
+            # so the round's bytes are those of the whole queue to < 0.1 %
+            "window_walk_ms": ms_w / args.dense_reps, "round_kernel_ms": ms / args.dense_reps,
+            "GBps_round_kernel": bytes_pass / (ms * 1e-3 / args.dense_reps) / 1e9,
+            "round_frac_of_peak": bytes_pass / (ms * 1e-3 / args.dense_reps) / 1e9 / HBM_PEAK_GBS,
+            "fixed_point_ok": bool(ok)}
         del dd, dec
 
     if "tenants" in extras:
