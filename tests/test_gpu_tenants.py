@@ -114,3 +114,46 @@ def test_tenant_bad_args(cs):
     assert cs.sched_gemm_bf16(x, x, c, 100, 128, 64) == cs.SCHED_E_INVALID
     k = torch.zeros(8, dtype=torch.int32, device=DEV)
     assert cs.sched_hist(k, torch.zeros(4096, dtype=torch.int32, device=DEV), 4096) == cs.SCHED_E_INVALID
+
+
+def _sparse_rows(n, K, offsets):
+    """k positions of the nonzero entries of each of n rows: for each offset
+    function f, column f(r) (all within [0, K))."""
+    return [sorted({f(r) % K for f in offsets}) for r in range(n)]
+
+
+@pytest.mark.parametrize("K", [(1 << 22) - 64, 1 << 22])
+def test_gemm_large_k_offsets(cs, K):
+    """The 256-tile kernel addresses a 256-row panel with 32-bit byte offsets
+    and takes K < 2^22; K = 2^22 - 64 puts its largest offsets within 0.4 % of
+    2^31, and K = 2^22 goes to the 128-tile kernel.  Sparse exact operands (1.0
+    in A, 2.0 in B) hit columns at the start, the middle and the last 64 of
+    every row; the product is a small integer, exact in fp32."""
+    M = N = 256
+    a_cols = _sparse_rows(M, K, [lambda r: r % 64, lambda r: K // 2 + (7 * r) % 64,
+                                 lambda r: K - 64 + r % 64])
+    b_cols = _sparse_rows(N, K, [lambda r: (3 * r) % 64, lambda r: K // 2 + (5 * r) % 64,
+                                 lambda r: K - 64 + r % 64])
+    A = torch.zeros(M * K, dtype=torch.int16, device=DEV)
+    B = torch.zeros(N * K, dtype=torch.int16, device=DEV)
+    ia = torch.tensor([r * K + k for r in range(M) for k in a_cols[r]], dtype=torch.int64)
+    ib = torch.tensor([r * K + k for r in range(N) for k in b_cols[r]], dtype=torch.int64)
+    A[ia.to(DEV)] = 0x3F80  # bf16 1.0
+    B[ib.to(DEV)] = 0x4000  # bf16 2.0
+    C = torch.full((M * N,), float("nan"), dtype=torch.float32, device=DEV)
+    assert cs.sched_gemm_bf16(A, B, C, M, N, K) == 0
+    torch.cuda.synchronize()
+    got = C.view(M, N).cpu().numpy().astype(np.float64)
+    del A, B, C
+    torch.cuda.empty_cache()
+    # reference: the dense product restricted to the columns that hold nonzeros
+    cols = sorted({k for r in a_cols for k in r} | {k for r in b_cols for k in r})
+    pos = {k: i for i, k in enumerate(cols)}
+    Ad = np.zeros((M, len(cols)))
+    Bd = np.zeros((N, len(cols)))
+    for r in range(M):
+        Ad[r, [pos[k] for k in a_cols[r]]] = 1.0
+    for r in range(N):
+        Bd[r, [pos[k] for k in b_cols[r]]] = 2.0
+    ref = Ad @ Bd.T
+    assert ref.max() > 0 and np.array_equal(got, ref)
