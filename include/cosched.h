@@ -168,7 +168,12 @@ int sched_release(sched_ctx_t *ctx, sched_job_t job, int32_t device, int64_t byt
 
 /* Returns the context to its state right after sched_create with every job
  * still registered: empty queue, no reservations, used = 0.  Slab blocks are
- * not touched (sched_slab_reset does that).  Synchronises. */
+ * not touched (sched_slab_reset does that).  Does not wait for the device:
+ * the reset kernels are ordered on the context's own stream.  Every later
+ * call sees the reset state: calls that work on that stream (the batched
+ * intake, passes and chains without a stream argument) follow it in stream
+ * order, and every other call -- or one given another stream -- first waits
+ * for the reset to finish. */
 int sched_reset(sched_ctx_t *ctx);
 
 /* Counters; see sched_stats_t. */

@@ -248,12 +248,25 @@ def sched_release_masked(ctx, d_mask, stream=None):
 
 def sched_pass_chain(ctx, rounds, d_masks=None, d_admitted=None, stream=None):
     """d_masks: uint8 device tensor [rounds - 1, n_mask] (or None)."""
+    rc, arr = sched_pass_chain_array(ctx, rounds, d_masks, d_admitted, stream)
+    return rc, [dict(zip(PASS_FIELDS, (int(v) for v in row))) for row in arr]
+
+
+# column order of sched_pass_chain_array's rows
+PASS_FIELDS = tuple(k for k, _ in sched_pass_result_t._fields_)
+
+
+def sched_pass_chain_array(ctx, rounds, d_masks=None, d_admitted=None, stream=None):
+    """As sched_pass_chain, with the results as one int64 array of shape
+    [rounds, len(PASS_FIELDS)] (columns in PASS_FIELDS order)."""
+    import numpy as np
     n_mask = 0 if d_masks is None else int(d_masks.shape[-1])
-    res = (sched_pass_result_t * rounds)()
+    res = np.zeros((rounds, len(PASS_FIELDS)), dtype=np.int64)
     cap = 0 if d_admitted is None else int(d_admitted.numel())
-    rc = lib().sched_pass_chain(ctx, rounds, _ptr(d_masks), n_mask, _stream(stream), res,
+    rc = lib().sched_pass_chain(ctx, rounds, _ptr(d_masks), n_mask, _stream(stream),
+                                res.ctypes.data,
                                 _ptr(d_admitted), cap)
-    return rc, [{k: getattr(r, k) for k, _ in sched_pass_result_t._fields_} for r in res]
+    return rc, res
 
 
 # ---------------------------------------------------------- stateless scan

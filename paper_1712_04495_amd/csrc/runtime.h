@@ -19,6 +19,9 @@ struct sched_ctx {
   int policy = SCHED_POLICY_MMU;
   int window_limit = 16;
   bool closing = false;
+  // sched_reset only orders its kernels on `stream`; until something waits for
+  // them, calls that could observe the state by another route settle first
+  bool reset_pending = false;
   hipStream_t stream = nullptr;
 
   schedk::AdmEngine eng;
@@ -55,6 +58,8 @@ struct sched_ctx {
 };
 
 int sched_run_pass_locked(sched_ctx *c, hipStream_t s, sched_pass_result_t *res);
+// Waits for a reset still in flight on the context stream (mutex held).
+int sched_settle_reset_locked(sched_ctx *c);
 int sched_priority_reorder_locked(sched_ctx *c, hipStream_t s);
 
 int sched_slab_init(sched_ctx *c, int64_t pool_bytes, int32_t n_tenants);

@@ -199,6 +199,7 @@ extern "C" int sched_register(sched_ctx_t *c, int32_t priority, int32_t timeout_
                               sched_job_t *out_job) {
   if (!c || !out_job) return SCHED_E_INVALID;
   std::lock_guard<std::mutex> g(c->mu);
+  if (int rc = sched_settle_reset_locked(c)) return rc;
   return register_locked(c, 1, priority, timeout_ms, out_job);
 }
 
@@ -206,6 +207,7 @@ extern "C" int sched_register_batch(sched_ctx_t *c, int32_t n, int32_t priority,
                                     int32_t timeout_ms, sched_job_t *out_first) {
   if (!c || !out_first) return SCHED_E_INVALID;
   std::lock_guard<std::mutex> g(c->mu);
+  if (int rc = sched_settle_reset_locked(c)) return rc;
   return register_locked(c, n, priority, timeout_ms, out_first);
 }
 
@@ -319,6 +321,7 @@ extern "C" int sched_admit(sched_ctx_t *c, sched_job_t job, int32_t device, int6
                            uint32_t flags) {
   if (!c) return SCHED_E_INVALID;
   std::unique_lock<std::mutex> lk(c->mu);
+  if (int rc = sched_settle_reset_locked(c)) return rc;
   if (job < 0 || job >= c->n_jobs || device != c->device || bytes <= 0) return SCHED_E_INVALID;
   if (bytes > c->capacity) return SCHED_E_TOOBIG;
   if (c->tail_h - c->head_h + 1 > c->q.capacity) return SCHED_E_NOMEM;
@@ -351,6 +354,7 @@ extern "C" int sched_admit(sched_ctx_t *c, sched_job_t job, int32_t device, int6
 extern "C" int sched_wait(sched_ctx_t *c, sched_job_t job, int32_t timeout_ms) {
   if (!c) return SCHED_E_INVALID;
   std::unique_lock<std::mutex> lk(c->mu);
+  if (int rc = sched_settle_reset_locked(c)) return rc;
   if (job < 0 || job >= c->n_jobs) return SCHED_E_INVALID;
   return wait_locked(c, lk, job, timeout_ms);
 }
@@ -366,6 +370,7 @@ static int read_res(sched_ctx *c, sched_job_t job, int64_t *v) {
 extern "C" int sched_release(sched_ctx_t *c, sched_job_t job, int32_t device, int64_t bytes) {
   if (!c) return SCHED_E_INVALID;
   std::lock_guard<std::mutex> g(c->mu);
+  if (int rc = sched_settle_reset_locked(c)) return rc;
   if (job < 0 || job >= c->n_jobs || bytes < 0) return SCHED_E_INVALID;
   if (device >= 0 && device != c->device) return SCHED_E_INVALID;
   SCHED_HIP_TRY(hipSetDevice(c->device));
@@ -384,6 +389,7 @@ extern "C" int sched_release(sched_ctx_t *c, sched_job_t job, int32_t device, in
 extern "C" int sched_reservation(sched_ctx_t *c, sched_job_t job, int64_t *out) {
   if (!c || !out) return SCHED_E_INVALID;
   std::lock_guard<std::mutex> g(c->mu);
+  if (int rc = sched_settle_reset_locked(c)) return rc;
   if (job < 0 || job >= c->n_jobs) return SCHED_E_INVALID;
   SCHED_HIP_TRY(hipSetDevice(c->device));
   return read_res(c, job, out);
@@ -392,6 +398,7 @@ extern "C" int sched_reservation(sched_ctx_t *c, sched_job_t job, int64_t *out) 
 extern "C" int sched_stats(sched_ctx_t *c, sched_stats_t *out) {
   if (!c || !out) return SCHED_E_INVALID;
   std::lock_guard<std::mutex> g(c->mu);
+  if (int rc = sched_settle_reset_locked(c)) return rc;
   SCHED_HIP_TRY(hipSetDevice(c->device));
   SCHED_HIP_TRY(hipMemcpyAsync(c->eng.h_ctl, c->eng.d_ctl, sizeof(DevCtl), hipMemcpyDeviceToHost,
                                c->stream));
@@ -424,6 +431,19 @@ extern "C" int sched_stats(sched_ctx_t *c, sched_stats_t *out) {
 static hipStream_t pick(sched_ctx *c, sched_stream_t s) {
   return s ? (hipStream_t)s : c->stream;
 }
+int sched_settle_reset_locked(sched_ctx *c) {
+  if (c->reset_pending) {
+    SCHED_HIP_TRY(hipStreamSynchronize(c->stream));
+    c->reset_pending = false;
+  }
+  return SCHED_OK;
+}
+// The caller's stream, ordered after a pending reset: work on the context
+// stream follows it in stream order, work elsewhere waits for it.
+static int pick_ordered(sched_ctx *c, sched_stream_t s, hipStream_t *out) {
+  *out = pick(c, s);
+  return *out == c->stream ? SCHED_OK : sched_settle_reset_locked(c);
+}
 
 extern "C" int sched_enqueue_batch(sched_ctx_t *c, int64_t n, const int32_t *d_job,
                                    const int64_t *d_demand, sched_stream_t stream) {
@@ -432,11 +452,13 @@ extern "C" int sched_enqueue_batch(sched_ctx_t *c, int64_t n, const int32_t *d_j
   if (n == 0) return SCHED_OK;
   if (c->tail_h - c->head_h + n > c->q.capacity) return SCHED_E_INVALID;
   SCHED_HIP_TRY(hipSetDevice(c->device));
-  hipStream_t s = pick(c, stream);
+  hipStream_t s;
+  if (int rc = pick_ordered(c, stream, &s)) return rc;
   int64_t n_bad = 0;
   if (int rc = adm_enqueue_checked(c->eng, c->q, c->tail_h, n, d_job, d_demand, c->d_prio_of_job,
                                    c->seq_next, c->n_jobs, c->capacity, s, &n_bad))
     return rc;
+  if (s == c->stream) c->reset_pending = false;  // the intake synchronised the stream
   if (n_bad) return SCHED_E_INVALID;
   c->seq_next += n;
   c->tail_h += n;
@@ -448,7 +470,9 @@ extern "C" int sched_pass(sched_ctx_t *c, sched_stream_t stream, sched_pass_resu
   std::lock_guard<std::mutex> g(c->mu);
   SCHED_HIP_TRY(hipSetDevice(c->device));
   sched_pass_result_t r{};
-  if (int rc = sched_run_pass_locked(c, pick(c, stream), &r)) return rc;
+  hipStream_t s;
+  if (int rc = pick_ordered(c, stream, &s)) return rc;
+  if (int rc = sched_run_pass_locked(c, s, &r)) return rc;
   if (out) *out = r;
   return SCHED_OK;
 }
@@ -459,9 +483,11 @@ extern "C" int sched_last_admitted(sched_ctx_t *c, int32_t *d_out, int64_t cap, 
   std::lock_guard<std::mutex> g(c->mu);
   SCHED_HIP_TRY(hipSetDevice(c->device));
   const int64_t n = std::min<int64_t>(cap, c->last_A);
+  hipStream_t s;
+  if (int rc = pick_ordered(c, stream, &s)) return rc;
   if (n > 0)
     SCHED_HIP_TRY(hipMemcpyAsync(d_out, c->q.adm_job + c->last_adm_off, sizeof(int32_t) * n,
-                                 hipMemcpyDeviceToDevice, pick(c, stream)));
+                                 hipMemcpyDeviceToDevice, s));
   *out_n = c->last_A;
   return SCHED_OK;
 }
@@ -476,7 +502,8 @@ extern "C" int sched_pass_chain(sched_ctx_t *c, int32_t rounds, const uint8_t *d
   if (n_mask > c->n_jobs || !c->host_seq.empty()) return SCHED_E_INVALID;
   if (c->policy != SCHED_POLICY_FIFO && c->policy != SCHED_POLICY_MMU) return SCHED_E_INVALID;
   SCHED_HIP_TRY(hipSetDevice(c->device));
-  hipStream_t s = pick(c, stream);
+  hipStream_t s;
+  if (int rc = pick_ordered(c, stream, &s)) return rc;
   if (int rc = adm_chain(c->eng, c->policy, c->q, c->jb, rounds, d_masks, n_mask, c->d_run_list, s))
     return rc;
   int64_t head_before = c->head_h, total = 0;
@@ -503,6 +530,7 @@ extern "C" int sched_pass_chain(sched_ctx_t *c, int32_t rounds, const uint8_t *d
     c->stats.rounds += h.rounds;
     c->stats.admitted += h.admitted;
   }
+  if (s == c->stream) c->reset_pending = false;  // the chain synchronised the stream
   const PassSummary &last = c->eng.h_sum[rounds - 1];
   c->head_h = last.head;
   c->tail_h = last.tail;
@@ -521,7 +549,9 @@ extern "C" int sched_release_masked(sched_ctx_t *c, const uint8_t *d_mask, int64
   std::lock_guard<std::mutex> g(c->mu);
   if (n > c->n_jobs) return SCHED_E_INVALID;
   SCHED_HIP_TRY(hipSetDevice(c->device));
-  return adm_release_masked(c->eng, c->jb, d_mask, n, pick(c, stream));
+  hipStream_t s;
+  if (int rc = pick_ordered(c, stream, &s)) return rc;
+  return adm_release_masked(c->eng, c->jb, d_mask, n, s);
 }
 
 // ---------------------------------------------------------------------------
@@ -598,7 +628,7 @@ extern "C" int sched_reset(sched_ctx_t *c) {
   k_reset_jobs<<<256, 256, 0, c->stream>>>(c->eng.d_ctl, c->jb);
   SCHED_HIP_TRY(hipGetLastError());
   if (int rc = adm_zero_decisions(c->q.decision, c->q.capacity, c->stream)) return rc;
-  SCHED_HIP_TRY(hipStreamSynchronize(c->stream));
+  c->reset_pending = true;
   // pending[j] counts the host-side waiting requests of job j, which are
   // exactly the entries of host_seq naming j
   for (const auto &kv : c->host_seq) c->pending[kv.second] = 0;

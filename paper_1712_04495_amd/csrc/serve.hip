@@ -665,6 +665,7 @@ extern "C" int sched_serve(sched_ctx_t *c, int64_t n, const sched_job_desc_t *jo
                            sched_serve_summary_t *summary) {
   if (!c || n < 0 || (n > 0 && (!jobs || !results)) || !opts) return SCHED_E_INVALID;
   std::unique_lock<std::mutex> lk(c->mu);
+  if (int rc = sched_settle_reset_locked(c)) return rc;
   if (n > c->jb.max_jobs) return SCHED_E_INVALID;
   for (int64_t i = 0; i < n; ++i)
     if (jobs[i].demand <= 0 || jobs[i].kind < 0 || jobs[i].kind > SCHED_JOB_HIST ||

@@ -524,6 +524,7 @@ static int slab_charge_locked(sched_ctx *c, int32_t t, int64_t v, int8_t *st) {
 extern "C" int sched_alloc(sched_ctx_t *c, sched_job_t job, size_t bytes, void **dev_ptr) {
   if (!c || !dev_ptr) return SCHED_E_INVALID;
   std::lock_guard<std::mutex> g(c->mu);
+  if (int rc = sched_settle_reset_locked(c)) return rc;
   if (!c->slab || job < 0 || job >= c->n_jobs || job >= c->slab->dev.n_tenants || bytes == 0)
     return SCHED_E_INVALID;
   SCHED_HIP_TRY(hipSetDevice(c->device));
@@ -559,6 +560,7 @@ extern "C" int sched_alloc(sched_ctx_t *c, sched_job_t job, size_t bytes, void *
 extern "C" int sched_free(sched_ctx_t *c, sched_job_t job, void *dev_ptr) {
   if (!c) return SCHED_E_INVALID;
   std::lock_guard<std::mutex> g(c->mu);
+  if (int rc = sched_settle_reset_locked(c)) return rc;
   if (!c->slab || job < 0 || job >= c->n_jobs || job >= c->slab->dev.n_tenants || !dev_ptr)
     return SCHED_E_INVALID;
   SCHED_HIP_TRY(hipSetDevice(c->device));
@@ -585,6 +587,7 @@ extern "C" int sched_free(sched_ctx_t *c, sched_job_t job, void *dev_ptr) {
 extern "C" int sched_slab_set_quotas(sched_ctx_t *c, int32_t n, const int64_t *h_quotas) {
   if (!c || n < 0 || (n > 0 && !h_quotas)) return SCHED_E_INVALID;
   std::lock_guard<std::mutex> g(c->mu);
+  if (int rc = sched_settle_reset_locked(c)) return rc;
   if (!c->slab || n > c->slab->dev.n_tenants) return SCHED_E_INVALID;
   for (int32_t i = 0; i < n; ++i)
     if (h_quotas[i] < 0) return SCHED_E_INVALID;
@@ -607,6 +610,7 @@ extern "C" int sched_slab_ops(sched_ctx_t *c, int64_t begin, int64_t end, const 
   if (end > begin && (!d_kind || !d_tenant || !d_size || !d_ref || !d_ptr || !d_status))
     return SCHED_E_INVALID;
   std::lock_guard<std::mutex> g(c->mu);
+  if (int rc = sched_settle_reset_locked(c)) return rc;
   if (!c->slab) return SCHED_E_INVALID;
   if (end == begin) return SCHED_OK;
   SCHED_HIP_TRY(hipSetDevice(c->device));
@@ -632,6 +636,7 @@ extern "C" int sched_slab_ops(sched_ctx_t *c, int64_t begin, int64_t end, const 
 extern "C" int sched_slab_info(sched_ctx_t *c, sched_slab_info_t *out) {
   if (!c || !out) return SCHED_E_INVALID;
   std::lock_guard<std::mutex> g(c->mu);
+  if (int rc = sched_settle_reset_locked(c)) return rc;
   if (!c->slab) return SCHED_E_INVALID;
   const SlabDev &d = c->slab->dev;
   sched_slab_info_t r{};
@@ -649,6 +654,7 @@ extern "C" int sched_slab_counters(sched_ctx_t *c, int32_t n, int64_t *h_charged
                                    int64_t *h_pool_used) {
   if (!c || n < 0 || (n > 0 && !h_charged) || !h_pool_used) return SCHED_E_INVALID;
   std::lock_guard<std::mutex> g(c->mu);
+  if (int rc = sched_settle_reset_locked(c)) return rc;
   if (!c->slab || n > c->slab->dev.n_tenants) return SCHED_E_INVALID;
   SCHED_HIP_TRY(hipSetDevice(c->device));
   if (c->slab->phase_recorded) SCHED_HIP_TRY(hipEventSynchronize(c->slab->last_phase));
@@ -661,6 +667,7 @@ extern "C" int sched_slab_counters(sched_ctx_t *c, int32_t n, int64_t *h_charged
 extern "C" int sched_slab_reset(sched_ctx_t *c) {
   if (!c) return SCHED_E_INVALID;
   std::lock_guard<std::mutex> g(c->mu);
+  if (int rc = sched_settle_reset_locked(c)) return rc;
   if (!c->slab) return SCHED_E_INVALID;
   SCHED_HIP_TRY(hipSetDevice(c->device));
   SlabState *s = c->slab;
