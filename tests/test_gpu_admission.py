@@ -373,3 +373,50 @@ def test_lifecycle_errors_and_timeout(cs):
         assert cs.sched_reservation(ctx, b) == (0, 200)
     finally:
         cs.sched_destroy(ctx)
+
+
+def test_ctx_reset_then_other_stream_and_host_reads(cs):
+    """sched_reset only orders its kernels on the context stream: a chain run
+    on another stream right after it, and host-side reads (stats, a
+    reservation), must still see the reset state; the array form of the chain
+    results equals the per-round dictionaries."""
+    q = c2_queue(seed=5, n=1 << 14, capacity=2 * 10**11)
+    n = q.demand.size
+    rc, ctx = cs.sched_create(policy=1, capacity_bytes=q.capacity, max_jobs=n,
+                              queue_capacity=n, window_limit=16)
+    assert rc == 0
+    try:
+        assert cs.sched_register_batch(ctx, n)[0] == 0
+        d_job = torch.arange(n, dtype=torch.int32, device=DEV)
+        d_dem = torch.from_numpy(q.demand).to(DEV)
+        coins = torch.from_numpy(q.coins).to(DEV)
+        ref = S.release_rounds(q.demand, q.capacity, q.coins, q.rounds, S.MMU)
+        # leave the context busy, then reset and read it from the host at once
+        assert cs.sched_enqueue_batch(ctx, d_job, d_dem) == 0
+        rc, _ = cs.sched_pass_chain(ctx, q.rounds, coins)
+        assert rc == 0
+        assert cs.sched_reset(ctx) == 0
+        rc, st = cs.sched_stats(ctx)
+        assert rc == 0 and st["used"] == 0
+        rc, v = cs.sched_reservation(ctx, int(ref[0].admitted[0]))
+        assert rc == 0 and v == 0
+        # reset again, then intake and chain on a stream of the caller's
+        assert cs.sched_reset(ctx) == 0
+        side = torch.cuda.Stream()
+        assert cs.sched_enqueue_batch(ctx, d_job, d_dem, stream=side) == 0
+        rc, arr = cs.sched_pass_chain_array(ctx, q.rounds, coins, stream=side)
+        assert rc == 0
+        col = {k: i for i, k in enumerate(cs.PASS_FIELDS)}
+        for r, rr in enumerate(ref):
+            assert arr[r, col["admitted"]] == rr.admitted.size, f"round {r}"
+            assert arr[r, col["free_after"]] == rr.R_after, f"round {r}"
+            assert arr[r, col["released"]] == rr.released.size, f"round {r}"
+        # and once more through the dictionary form, on the context stream
+        assert cs.sched_reset(ctx) == 0
+        assert cs.sched_enqueue_batch(ctx, d_job, d_dem) == 0
+        rc, res = cs.sched_pass_chain(ctx, q.rounds, coins)
+        assert rc == 0
+        for r, pr in enumerate(res):
+            assert [pr[k] for k in cs.PASS_FIELDS] == [int(v) for v in arr[r]], f"round {r}"
+    finally:
+        cs.sched_destroy(ctx)
