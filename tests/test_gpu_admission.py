@@ -420,3 +420,36 @@ def test_ctx_reset_then_other_stream_and_host_reads(cs):
             assert [pr[k] for k in cs.PASS_FIELDS] == [int(v) for v in arr[r]], f"round {r}"
     finally:
         cs.sched_destroy(ctx)
+
+
+def test_enqueue_batch_alignment_and_wrap(cs):
+    """Batched intake at ring positions that are and are not multiples of 4,
+    across the ring's end, and from an input that is not 16-B aligned: each
+    pass admits the batch exactly as the oracle does."""
+    C, n_jobs = 10**9, 64
+    rng = np.random.default_rng(9)
+    rc, ctx = cs.sched_create(policy=cs.SCHED_POLICY_MMU, capacity_bytes=C, max_jobs=n_jobs,
+                              queue_capacity=1024)
+    assert rc == 0
+    try:
+        assert cs.sched_register_batch(ctx, n_jobs)[0] == 0
+        used = 0
+        for k, offset in ((5, 0), (1003, 0), (3, 0), (257, 0), (1000, 0), (6, 1), (401, 1)):
+            j = rng.integers(0, n_jobs, k + offset).astype(np.int32)
+            d = rng.integers(1, 100, k + offset).astype(np.int64)
+            dj = torch.from_numpy(j).to(DEV)[offset:]   # offset 1: a 4-B shifted view
+            dd = torch.from_numpy(d).to(DEV)[offset:]
+            assert cs.sched_enqueue_batch(ctx, dj, dd) == 0
+            rc, res = cs.sched_pass(ctx)
+            assert rc == 0
+            admit, R2 = S.mmu_pass(d[offset:], C - used)
+            assert admit.all() and res["admitted"] == k and res["free_after"] == R2
+            used += int(d[offset:].sum())
+            out = torch.full((k,), -1, dtype=torch.int32, device=DEV)
+            rc, n = cs.sched_last_admitted(ctx, out)
+            assert rc == 0 and n == k
+            assert np.array_equal(out.cpu().numpy(), j[offset:]), (k, offset)
+        rc, st = cs.sched_stats(ctx)
+        assert rc == 0 and st["used"] == used and st["pending"] == 0
+    finally:
+        cs.sched_destroy(ctx)
