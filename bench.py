@@ -122,6 +122,11 @@ def cosched_run(cs, name, n_jobs, dev_free, n_streams=3):
         cs.sched_destroy(ctx)
     out["speedup_vs_serial"] = (out["coscheduled"]["jobs_per_s"] /
                                 max(out["serial"]["jobs_per_s"], 1e-12))
+    # what removing the serial run's idle time alone could give: its makespan
+    # over the time the device had a job kernel running; beyond it, the gain
+    # comes from jobs that leave the device partly idle running side by side
+    out["serial_idle_ceiling"] = (out["serial"]["makespan_s"] /
+                                  max(out["serial"]["dev_busy_s"], 1e-12))
     return out
 
 
@@ -170,7 +175,7 @@ def tenant_measure(cs, torch, dev):
     """Event-timed tenant kernels against their roofline: triad and histogram
     against HBM, GEMM against dense bf16 MFMA."""
     out = {}
-    n = 1 << 28                                    # 1 GiB per fp32 array
+    n = 1 << 29                                    # 2 GiB per fp32 array, 6 GiB in all
     b = torch.empty(n, dtype=torch.float32, device=dev)
     c = torch.empty_like(b)
     a = torch.empty_like(b)
@@ -271,8 +276,21 @@ def cpu_baseline_c2(q, seconds):
             break
     dt = time.perf_counter() - t0
     return {"value": admitted / dt, "unit": "admissions/s", "cores": 1, "kind": "oracle",
+            "cpu": cpu_model(),
             "sample": f"{steps} full steps (8 release/admit passes over 2^{q.n.bit_length() - 1} "
                       f"requests) in {dt:.1f} s, pure numpy/Python, one thread"}, per_pass
+
+
+def cpu_model():
+    """The host CPU's model name (from /proc/cpuinfo), for the oracle timing."""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
@@ -512,6 +530,15 @@ def main():
 
     if "tenants" in extras:
         out["tenants"] = tenant_measure(cs, torch, dev)
+        # the triad over 6 GiB is the achievable-bandwidth reference: every
+        # HBM-bound figure is also reported as a fraction of it
+        ach = out["tenants"]["triad"]["GBps"]
+        out["hbm_achieved_GBps"] = ach
+        out["tenants"]["hist"]["frac_of_achieved"] = out["tenants"]["hist"]["GBps"] / ach
+        if "dense_scan" in out:
+            ds = out["dense_scan"]
+            ds["frac_of_achieved"] = ds["GBps_kernels"] / ach
+            ds["round_frac_of_achieved"] = ds["GBps_round_kernel"] / ach
         print(f"[bench] tenants: {json.dumps(out['tenants'])}", file=sys.stderr, flush=True)
     if "slab" in extras:
         out["slab"] = slab_measure(cs, torch, dev)
