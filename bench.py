@@ -60,8 +60,9 @@ def parse():
     ap.add_argument("--extras", default="dense,tenants,slab",
                     help="measurements to add after the admission steps (dense, tenants, "
                          "slab; empty = none)")
-    ap.add_argument("--cosched", default="c1,c5",
-                    help="co-scheduled vs serial runs to add (c1, c4, c5; empty = none)")
+    ap.add_argument("--cosched", default="c1,c5,hol",
+                    help="co-scheduled vs serial runs to add (c1, c4, c5; hol = the "
+                         "head-of-line study, FIFO vs MMU; empty = none)")
     ap.add_argument("--cosched-streams", type=int, default=3,
                     help="HIP streams for single-job launches in the co-scheduled runs (with "
                          "more streams than the process's hardware queues, the scheduler's "
@@ -127,6 +128,51 @@ def cosched_run(cs, name, n_jobs, dev_free, n_streams=3):
     # comes from jobs that leave the device partly idle running side by side
     out["serial_idle_ceiling"] = (out["serial"]["makespan_s"] /
                                   max(out["serial"]["dev_busy_s"], 1e-12))
+    return out
+
+
+def nearest_rank(x, p):
+    """p-th percentile by nearest rank: sorted[ceil(p n / 100) - 1]."""
+    import numpy as np
+    x = np.sort(np.asarray(x, dtype=np.float64))
+    if x.size == 0:
+        return float("nan")
+    return float(x[max(int(np.ceil(p * x.size / 100.0)) - 1, 0)])
+
+
+def hol_run(cs, n_streams=3):
+    """Head-of-line study: the HOL mix served in real time under FIFO and MMU
+    (co-scheduled), with the small jobs' and the blocker's waits."""
+    import numpy as np
+    from workloads import HOL_BLOCKER, HOL_SMALL, hol_jobs, job_table
+    mix = hol_jobs()
+    jt = job_table(mix)
+    cls = mix.extra["cls"]
+    out = {"jobs": mix.n, "capacity_bytes": int(mix.capacity),
+           "shape": "20 GiB triad at 0, 16 GiB blocker at 1 ms, 200 triads of 64-256 MiB "
+                    "from 2 ms at 1000/s"}
+    for label, policy in (("fifo", cs.SCHED_POLICY_FIFO), ("mmu", cs.SCHED_POLICY_MMU)):
+        print(f"[bench] hol {label}: {mix.n} jobs", file=sys.stderr, flush=True)
+        rc, ctx = cs.sched_create(policy=policy, capacity_bytes=mix.capacity, max_jobs=mix.n,
+                                  queue_capacity=4096, window_limit=16)
+        assert rc == 0, rc
+        try:
+            rc, res, sm = cs.sched_serve(ctx, jt, n_streams=n_streams, use_graph=1)
+            assert rc == 0, rc
+        finally:
+            cs.sched_destroy(ctx)
+        wait = res["t_admit"] - res["t_arrive"]
+        small = cls == HOL_SMALL
+        blk = int(np.flatnonzero(cls == HOL_BLOCKER)[0])
+        out[label] = {"jobs_per_s": sm["jobs_per_s"], "makespan_s": sm["makespan_s"],
+                      "small_p50_wait_s": nearest_rank(wait[small], 50),
+                      "small_p99_wait_s": nearest_rank(wait[small], 99),
+                      "blocker_wait_s": float(wait[blk]),
+                      "small_admitted_before_blocker":
+                          int((res["t_admit"][small] < res["t_admit"][blk]).sum()),
+                      "completed": sm["completed"], "violations": sm["violations"]}
+    out["small_p99_wait_fifo_over_mmu"] = (out["fifo"]["small_p99_wait_s"] /
+                                           max(out["mmu"]["small_p99_wait_s"], 1e-9))
     return out
 
 
@@ -549,9 +595,12 @@ def main():
         free, _ = torch.cuda.mem_get_info()
         out["coschedule"] = {}
         for name in [x for x in args.cosched.split(",") if x]:
-            out["coschedule"][name] = cosched_run(cs, name,
-                                                  args.c5_jobs if name == "c5" else args.c4_jobs,
-                                                  int(free), args.cosched_streams)
+            if name == "hol":
+                out["coschedule"][name] = hol_run(cs, args.cosched_streams)
+            else:
+                out["coschedule"][name] = cosched_run(cs, name,
+                                                      args.c5_jobs if name == "c5" else args.c4_jobs,
+                                                      int(free), args.cosched_streams)
             print(f"[bench] {name}: {json.dumps(out['coschedule'][name])}", file=sys.stderr,
                   flush=True)
 

@@ -399,7 +399,12 @@ typedef struct {
 
 typedef struct {
   int32_t mode;        /* SCHED_SERVE_REALTIME / SCHED_SERVE_VIRTUAL           */
-  int32_t n_streams;   /* stream pool for single-job launches                 */
+  int32_t n_streams;   /* stream pool for single-job launches; without
+                          batching capped at the hardware queues
+                          (GPU_MAX_HW_QUEUES, default 4) left after the
+                          control stream and one queue for the runtime's own
+                          work; each job goes to the stream with the least
+                          nominal work still in flight                        */
   int32_t serial;      /* 1: every demand := capacity (exclusive execution)   */
   int32_t batch_small; /* 1: persistent batched launch for small triads        */
   int64_t small_bytes; /* demand threshold for batching                       */

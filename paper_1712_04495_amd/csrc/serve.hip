@@ -19,6 +19,7 @@
 //    with a CPU replay.
 #include <algorithm>
 #include <chrono>
+#include <cstdlib>
 #include <cmath>
 #include <deque>
 #include <iterator>
@@ -213,10 +214,23 @@ struct Serve {
 
   int init() {
     stream_ctl = c->stream;
-    const int ns = std::max(1, o.n_streams);
+    // HIP spreads a process's streams over its hardware queues
+    // (GPU_MAX_HW_QUEUES, 4 by default) round robin in creation order.  A job
+    // stream that shares the control stream's queue makes every admission pass
+    // wait in order behind job kernels: on the head-of-line mix, three job
+    // streams beside the control stream made a pass take ~0.5 ms instead of
+    // ~0.1 ms.  Without batching, job streams are therefore capped at the
+    // queues left after the control stream and one for the runtime's own
+    // (null-stream) work.  Batching serves oversubscribed throughput runs,
+    // where more job streams pay off despite slower passes (C5: ~25 K jobs/s
+    // with three job streams, ~22 K with two), so there the request stands.
+    const bool batching = o.batch_small && !o.serial;
+    int hw_queues = 4;
+    if (const char *q = getenv("GPU_MAX_HW_QUEUES")) hw_queues = std::max(1, atoi(q));
+    const int ns = std::max(1, batching ? o.n_streams : std::min(o.n_streams, hw_queues - 2));
+    if (batching) SCHED_HIP_TRY(hipStreamCreate(&bstream));
     streams.resize(ns);
     for (auto &s : streams) SCHED_HIP_TRY(hipStreamCreate(&s));
-    SCHED_HIP_TRY(hipStreamCreate(&bstream));
     inflight.resize(ns + 1);
     if (o.mode == SCHED_SERVE_REALTIME) {
       arena.size = uint64_t(rup(c->capacity, 4096));
@@ -427,10 +441,34 @@ struct Serve {
     return SCHED_OK;
   }
 
+  // The job stream with the least expected backlog: the sum of the nominal
+  // durations of the jobs still in flight on it (ties in round-robin order).
+  // Streams run their jobs in order, so a short job placed behind a long one
+  // would hold its reservation until the long one ends.
+  size_t pick_stream() const {
+    size_t best = next_stream % streams.size();
+    double best_load = backlog(best);
+    for (size_t k = 1; k < streams.size(); ++k) {
+      const size_t si = (next_stream + k) % streams.size();
+      const double l = backlog(si);
+      if (l < best_load) {
+        best = si;
+        best_load = l;
+      }
+    }
+    return best;
+  }
+  double backlog(size_t si) const {
+    double t = 0.0;
+    for (const Running &r : inflight[si])
+      if (r.job >= 0) t += J[r.job].vdur_s;
+    return t;
+  }
+
   // Launches admitted job j, or defers it while no contiguous range fits.
   int start_single(int32_t j) {
     Running r{};
-    const size_t si = next_stream % streams.size();
+    const size_t si = pick_stream();
     const int rc = launch_single(j, streams[si], &r);
     if (rc == SCHED_NOT_READY) {
       deferred.push_back(j);
@@ -449,7 +487,7 @@ struct Serve {
     while (!deferred.empty()) {
       const int32_t j = deferred.front();
       Running r{};
-      const size_t si = next_stream % streams.size();
+      const size_t si = pick_stream();
       const int rc = launch_single(j, streams[si], &r);
       if (rc == SCHED_NOT_READY) break;
       if (rc) return rc;

@@ -78,6 +78,19 @@ def test_virtual_priority_equals_oracle(cs, policy):
     assert np.array_equal(res["t_end"][ok], ref["t_end"][ok])
 
 
+@pytest.mark.parametrize("policy", [0, 1])
+def test_virtual_hol_equals_oracle(cs, policy):
+    """The head-of-line study (a 16 GiB request that cannot fit beside a
+    20 GiB job, then 200 small jobs): the device loop's schedule equals the
+    oracle's entry by entry under FIFO and MMU."""
+    from workloads import hol_jobs
+    mix = hol_jobs()
+    res, sm, ref = _virtual(cs, mix, policy)
+    assert np.array_equal(res["t_admit"], ref["t_admit"])
+    assert np.array_equal(res["t_end"], ref["t_end"])
+    assert sm["completed"] == mix.n and sm["violations"] == 0
+
+
 def test_virtual_c5_prefix_equals_oracle(cs):
     mix = c5_jobs(5, n=3000, capacity=200 * GiB)
     res, sm, ref = _virtual(cs, mix, 1)

@@ -97,3 +97,35 @@ def test_percentile_nearest_rank():
     assert V.percentile(x, 50) == 35
     assert V.percentile(x, 100) == 50
     assert V.percentile(list(range(1, 101)), 99) == 99
+
+
+def test_head_of_line_fifo_vs_mmu():
+    """The head-of-line case of Sec. V: a waiting request that does not fit
+    holds every later one under FIFO, while MMU serves the later ones that fit
+    (and, here, does not delay the blocker: the small jobs end long before the
+    long job frees its memory)."""
+    from workloads import HOL_BLOCKER, HOL_LONG, HOL_SMALL, hol_jobs, job_table
+    mix = hol_jobs()
+    jt = job_table(mix)
+    cls = mix.extra["cls"]
+    long_i = int(np.flatnonzero(cls == HOL_LONG)[0])
+    blk = int(np.flatnonzero(cls == HOL_BLOCKER)[0])
+    small = cls == HOL_SMALL
+    # the blocker fits only once the long job has ended
+    assert mix.demand[long_i] + mix.demand[blk] > mix.capacity
+    out = {}
+    for policy in (S.FIFO, S.MMU):
+        ref = V.simulate(jt["arrival_s"], jt["demand"], jt["vdur_s"], mix.capacity, policy,
+                         prio=jt["priority"])
+        assert ref["t_admit"][blk] == ref["t_end"][long_i]
+        out[policy] = ref
+    fifo, mmu = out[S.FIFO], out[S.MMU]
+    # FIFO: no small job passes the blocker
+    assert np.all(fifo["t_admit"][small] >= fifo["t_admit"][blk])
+    # MMU: every small job that arrives while the long job runs is admitted
+    # on arrival (the free memory around it holds each of them)
+    during = small & (jt["arrival_s"] < mmu["t_end"][long_i])
+    assert during.sum() > 30
+    assert np.array_equal(mmu["t_admit"][during], jt["arrival_s"][during])
+    # and FIFO's small jobs that arrived during the long job waited for it
+    assert np.all(fifo["t_admit"][during] >= fifo["t_end"][long_i])

@@ -265,6 +265,32 @@ def c4_jobs(seed: int = 4, n: int = 10_000, capacity: int = 280 * 10**9,
     return JobMix(seed, arrival, kind, size, demand, capacity, "c4")
 
 
+HOL_LONG, HOL_BLOCKER, HOL_SMALL = 0, 1, 2
+
+
+def hol_jobs(seed: int = 6, n_small: int = 200, capacity: int = 32 * GiB,
+             small_rate: float = 1000.0) -> JobMix:
+    """HOL (head-of-line study, FIFO vs MMU): a long triad of 20 GiB footprint
+    at t = 0, then at 1 ms a 16 GiB triad that cannot fit beside it, then
+    ``n_small`` triads of 64-256 MiB footprint (log-uniform) arriving from 2 ms
+    at a Poisson rate ``small_rate``.  Under FIFO the blocker holds every small
+    job until the long one ends; under MMU they fill the free memory around
+    it.  The small jobs' offered traffic (~1.4 TB/s at the default rate) stays
+    well below HBM bandwidth, so their waits show the admission policy rather
+    than a saturated device.  ``extra["cls"]`` labels the jobs HOL_LONG /
+    HOL_BLOCKER / HOL_SMALL."""
+    rng = np.random.default_rng(seed)
+    small = np.exp2(rng.uniform(26.0, 28.0, size=n_small))
+    foot = np.concatenate([[20.0 * GiB, 16.0 * GiB], small])
+    tri_n = ((foot // (12 * PAGE)).astype(np.int64) * (12 * PAGE)) // 12
+    arrival = np.concatenate([[0.0, 1e-3], 2e-3 + np.cumsum(rng.exponential(1.0 / small_rate,
+                                                                             size=n_small))])
+    cls = np.concatenate([[HOL_LONG, HOL_BLOCKER], np.full(n_small, HOL_SMALL)]).astype(np.int32)
+    n = n_small + 2
+    return JobMix(seed, arrival, np.full(n, KIND_TRIAD, np.int32), tri_n, triad_demand(tri_n),
+                  capacity, "hol", {"cls": cls})
+
+
 def c5_jobs(seed: int = 5, n: int = 50_000, capacity: int = 280 * 10**9,
             small_frac: float = 0.7, alpha: float = 1.2, oversub: float = 4.0) -> JobMix:
     """C5: oversubscribed batch of triads, all present at t = 0.  A fraction
