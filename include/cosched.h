@@ -84,7 +84,9 @@ typedef struct {
 typedef struct {
   int64_t capacity;        /* bytes managed                                    */
   int64_t used;            /* sum of reservations of running jobs (Sec. III-B) */
-  int64_t pending;         /* requests waiting in the queue                    */
+  int64_t pending;         /* entries in the queue: waiting requests, plus
+                              withdrawn ones (timeouts, sanity checks) until
+                              a pass that admits past them compacts them away */
   int64_t running;         /* jobs holding a reservation                       */
   int64_t passes;          /* admission passes run                             */
   int64_t rounds;          /* first-fit rounds run (all passes)                */
@@ -165,6 +167,22 @@ int sched_wait(sched_ctx_t *ctx, sched_job_t job, int32_t timeout_ms);
  * bytes exceeds the job's reservation, bytes < 0 or the device is not the
  * context's; nothing changes on error. */
 int sched_release(sched_ctx_t *ctx, sched_job_t job, int32_t device, int64_t bytes);
+
+/* Names the process that holds the job's memory (Sec. III-B keeps the
+ * clients' processes in the shared state): pid > 0 makes the job subject to
+ * the sanity check, pid = 0 exempts it (the default).  SCHED_E_INVALID for
+ * an unknown job or pid < 0.  Host-side only. */
+int sched_set_owner(sched_ctx_t *ctx, sched_job_t job, int32_t pid);
+
+/* Sanity check (Sec. III-B, third robustness feature; Sec. IV): every job
+ * whose owner process no longer exists (kill(pid, 0) fails with ESRCH) has
+ * its waiting requests withdrawn and its whole reservation released, after
+ * which one pass serves the waiting requests.  The library also runs it when
+ * an admission does not fit, when a job releases everything (its shutdown)
+ * and every 50 ms while a caller waits for memory.  *reclaimed_jobs and
+ * *reclaimed_bytes (either may be NULL) receive what was reclaimed.
+ * Synchronises. */
+int sched_sanity_check(sched_ctx_t *ctx, int64_t *reclaimed_jobs, int64_t *reclaimed_bytes);
 
 /* Returns the context to its state right after sched_create with every job
  * still registered: empty queue, no reservations, used = 0.  Slab blocks are

@@ -179,14 +179,41 @@ class Scheduler:
     capacity: int
     policy: int = MMU
     used: int = 0
-    jobs: dict = field(default_factory=dict)        # job -> {"prio", "timeout_ms", "res"}
+    jobs: dict = field(default_factory=dict)        # job -> {"prio", "timeout_ms", "res", "owner"}
+    alive: object = None                            # pid -> bool, for the sanity checks
     requests: list = field(default_factory=list)    # all requests by rid
     log: list = field(default_factory=list)
 
     def register(self, prio: int = 0, timeout_ms: int = 60000) -> int:
         j = len(self.jobs)
-        self.jobs[j] = {"prio": int(prio), "timeout_ms": int(timeout_ms), "res": 0}
+        self.jobs[j] = {"prio": int(prio), "timeout_ms": int(timeout_ms), "res": 0, "owner": 0}
         return j
+
+    def set_owner(self, job: int, pid: int) -> int:
+        """The process that holds the job's memory (0: none, never reclaimed)."""
+        if job not in self.jobs or pid < 0:
+            return E_INVALID
+        self.jobs[job]["owner"] = int(pid)
+        return OK
+
+    def sanity(self, alive) -> tuple:
+        """Sanity check (Sec. III-B, third robustness feature; Sec. IV): every
+        job whose owner process is no longer alive loses its waiting requests
+        and its whole reservation, which then serves the waiters (one pass,
+        when anything was reclaimed).  ``alive(pid)`` answers for a process.
+        Returns (jobs reclaimed, bytes reclaimed)."""
+        jobs, nbytes = 0, 0
+        for j, info in self.jobs.items():
+            if info["owner"] > 0 and not alive(info["owner"]):
+                self.withdraw(j)
+                nbytes += info["res"]
+                self.used -= info["res"]
+                info["res"] = 0
+                info["owner"] = 0
+                jobs += 1
+        if jobs:
+            self.run_pass()
+        return jobs, nbytes
 
     def pending(self):
         return [r for r in self.requests if r.state == "PENDING"]
@@ -220,7 +247,12 @@ class Scheduler:
         r = Request(len(self.requests), job, self.jobs[job]["prio"], int(nbytes))
         self.requests.append(r)
         got = self.run_pass()
-        return OK if r.rid in got else NOT_READY
+        if r.rid in got:
+            return OK
+        # memory is insufficient: check whether holders are still alive
+        if self.alive is not None and self.sanity(self.alive)[0]:
+            return OK if r.state == "ADMITTED" else NOT_READY
+        return NOT_READY
 
     def withdraw(self, job: int) -> int:
         """A blocking pre-allocation whose timeout expired: its waiting requests
@@ -245,6 +277,10 @@ class Scheduler:
         self.jobs[job]["res"] -= amount
         self.used -= amount
         self.run_pass()
+        # releasing everything is the client's shutdown (Sec. IV): it also
+        # checks that the other holders are alive
+        if nbytes == 0 and self.alive is not None:
+            self.sanity(self.alive)
         return OK
 
     def check_invariants(self):

@@ -113,6 +113,8 @@ _SIGS = {
     "sched_last_admitted": (i32, [vp, vp, i64, C.POINTER(i64), vp]),
     "sched_release_masked": (i32, [vp, vp, i64, vp]),
     "sched_pass_chain": (i32, [vp, i32, vp, i64, vp, vp, vp, i64]),
+    "sched_set_owner": (i32, [vp, i32, i32]),
+    "sched_sanity_check": (i32, [vp, vp, vp]),
     "sched_scan_workspace_size": (C.c_size_t, [i64]),
     "sched_scan": (i32, [i32, i64, vp, i64, vp, i32, i32, vp, C.c_size_t, vp,
                          C.POINTER(sched_scan_result_t)]),
@@ -214,6 +216,17 @@ def sched_stats(ctx):
     s = sched_stats_t()
     rc = lib().sched_stats(ctx, C.byref(s))
     return rc, {k: getattr(s, k) for k, _ in sched_stats_t._fields_}
+
+
+def sched_set_owner(ctx, job, pid):
+    return lib().sched_set_owner(ctx, job, pid)
+
+
+def sched_sanity_check(ctx):
+    """Returns (rc, reclaimed_jobs, reclaimed_bytes)."""
+    nj, nb = i64(), i64()
+    rc = lib().sched_sanity_check(ctx, C.byref(nj), C.byref(nb))
+    return rc, nj.value, nb.value
 
 
 def sched_reservation(ctx, job):

@@ -35,6 +35,9 @@ struct sched_ctx {
   // host-side bookkeeping
   int32_t n_jobs = 0;
   std::vector<int32_t> prio, timeout_ms, pending;
+  // owner[j]: process holding job j's memory (0: none); owned: the jobs whose
+  // owner was set, for the sanity check (entries cleared since are skipped)
+  std::vector<int32_t> owner, owned;
   std::unordered_map<int64_t, int32_t> host_seq;  // waiting requests made with sched_admit
   std::vector<int64_t> last_admitted_seqs;
   int64_t seq_next = 0;

@@ -8,6 +8,8 @@
 // context mutex serialises the calls (the role the file lock plays in the
 // paper), admission passes run on the device, and waiters block on a
 // condition variable that every pass signals (the role of the user signal).
+#include <signal.h>
+#include <cerrno>
 #include <algorithm>
 #include <chrono>
 #include <condition_variable>
@@ -140,6 +142,7 @@ extern "C" int sched_create(const sched_config_t *cfg, sched_ctx_t **out) {
   c->prio.assign(cfg->max_jobs, 0);
   c->timeout_ms.assign(cfg->max_jobs, 60000);
   c->pending.assign(cfg->max_jobs, 0);
+  c->owner.assign(cfg->max_jobs, 0);
   int rc = SCHED_OK;
   if (hipStreamCreate(&c->stream) != hipSuccess) rc = SCHED_E_INTERNAL;
   if (rc == SCHED_OK) rc = ctx_alloc(c);
@@ -303,12 +306,60 @@ static int withdraw_locked(sched_ctx *c, sched_job_t job) {
   return SCHED_OK;
 }
 
+static int read_res(sched_ctx *c, sched_job_t job, int64_t *v);
+
+static bool pid_alive(int32_t pid) { return kill(pid, 0) == 0 || errno == EPERM; }
+
+// Sanity check (Sec. III-B, third robustness feature; Sec. IV): every job
+// whose owner process has ended loses its waiting requests and its whole
+// reservation, which then serves the waiting requests (one pass, run only
+// when something was reclaimed).
+static int sanity_locked(sched_ctx *c, int64_t *out_jobs, int64_t *out_bytes) {
+  int64_t nj = 0, nb = 0;
+  for (size_t k = 0; k < c->owned.size();) {
+    const int32_t j = c->owned[k];
+    if (c->owner[j] > 0 && pid_alive(c->owner[j])) {
+      ++k;
+      continue;
+    }
+    if (c->owner[j] > 0) {
+      if (c->pending[j] > 0)
+        if (int rc = withdraw_locked(c, j)) return rc;
+      int64_t res = 0;
+      if (int rc = read_res(c, j, &res)) return rc;
+      if (res > 0) {
+        k_release_one<<<1, 1, 0, c->stream>>>(c->eng.d_ctl, c->jb, j, res);
+        SCHED_HIP_TRY(hipGetLastError());
+        c->stats.released_bytes += res;
+        nb += res;
+      }
+      c->owner[j] = 0;
+      ++nj;
+    }
+    c->owned[k] = c->owned.back();  // reclaimed now or cleared before
+    c->owned.pop_back();
+  }
+  if (nj) {
+    if (int rc = sched_run_pass_locked(c, c->stream, nullptr)) return rc;
+    c->cv.notify_all();
+  }
+  if (out_jobs) *out_jobs = nj;
+  if (out_bytes) *out_bytes = nb;
+  return SCHED_OK;
+}
+
 static int wait_locked(sched_ctx *c, std::unique_lock<std::mutex> &lk, sched_job_t job,
                        int32_t timeout_ms) {
   if (timeout_ms < 0) timeout_ms = c->timeout_ms[job];
   const auto deadline = std::chrono::steady_clock::now() + std::chrono::milliseconds(timeout_ms);
+  // a blocked client checks every 50 ms that the holders are still alive
+  const auto tick = std::chrono::milliseconds(50);
   while (c->pending[job] > 0 && !c->closing) {
-    if (c->cv.wait_until(lk, deadline) == std::cv_status::timeout) break;
+    const auto now = std::chrono::steady_clock::now();
+    if (now >= deadline) break;
+    c->cv.wait_until(lk, std::min(deadline, now + tick));
+    if (c->pending[job] > 0 && !c->closing)
+      if (int rc = sanity_locked(c, nullptr, nullptr)) return rc;
   }
   if (c->pending[job] == 0) return SCHED_OK;
   // timed out: withdraw under the mutex, so the request is either admitted
@@ -342,6 +393,10 @@ extern "C" int sched_admit(sched_ctx_t *c, sched_job_t job, int32_t device, int6
   c->host_seq[seq] = job;
   c->pending[job] += 1;
   if (int rc = sched_run_pass_locked(c, c->stream, nullptr)) return rc;
+  // memory is insufficient: check whether the holders are still alive (a
+  // reclaim runs a pass of its own)
+  if (c->host_seq.find(seq) != c->host_seq.end())
+    if (int rc = sanity_locked(c, nullptr, nullptr)) return rc;
   if (c->host_seq.find(seq) == c->host_seq.end()) {
     // admitted in this pass; other requests of the job may still wait
     if (c->pending[job] == 0 || (flags & SCHED_NONBLOCK)) return SCHED_OK;
@@ -383,7 +438,28 @@ extern "C" int sched_release(sched_ctx_t *c, sched_job_t job, int32_t device, in
     SCHED_HIP_TRY(hipGetLastError());
     c->stats.released_bytes += amount;
   }
-  return sched_run_pass_locked(c, c->stream, nullptr);
+  if (int rc = sched_run_pass_locked(c, c->stream, nullptr)) return rc;
+  // releasing everything is the client's shutdown (Sec. IV): check the other
+  // holders as well
+  return bytes == 0 ? sanity_locked(c, nullptr, nullptr) : SCHED_OK;
+}
+
+extern "C" int sched_set_owner(sched_ctx_t *c, sched_job_t job, int32_t pid) {
+  if (!c) return SCHED_E_INVALID;
+  std::lock_guard<std::mutex> g(c->mu);
+  if (job < 0 || job >= c->n_jobs || pid < 0) return SCHED_E_INVALID;
+  if (pid > 0 && c->owner[job] == 0) c->owned.push_back(job);
+  c->owner[job] = pid;
+  return SCHED_OK;
+}
+
+extern "C" int sched_sanity_check(sched_ctx_t *c, int64_t *reclaimed_jobs,
+                                  int64_t *reclaimed_bytes) {
+  if (!c) return SCHED_E_INVALID;
+  std::lock_guard<std::mutex> g(c->mu);
+  if (int rc = sched_settle_reset_locked(c)) return rc;
+  SCHED_HIP_TRY(hipSetDevice(c->device));
+  return sanity_locked(c, reclaimed_jobs, reclaimed_bytes);
 }
 
 extern "C" int sched_reservation(sched_ctx_t *c, sched_job_t job, int64_t *out) {

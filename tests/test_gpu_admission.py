@@ -453,3 +453,98 @@ def test_enqueue_batch_alignment_and_wrap(cs):
         assert rc == 0 and st["used"] == used and st["pending"] == 0
     finally:
         cs.sched_destroy(ctx)
+
+
+# --------------------------------------------------------------------------
+# Sanity check (Sec. III-B third robustness feature, Sec. IV)
+# --------------------------------------------------------------------------
+def _dead_pid():
+    """A process id no process can have: above the kernel's pid_max."""
+    try:
+        with open("/proc/sys/kernel/pid_max") as f:
+            return int(f.read()) + 1
+    except OSError:
+        return (1 << 22) + 1
+
+
+def test_sanity_reclaims_dead_owner_on_admit_and_shutdown(cs):
+    import os
+    dead = _dead_pid()
+    alive = lambda pid: pid != dead
+    rc, ctx = cs.sched_create(policy=cs.SCHED_POLICY_MMU, capacity_bytes=10_000, max_jobs=8,
+                              queue_capacity=256)
+    assert rc == 0
+    sc = S.Scheduler(capacity=10_000, policy=S.MMU)
+    sc.alive = alive
+    try:
+        jobs = [cs.sched_register(ctx)[1] for _ in range(5)]
+        for _ in range(5):
+            sc.register()
+        a, b, c, d, e = jobs
+        assert cs.sched_set_owner(ctx, a, dead) == 0 and sc.set_owner(a, dead) == S.OK
+        assert cs.sched_set_owner(ctx, b, os.getpid()) == 0 and sc.set_owner(b, os.getpid()) == S.OK
+        assert cs.sched_set_owner(ctx, a, -1) == cs.SCHED_E_INVALID
+        # a and b fit; c does not beside them, so the admission checks the
+        # holders: a's process is gone, its 6000 bytes serve c at once
+        for j, nb in ((a, 6000), (b, 3000), (c, 2000)):
+            assert cs.sched_admit(ctx, j, 0, nb, cs.SCHED_NONBLOCK) == sc.admit(j, 0, nb) == 0
+        for j in jobs:
+            assert cs.sched_reservation(ctx, j)[1] == sc.jobs[j]["res"]
+        # a second dead holder, found at another job's shutdown
+        assert cs.sched_set_owner(ctx, d, os.getpid()) == 0 and sc.set_owner(d, os.getpid()) == 0
+        assert cs.sched_admit(ctx, d, 0, 4000, cs.SCHED_NONBLOCK) == sc.admit(d, 0, 4000) == 0
+        assert cs.sched_admit(ctx, e, 0, 5000, cs.SCHED_NONBLOCK) == sc.admit(e, 0, 5000) \
+            == cs.SCHED_NOT_READY
+        assert cs.sched_set_owner(ctx, d, dead) == 0 and sc.set_owner(d, dead) == 0
+        assert cs.sched_release(ctx, c, 0, 0) == sc.release(c, 0, 0) == 0
+        for j in jobs:
+            assert cs.sched_reservation(ctx, j)[1] == sc.jobs[j]["res"], j
+        rc, st = cs.sched_stats(ctx)
+        assert st["used"] == sc.used == 8000 and st["pending"] == 0
+        # nothing left to reclaim; an explicit check finds nothing
+        assert cs.sched_sanity_check(ctx) == (0, 0, 0)
+    finally:
+        cs.sched_destroy(ctx)
+
+
+def test_sanity_while_waiting_and_explicit(cs):
+    """A blocked admission checks the holders while it waits: once the
+    holder's process is gone (here: its owner becomes a pid no process has)
+    the waiter is admitted; an explicit check reports what it reclaimed and
+    withdraws the dead job's own waiting requests."""
+    import os
+    import threading
+    rc, ctx = cs.sched_create(policy=cs.SCHED_POLICY_FIFO, capacity_bytes=10_000, max_jobs=8,
+                              queue_capacity=256)
+    assert rc == 0
+    try:
+        a = cs.sched_register(ctx)[1]
+        b = cs.sched_register(ctx, timeout_ms=20_000)[1]
+        c = cs.sched_register(ctx)[1]
+        assert cs.sched_set_owner(ctx, a, os.getpid()) == 0
+        assert cs.sched_admit(ctx, a, 0, 9000, cs.SCHED_NONBLOCK) == 0
+        out = {}
+        t = threading.Thread(target=lambda: out.update(rc=cs.sched_admit(ctx, b, 0, 5000, 0)))
+        t.start()
+        t.join(0.3)
+        assert t.is_alive()                       # b waits: a holds 9000 and is alive
+        assert cs.sched_set_owner(ctx, a, _dead_pid()) == 0
+        t.join(10.0)
+        assert not t.is_alive() and out["rc"] == 0
+        assert cs.sched_reservation(ctx, a)[1] == 0 and cs.sched_reservation(ctx, b)[1] == 5000
+        # the explicit form: c holds memory and waits for more, then dies
+        assert cs.sched_set_owner(ctx, c, os.getpid()) == 0
+        assert cs.sched_admit(ctx, c, 0, 4000, cs.SCHED_NONBLOCK) == 0
+        assert cs.sched_admit(ctx, c, 0, 3000, cs.SCHED_NONBLOCK) == cs.SCHED_NOT_READY
+        assert cs.sched_set_owner(ctx, c, _dead_pid()) == 0
+        assert cs.sched_sanity_check(ctx) == (0, 1, 4000)
+        rc, st = cs.sched_stats(ctx)
+        assert st["used"] == 5000
+        # c's waiting request was withdrawn: with the whole pool free it is
+        # still never admitted
+        assert cs.sched_release(ctx, b, 0, 0) == 0
+        assert cs.sched_reservation(ctx, c)[1] == 0
+        rc, st = cs.sched_stats(ctx)
+        assert st["used"] == 0
+    finally:
+        cs.sched_destroy(ctx)

@@ -315,3 +315,74 @@ def test_c2_shape():
     assert np.all(q.demand % 4096 == 0)
     assert q.coins.shape == (7, 1 << 16)
     assert 280 * 10**9 % 4096 == 0
+
+
+# --------------------------------------------------------------------------
+# Sanity check (Sec. III-B third robustness feature, Sec. IV): memory of
+# clients whose process has ended is reclaimed for the waiting clients
+# --------------------------------------------------------------------------
+def _sched_with_dead(dead):
+    sc = S.Scheduler(capacity=10_000, policy=S.MMU)
+    sc.alive = lambda pid: pid not in dead
+    return sc
+
+
+def test_sanity_reclaims_on_insufficient_memory():
+    dead = set()
+    sc = _sched_with_dead(dead)
+    a, b, c = sc.register(), sc.register(), sc.register()
+    assert sc.set_owner(a, 101) == S.OK and sc.set_owner(b, 102) == S.OK
+    assert sc.admit(a, 0, 6000) == S.OK and sc.admit(b, 0, 3000) == S.OK
+    dead.add(101)                      # a's process ends without post-freeing
+    # c does not fit beside a and b (6000 + 3000 + 2000 > 10000): the sanity
+    # check frees a's 6000 bytes and c is admitted in the same call
+    assert sc.admit(c, 0, 2000) == S.OK
+    assert sc.jobs[a]["res"] == 0 and sc.jobs[b]["res"] == 3000 and sc.jobs[c]["res"] == 2000
+    assert sc.used == 5000 and sc.check_invariants()
+    assert sc.jobs[a]["owner"] == 0    # reclaimed once
+
+
+def test_sanity_withdraws_requests_of_dead_jobs():
+    dead = set()
+    sc = _sched_with_dead(dead)
+    a, b = sc.register(), sc.register()
+    sc.set_owner(a, 201)
+    assert sc.admit(a, 0, 7000) == S.OK
+    assert sc.admit(a, 0, 5000) == S.NOT_READY     # a's second request waits
+    dead.add(201)
+    assert sc.sanity(sc.alive) == (1, 7000)
+    # the waiting request was withdrawn, not admitted by the reclaim pass
+    assert [r.state for r in sc.requests] == ["ADMITTED", "WITHDRAWN"]
+    assert sc.used == 0 and sc.admit(b, 0, 10_000) == S.OK
+
+
+def test_sanity_keeps_live_and_ownerless_holders():
+    sc = _sched_with_dead({301})
+    a, b, c = sc.register(), sc.register(), sc.register()
+    sc.set_owner(a, 300)               # alive
+    # b has no owner (0): never reclaimed, whatever the liveness answers
+    assert sc.admit(a, 0, 4000) == S.OK and sc.admit(b, 0, 5000) == S.OK
+    n_pass = len(sc.log)
+    assert sc.admit(c, 0, 3000) == S.NOT_READY
+    assert len(sc.log) == n_pass + 1   # the admit's own pass only: nothing reclaimed
+    assert sc.sanity(sc.alive) == (0, 0) and sc.used == 9000
+
+
+def test_sanity_at_shutdown_serves_waiters():
+    dead = set()
+    sc = _sched_with_dead(dead)
+    a, b, c = sc.register(), sc.register(), sc.register()
+    sc.set_owner(a, 401)
+    assert sc.admit(a, 0, 5000) == S.OK and sc.admit(b, 0, 4000) == S.OK
+    assert sc.admit(c, 0, 6000) == S.NOT_READY
+    dead.add(401)
+    # b's shutdown (release of everything) frees 4000 -- not enough for c --
+    # then checks the other holders: a's 5000 come back and c is admitted
+    assert sc.release(b, 0, 0) == S.OK
+    assert sc.jobs[c]["res"] == 6000 and sc.used == 6000 and sc.check_invariants()
+
+
+def test_set_owner_rejects_bad_args():
+    sc = S.Scheduler(capacity=100)
+    a = sc.register()
+    assert sc.set_owner(a, -1) == S.E_INVALID and sc.set_owner(7, 1) == S.E_INVALID
