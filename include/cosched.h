@@ -194,6 +194,41 @@ int sched_sanity_check(sched_ctx_t *ctx, int64_t *reclaimed_jobs, int64_t *recla
  * for the reset to finish. */
 int sched_reset(sched_ctx_t *ctx);
 
+/* Checkpoint (Sec. III-B, first robustness feature: a backup of the shared
+ * state).  Writes into the caller's host buffer buf[0, cap) a self-contained
+ * little-endian record of the admission state:
+ *   header (64 B): magic "SCHEDCK1", version 1 (u32), policy (i32),
+ *     capacity, used (i64), n_jobs (i32), 0 (i32), n_pending (i64),
+ *     checksum (u64, FNV-1a 64 over the whole record with this field 0), 0;
+ *   per registered job (24 B): priority, timeout_ms, owner pid, 0 (i32),
+ *     reservation in bytes (i64);
+ *   per waiting request (16 B): demand (i64), job, priority (i32), in the
+ *     order the policy serves them: arrival order, or (priority, arrival)
+ *     under the priority policies.  Withdrawn requests are left out.
+ * *out_bytes receives the record's size.  buf = NULL asks for an upper bound
+ * of that size (cap is ignored).  SCHED_E_INVALID if cap is too small;
+ * SCHED_E_INTERNAL if the live state fails the integrity check of
+ * sched_restore (then no record is handed out).  Slab blocks, counters and
+ * the device's decision bytes are not part of it.  Work the caller queued on
+ * its own streams (sched_enqueue_batch, sched_pass_chain) must be complete.
+ * Synchronises. */
+int sched_checkpoint(sched_ctx_t *ctx, void *buf, size_t cap, size_t *out_bytes);
+
+/* Integrity check and recovery (Sec. III-B, second robustness feature;
+ * Sec. IV, initialisation).  Loads a record written by sched_checkpoint into
+ * ctx, which must be fresh: no job registered, an empty queue, the record's
+ * policy and capacity, and room for its waiting requests in the queue.  The
+ * record is checked first -- magic, version, size, checksum, every
+ * reservation in [0, capacity] with their sum equal to the used total, every
+ * request naming a job of the record with that job's priority and a demand
+ * in [1, capacity] -- and a record that fails, or a context that is not
+ * fresh, gives SCHED_E_INVALID with ctx untouched (the caller then keeps the
+ * freshly initialised state).  On success the jobs get ids 0..n_jobs-1 with
+ * their priority, timeout, owner and reservation, and the requests wait in
+ * the record's order as if made by sched_admit: sched_wait works on them and
+ * the next pass serves them.  Buffer owned by the caller.  Synchronises. */
+int sched_restore(sched_ctx_t *ctx, const void *buf, size_t bytes);
+
 /* Counters; see sched_stats_t. */
 int sched_stats(sched_ctx_t *ctx, sched_stats_t *out);
 

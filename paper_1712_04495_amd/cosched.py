@@ -115,6 +115,8 @@ _SIGS = {
     "sched_pass_chain": (i32, [vp, i32, vp, i64, vp, vp, vp, i64]),
     "sched_set_owner": (i32, [vp, i32, i32]),
     "sched_sanity_check": (i32, [vp, vp, vp]),
+    "sched_checkpoint": (i32, [vp, vp, C.c_size_t, C.POINTER(C.c_size_t)]),
+    "sched_restore": (i32, [vp, vp, C.c_size_t]),
     "sched_scan_workspace_size": (C.c_size_t, [i64]),
     "sched_scan": (i32, [i32, i64, vp, i64, vp, i32, i32, vp, C.c_size_t, vp,
                          C.POINTER(sched_scan_result_t)]),
@@ -227,6 +229,30 @@ def sched_sanity_check(ctx):
     nj, nb = i64(), i64()
     rc = lib().sched_sanity_check(ctx, C.byref(nj), C.byref(nb))
     return rc, nj.value, nb.value
+
+
+def sched_checkpoint(ctx):
+    """Returns (rc, record bytes); the buffer is sized by the library's own
+    size query first."""
+    n = C.c_size_t()
+    rc = lib().sched_checkpoint(ctx, None, 0, C.byref(n))
+    if rc:
+        return rc, b""
+    buf = C.create_string_buffer(max(n.value, 1))
+    rc = lib().sched_checkpoint(ctx, buf, n.value, C.byref(n))
+    return rc, (buf.raw[: n.value] if rc == 0 else b"")
+
+
+def sched_checkpoint_size(ctx):
+    """Returns (rc, upper bound of the record's size)."""
+    n = C.c_size_t()
+    rc = lib().sched_checkpoint(ctx, None, 0, C.byref(n))
+    return rc, n.value
+
+
+def sched_restore(ctx, record: bytes):
+    buf = C.create_string_buffer(bytes(record), len(record))
+    return lib().sched_restore(ctx, buf, len(record))
 
 
 def sched_reservation(ctx, job):

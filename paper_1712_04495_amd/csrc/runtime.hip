@@ -717,3 +717,254 @@ extern "C" int sched_reset(sched_ctx_t *c) {
 }
 
 extern "C" const char *sched_version(void) { return "sched-mi355x 0.1 (gfx950)"; }
+
+// ---------------------------------------------------------------------------
+// Checkpoint and restore (Sec. III-B, first and second robustness features:
+// a backup of the shared state, and an integrity check that recovers from it)
+// ---------------------------------------------------------------------------
+namespace {
+
+// Buffer layout, little-endian: the header, then per registered job
+// {prio, timeout_ms, owner, 0 : int32; reservation : int64}, then per waiting
+// request in queue order {demand : int64; job, prio : int32}.  The checksum is
+// FNV-1a 64 (Fowler, Noll, Vo) over the whole buffer with its own field zero.
+struct CkptHeader {
+  char magic[8];
+  uint32_t version;
+  int32_t policy;
+  int64_t capacity;
+  int64_t used;
+  int32_t n_jobs;
+  int32_t reserved;
+  int64_t n_pending;
+  uint64_t checksum;
+  uint64_t pad;
+};
+static_assert(sizeof(CkptHeader) == 64, "checkpoint header layout");
+struct CkptJob {
+  int32_t prio, timeout_ms, owner, zero;
+  int64_t res;
+};
+struct CkptReq {
+  int64_t demand;
+  int32_t job, prio;
+};
+constexpr char kCkptMagic[8] = {'S', 'C', 'H', 'E', 'D', 'C', 'K', '1'};
+
+uint64_t fnv1a64(const unsigned char *p, size_t n, uint64_t h = 0xcbf29ce484222325ULL) {
+  for (size_t i = 0; i < n; ++i) {
+    h ^= p[i];
+    h *= 0x100000001b3ULL;
+  }
+  return h;
+}
+
+uint64_t ckpt_checksum(const unsigned char *buf, size_t bytes) {
+  CkptHeader h;
+  memcpy(&h, buf, sizeof h);
+  h.checksum = 0;
+  const uint64_t x = fnv1a64(reinterpret_cast<const unsigned char *>(&h), sizeof h);
+  return fnv1a64(buf + sizeof h, bytes - sizeof h, x);
+}
+
+__global__ void k_set_used(DevCtl *c, int64_t used) { c->used = used; }
+
+// Integrity check of a checkpoint (Sec. III-B, second robustness feature):
+// the format, the checksum, then the accounting invariants of the shared
+// state -- every reservation within [0, capacity], their sum equal to the
+// used total, every waiting request naming a job of the checkpoint with that
+// job's priority and a demand in [1, capacity].
+bool ckpt_parse(const unsigned char *in, size_t bytes, int32_t max_jobs, CkptHeader *h,
+                std::vector<CkptJob> *jobs, std::vector<CkptReq> *reqs) {
+  if (bytes < sizeof(CkptHeader)) return false;
+  memcpy(h, in, sizeof *h);
+  if (memcmp(h->magic, kCkptMagic, 8) != 0 || h->version != 1) return false;
+  if (h->n_jobs < 0 || h->n_jobs > max_jobs || h->n_pending < 0 ||
+      uint64_t(h->n_pending) > bytes / sizeof(CkptReq))
+    return false;
+  if (bytes != sizeof *h + sizeof(CkptJob) * size_t(h->n_jobs) +
+                   sizeof(CkptReq) * size_t(h->n_pending))
+    return false;
+  if (ckpt_checksum(in, bytes) != h->checksum) return false;
+  if (h->capacity <= 0 || h->used < 0 || h->used > h->capacity) return false;
+  jobs->resize(h->n_jobs);
+  reqs->resize(h->n_pending);
+  if (h->n_jobs) memcpy(jobs->data(), in + sizeof *h, sizeof(CkptJob) * size_t(h->n_jobs));
+  if (h->n_pending)
+    memcpy(reqs->data(), in + sizeof *h + sizeof(CkptJob) * size_t(h->n_jobs),
+           sizeof(CkptReq) * size_t(h->n_pending));
+  int64_t sum = 0;
+  for (const CkptJob &r : *jobs) {
+    if (r.res < 0 || r.res > h->capacity - sum || r.owner < 0 || r.zero != 0) return false;
+    sum += r.res;
+  }
+  if (sum != h->used) return false;
+  for (const CkptReq &r : *reqs)
+    if (r.job < 0 || r.job >= h->n_jobs || r.demand < 1 || r.demand > h->capacity ||
+        r.prio != (*jobs)[r.job].prio)
+      return false;
+  return true;
+}
+
+}  // namespace
+
+extern "C" int sched_checkpoint(sched_ctx_t *c, void *buf, size_t cap, size_t *out_bytes) {
+  if (!c || !out_bytes) return SCHED_E_INVALID;
+  std::lock_guard<std::mutex> g(c->mu);
+  if (int rc = sched_settle_reset_locked(c)) return rc;
+  SCHED_HIP_TRY(hipSetDevice(c->device));
+  SCHED_HIP_TRY(hipMemcpyAsync(c->eng.h_ctl, c->eng.d_ctl, sizeof(DevCtl), hipMemcpyDeviceToHost,
+                               c->stream));
+  SCHED_HIP_TRY(hipStreamSynchronize(c->stream));
+  const int64_t head = c->eng.h_ctl->head, tail = c->eng.h_ctl->tail, used = c->eng.h_ctl->used;
+  const int64_t live = tail - head;
+  if (live < 0 || live > c->q.capacity) return SCHED_E_INTERNAL;
+  const size_t bound = sizeof(CkptHeader) + sizeof(CkptJob) * size_t(c->n_jobs) +
+                       sizeof(CkptReq) * size_t(live);
+  if (!buf) {  // size query: an upper bound (withdrawn entries are dropped)
+    *out_bytes = bound;
+    return SCHED_OK;
+  }
+  std::vector<int64_t> res(c->n_jobs), dem(live), seq(live);
+  std::vector<int32_t> job(live), pri(live);
+  if (c->n_jobs)
+    SCHED_HIP_TRY(hipMemcpy(res.data(), c->jb.res, sizeof(int64_t) * c->n_jobs,
+                            hipMemcpyDeviceToHost));
+  // the live ring range in at most two pieces
+  const int64_t Q = c->q.capacity;
+  for (int64_t done = 0; done < live;) {
+    const int64_t p = (head + done) & (Q - 1);
+    const int64_t n = std::min(live - done, Q - p);
+    SCHED_HIP_TRY(hipMemcpy(dem.data() + done, c->q.demand + p, sizeof(int64_t) * n,
+                            hipMemcpyDeviceToHost));
+    SCHED_HIP_TRY(hipMemcpy(job.data() + done, c->q.job + p, sizeof(int32_t) * n,
+                            hipMemcpyDeviceToHost));
+    SCHED_HIP_TRY(hipMemcpy(pri.data() + done, c->q.prio + p, sizeof(int32_t) * n,
+                            hipMemcpyDeviceToHost));
+    SCHED_HIP_TRY(hipMemcpy(seq.data() + done, c->q.seq + p, sizeof(int64_t) * n,
+                            hipMemcpyDeviceToHost));
+    done += n;
+  }
+  // waiting requests in the order the policy serves them: arrival order, or
+  // (priority, arrival) for the priority policies; withdrawn entries dropped
+  std::vector<int64_t> order;
+  order.reserve(live);
+  for (int64_t i = 0; i < live; ++i)
+    if (dem[i] >= 0) order.push_back(i);
+  const bool by_prio = c->policy == SCHED_POLICY_PRIO_FIFO || c->policy == SCHED_POLICY_PRIO_MMU;
+  std::sort(order.begin(), order.end(), [&](int64_t a, int64_t b) {
+    if (by_prio && pri[a] != pri[b]) return pri[a] < pri[b];
+    return seq[a] < seq[b];
+  });
+  const int64_t waiting = int64_t(order.size());
+  const size_t bytes = sizeof(CkptHeader) + sizeof(CkptJob) * size_t(c->n_jobs) +
+                       sizeof(CkptReq) * size_t(waiting);
+  if (cap < bytes) return SCHED_E_INVALID;
+  unsigned char *out = static_cast<unsigned char *>(buf);
+  CkptHeader h{};
+  memcpy(h.magic, kCkptMagic, 8);
+  h.version = 1;
+  h.policy = c->policy;
+  h.capacity = c->capacity;
+  h.used = used;
+  h.n_jobs = c->n_jobs;
+  h.n_pending = waiting;
+  size_t at = sizeof h;
+  for (int32_t j = 0; j < c->n_jobs; ++j) {
+    const CkptJob r{c->prio[j], c->timeout_ms[j], c->owner[j], 0, res[j]};
+    memcpy(out + at, &r, sizeof r);
+    at += sizeof r;
+  }
+  for (const int64_t i : order) {
+    const CkptReq r{dem[i], job[i], pri[i]};
+    memcpy(out + at, &r, sizeof r);
+    at += sizeof r;
+  }
+  memcpy(out, &h, sizeof h);
+  h.checksum = ckpt_checksum(out, bytes);
+  memcpy(out, &h, sizeof h);
+  // a state that fails the integrity check is never handed out as a backup
+  CkptHeader hv;
+  std::vector<CkptJob> jv;
+  std::vector<CkptReq> rv;
+  if (!ckpt_parse(out, bytes, c->jb.max_jobs, &hv, &jv, &rv)) return SCHED_E_INTERNAL;
+  *out_bytes = bytes;
+  return SCHED_OK;
+}
+
+extern "C" int sched_restore(sched_ctx_t *c, const void *buf, size_t bytes) {
+  if (!c || !buf) return SCHED_E_INVALID;
+  std::lock_guard<std::mutex> g(c->mu);
+  if (int rc = sched_settle_reset_locked(c)) return rc;
+  CkptHeader h;
+  std::vector<CkptJob> jobs;
+  std::vector<CkptReq> reqs;
+  if (!ckpt_parse(static_cast<const unsigned char *>(buf), bytes, c->jb.max_jobs, &h, &jobs, &reqs))
+    return SCHED_E_INVALID;
+  // the target is a fresh context of the same pool and policy
+  if (h.policy != c->policy || h.capacity != c->capacity || c->n_jobs != 0 ||
+      c->tail_h != c->head_h || h.n_pending > c->q.capacity)
+    return SCHED_E_INVALID;
+  // apply: the jobs, their reservations, the used total, the waiting queue
+  SCHED_HIP_TRY(hipSetDevice(c->device));
+  std::vector<int32_t> pr(h.n_jobs), st(h.n_jobs);
+  std::vector<int64_t> rs(h.n_jobs);
+  for (int32_t j = 0; j < h.n_jobs; ++j) {
+    pr[j] = jobs[j].prio;
+    rs[j] = jobs[j].res;
+    st[j] = jobs[j].res > 0 ? 1 : 0;
+  }
+  std::vector<int32_t> qj(h.n_pending);
+  std::vector<int64_t> qd(h.n_pending);
+  for (int64_t i = 0; i < h.n_pending; ++i) {
+    qj[i] = reqs[i].job;
+    qd[i] = reqs[i].demand;
+  }
+  int32_t *dj = nullptr;
+  int64_t *dd = nullptr;
+  hipError_t e = hipSuccess;
+  if (h.n_pending) {
+    e = hipMalloc(&dj, sizeof(int32_t) * h.n_pending);
+    if (e == hipSuccess) e = hipMalloc(&dd, sizeof(int64_t) * h.n_pending);
+    if (e == hipSuccess)
+      e = hipMemcpy(dj, qj.data(), sizeof(int32_t) * h.n_pending, hipMemcpyHostToDevice);
+    if (e == hipSuccess)
+      e = hipMemcpy(dd, qd.data(), sizeof(int64_t) * h.n_pending, hipMemcpyHostToDevice);
+  }
+  if (e == hipSuccess && h.n_jobs) {
+    e = hipMemcpy(c->d_prio_of_job, pr.data(), sizeof(int32_t) * h.n_jobs, hipMemcpyHostToDevice);
+    if (e == hipSuccess)
+      e = hipMemcpy(c->jb.res, rs.data(), sizeof(int64_t) * h.n_jobs, hipMemcpyHostToDevice);
+    if (e == hipSuccess)
+      e = hipMemcpy(c->jb.state, st.data(), sizeof(int32_t) * h.n_jobs, hipMemcpyHostToDevice);
+  }
+  int rc = e == hipSuccess ? SCHED_OK : SCHED_E_INTERNAL;
+  if (rc == SCHED_OK) {
+    k_set_used<<<1, 1, 0, c->stream>>>(c->eng.d_ctl, h.used);
+    if (hipGetLastError() != hipSuccess) rc = SCHED_E_INTERNAL;
+  }
+  if (rc == SCHED_OK && h.n_pending)
+    rc = adm_enqueue(c->eng, c->q, c->tail_h, h.n_pending, dj, dd, c->d_prio_of_job, c->seq_next,
+                     c->stream);
+  if (rc == SCHED_OK && hipStreamSynchronize(c->stream) != hipSuccess) rc = SCHED_E_INTERNAL;
+  if (dj) (void)hipFree(dj);
+  if (dd) (void)hipFree(dd);
+  if (rc) return rc;
+  for (int32_t j = 0; j < h.n_jobs; ++j) {
+    c->prio[j] = jobs[j].prio;
+    c->timeout_ms[j] = jobs[j].timeout_ms;
+    c->owner[j] = jobs[j].owner;
+    if (jobs[j].owner > 0) c->owned.push_back(j);
+  }
+  c->n_jobs = h.n_jobs;
+  // the restored requests wait like requests made here: sched_wait works on
+  // them and the passes report their admission
+  for (int64_t i = 0; i < h.n_pending; ++i) {
+    c->host_seq[c->seq_next + i] = qj[i];
+    c->pending[qj[i]] += 1;
+  }
+  c->seq_next += h.n_pending;
+  c->tail_h += h.n_pending;
+  c->used_h = h.used;
+  return SCHED_OK;
+}
