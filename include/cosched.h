@@ -312,6 +312,15 @@ int sched_scan(int32_t policy, int64_t n, const int64_t *d_demand, int64_t R, ui
                int32_t write_all, int32_t window_limit, void *d_ws, size_t ws_bytes,
                sched_stream_t stream, sched_scan_result_t *out);
 
+/* Look-back bound of the grid rounds (the HBM-bound part of a pass: a
+ * single-pass prefix scan across workgroups, Sec. V policies).  A tile waits
+ * for a predecessor's published sum at most `polls` polls (default 2048),
+ * then sums that predecessor's demands itself; results do not depend on it.
+ * 0 makes every look-back compute missing sums at once (used by tests to
+ * exercise that path).  Process-wide; applies to rounds launched afterwards.
+ * SCHED_E_INVALID for polls < 0. */
+int sched_set_lookback_polls(int32_t polls);
+
 /* ======================================================================== */
 /* Quota-checked slab sub-allocator                                          */
 /* ======================================================================== */

@@ -118,6 +118,7 @@ _SIGS = {
     "sched_checkpoint": (i32, [vp, vp, C.c_size_t, C.POINTER(C.c_size_t)]),
     "sched_restore": (i32, [vp, vp, C.c_size_t]),
     "sched_scan_workspace_size": (C.c_size_t, [i64]),
+    "sched_set_lookback_polls": (i32, [i32]),
     "sched_scan": (i32, [i32, i64, vp, i64, vp, i32, i32, vp, C.c_size_t, vp,
                          C.POINTER(sched_scan_result_t)]),
     "sched_alloc": (i32, [vp, i32, C.c_size_t, C.POINTER(vp)]),
@@ -229,6 +230,10 @@ def sched_sanity_check(ctx):
     nj, nb = i64(), i64()
     rc = lib().sched_sanity_check(ctx, C.byref(nj), C.byref(nb))
     return rc, nj.value, nb.value
+
+
+def sched_set_lookback_polls(polls):
+    return lib().sched_set_lookback_polls(polls)
 
 
 def sched_checkpoint(ctx):

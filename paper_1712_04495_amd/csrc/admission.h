@@ -54,12 +54,9 @@ struct DevCtl {
   int32_t pad;
   int64_t adm_base;        // where the next admitted list starts (chains append)
   RoundRec rec[4];
-  // the ticket counters take a 256-byte line of their own: every workgroup
-  // of a round hits the active one, and any other word on that line (the
-  // break marker above all, read per ticket) would be slowed down with it
-  alignas(256) unsigned long long ticket[4];
-  unsigned long long ticket_pad[28];
-  long long break_tile[4];           // read per ticket: kept off the counters' lines too
+  // the break markers are read once per tile by every workgroup of a round:
+  // they take a 256-byte line of their own, away from any word that changes
+  alignas(256) long long break_tile[4];
   long long break_pad[28];
   unsigned long long tiles_done[4];  // tiles finished in the round of a slot
   unsigned long long round_sum[4];   // candidate sums of those tiles
@@ -76,6 +73,8 @@ struct PassSummary {
   int32_t done, pad;
 };
 constexpr int MAX_CHAIN = 256;
+constexpr int32_t LOOKBACK_POLLS_DEFAULT = 2048;
+void adm_set_lookback_polls(int32_t polls);
 
 struct AdmEngine {
   DevCtl *d_ctl = nullptr;

@@ -18,13 +18,19 @@
 //    launch.
 //  * k_round: a persistent grid that computes one round over the whole
 //    remaining queue with a single-pass decoupled look-back scan.  Tiles are
-//    taken from an atomic ticket in queue order; each tile publishes its
-//    candidate sum (saturated at R + 1) and then its inclusive prefix in one
-//    64-bit word (epoch:16 | status:2 | value:46).  Only the tile that holds
+//    dealt to the workgroups in an interleaved static order (workgroup b
+//    takes tiles b, b + G, b + 2G, ...), so the grid streams one contiguous
+//    stretch of the queue at a time; each tile publishes its candidate sum
+//    (saturated at R + 1) and then its inclusive prefix in one 64-bit word
+//    (epoch:16 | status:2 | value:46).  A look-back polls a missing
+//    predecessor a bounded number of times and then sums that predecessor's
+//    candidates from its demands itself, so no workgroup ever depends on
+//    another one being resident.  Only the tile that holds
 //    the break runs an ordered scan; every other tile either admits all of
 //    its candidates or, lying past the break, admits nothing.  This is the
 //    HBM-bound regime (the final round of a pass that never exhausts memory
 //    reads every remaining demand once).
+#include <atomic>
 #include <climits>
 #include <cstring>
 
@@ -41,11 +47,10 @@ __device__ __forceinline__ unsigned long long pack_flag(uint32_t epoch, uint64_t
   return (static_cast<unsigned long long>(epoch) << 48) | (st << 46) | uint64_t(v);
 }
 
-// The launch that follows L uses slot (L + 1) & 3: clear its ticket and break
-// marker.  Launch L - 3 was the last user of that slot and has finished.
+// The launch that follows L uses slot (L + 1) & 3: clear its break marker and
+// counters.  Launch L - 3 was the last user of that slot and has finished.
 __device__ __forceinline__ void reset_next_slot(DevCtl *c, uint32_t L) {
   const int nx = (L + 1) & 3;
-  c->ticket[nx] = 0;
   c->break_tile[nx] = LLONG_MAX;
   c->tiles_done[nx] = 0;
   c->round_sum[nx] = 0;
@@ -90,7 +95,6 @@ __device__ __forceinline__ void pass_init(DevCtl *c, uint32_t L, int filter, int
   c->rec[s].R = R0;
   c->rec[s].start = start;
   c->rec[s].done = (start >= end || R0 <= 0) ? 1 : 0;
-  c->ticket[s] = 0;
   c->break_tile[s] = LLONG_MAX;
   c->tiles_done[s] = 0;
   c->round_sum[s] = 0;
@@ -403,13 +407,14 @@ __device__ __forceinline__ void round_load(const int64_t *__restrict__ demand, i
 // One tile of a round (whole workgroup).  raw: the tile's demands from
 // round_load.  Returns true when the tile lies past the round's break (so
 // does every later tile).
-__device__ __forceinline__ bool round_tile(DevCtl *c, uint8_t *__restrict__ decision, int64_t mask,
+__device__ __forceinline__ bool round_tile(DevCtl *c, const int64_t *__restrict__ demand,
+                                           uint8_t *__restrict__ decision, int64_t mask,
                                            unsigned long long *flags, int s, int nx,
-                                           uint32_t epoch, int64_t R, int64_t cap, bool filter,
-                                           int64_t end, long long t, int64_t base,
-                                           const int64_t (&raw)[RND_ITEMS], int64_t *red,
-                                           int64_t &s_E, int64_t &s_brk_sum, int64_t &acc_sum,
-                                           int64_t &acc_cnt, int64_t &acc_hi) {
+                                           uint32_t epoch, int32_t polls, int64_t R, int64_t cap,
+                                           bool filter, int64_t start, int64_t end, long long t,
+                                           int64_t base, const int64_t (&raw)[RND_ITEMS],
+                                           int64_t *red, int64_t &s_E, int64_t &s_brk_sum,
+                                           int64_t &acc_sum, int64_t &acc_cnt, int64_t &acc_hi) {
   const int tid = threadIdx.x;
   int64_t x[RND_ITEMS];
   int64_t tsum = 0;
@@ -439,7 +444,10 @@ __device__ __forceinline__ bool round_tile(DevCtl *c, uint8_t *__restrict__ deci
   if (tid < WAVE) {
     // Wave 0 looks back 64 predecessors at a time: lane l reads the flag of
     // tile p - l.  The nearest inclusive flag ends the walk once every
-    // nearer predecessor has published its aggregate.
+    // nearer predecessor has published its aggregate.  A predecessor still
+    // missing after `polls` polls has its aggregate computed here from its
+    // demands (lane l then holds it in `own`), so the walk never depends on
+    // the workgroup that owns that tile having started.
     const int lane = tid;
     int64_t E = 0;
     if (t == 0) {
@@ -447,30 +455,67 @@ __device__ __forceinline__ bool round_tile(DevCtl *c, uint8_t *__restrict__ deci
     } else {
       if (lane == 0) st_relaxed(&flags[t], pack_flag(epoch, FL_AGG, A));
       long long p = t - 1;
+      int32_t waited = 0;
+      bool has_own = false;
+      int64_t own = 0;
       for (;;) {
         const long long qq = p - lane;
         const unsigned long long f =
             qq >= 0 ? ld_relaxed(&flags[qq]) : pack_flag(epoch, FL_INC, 0);
-        const uint64_t st = (f >> 46) & 3;
-        const bool valid = uint32_t(f >> 48) == epoch && st != 0;
+        uint64_t st = (f >> 46) & 3;
+        bool valid = uint32_t(f >> 48) == epoch && st != 0;
+        int64_t fv = int64_t(f & VMASK);
+        if (!valid && has_own) {
+          valid = true;
+          st = FL_AGG;
+          fv = own;
+        }
         const uint64_t inc_b = __ballot(valid && st == FL_INC);
         const uint64_t bad_b = __ballot(!valid);
         const int fi = inc_b ? __builtin_ctzll(inc_b) : WAVE;
         const uint64_t need = fi >= WAVE - 1 ? ~0ULL : ((2ULL << fi) - 1);
         if (bad_b & need) {
           // a predecessor that saw the break marker first may never publish
-          if (ld_relaxed(&c->break_tile[s]) < t) {
+          // (the marker is read once for the whole wave)
+          const long long bt = ld_relaxed(&c->break_tile[s]);
+          const long long btw = (long long)(((unsigned long long)__builtin_amdgcn_readfirstlane(
+                                                 int(uint64_t(bt) >> 32)) << 32) |
+                                            uint32_t(__builtin_amdgcn_readfirstlane(int(bt))));
+          if (btw < t) {
             E = cap;
             break;
           }
-          __builtin_amdgcn_s_sleep(1);
+          if (waited < polls) {
+            ++waited;
+            __builtin_amdgcn_s_sleep(1);
+            continue;
+          }
+          // the nearest missing predecessor: sum its candidates (every
+          // lane with qq < 0 is valid, so q >= 0; q < t < n_tiles)
+          const int b = __builtin_ctzll(bad_b & need);
+          const int64_t qbase = start + int64_t(p - b) * TILE;
+          int64_t part = 0;
+          for (int k = 0; k < TILE / WAVE; ++k) {
+            const int64_t pos = qbase + int64_t(k) * WAVE + lane;
+            if (pos < end) {
+              const int64_t v = demand[pos & mask];
+              if (v >= 0 && (!filter || v <= R)) part = sat_add(part, v, cap);
+            }
+          }
+          const int64_t agg = wave_sum(part);  // <= 64 * cap, no overflow
+          if (lane == b) {
+            has_own = true;
+            own = agg < cap ? agg : cap;
+          }
+          waited = 0;
           continue;
         }
-        const int64_t v = lane <= fi ? int64_t(f & VMASK) : 0;
+        const int64_t v = lane <= fi ? fv : 0;
         const int64_t w = wave_sum(v);  // <= 64 * cap, no overflow
         E = sat_add(E, w < cap ? w : cap, cap);
         if (fi < WAVE || E >= cap) break;
         p -= WAVE;
+        has_own = false;
       }
       if (lane == 0) st_relaxed(&flags[t], pack_flag(epoch, FL_INC, sat_add(E, A, cap)));
     }
@@ -560,28 +605,17 @@ __device__ __forceinline__ bool round_tile(DevCtl *c, uint8_t *__restrict__ deci
   return false;
 }
 
-// Tiles are handed out in tickets of TILES_PER_TICKET consecutive tiles: a
-// quarter of the ticket atomics (one counter serves the whole grid).  A
-// workgroup takes its next ticket while it decides the current one and loads
-// each tile while the one before it is decided (the first tile of the next
-// ticket during the last tile of this one).  A tile's look-back only waits
-// for lower tiles, which belong to earlier tickets (held by running
-// workgroups, which never wait for a higher tile) or come earlier in the same
-// ticket.
-constexpr int TILES_PER_TICKET = 4;
-__device__ __forceinline__ long long take_ticket(DevCtl *c, int s, long long n_tiles) {
-  const long long k = (long long)add_relaxed(&c->ticket[s], 1ULL);
-  const long long t0 = k * TILES_PER_TICKET;
-  const long long bt = ld_relaxed(&c->break_tile[s]);
-  return (t0 < n_tiles && t0 <= bt) ? t0 : -1;
-}
-
+// Workgroup b of G decides tiles b, b + G, b + 2G, ... in that order, and
+// loads each tile while the one before it is decided.  It stops at the end of
+// the queue or past the round's break (the marker is read by one thread and
+// shared through LDS, so every thread takes the same branch).  The loop is
+// unrolled by two so that both tile buffers stay in registers.
 __global__ __launch_bounds__(RND_THREADS) void k_round(DevCtl *c, const int64_t *__restrict__ demand,
                                                        uint8_t *__restrict__ decision, int64_t mask,
                                                        unsigned long long *flags, uint32_t L,
-                                                       uint32_t epoch) {
+                                                       uint32_t epoch, int32_t polls) {
   __shared__ int64_t red[RND_THREADS / WAVE];
-  __shared__ long long s_tk[2];  // next ticket, by iteration parity
+  __shared__ long long s_bt;
   __shared__ int64_t s_E;
   __shared__ int64_t s_brk_sum;
   const int tid = threadIdx.x;
@@ -596,54 +630,50 @@ __global__ __launch_bounds__(RND_THREADS) void k_round(DevCtl *c, const int64_t 
   const int64_t cap = R + 1;
   const bool filter = c->filter != 0;
   const long long n_tiles = (end - start + TILE - 1) / TILE;
+  const long long G = gridDim.x;
   // thread 0's totals over the whole tiles this workgroup decided
   int64_t acc_sum = 0, acc_cnt = 0, acc_hi = -1;
-
-  if (tid == 0) s_tk[1] = take_ticket(c, s, n_tiles);
-  __syncthreads();
-  long long t0 = s_tk[1];
-  int64_t xa[RND_ITEMS], xb[RND_ITEMS];
-  if (t0 >= 0) round_load(demand, mask, start + int64_t(t0) * TILE, end, xa);
-  for (int it = 0;; ++it) {
-    if (t0 < 0) {
-      if (tid == 0) {
-        if (acc_cnt) {
-          add_relaxed(&c->p_admitted, acc_cnt);
-          max_relaxed(&c->p_hi, acc_hi);
-        }
-        block_done(c, s, nx, acc_sum, R, end, gridDim.x);
-      }
-      break;
-    }
-    const int par = it & 1;
-    // read by the other threads only after the first tile's barriers
-    if (tid == 0) s_tk[par] = take_ticket(c, s, n_tiles);
-    bool next_loaded = false, past = false;
-#pragma unroll
-    for (int u = 0; u < TILES_PER_TICKET; ++u) {
-      const long long t = t0 + u;
-      if (t >= n_tiles) break;
-      if (u + 1 < TILES_PER_TICKET) {
-        if (t + 1 < n_tiles)
-          round_load(demand, mask, start + int64_t(t + 1) * TILE, end, (u & 1) ? xa : xb);
-      } else if (u > 0) {
-        const long long tn = s_tk[par];
-        if (tn >= 0) {
-          round_load(demand, mask, start + int64_t(tn) * TILE, end, xa);
-          next_loaded = true;
-        }
-      }
-      past = round_tile(c, decision, mask, flags, s, nx, epoch, R, cap, filter, end, t,
-                        start + int64_t(t) * TILE, (u & 1) ? xb : xa, red, s_E, s_brk_sum,
-                        acc_sum, acc_cnt, acc_hi);
-      if (past) break;
-    }
+  // The tile after t for this workgroup, or -1.  Thread 0 reads the break
+  // marker before t is decided (so the read overlaps that work; a marker
+  // set meanwhile is seen one tile later, and a tile past the break finds
+  // that out itself) and shares it through LDS after t, so that every
+  // thread takes the same branch.
+  long long bt = LLONG_MAX;
+  auto next_tile = [&](long long t) -> long long {
+    if (tid == 0) s_bt = bt;
     __syncthreads();
-    // past the break, so is every later tile: leave them unpublished (a
-    // later look-back that meets them reads the break marker instead)
-    const long long tn = past ? -1 : s_tk[par];
-    if (!next_loaded && tn >= 0) round_load(demand, mask, start + int64_t(tn) * TILE, end, xa);
-    t0 = tn;
+    const long long tn = t + G;
+    return (tn < n_tiles && tn <= s_bt) ? tn : -1;
+  };
+
+  long long t = (long long)blockIdx.x < n_tiles ? (long long)blockIdx.x : -1;
+  int64_t xa[RND_ITEMS], xb[RND_ITEMS];
+  if (t >= 0) round_load(demand, mask, start + int64_t(t) * TILE, end, xa);
+  while (t >= 0) {
+    if (tid == 0) bt = ld_relaxed(&c->break_tile[s]);
+    long long tn = t + G < n_tiles ? t + G : -1;
+    if (tn >= 0) round_load(demand, mask, start + int64_t(tn) * TILE, end, xb);
+    if (round_tile(c, demand, decision, mask, flags, s, nx, epoch, polls, R, cap, filter, start,
+                   end, t, start + int64_t(t) * TILE, xa, red, s_E, s_brk_sum, acc_sum, acc_cnt,
+                   acc_hi))
+      break;
+    t = next_tile(t);
+    if (t < 0) break;
+    if (tid == 0) bt = ld_relaxed(&c->break_tile[s]);
+    tn = t + G < n_tiles ? t + G : -1;
+    if (tn >= 0) round_load(demand, mask, start + int64_t(tn) * TILE, end, xa);
+    if (round_tile(c, demand, decision, mask, flags, s, nx, epoch, polls, R, cap, filter, start,
+                   end, t, start + int64_t(t) * TILE, xb, red, s_E, s_brk_sum, acc_sum, acc_cnt,
+                   acc_hi))
+      break;
+    t = next_tile(t);
+  }
+  if (tid == 0) {
+    if (acc_cnt) {
+      add_relaxed(&c->p_admitted, acc_cnt);
+      max_relaxed(&c->p_hi, acc_hi);
+    }
+    block_done(c, s, nx, acc_sum, R, end, gridDim.x);
   }
 }
 
@@ -1137,14 +1167,14 @@ int adm_engine_init(AdmEngine &e, int device, int64_t max_entries) {
   SCHED_HIP_TRY(hipMemset(e.d_flags, 0, sizeof(unsigned long long) * e.max_tiles));
   int cus = 0;
   SCHED_HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device));
-  // the round grid is at most what the device holds at once: more workgroups
-  // only add ticket traffic (tiles are handed out dynamically anyway).  Two
-  // per CU stream a candidate-free round faster than three (each workgroup
-  // walks 4 consecutive tiles per ticket, and fewer concurrent streams of
-  // 128 KiB spread better over the HBM channels).
+  // The round grid: three workgroups per CU (at most what the device holds
+  // at once).  With tiles dealt in interleaved order a candidate-free round
+  // of 2^26 entries streams in ~111 us with three or four per CU and ~118 us
+  // with two: each workgroup keeps two tiles of loads in flight, so the
+  // third adds the memory parallelism a round needs; a fourth adds nothing.
   int per_cu = 0;
   SCHED_HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_round, RND_THREADS, 0));
-  per_cu = per_cu < 1 ? 1 : (per_cu > 2 ? 2 : per_cu);
+  per_cu = per_cu < 1 ? 1 : (per_cu > 3 ? 3 : per_cu);
   e.round_grid = cus * per_cu;
   e.launch = 1;
   e.epoch = 0;
@@ -1207,6 +1237,11 @@ static void fill_out(const PassSummary &h, PassOut *out) {
   out->released_bytes = h.released_bytes;
 }
 
+// Polls a round's look-back makes on a missing predecessor before it sums
+// that predecessor's candidates itself (process-wide).
+static std::atomic<int32_t> g_lookback_polls{LOOKBACK_POLLS_DEFAULT};
+void adm_set_lookback_polls(int32_t polls) { g_lookback_polls.store(polls); }
+
 // Round kernels until the pass recorded in slot L & 3 is done; returns the
 // launch id whose slot holds the final state.
 static int run_rounds(AdmEngine &e, const int64_t *demand, uint8_t *decision, int64_t mask,
@@ -1223,7 +1258,8 @@ static int run_rounds(AdmEngine &e, const int64_t *demand, uint8_t *decision, in
       if (int rc = next_epoch(e, s, &ep)) return rc;
       SCHED_PROF_LAUNCH("k_round", s,
                         (k_round<<<grid, RND_THREADS, 0, s>>>(e.d_ctl, demand, decision, mask,
-                                                              e.d_flags, L, ep)));
+                                                              e.d_flags, L, ep,
+                                                              g_lookback_polls.load())));
       SCHED_HIP_TRY(hipGetLastError());
       L = advance(e);
     }

@@ -716,6 +716,12 @@ extern "C" int sched_reset(sched_ctx_t *c) {
   return SCHED_OK;
 }
 
+extern "C" int sched_set_lookback_polls(int32_t polls) {
+  if (polls < 0) return SCHED_E_INVALID;
+  adm_set_lookback_polls(polls);
+  return SCHED_OK;
+}
+
 extern "C" const char *sched_version(void) { return "sched-mi355x 0.1 (gfx950)"; }
 
 // ---------------------------------------------------------------------------

@@ -64,6 +64,25 @@ def test_scan_adversarial_rounds(cs, wl):
     _check(cs, cs.SCHED_POLICY_MMU, d, R, wl)
 
 
+@pytest.mark.parametrize("pol", [0, 1])
+def test_scan_lookback_computes_missing_sums(cs, pol):
+    """With no polling at all, a look-back that meets a predecessor tile which
+    has not published its sum yet computes that sum from the tile's demands
+    itself.  Decisions stay equal to the oracle's (1 to 80 tiles, grid rounds
+    from the start, breaks in many tiles)."""
+    assert cs.sched_set_lookback_polls(-1) == cs.SCHED_E_INVALID
+    assert cs.sched_set_lookback_polls(0) == 0
+    try:
+        for n in (4097, 3 * 4096 + 17, 50_000, 80 * 4096 - 3):
+            rng = np.random.default_rng(n + pol)
+            d = random_queue(int(rng.integers(1 << 30)), n, 1000, holes=0.05)
+            tot = int(d[d >= 0].sum())
+            for R in sorted({999, tot // 3, max(tot - 1, 0), tot + 5}):
+                _check(cs, pol, d, R, 0)
+    finally:
+        assert cs.sched_set_lookback_polls(2048) == 0
+
+
 @pytest.mark.parametrize("wl", [0, 16])
 def test_scan_c2_pass0(cs, wl):
     q = c2_queue(seed=2)
