@@ -215,18 +215,26 @@ def test_ctx_chain_equals_oracle(cs, policy, seed, n):
         cs.sched_destroy(ctx)
 
 
+# (jobs, requests, rounds, capacity, demand bound): "few" repeats jobs often;
+# "many" admits tens of thousands of requests per pass, so the running list
+# outgrows the part the chain keeps in LDS and admissions reach past the queue
+# entries whose release bytes are fetched ahead
+CHAIN_SHAPES = {"few": (300, 2000, 12, 10**6, 10**6 // 40),
+                "many": (60_000, 60_000, 6, 2 * 10**7, 1000)}
+
+
 @pytest.mark.parametrize("policy", [0, 1])
-@pytest.mark.parametrize("seed", [11, 12])
-def test_ctx_chain_repeated_jobs(cs, policy, seed):
+@pytest.mark.parametrize("seed,shape", [(11, "few"), (12, "few"), (13, "many")])
+def test_ctx_chain_repeated_jobs(cs, policy, seed, shape):
     """Chain rounds where jobs have several requests in the queue: a job can be
     released and admitted again within one chain, and several of its requests
     can be admitted by one pass.  Reference: per round, every masked job that
     holds a reservation releases all of it (Sec. IV post-free, 0 bytes), then
     one oracle pass (Sec. V) runs over the waiting requests in order."""
     rng = np.random.default_rng(seed)
-    n_jobs, n_req, rounds, C = 300, 2000, 12, 10**6
+    n_jobs, n_req, rounds, C, dmax = CHAIN_SHAPES[shape]
     job = rng.integers(0, n_jobs, n_req).astype(np.int32)
-    dem = rng.integers(1, C // 40, n_req).astype(np.int64)
+    dem = rng.integers(1, dmax, n_req).astype(np.int64)
     masks = (rng.random((rounds - 1, n_jobs)) < 0.4).astype(np.uint8)
     # reference
     res = np.zeros(n_jobs, np.int64)
@@ -252,7 +260,10 @@ def test_ctx_chain_repeated_jobs(cs, policy, seed):
         used = C - R2
         pend = pend[~adm]
         ref.append((job[got].astype(np.int64), R2, rel_jobs, rel_bytes))
-    rc, ctx = cs.sched_create(policy=policy, capacity_bytes=C, max_jobs=n_jobs, queue_capacity=4096)
+    if shape == "many":
+        assert ref[0][0].size > 12288 and max(x[0].size for x in ref[1:]) > 1536
+    rc, ctx = cs.sched_create(policy=policy, capacity_bytes=C, max_jobs=n_jobs,
+                              queue_capacity=1 << int(np.ceil(np.log2(max(n_req, 4096)))))
     assert rc == 0
     try:
         assert cs.sched_register_batch(ctx, n_jobs)[0] == 0
