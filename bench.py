@@ -571,7 +571,10 @@ def main():
             "window_walk_ms": ms_w / args.dense_reps, "round_kernel_ms": ms / args.dense_reps,
             "GBps_round_kernel": bytes_pass / (ms * 1e-3 / args.dense_reps) / 1e9,
             "round_frac_of_peak": bytes_pass / (ms * 1e-3 / args.dense_reps) / 1e9 / HBM_PEAK_GBS,
-            "fixed_point_ok": bool(ok)}
+            "fixed_point_ok": bool(ok),
+            # HBM bytes per grid round measured with FETCH_SIZE / WRITE_SIZE
+            # (committed record; None once the kernel's source has changed)
+            "round_traffic_bytes": traffic_for("k_round"), "round_algorithmic_bytes": bytes_pass}
         del dd, dec
 
     if "tenants" in extras:
