@@ -314,7 +314,7 @@ int sched_scan(int32_t policy, int64_t n, const int64_t *d_demand, int64_t R, ui
 
 /* Look-back bound of the grid rounds (the HBM-bound part of a pass: a
  * single-pass prefix scan across workgroups, Sec. V policies).  A tile waits
- * for a predecessor's published sum at most `polls` polls (default 2048),
+ * for a predecessor's published sum at most `polls` polls (default 256),
  * then sums that predecessor's demands itself; results do not depend on it.
  * 0 makes every look-back compute missing sums at once (used by tests to
  * exercise that path).  Process-wide; applies to rounds launched afterwards.

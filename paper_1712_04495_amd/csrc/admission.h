@@ -73,7 +73,7 @@ struct PassSummary {
   int32_t done, pad;
 };
 constexpr int MAX_CHAIN = 256;
-constexpr int32_t LOOKBACK_POLLS_DEFAULT = 2048;
+constexpr int32_t LOOKBACK_POLLS_DEFAULT = 256;
 void adm_set_lookback_polls(int32_t polls);
 
 struct AdmEngine {

@@ -80,7 +80,7 @@ def test_scan_lookback_computes_missing_sums(cs, pol):
             for R in sorted({999, tot // 3, max(tot - 1, 0), tot + 5}):
                 _check(cs, pol, d, R, 0)
     finally:
-        assert cs.sched_set_lookback_polls(2048) == 0
+        assert cs.sched_set_lookback_polls(256) == 0      # the library default
 
 
 @pytest.mark.parametrize("wl", [0, 16])
