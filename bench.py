@@ -544,7 +544,9 @@ def main():
         dec = torch.zeros(qd.n, dtype=torch.uint8, device=dev)
         rc, r0 = cs.sched_scan(cs.SCHED_POLICY_MMU, dd, qd.capacity, dec, window_limit=args.dense_window)
         assert rc == 0
-        cs.sched_profile(True)
+        # whole passes timed without kernel timing (its events cost time of
+        # their own), then the kernels timed over as many passes again
+        torch.cuda.synchronize()
         t1 = time.perf_counter()
         for _ in range(args.dense_reps):
             rc, r = cs.sched_scan(cs.SCHED_POLICY_MMU, dd, qd.capacity, dec,
@@ -552,6 +554,12 @@ def main():
             assert rc == 0
         torch.cuda.synchronize()
         ddt = (time.perf_counter() - t1) / args.dense_reps
+        cs.sched_profile(True)
+        for _ in range(args.dense_reps):
+            rc, r = cs.sched_scan(cs.SCHED_POLICY_MMU, dd, qd.capacity, dec,
+                                  window_limit=args.dense_window)
+            assert rc == 0
+        torch.cuda.synchronize()
         rc, ms, launches = cs.sched_profile_read("k_round")
         rc, ms_w, launches_w = cs.sched_profile_read("k_window")
         cs.sched_profile(0)
