@@ -680,12 +680,17 @@ extern "C" int sched_scan(int32_t policy, int64_t n, const int64_t *d_demand, in
   return SCHED_OK;
 }
 
-__global__ void k_reset_jobs(DevCtl *c, JobArrays jb) {
-  for (int64_t j = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; j < jb.max_jobs;
-       j += int64_t(gridDim.x) * blockDim.x) {
+// Reservations, states and the queue's decision bytes (q_cap of them, a power
+// of two >= 256, 16-byte aligned) to zero in one launch.
+__global__ void k_reset_jobs(DevCtl *c, JobArrays jb, uint8_t *decision, int64_t q_cap) {
+  const int64_t t0 = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
+  const int64_t stride = int64_t(gridDim.x) * blockDim.x;
+  for (int64_t j = t0; j < jb.max_jobs; j += stride) {
     jb.res[j] = 0;
     jb.state[j] = 0;
   }
+  uint4 *d16 = reinterpret_cast<uint4 *>(decision);
+  for (int64_t i = t0; i < q_cap / 16; i += stride) d16[i] = make_uint4(0, 0, 0, 0);
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     c->used = 0;
     c->head = 0;
@@ -701,9 +706,12 @@ extern "C" int sched_reset(sched_ctx_t *c) {
   if (!c) return SCHED_E_INVALID;
   std::lock_guard<std::mutex> g(c->mu);
   SCHED_HIP_TRY(hipSetDevice(c->device));
-  k_reset_jobs<<<256, 256, 0, c->stream>>>(c->eng.d_ctl, c->jb);
+  {
+    const int64_t items = std::max<int64_t>(c->jb.max_jobs, c->q.capacity / 16);
+    const int grid = int(std::min<int64_t>((items + 255) / 256, 4096));
+    k_reset_jobs<<<grid, 256, 0, c->stream>>>(c->eng.d_ctl, c->jb, c->q.decision, c->q.capacity);
+  }
   SCHED_HIP_TRY(hipGetLastError());
-  if (int rc = adm_zero_decisions(c->q.decision, c->q.capacity, c->stream)) return rc;
   c->reset_pending = true;
   // pending[j] counts the host-side waiting requests of job j, which are
   // exactly the entries of host_seq naming j
