@@ -178,7 +178,8 @@ def hol_run(cs, n_streams=3):
 
 def c2_step(cs, ctx, d_job, d_dem, coins):
     """reset + intake of the whole queue + the release/admit rounds chained
-    on the device (one host synchronisation per step)."""
+    on the device.  Two host synchronisations per step: the intake waits for
+    its validity verdict, the chain for its round summaries."""
     assert cs.sched_reset(ctx) == 0
     assert cs.sched_enqueue_batch(ctx, d_job, d_dem) == 0
     rc, res = cs.sched_pass_chain_array(ctx, coins.shape[0] + 1, coins)
