@@ -246,3 +246,39 @@ def test_recovered_dead_holder_is_reclaimed(cs):
     finally:
         cs.sched_destroy(ctx)
         cs.sched_destroy(ctx2)
+
+
+def test_restore_needs_room_for_the_waiting_requests(cs):
+    """A record with more waiting requests than the target's queue holds is
+    refused (the target stays fresh); a large enough queue takes it."""
+    rc, ctx = cs.sched_create(policy=0, capacity_bytes=1000, max_jobs=4, queue_capacity=1024)
+    assert rc == 0
+    made = [ctx]
+    try:
+        ref = S.Scheduler(1000, S.FIFO)
+        a = cs.sched_register(ctx, 0, 50)[1]
+        b = cs.sched_register(ctx, 0, 50)[1]
+        ref.register(0, 50)
+        ref.register(0, 50)
+        assert cs.sched_admit(ctx, a, 0, 1000, cs.SCHED_NONBLOCK) == ref.admit(a, 0, 1000) == 0
+        for _ in range(300):
+            assert cs.sched_admit(ctx, b, 0, 1, cs.SCHED_NONBLOCK) == ref.admit(b, 0, 1) == 1
+        rc, rec = cs.sched_checkpoint(ctx)
+        assert rc == 0 and rec == CK.encode(ref) and len(rec) == 64 + 2 * 24 + 300 * 16
+        rc, small = cs.sched_create(policy=0, capacity_bytes=1000, max_jobs=4, queue_capacity=256)
+        assert rc == 0
+        made.append(small)
+        assert cs.sched_restore(small, rec) == cs.SCHED_E_INVALID
+        assert cs.sched_checkpoint(small) == (0, CK.encode(S.Scheduler(1000, S.FIFO)))
+        rc, big = cs.sched_create(policy=0, capacity_bytes=1000, max_jobs=4, queue_capacity=512)
+        assert rc == 0
+        made.append(big)
+        assert cs.sched_restore(big, rec) == 0
+        assert cs.sched_checkpoint(big) == (0, rec)
+        # the restored waiters are served once a frees its memory (FIFO, in order)
+        ref2 = CK.restore(rec, S.FIFO, 1000, 4)
+        assert cs.sched_release(big, a, -1, 0) == ref2.release(a, -1, 0) == 0
+        assert cs.sched_reservation(big, b) == (0, ref2.jobs[b]["res"]) and ref2.jobs[b]["res"] == 300
+    finally:
+        for c in made:
+            cs.sched_destroy(c)
