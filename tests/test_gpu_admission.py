@@ -83,6 +83,36 @@ def test_scan_lookback_computes_missing_sums(cs, pol):
         assert cs.sched_set_lookback_polls(256) == 0      # the library default
 
 
+def test_scan_grid_rounds_beside_a_busy_device(cs):
+    """Grid rounds (many breaks, so tiles look back) while a long triad on
+    another stream holds compute units: some round workgroups start late, and
+    look-backs that outwait the poll bound sum the missing tiles themselves.
+    Decisions equal those of the same scan on an idle device and form the
+    first-fit fixed point."""
+    n = 1 << 21
+    d = random_queue(77, n, 1000, holes=0.05)
+    R = int(d[d >= 0].sum()) // 3
+    ref_dec, ref_r = _scan(cs, cs.SCHED_POLICY_MMU, d, R, 0)
+    assert S.first_fit_fixed_point(d, R, ref_dec.astype(bool)) and ref_r["rounds"] >= 3
+    m = 1 << 27
+    a = torch.empty(m, dtype=torch.float32, device=DEV)
+    b, c = torch.empty_like(a), torch.empty_like(a)
+    assert cs.sched_triad_fill(b, c, 3) == 0
+    torch.cuda.synchronize()
+    busy, scan_s = torch.cuda.Stream(), torch.cuda.Stream()
+    dd = torch.from_numpy(d).to(DEV)
+    dec = torch.full((n,), 7, dtype=torch.uint8, device=DEV)
+    torch.cuda.synchronize()
+    assert cs.sched_triad(a, b, c, 3.0, 40, stream=busy) == 0
+    rc, r = cs.sched_scan(cs.SCHED_POLICY_MMU, dd, R, dec, write_all=1, window_limit=0,
+                          stream=scan_s)
+    assert rc == 0
+    torch.cuda.synchronize()
+    got = dec.cpu().numpy()
+    assert np.array_equal(got, ref_dec)
+    assert r["free_after"] == ref_r["free_after"] and r["rounds"] == ref_r["rounds"]
+
+
 @pytest.mark.parametrize("wl", [0, 16])
 def test_scan_c2_pass0(cs, wl):
     q = c2_queue(seed=2)
