@@ -15,6 +15,7 @@ Conventions shared with the C-ABI contract (stated, not imported):
 """
 from __future__ import annotations
 
+import itertools
 from dataclasses import dataclass, field
 
 import numpy as np
@@ -40,10 +41,18 @@ def fifo_pass(demand, R: int):
     the next one is served; the first client that does not fit stops the pass.
 
     The admitted set is therefore the longest prefix of present entries whose
-    demand sum is <= R.  Returns (admit: bool[n], R_after)."""
+    demand sum is <= R.  Returns (admit: bool[n], R_after).
+
+    The prefix sums are exact for any int64 demands: numpy's int64 cumsum is
+    used only when no sum can leave the int64 range, Python integers
+    otherwise."""
     d = np.asarray(demand, dtype=np.int64)
     present = d >= 0
-    S = np.cumsum(np.where(present, d, 0))
+    if d.size == 0 or int(d.max()) * d.size < 2**63:
+        S = np.cumsum(np.where(present, d, 0))
+    else:
+        S = np.fromiter(itertools.accumulate(v if v >= 0 else 0 for v in d.tolist()),
+                        dtype=object, count=d.size)
     over = np.nonzero(present & (S > R))[0]
     k = int(over[0]) if over.size else d.size
     admit = present.copy()

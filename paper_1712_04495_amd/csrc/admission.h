@@ -90,9 +90,13 @@ struct AdmEngine {
   int round_grid = 0;               // persistent grid of the round kernel
   int rounds_per_check = 1;         // round launches between host checks
   int device = 0;
+  bool sum_copy = false;            // d_sum is plain device memory: copy it to h_sum
 };
 
 int adm_engine_init(AdmEngine &e, int device, int64_t max_entries);
+// The round kernel's persistent grid for the device (sets e.round_grid).
+int adm_engine_grid(AdmEngine &e, int device);
+int adm_fill_u64(unsigned long long *p, int64_t n, unsigned long long v, hipStream_t s);
 void adm_engine_free(AdmEngine &e);
 
 struct PassOut {

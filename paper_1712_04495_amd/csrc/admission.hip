@@ -418,12 +418,17 @@ __device__ __forceinline__ bool round_tile(DevCtl *c, const int64_t *__restrict_
   const int tid = threadIdx.x;
   int64_t x[RND_ITEMS];
   int64_t tsum = 0;
+  // Candidates are clamped to cap = R + 1 (only FIFO, which does not filter,
+  // sees larger ones): a prefix exceeds R exactly when the unclamped one
+  // does, and every sum below stays under 2^59, so no addition can wrap
+  // whatever the int64 demands are.
 #pragma unroll
   for (int j = 0; j < RND_ITEMS; ++j) {
     const int64_t v = raw[j];
     const bool cd = v >= 0 && (!filter || v <= R);
-    x[j] = cd ? v : -1;
-    tsum += cd ? v : 0;
+    const int64_t vc = v < cap ? v : cap;
+    x[j] = cd ? vc : -1;
+    tsum += cd ? vc : 0;
   }
   const int64_t Araw = block_sum<RND_THREADS>(tsum, red);
   const int64_t A = Araw < cap ? Araw : cap;
@@ -499,7 +504,7 @@ __device__ __forceinline__ bool round_tile(DevCtl *c, const int64_t *__restrict_
             const int64_t pos = qbase + int64_t(k) * WAVE + lane;
             if (pos < end) {
               const int64_t v = demand[pos & mask];
-              if (v >= 0 && (!filter || v <= R)) part = sat_add(part, v, cap);
+              if (v >= 0 && (!filter || v <= R)) part = sat_add(part, v < cap ? v : cap, cap);
             }
           }
           const int64_t agg = wave_sum(part);  // <= 64 * cap, no overflow
@@ -1165,6 +1170,13 @@ int adm_engine_init(AdmEngine &e, int device, int64_t max_entries) {
   SCHED_HIP_TRY(hipHostGetDevicePointer((void **)&e.d_flag, e.h_flag, 0));
   SCHED_HIP_TRY(hipMalloc(&e.d_flags, sizeof(unsigned long long) * e.max_tiles));
   SCHED_HIP_TRY(hipMemset(e.d_flags, 0, sizeof(unsigned long long) * e.max_tiles));
+  if (int rc = adm_engine_grid(e, device)) return rc;
+  e.launch = 1;
+  e.epoch = 0;
+  return SCHED_OK;
+}
+
+int adm_engine_grid(AdmEngine &e, int device) {
   int cus = 0;
   SCHED_HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device));
   // The round grid: three workgroups per CU (at most what the device holds
@@ -1176,8 +1188,13 @@ int adm_engine_init(AdmEngine &e, int device, int64_t max_entries) {
   SCHED_HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_round, RND_THREADS, 0));
   per_cu = per_cu < 1 ? 1 : (per_cu > 3 ? 3 : per_cu);
   e.round_grid = cus * per_cu;
-  e.launch = 1;
-  e.epoch = 0;
+  return SCHED_OK;
+}
+
+int adm_fill_u64(unsigned long long *p, int64_t n, unsigned long long v, hipStream_t s) {
+  if (n <= 0) return SCHED_OK;
+  k_fill_u64<<<grid_for(n, 256, 4096), 256, 0, s>>>(p, n, v);
+  SCHED_HIP_TRY(hipGetLastError());
   return SCHED_OK;
 }
 
@@ -1218,6 +1235,8 @@ static int next_epoch(AdmEngine &e, hipStream_t s, uint32_t *ep) {
 static int read_summary(AdmEngine &e, uint32_t L, hipStream_t s) {
   k_summary<<<1, 64, 0, s>>>(e.d_ctl, L, e.d_sum);
   SCHED_HIP_TRY(hipGetLastError());
+  if (e.sum_copy)
+    SCHED_HIP_TRY(hipMemcpyAsync(e.h_sum, e.d_sum, sizeof(PassSummary), hipMemcpyDeviceToHost, s));
   SCHED_HIP_TRY(hipStreamSynchronize(s));
   return SCHED_OK;
 }

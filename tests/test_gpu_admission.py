@@ -56,6 +56,41 @@ def test_scan_random(cs, n, wl, pol):
         _check(cs, pol, d, R, wl)
 
 
+def _huge_queue(seed, n):
+    """Small demands with entries near 2^62 mixed in (a few per tile): the
+    int64 sums of such a queue wrap unless candidates are clamped."""
+    rng = np.random.default_rng(seed)
+    d = random_queue(int(rng.integers(1 << 30)), n, 1000, holes=0.05)
+    big = rng.random(n) < 0.01
+    d[big] = (1 << 62) - rng.integers(0, 1 << 20, int(big.sum()))
+    return d
+
+
+@pytest.mark.parametrize("n", [5, 4097, 3 * 4096 + 17, 50_000])
+@pytest.mark.parametrize("wl", [0, 1])
+@pytest.mark.parametrize("pol", [0, 1])
+def test_scan_huge_demands(cs, n, wl, pol):
+    """Demands near 2^62 (any non-negative int64 is a valid demand): under
+    FIFO no candidate is filtered, so the grid round's tile sums, its break
+    scan and its look-back self-sums must not wrap.  The first case is
+    [1, 2^62, 2^62, 2^62, 2^62] at R = 10: only the first entry fits."""
+    if n == 5:
+        d = np.array([1] + [1 << 62] * 4, np.int64)
+        Rs = [10]
+    else:
+        d = _huge_queue(n + wl, n)
+        small = d[(d >= 0) & (d < (1 << 40))]
+        Rs = [10, int(small.sum()) // 2, int(small.sum()) + 5]
+    for R in Rs:
+        _check(cs, pol, d, R, wl)
+    assert cs.sched_set_lookback_polls(0) == 0     # every look-back sums its predecessors
+    try:
+        for R in Rs:
+            _check(cs, pol, d, R, 0)
+    finally:
+        assert cs.sched_set_lookback_polls(256) == 0
+
+
 @pytest.mark.parametrize("wl", [0, 4])
 def test_scan_adversarial_rounds(cs, wl):
     # [1, R, 1, R-1, ...]: every round admits one entry and breaks on the next

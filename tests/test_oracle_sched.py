@@ -386,3 +386,41 @@ def test_set_owner_rejects_bad_args():
     sc = S.Scheduler(capacity=100)
     a = sc.register()
     assert sc.set_owner(a, -1) == S.E_INVALID and sc.set_owner(7, 1) == S.E_INVALID
+
+
+def _fifo_python(d, R):
+    """Policy 1 with Python integers, entry by entry (no numpy sums)."""
+    admit, s = [], 0
+    for v in d:
+        v = int(v)
+        if v < 0:
+            admit.append(False)
+            continue
+        if s + v > R:
+            break
+        s += v
+        admit.append(True)
+    admit += [False] * (len(d) - len(admit))
+    return np.array(admit, bool), R - s
+
+
+@pytest.mark.parametrize("seed", range(20))
+def test_fifo_pass_exact_for_huge_demands(seed):
+    """Demands near 2^62: the prefix sums leave the int64 range, where an
+    int64 cumsum wraps (five such demands after a 1 sum to 1 modulo 2^64 and
+    would read as fitting R = 10).  The pass equals the entry-by-entry Python
+    integer walk."""
+    d = np.array([1] + [1 << 62] * 4, np.int64)
+    a, R2 = S.fifo_pass(d, 10)
+    assert list(a) == [True, False, False, False, False] and R2 == 9
+    rng = np.random.default_rng(seed)
+    n = int(rng.integers(1, 60))
+    d = rng.integers(0, 1000, n).astype(np.int64)
+    big = rng.random(n) < 0.3
+    d[big] = (1 << 62) - rng.integers(0, 1 << 20, int(big.sum()))
+    d[rng.random(n) < 0.1] = -1
+    for R in (0, 10, 5000, (1 << 62) + 7, (1 << 63) - 1):
+        a, R2 = S.fifo_pass(d, R)
+        ra, rR2 = _fifo_python(d, R)
+        assert np.array_equal(a, ra) and R2 == rR2
+        assert S.fifo_prefix_check(d, R, a)
