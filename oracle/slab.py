@@ -98,8 +98,11 @@ def check_log(kind, tenant, size, ref, quotas, pool: int, class_cap, phase_len: 
     first violated invariant; returns a dict of counts otherwise.
 
     Per phase (ops of one phase are concurrent, phases are ordered):
-    * frees: OK exactly when they name an alloc of the same tenant from an
-      earlier phase that succeeded and is not yet freed; otherwise invalid;
+    * frees: a free can succeed only when it names an alloc of the same
+      tenant from an earlier phase that succeeded and is not yet freed; of
+      the frees of one phase that name the same such alloc exactly one
+      succeeds (a block is returned once, Sec. IV), every other free is
+      invalid;
     * successful allocs: inside [pool_base, pool_base + span) (span defaults
       to the pool size) and aligned to their class size;
     * after the phase: live blocks do not overlap, each tenant's charge is
@@ -143,16 +146,18 @@ def check_log(kind, tenant, size, ref, quotas, pool: int, class_cap, phase_len: 
         r = ref[fi]
         valid_ref = (r >= 0) & (r < p0)
         rr = np.where(valid_ref, r, 0)
-        expect_ok = valid_ref & (kind[rr] == OP_ALLOC) & held[rr] & (tenant[rr] == tenant[fi])
-        # one free per alloc is all the generator produces; two frees of one
-        # block in the same phase: only one may succeed
-        if fi.size:
-            uniq, cnt = np.unique(rr[expect_ok], return_counts=True)
-            assert np.all(cnt == 1), "two frees of one block in one phase"
+        can_ok = valid_ref & (kind[rr] == OP_ALLOC) & held[rr] & (tenant[rr] == tenant[fi])
         got_ok = status[fi] == ST_OK
-        bad = np.nonzero(got_ok != expect_ok)[0]
+        bad = np.nonzero(got_ok & ~can_ok)[0]
         assert bad.size == 0, f"free status wrong at op {int(fi[bad[0]])}"
-        assert np.all(status[fi][~expect_ok] == ST_INVALID), "failed free not reported invalid"
+        # every held alloc named in the phase is freed exactly once
+        named, inv = np.unique(rr[can_ok], return_inverse=True)
+        wins = np.bincount(inv, weights=got_ok[can_ok].astype(np.int64), minlength=named.size)
+        bad = np.nonzero(wins != 1)[0]
+        assert bad.size == 0, (f"free status wrong: alloc op {int(named[bad[0]])} freed "
+                               f"{int(wins[bad[0]])} times in one phase")
+        assert np.all(status[fi][~got_ok] == ST_INVALID), "failed free not reported invalid"
+        expect_ok = got_ok
         # --- allocs ----------------------------------------------------------
         ai = idx[is_alloc]
         a_st = status[ai]

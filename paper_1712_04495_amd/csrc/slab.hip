@@ -15,6 +15,11 @@
 //     the start of a phase plus the charges of allocations that got past it;
 //   * a free checks that the block lies in the pool, is aligned, belongs to
 //     the freeing tenant and is live, clears its bit and returns the charges.
+//     Each block's owner word holds (allocating op, tenant); a free takes the
+//     block back with one compare-and-swap of that word to "empty" before it
+//     clears the bit, so of two frees that name one allocation only one can
+//     succeed, and a free can never take a block that a later allocation
+//     (of any tenant) claimed in the meantime.
 // A batch of concurrent ops (a phase) first sums, per tenant and for the
 // pool, the class bytes its allocations could take.  A counter that cannot
 // reach its limit even if all of them succeed needs no compare-and-swap: its
@@ -60,7 +65,7 @@ struct SlabDev {
   int64_t n_words[N_CLASSES];
   int64_t owner_off[N_CLASSES];  // offset of the class owner table in `owner`
   unsigned long long *bits;
-  int32_t *owner;
+  unsigned long long *owner;     // per block: owner_word(op, tenant), or OWNER_EMPTY
   int64_t *charged;              // per tenant
   int64_t *pool_used;            // one counter
   const int64_t *quota;          // per tenant
@@ -68,6 +73,13 @@ struct SlabDev {
   uint8_t *unbounded;            // per tenant, then the pool: 1 = cannot bind this phase
   int32_t n_tenants;
 };
+
+constexpr unsigned long long OWNER_EMPTY = ~0ULL;
+// Owner word of a block: the low 32 bits of the allocating op's index and the
+// tenant.  A phase free names its alloc op, so it must find exactly this word.
+__device__ __forceinline__ unsigned long long owner_word(uint64_t op, int32_t t) {
+  return ((op & 0xffffffffULL) << 32) | uint32_t(t);
+}
 
 constexpr int PH_THREADS = 256;
 constexpr int PH_LDS_TENANTS = 1024;  // tenants aggregated in LDS; beyond: direct atomics
@@ -98,7 +110,8 @@ __device__ __forceinline__ bool charge(int64_t *ctr, int64_t v, int64_t limit) {
   }
 }
 
-__device__ bool slab_claim(const SlabDev &s, int c, int32_t t, uint64_t hint, uint64_t *out_ptr);
+__device__ bool slab_claim(const SlabDev &s, int c, int32_t t, uint64_t hint, uint64_t op,
+                           uint64_t *out_ptr);
 
 // One allocation with every counter charged by compare-and-swap (the
 // single-op entry point).
@@ -112,15 +125,18 @@ __device__ int8_t slab_alloc_one(const SlabDev &s, int32_t t, int64_t size, uint
     add_relaxed(&s.charged[t], -cs);
     return ST_NOMEM_POOL;
   }
-  if (slab_claim(s, c, t, hint, out_ptr)) return ST_OK;
+  if (slab_claim(s, c, t, hint, hint, out_ptr)) return ST_OK;
   add_relaxed(s.pool_used, -cs);
   add_relaxed(&s.charged[t], -cs);
   return ST_NOMEM_CLASS;
 }
 
 // Clears the block's bit if the free is valid; the caller returns the
-// charges (*cs = class bytes on ST_OK).
-__device__ int8_t slab_free_claim(const SlabDev &s, int32_t t, uint64_t ptr, int64_t *cs_out) {
+// charges (*cs = class bytes on ST_OK).  op >= 0: the free names the alloc op
+// that returned ptr, whose owner word the block must still hold; op < 0: any
+// block the tenant holds (the pointer-only single-op free).
+__device__ int8_t slab_free_claim(const SlabDev &s, int32_t t, uint64_t ptr, int64_t op,
+                                  int64_t *cs_out) {
   if (t < 0 || t >= s.n_tenants) return ST_INVALID;
   const uint64_t b0 = uint64_t(s.base);
   if (ptr < b0 || ptr >= b0 + uint64_t(N_CLASSES) * uint64_t(s.region_bytes)) return ST_INVALID;
@@ -131,18 +147,25 @@ __device__ int8_t slab_free_claim(const SlabDev &s, int32_t t, uint64_t ptr, int
   if (roff % cs) return ST_INVALID;
   const int64_t blk = roff / cs;
   if (blk >= s.cap[c]) return ST_INVALID;
-  if (s.owner[s.owner_off[c] + blk] != t) return ST_INVALID;
+  unsigned long long *ow = s.owner + s.owner_off[c] + blk;
+  unsigned long long want = op >= 0 ? owner_word(uint64_t(op), t) : ld_relaxed(ow);
+  if (want == OWNER_EMPTY || int32_t(uint32_t(want)) != t) return ST_INVALID;
+  // taking the owner word first makes the free exclusive: a second free of
+  // the same allocation, or one racing a new claim of the block, fails here
+  if (!__hip_atomic_compare_exchange_strong(ow, &want, OWNER_EMPTY, __ATOMIC_RELAXED,
+                                            __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
+    return ST_INVALID;
   const unsigned long long bit = 1ULL << (blk & 63);
   const unsigned long long old = __hip_atomic_fetch_and(s.bits + s.words_off[c] + (blk >> 6), ~bit,
                                                         __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  if (!(old & bit)) return ST_INVALID;  // not live: double free
+  if (!(old & bit)) return ST_INVALID;  // an owner word on a free block: never written so
   *cs_out = cs;
   return ST_OK;
 }
 
 __device__ int8_t slab_free_one(const SlabDev &s, int32_t t, uint64_t ptr) {
   int64_t cs = 0;
-  const int8_t st = slab_free_claim(s, t, ptr, &cs);
+  const int8_t st = slab_free_claim(s, t, ptr, -1, &cs);
   if (st == ST_OK) {
     add_relaxed(s.pool_used, -cs);
     add_relaxed(&s.charged[t], -cs);
@@ -150,8 +173,10 @@ __device__ int8_t slab_free_one(const SlabDev &s, int32_t t, uint64_t ptr) {
   return st;
 }
 
-// Claims a free block of class c (charges already settled by the caller).
-__device__ bool slab_claim(const SlabDev &s, int c, int32_t t, uint64_t hint, uint64_t *out_ptr) {
+// Claims a free block of class c (charges already settled by the caller) for
+// alloc op `op` of tenant t.
+__device__ bool slab_claim(const SlabDev &s, int c, int32_t t, uint64_t hint, uint64_t op,
+                           uint64_t *out_ptr) {
   const int64_t cs = int64_t(1) << (MIN_LOG2 + c);
   const int64_t nw = s.n_words[c];
   unsigned long long *bits = s.bits + s.words_off[c];
@@ -167,7 +192,7 @@ __device__ bool slab_claim(const SlabDev &s, int c, int32_t t, uint64_t hint, ui
           __hip_atomic_fetch_or(bits + w, bit, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       if (!(old & bit)) {
         const int64_t blk = w * 64 + b;
-        s.owner[s.owner_off[c] + blk] = t;
+        st_relaxed(s.owner + s.owner_off[c] + blk, owner_word(op, t));
         *out_ptr = uint64_t(s.base + int64_t(c) * s.region_bytes + blk * cs);
         return true;
       }
@@ -306,7 +331,7 @@ __global__ __launch_bounds__(PH_THREADS) void k_slab_phase(
         const int64_t r = ref[i];
         if (k == OPK_FREE && r >= 0 && r < begin && kind[r] == OPK_ALLOC && status[r] == ST_OK) {
           int64_t fcs = 0;
-          st = slab_free_claim(s, t, ptr[r], &fcs);
+          st = slab_free_claim(s, t, ptr[r], r, &fcs);
           if (st == ST_OK) {
             tenant_delta = -fcs;
             pool_delta = -fcs;
@@ -320,7 +345,7 @@ __global__ __launch_bounds__(PH_THREADS) void k_slab_phase(
       if (!pooled) {
         st = ST_NOMEM_POOL;
         if (!t_free_run) add_relaxed(&s.charged[t], -cs);
-      } else if (slab_claim(s, c, t, uint64_t(i) * 0x9E3779B97F4A7C15ULL, &p)) {
+      } else if (slab_claim(s, c, t, uint64_t(i) * 0x9E3779B97F4A7C15ULL, uint64_t(i), &p)) {
         st = ST_OK;
         if (t_free_run) tenant_delta = cs;
         if (pool_free_run) pool_delta = cs;
@@ -385,6 +410,10 @@ __global__ void k_slab_reset_bits(SlabDev s) {
       }
       bits[w] = v;
     }
+    unsigned long long *ow = s.owner + s.owner_off[c];
+    for (int64_t b = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; b < cap;
+         b += int64_t(gridDim.x) * blockDim.x)
+      ow[b] = OWNER_EMPTY;
   }
 }
 
@@ -430,7 +459,7 @@ int sched_slab_init(sched_ctx *c, int64_t pool_bytes, int32_t n_tenants) {
   }
   SCHED_HIP_TRY(hipMalloc(&d.base, size_t(region) * N_CLASSES));
   SCHED_HIP_TRY(hipMalloc(&d.bits, sizeof(unsigned long long) * words));
-  SCHED_HIP_TRY(hipMalloc(&d.owner, sizeof(int32_t) * owners));
+  SCHED_HIP_TRY(hipMalloc(&d.owner, sizeof(unsigned long long) * owners));
   SCHED_HIP_TRY(hipMalloc(&d.charged, sizeof(int64_t) * n_tenants));
   SCHED_HIP_TRY(hipMemset(d.charged, 0, sizeof(int64_t) * n_tenants));
   SCHED_HIP_TRY(hipMalloc(&d.pool_used, sizeof(int64_t)));

@@ -138,3 +138,88 @@ def test_lifecycle_alloc_free_quota(cs):
         assert ch == [0, 0] and pool == 0
     finally:
         cs.sched_destroy(ctx)
+
+
+def test_duplicate_frees_with_concurrent_allocs(cs):
+    """Frees that name the same allocation twice in one phase, beside
+    allocations of the same class that can only succeed on blocks freed in
+    that phase: exactly one free of each pair succeeds, no block is handed out
+    while still held, and the device counters equal the log's (check_log).
+    Phase 0 fills class 0 (256 B) completely; phase 1 frees 1024 of its blocks,
+    each named by two frees, while 2048 allocations compete for them; phase 2
+    frees everything still held once."""
+    from workloads import OP_ALLOC, OP_FREE
+    pool = 13 << 20                       # 1 MiB regions: class 0 holds 4096 blocks
+    region, cap = design_capacity(pool)
+    T = 4
+    rng = np.random.default_rng(11)
+    kind, ten, size, ref = [], [], [], []
+
+    def op(k, t, sz=0, r=-1):
+        kind.append(k), ten.append(t), size.append(sz), ref.append(r)
+
+    n0 = int(cap[0])
+    for i in range(n0):                   # phase 0
+        op(OP_ALLOC, i % T, 256)
+    victims = rng.choice(n0, 1024, replace=False)
+    ph1 = []
+    for v in victims:
+        ph1 += [(OP_FREE, int(v) % T, 0, int(v))] * 2
+    ph1 += [(OP_ALLOC, int(t), 200, -1) for t in rng.integers(0, T, 2048)]
+    for j in rng.permutation(len(ph1)):   # phase 1, interleaved
+        op(*ph1[j])
+    p1 = n0
+    held0 = sorted(set(range(n0)) - set(int(v) for v in victims))
+    ph2 = [(OP_FREE, i % T, 0, i) for i in held0]
+    ph2 += [(OP_FREE, ten[p1 + j], 0, p1 + j) for j in range(len(ph1)) if kind[p1 + j] == OP_ALLOC]
+    for j in rng.permutation(len(ph2)):   # phase 2
+        op(*ph2[j])
+    kind = np.array(kind, np.uint8)
+    ten = np.array(ten, np.int32)
+    size = np.array(size, np.int64)
+    ref = np.array(ref, np.int64)
+    quotas = np.full(T, 1 << 30, np.int64)
+    bounds = [0, n0, n0 + len(ph1), kind.size]
+    rc, ctx = cs.sched_create(capacity_bytes=1 << 40, max_jobs=16, max_tenants=T,
+                              slab_pool_bytes=pool, queue_capacity=4096)
+    assert rc == 0
+    try:
+        assert cs.sched_slab_set_quotas(ctx, quotas) == 0
+        rc, info = cs.sched_slab_info(ctx)
+        dk, dt, ds, dr = (torch.from_numpy(x).to(DEV) for x in (kind, ten, size, ref))
+        ptr = torch.zeros(kind.size, dtype=torch.int64, device=DEV)
+        st = torch.full((kind.size,), -1, dtype=torch.int8, device=DEV)
+        for b0, b1 in zip(bounds[:-1], bounds[1:]):
+            assert cs.sched_slab_ops(ctx, b0, b1, dk, dt, ds, dr, ptr, st) == 0
+        torch.cuda.synchronize()
+        rc, charged, pool_used = cs.sched_slab_counters(ctx, T)
+        assert rc == 0
+        st_h = st.cpu().numpy()
+        ptr_h = ptr.cpu().numpy().view(np.uint64)
+    finally:
+        cs.sched_destroy(ctx)
+    # phases of unequal length: check_log runs on fixed-length phases, so it
+    # is given each phase's ops padded to one length with invalid frees
+    L = max(b1 - b0 for b0, b1 in zip(bounds[:-1], bounds[1:]))
+    pk, pt, ps, pr, pst, pp = [], [], [], [], [], []
+    remap = {}
+    for b0, b1 in zip(bounds[:-1], bounds[1:]):
+        base = len(pk)
+        for i in range(b0, b1):
+            remap[i] = base + i - b0
+        for i in range(b0, b1):
+            pk.append(kind[i]), pt.append(ten[i]), ps.append(size[i])
+            pr.append(remap[int(ref[i])] if ref[i] >= 0 else -1)
+            pst.append(st_h[i]), pp.append(ptr_h[i])
+        for _ in range(L - (b1 - b0)):
+            pk.append(OP_FREE), pt.append(0), ps.append(0), pr.append(-1)
+            pst.append(A.ST_INVALID), pp.append(0)
+    res = A.check_log(np.array(pk, np.uint8), np.array(pt), np.array(ps), np.array(pr), quotas,
+                      pool, cap, L, np.array(pst), np.array(pp, np.uint64), info["pool_base"],
+                      final_charged=charged, final_pool=pool_used, span=13 * info["region_bytes"])
+    fr1 = st_h[n0:n0 + len(ph1)][kind[n0:n0 + len(ph1)] == OP_FREE]
+    print(f"  phase-1 frees ok={int((fr1 == 0).sum())} of {fr1.size}; "
+          f"allocs ok={int((st_h[n0:n0 + len(ph1)][kind[n0:n0 + len(ph1)] == OP_ALLOC] == 0).sum())}",
+          flush=True)
+    assert int((fr1 == 0).sum()) == 1024
+    assert res["pool_used"] == 0 and list(res["charged"]) == [0] * T

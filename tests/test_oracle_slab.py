@@ -148,3 +148,31 @@ def test_checker_allows_justified_rejects():
     with pytest.raises(AssertionError):
         A.check_log(k, t, s, r, [1024], 1 << 20, cap, 2, np.array([A.ST_QUOTA, A.ST_QUOTA]),
                     np.zeros(2, np.uint64), 1 << 40)
+
+
+def test_checker_two_frees_of_one_block_in_a_phase():
+    """Two frees naming one allocation in the same phase (plus a concurrent
+    allocation of the same class that may reuse the block): exactly one free
+    succeeds and the other is invalid, whichever of the two wins.  Both
+    succeeding, or neither, is a mistake the checker reports."""
+    # phase 0: three allocations; phase 1: two frees of op 0 and a new one
+    k, t, s, r = _ops([("a", 0, 256), ("a", 1, 256), ("a", 1, 256),
+                       ("f", 0, 0), ("f", 0, 0), ("a", 0, 256)])
+    cap = np.full(13, 10)
+    base = 1 << 40
+    ptr = np.array([base, base + 256, base + 512, 0, 0, base], np.uint64)
+    for st in ([A.ST_OK] * 3 + [A.ST_OK, A.ST_INVALID, A.ST_OK],
+               [A.ST_OK] * 3 + [A.ST_INVALID, A.ST_OK, A.ST_OK]):
+        # the new allocation took the freed block's address: no overlap,
+        # since the first block is no longer held
+        res = A.check_log(k, t, s, r, [1024, 1024], 1 << 20, cap, 3, np.array(st), ptr, base)
+        assert res["free_ok"] == 1 and list(res["charged"]) == [256, 512]
+    for st in ([A.ST_OK] * 3 + [A.ST_OK, A.ST_OK, A.ST_OK],
+               [A.ST_OK] * 3 + [A.ST_INVALID, A.ST_INVALID, A.ST_OK]):
+        with pytest.raises(AssertionError):
+            A.check_log(k, t, s, r, [1024, 1024], 1 << 20, cap, 3, np.array(st),
+                        np.array([base, base + 256, base + 512, 0, 0, base + 768], np.uint64),
+                        base)
+    # the sequential simulator: the second free is invalid
+    st = A.simulate(k, t, s, r, [1024, 1024], 1 << 20, cap)
+    assert list(st) == [A.ST_OK] * 3 + [A.ST_OK, A.ST_INVALID, A.ST_OK]
