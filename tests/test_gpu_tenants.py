@@ -92,6 +92,21 @@ def test_gemm_full(cs, M, N, K):
     got = C.cpu().numpy().astype(np.float64)
     err = np.abs(got - ref) / np.maximum(np.abs(ref), 1.0)
     assert err.max() <= 2e-2, err.max()
+    A = np.abs(T.gemm_operand(1, np.arange(M), K))
+    B = np.abs(T.gemm_operand(2, np.arange(N), K))
+    _assert_fp32_bound(got, ref, A @ B.T, K)
+
+
+def _assert_fp32_bound(got, ref, abs_dot, K):
+    """The operands are exact bf16 values with 8 significant bits, so every
+    product a*b is exact in fp32 and the only error is the fp32 accumulation:
+    for any summation order |c - r| <= gamma_K * sum_k |a_k b_k| with
+    gamma_K = K u / (1 - K u), u = 2^-24.  A dropped or repeated k-step moves
+    an entry by a whole product, far beyond this bound."""
+    u = 2.0 ** -24
+    gamma = K * u / (1 - K * u)
+    bad = np.abs(got - ref) > gamma * abs_dot
+    assert not bad.any(), (np.argwhere(bad)[:3], np.abs(got - ref).max())
 
 
 @pytest.mark.parametrize("N", [2048, 4096, 8192])
@@ -106,6 +121,9 @@ def test_gemm_sampled(cs, N):
     got = C[torch.from_numpy(mi).to(DEV), torch.from_numpy(ni).to(DEV)].cpu().numpy()
     err = np.abs(got - ref) / np.maximum(np.abs(ref), 1.0)
     assert err.max() <= 2e-2, err.max()
+    A = np.abs(T.gemm_operand(3, mi, N))
+    B = np.abs(T.gemm_operand(4, ni, N))
+    _assert_fp32_bound(got.astype(np.float64), ref, np.einsum("ik,ik->i", A, B), N)
 
 
 def test_tenant_bad_args(cs):
