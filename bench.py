@@ -60,7 +60,7 @@ def parse():
     ap.add_argument("--extras", default="dense,tenants,slab",
                     help="measurements to add after the admission steps (dense, tenants, "
                          "slab; empty = none)")
-    ap.add_argument("--cosched", default="c1,c5,hol",
+    ap.add_argument("--cosched", default="c1,c4,c5,hol",
                     help="co-scheduled vs serial runs to add (c1, c4, c5; hol = the "
                          "head-of-line study, FIFO vs MMU; empty = none)")
     ap.add_argument("--cosched-streams", type=int, default=3,
@@ -70,10 +70,22 @@ def parse():
                          "behind them)")
     ap.add_argument("--c5-jobs", type=int, default=50_000)
     ap.add_argument("--c4-jobs", type=int, default=10_000)
+    ap.add_argument("--tune-cache", default="",
+                    help="file for the batch autotuner's result (default: one per GPU "
+                         "architecture and batch-kernel source hash in the temp directory)")
     return ap.parse_args()
 
 
-def cosched_run(cs, name, n_jobs, dev_free, n_streams=3):
+def tune_cache_path(torch):
+    """The autotuner's cache file, keyed by GPU architecture and by the hash of
+    the batch kernel's source, so a changed kernel or another GPU tunes again."""
+    import tempfile
+    arch = torch.cuda.get_device_properties(0).gcnArchName.split(":")[0]
+    sha = _sha256("paper_1712_04495_amd/csrc/batch.hip")[:16]
+    return os.path.join(tempfile.gettempdir(), f"cosched_batch_tune_{arch}_{sha}.json")
+
+
+def cosched_run(cs, name, n_jobs, dev_free, n_streams=3, tune_cache=""):
     """One job mix co-scheduled (MMU, batching of small triads) and exclusive
     serial (every demand := capacity).  Returns a dict of results."""
     import numpy as np
@@ -97,8 +109,7 @@ def cosched_run(cs, name, n_jobs, dev_free, n_streams=3):
            "policy": "fifo" if policy == 0 else "mmu"}
     try:
         for label, kw in (("coscheduled", dict(n_streams=n_streams, batch_small=batch, use_graph=1,
-                                               tune_cache=os.path.join(ROOT, "gpurun_out",
-                                                                       "batch_tune.json"))),
+                                               tune_cache=tune_cache)),
                           ("serial", dict(n_streams=1, serial=1))):
             print(f"[bench] {name} {label}: {mix.n} jobs", file=sys.stderr, flush=True)
             rc, res, sm = cs.sched_serve(ctx, jt, **kw)
@@ -117,7 +128,9 @@ def cosched_run(cs, name, n_jobs, dev_free, n_streams=3):
                           "deferred": sm["deferred"]}
             if label == "coscheduled" and batch:
                 out[label]["autotuned"] = {"block": sm["tuned_block"], "chunk": sm["tuned_chunk"],
-                                           "per_cu": sm["tuned_per_cu"]}
+                                           "per_cu": sm["tuned_per_cu"],
+                                           "tuner_ran": sm["tuned_from_cache"] == 0,
+                                           "cache": tune_cache}
             out[label]["completed_ok"] = int(ok.sum())
     finally:
         cs.sched_destroy(ctx)
@@ -128,6 +141,20 @@ def cosched_run(cs, name, n_jobs, dev_free, n_streams=3):
     # comes from jobs that leave the device partly idle running side by side
     out["serial_idle_ceiling"] = (out["serial"]["makespan_s"] /
                                   max(out["serial"]["dev_busy_s"], 1e-12))
+    # roofline-bound ceiling of the co-scheduled/serial ratio: no schedule can
+    # finish before the mix's HBM bytes at peak bandwidth, its GEMM flops at
+    # peak bf16 MFMA rate, or the last arrival
+    kind, size = np.asarray(jt["kind"]), np.asarray(jt["size"], dtype=np.float64)
+    tri, gem, his = kind == 0, kind == 1, kind == 2
+    hbm_bytes = (float(((8 + 12 * 10) * size[tri]).sum()) + float((8 * size[his]).sum())
+                 + float((8 * size[gem] ** 2).sum()) + float((4 * size[gem] ** 2).sum()))
+    flops = float((2 * size[gem] ** 3).sum())
+    t_floor = max(hbm_bytes / (HBM_PEAK_GBS * 1e9), flops / 2.5e15, float(jt["arrival_s"][-1]))
+    out["roofline_ceiling"] = {"hbm_bytes": hbm_bytes, "gemm_flops": flops,
+                               "t_floor_s": t_floor,
+                               "ratio_ceiling": out["serial"]["makespan_s"] / t_floor,
+                               "note": "serial makespan over max(bytes / 8 TB/s, flops / "
+                                       "2.5 PFLOP/s, last arrival)"}
     return out
 
 
@@ -308,36 +335,75 @@ def slab_measure(cs, torch, dev):
 
 
 def cpu_baseline_c2(q, seconds):
-    """The oracle as it stands, on host cores, on whole C2 steps."""
+    """The oracle as it stands, on one host core, on whole C2 steps: the plain
+    sequential C loop (gcc -O2) and the numpy/Python statement, each for about
+    half of `seconds`.  `value` is the compiled oracle's rate."""
+    from oracle import c2seq
     from oracle import sched as S
-    t0 = time.perf_counter()
-    steps = 0
-    admitted = 0
-    per_pass = None
-    while True:
+    c2seq.lib()
+
+    def timed(fn, budget):
+        t0 = time.perf_counter()
+        steps, admitted, last = 0, 0, None
+        while True:
+            admitted, last = fn(admitted)
+            steps += 1
+            if time.perf_counter() - t0 >= budget:
+                break
+        return steps, admitted, time.perf_counter() - t0, last
+
+    def run_c(acc):
+        res = c2seq.release_rounds(q.demand, q.capacity, q.coins, q.rounds, S.MMU)
+        return acc + sum(int(r[0].size) for r in res), [(int(r[0].size), int(r[1])) for r in res]
+
+    def run_py(acc):
         res = S.release_rounds(q.demand, q.capacity, q.coins, q.rounds, S.MMU)
-        admitted += sum(int(r.admitted.size) for r in res)
-        per_pass = [(int(r.admitted.size), int(r.R_after)) for r in res]
-        steps += 1
-        if time.perf_counter() - t0 >= seconds:
-            break
-    dt = time.perf_counter() - t0
-    return {"value": admitted / dt, "unit": "admissions/s", "cores": 1, "kind": "oracle",
-            "cpu": cpu_model(),
-            "sample": f"{steps} full steps (8 release/admit passes over 2^{q.n.bit_length() - 1} "
-                      f"requests) in {dt:.1f} s, pure numpy/Python, one thread"}, per_pass
+        return (acc + sum(int(r.admitted.size) for r in res),
+                [(int(r.admitted.size), int(r.R_after)) for r in res])
+
+    c_steps, c_adm, c_dt, c_last = timed(run_c, seconds / 2)
+    p_steps, p_adm, p_dt, p_last = timed(run_py, seconds / 2)
+    assert c_last == p_last, "the C and numpy oracles disagree"
+    host = host_info()
+    return {"value": c_adm / c_dt, "unit": "admissions/s", "cores": 1, "kind": "oracle",
+            "cpu": host["model"], "nproc": host["nproc"], "cpu_count": host["cpu_count"],
+            "sample": f"{c_steps} full steps (intake of 2^{q.n.bit_length() - 1} requests + "
+                      f"{q.rounds} release/admit passes) in {c_dt:.1f} s, plain sequential C "
+                      f"(oracle/c2seq.c, gcc -O2), one thread",
+            "us_per_step": 1e6 * c_dt / c_steps,
+            "python": {"value": p_adm / p_dt, "unit": "admissions/s", "cores": 1,
+                       "us_per_step": 1e6 * p_dt / p_steps,
+                       "sample": f"{p_steps} full steps in {p_dt:.1f} s, numpy/Python "
+                                 f"(oracle/sched.py release_rounds), one thread"}}, c_last
 
 
-def cpu_model():
-    """The host CPU's model name (from /proc/cpuinfo), for the oracle timing."""
+def host_info():
+    """The host CPU: model name (lscpu, else /proc/cpuinfo), the cores this
+    process may run on (nproc) and the cores the machine has."""
+    import subprocess
+    model = "unknown"
     try:
-        with open("/proc/cpuinfo") as f:
-            for line in f:
-                if line.startswith("model name"):
-                    return line.split(":", 1)[1].strip()
-    except OSError:
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
+        for line in out.splitlines():
+            if line.strip().startswith("Model name:"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except (OSError, subprocess.SubprocessError):
         pass
-    return "unknown"
+    if model == "unknown":
+        try:
+            with open("/proc/cpuinfo") as f:
+                for line in f:
+                    if line.startswith("model name"):
+                        model = line.split(":", 1)[1].strip()
+                        break
+        except OSError:
+            pass
+    try:
+        nproc = len(os.sched_getaffinity(0))
+    except AttributeError:
+        nproc = os.cpu_count()
+    return {"model": model, "nproc": nproc, "cpu_count": os.cpu_count()}
 
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
@@ -515,17 +581,18 @@ def main():
                                          "us_per_pass": 1e6 * sync_dt / args.steps / q.rounds}},
     }
     if profile:
-        # algorithmic bytes of a chain (one k_chain launch, all rounds):
-        #   release step: 4 B id + 4 B state + 1 B mask per running job it
-        #            looks at, 8 B reservation read + 12 B written per
-        #            released job;
-        #   pass:    8 B demand read + 1 B decision written per decided entry;
-        #   compaction: 25 B read + 24 B written per entry of [head, last
-        #            admitted].
-        # The running list is built once per chain (4 B state per job slot).
-        alg = {"k_chain": 9 * prof["considered"] + 20 * prof["released"] + 9 * prof["scanned"]
-                          + 49 * prof["compacted"],
-               "k_run_list": 4 * n * prof_steps}
+        # Algorithmic bytes of the dominant kernel: 8 B demand read + 1 B
+        # decision written per queue entry a pass inspects (the admission
+        # decision itself).  What the chain also moves for the release step
+        # (4 B id + 4 B state + 1 B mask per running job it looks at, 8 B
+        # reservation read + 12 B written per released job) and the compaction
+        # (25 B read + 24 B written per entry of [head, last admitted]) is
+        # reported beside it, not counted in `achieved`.
+        per_step_decide = 9 * prof["scanned"]
+        side = {"release_bytes": 9 * prof["considered"] + 20 * prof["released"],
+                "compaction_bytes": 49 * prof["compacted"],
+                "run_list_bytes": 4 * n * prof_steps}
+        alg = {"k_chain": per_step_decide, "k_run_list": side["run_list_bytes"]}
         dom = max(kern, key=lambda k: kern[k][0])
         ms, launches = kern[dom]
         avg_s = ms * 1e-3 / max(launches, 1)
@@ -534,6 +601,10 @@ def main():
         out["roofline"] = {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                            "frac": ach / HBM_PEAK_GBS, "traffic": traffic_for(dom), "kernel": dom,
                            "avg_launch_us": avg_s * 1e6, "bytes_per_launch": bytes_per_launch,
+                           "inspected_entries_per_launch": prof["scanned"] / max(launches, 1),
+                           "bytes_per_unit": "9 B per inspected queue entry (8 B demand + 1 B "
+                                             "decision)",
+                           "side_bytes_per_launch": {k: v / max(launches, 1) for k, v in side.items()},
                            "profiled_steps": prof_steps,
                            "kernels_ms_per_step": {k: v[0] / prof_steps for k, v in kern.items()}}
 
@@ -612,7 +683,8 @@ def main():
             else:
                 out["coschedule"][name] = cosched_run(cs, name,
                                                       args.c5_jobs if name == "c5" else args.c4_jobs,
-                                                      int(free), args.cosched_streams)
+                                                      int(free), args.cosched_streams,
+                                                      args.tune_cache or tune_cache_path(torch))
             print(f"[bench] {name}: {json.dumps(out['coschedule'][name])}", file=sys.stderr,
                   flush=True)
 

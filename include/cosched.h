@@ -493,6 +493,9 @@ typedef struct {
   double host_pass_s, host_launch_s, host_poll_s, host_idle_s, dev_busy_s;
   double host_alloc_s; /* part of host_launch_s spent allocating job memory     */
   int64_t deferred;    /* launches that waited for a contiguous device range    */
+  int64_t tuned_from_cache; /* batching: 1 = shape read from tune_cache, 0 = the
+                               tuner timed its candidates in this run; -1 = no
+                               batching                                         */
 } sched_serve_summary_t;
 
 /* Runs n jobs (jobs[i] is job handle i; the context needs max_jobs >= n and

@@ -14,6 +14,9 @@ Memory Safe GPU Co-Scheduling", IEEE TPDS 2017; arXiv:1712.04495):
                    concurrent allocator phases.
 * ``tenants``   -- references for the synthetic tenant jobs (fp32 triad,
                    int32 histogram, bf16 GEMM in fp64).
+* ``c2seq``     -- the release/admit rounds of ``sched`` restated as a plain
+                   sequential C loop (``c2seq.c``, gcc -O2), to time the
+                   oracle as compiled code on one host core.
 
 Only ``tests/``, ``__graft_entry__.smoke()`` and ``bench.py``'s CPU-baseline
 leg may import this package.  It shares no code with the HIP path in

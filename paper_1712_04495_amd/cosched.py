@@ -81,7 +81,7 @@ class sched_serve_summary_t(C.Structure):
                                       "tuned_chunk", "tuned_per_cu")]
                 + [(n, C.c_double) for n in ("host_pass_s", "host_launch_s", "host_poll_s",
                                              "host_idle_s", "dev_busy_s", "host_alloc_s")]
-                + [("deferred", i64)])
+                + [("deferred", i64), ("tuned_from_cache", i64)])
 
 
 SCHED_JOB_TRIAD = 0

@@ -54,6 +54,7 @@ struct BatchEngine {
   int64_t chunk = 1 << 16;
   int best_block = 256, best_per_cu = 4;
   bool tuned = false;
+  bool from_cache = false;     // the shape was read from the tuner's cache file
   double tune_ms = 0.0;
   std::vector<BatchGraph> graphs;
 };

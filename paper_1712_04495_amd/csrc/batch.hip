@@ -210,6 +210,7 @@ int batch_autotune(BatchEngine &b, const char *cache_path, hipStream_t s) {
         b.chunk = ch;
         b.per_cu = per;
         b.tuned = true;
+        b.from_cache = true;
         return SCHED_OK;
       }
     }
@@ -258,6 +259,7 @@ int batch_autotune(BatchEngine &b, const char *cache_path, hipStream_t s) {
   b.block = b.best_block;
   b.per_cu = b.best_per_cu;
   b.tuned = true;
+  b.from_cache = false;
   b.tune_ms = best / 3;
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);

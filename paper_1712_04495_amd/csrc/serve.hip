@@ -259,6 +259,7 @@ struct Serve {
       sum.tuned_block = beng->block;
       sum.tuned_chunk = beng->chunk;
       sum.tuned_per_cu = beng->per_cu;
+      sum.tuned_from_cache = beng->from_cache ? 1 : 0;
     }
     SCHED_HIP_TRY(hipDeviceSynchronize());
     SCHED_HIP_TRY(hipEventCreate(&ev0));
@@ -717,6 +718,7 @@ extern "C" int sched_serve(sched_ctx_t *c, int64_t n, const sched_job_desc_t *jo
   if (c->n_jobs < n) c->n_jobs = int32_t(n);
   for (int64_t i = 0; i < n; ++i) results[i] = sched_job_result_t{};
   Serve s{};
+  s.sum.tuned_from_cache = -1;
   s.c = c;
   s.J = jobs;
   s.n = n;
