@@ -124,8 +124,16 @@ def cosched_run(cs, name, n_jobs, dev_free, n_streams=3, tune_cache=""):
                           "batched_jobs": sm["batched_jobs"], "wall_s": sm["wall_s"],
                           "host_s": {k: sm["host_" + k + "_s"] for k in ("pass", "launch", "poll",
                                                                           "idle")},
-                          "dev_busy_s": sm["dev_busy_s"], "host_alloc_s": sm["host_alloc_s"],
-                          "deferred": sm["deferred"]}
+                          "dev_busy_s": sm["dev_busy_s"],
+                          "memory": {k: sm[k] for k in ("placements", "slot_waits",
+                                                        "placement_slots", "pool_pages",
+                                                        "peak_pages", "pages_left",
+                                                        "charged_left", "page_check")}}
+            # wait = placement - arrival (the summary's); the admission part alone
+            w_adm = np.sort((res["t_admit"] - res["t_arrive"])[ok])
+            if w_adm.size:
+                out[label]["p50_admit_wait_s"] = float(w_adm[int(np.ceil(0.5 * w_adm.size)) - 1])
+                out[label]["p99_admit_wait_s"] = float(w_adm[int(np.ceil(0.99 * w_adm.size)) - 1])
             if label == "coscheduled" and batch:
                 out[label]["autotuned"] = {"block": sm["tuned_block"], "chunk": sm["tuned_chunk"],
                                            "per_cu": sm["tuned_per_cu"],

@@ -427,9 +427,19 @@ int sched_gemm_bf16(const uint16_t *A, const uint16_t *Bt, float *C, int64_t M, 
  * batch_small, admitted triads under small_bytes are packed into one
  * persistent launch (a HIP graph replay when use_graph) whose block and
  * chunk shape come from an autotuner (cached in tune_cache when non-NULL).
- * Each job allocates only what its kind needs, which must fit its declared
- * demand; an allocation failure inside a reservation is a memory-safety
- * violation (counted, job status SCHED_E_NOMEM). */
+ *
+ * Memory: right after the pass that admits it, a job (or a batch of small
+ * ones) is placed in a device page pool of 64 KiB pages: its buffers (each
+ * rounded up to 4 KiB, at most its declared demand) are charged to the job
+ * against its reservation -- the slab's per-tenant counters, tenants = jobs
+ * -- and mapped page by page, so no contiguous range is needed.  The pool
+ * holds the capacity plus one page per placement slot (max_placed, default
+ * min(n, 16384)); an admitted job waits for a slot only when all are taken
+ * (slot_waits).  A placement that fails for an admitted job is a
+ * memory-safety violation (counted; the job's status is SCHED_E_NOMEM and
+ * its work does nothing).  The context's slab, if it has one, must have
+ * tenants = jobs with reservations as quotas; a context without one gets a
+ * small one.  A GEMM job's N must be a power of two in [256, 16384]. */
 #define SCHED_JOB_TRIAD 0  /* size = fp32 elements per array (3 arrays)       */
 #define SCHED_JOB_GEMM 1   /* size = N of an N x N x N bf16 GEMM               */
 #define SCHED_JOB_HIST 2   /* size = uint32 keys                              */
@@ -449,14 +459,23 @@ typedef struct {
   uint64_t seed;      /* input contents                                       */
 } sched_job_desc_t;
 
+#define SCHED_GEMM_SAMPLES 8
+
 typedef struct {
   double t_arrive;    /* seconds from the start                               */
   double t_admit;     /* when the pass that admitted it returned              */
+  double t_place;     /* when its placement was issued (>= t_admit)           */
   double t_start;     /* device time its work could start                     */
   double t_end;       /* device time its work ended                           */
-  uint64_t digest;    /* sum of the 32-bit words of its output (when digest)  */
+  /* with digest: sum over the output's 32-bit words w_i of (s_i | 1) * w_i
+   * mod 2^64, s_i = SplitMix64 output i for state 0x6A09E667F3BCC908 (the
+   * triad's a, the GEMM's C in row-major order, the 4096 histogram bins)    */
+  uint64_t digest;
   int32_t status;     /* SCHED_OK, SCHED_E_TOOBIG, SCHED_E_NOMEM, ...         */
   int32_t batched;    /* 1 if it ran inside a batched launch                  */
+  /* with digest, GEMM jobs: C's element p_k (row-major) for k < 8, p_k =
+   * (SplitMix64 output k for state (seed << 32) ^ 0xBB67AE8584CAA73B) mod N^2 */
+  float sample[SCHED_GEMM_SAMPLES];
 } sched_job_result_t;
 
 typedef struct {
@@ -474,7 +493,7 @@ typedef struct {
   int32_t digest;      /* 1: compute each job's output digest                  */
   double time_scale;   /* arrival times are multiplied by this (0 = 1)         */
   int32_t use_graph;   /* 1: replay the batched launch as a HIP graph          */
-  int32_t pad;
+  int32_t max_placed;  /* placement slots (0: min(n, 16384))                   */
   const char *tune_cache; /* JSON file for the autotuner result, or NULL       */
 } sched_serve_opts_t;
 
@@ -482,7 +501,8 @@ typedef struct {
   double wall_s;       /* host time of the whole run                           */
   double makespan_s;   /* last job end                                         */
   double jobs_per_s;   /* completed / makespan                                 */
-  double p50_wait_s, p99_wait_s, p50_turn_s, p99_turn_s; /* nearest rank       */
+  /* nearest rank; wait = placement - arrival, turnaround = end - arrival    */
+  double p50_wait_s, p99_wait_s, p50_turn_s, p99_turn_s;
   int64_t completed, rejected, violations, passes, batches, batched_jobs;
   int64_t peak_used, max_running;
   int64_t tuned_block, tuned_chunk, tuned_per_cu;
@@ -491,11 +511,16 @@ typedef struct {
    * releases, and idle waits; dev_busy_s is the time at least one job was
    * running on the device (union of the jobs' [start, end] intervals) */
   double host_pass_s, host_launch_s, host_poll_s, host_idle_s, dev_busy_s;
-  double host_alloc_s; /* part of host_launch_s spent allocating job memory     */
-  int64_t deferred;    /* launches that waited for a contiguous device range    */
   int64_t tuned_from_cache; /* batching: 1 = shape read from tune_cache, 0 = the
                                tuner timed its candidates in this run; -1 = no
                                batching                                         */
+  /* page pool (real-time mode) */
+  int64_t slot_waits;      /* admitted jobs that waited for a placement slot  */
+  int64_t placements;      /* placements made (a batch is one)                */
+  int64_t placement_slots, pool_pages, peak_pages;
+  int64_t pages_left, charged_left; /* at the end: both 0                     */
+  int64_t page_check;      /* free-list entries duplicated or out of range at
+                              the end (0), -1 if placements were left          */
 } sched_serve_summary_t;
 
 /* Runs n jobs (jobs[i] is job handle i; the context needs max_jobs >= n and
@@ -524,6 +549,13 @@ int sched_profile_read(const char *kernel, double *total_ms, int64_t *launches);
 
 /* Library version string. */
 const char *sched_version(void);
+
+/* sizeof of the ABI's structures, for bindings to check their layouts: 0
+ * sched_config_t, 1 sched_stats_t, 2 sched_pass_result_t, 3
+ * sched_job_desc_t, 4 sched_job_result_t, 5 sched_serve_opts_t, 6
+ * sched_serve_summary_t, 7 sched_slab_info_t, 8 sched_scan_result_t; -1 for
+ * any other value.  Touches no device. */
+int64_t sched_abi_sizeof(int32_t which);
 
 #ifdef __cplusplus
 }

@@ -119,3 +119,42 @@ def bf16_round(x):
     lsb = (f >> np.uint64(16)) & np.uint64(1)
     r = ((f + np.uint64(0x7FFF) + lsb) >> np.uint64(16)) << np.uint64(16)
     return (r & np.uint64(0xFFFFFFFF)).astype(np.uint32).view(np.float32).astype(np.float64)
+
+
+# --------------------------------------------------------------------------
+# Output digest and GEMM sample positions reported by the serving loop
+# --------------------------------------------------------------------------
+# Not part of the method: an encoding of a job's output that the serving
+# loop computes on the device, so that results inside a mix can be checked
+# element by element without copying them out.
+DIGEST_KEY = 0x6A09E667F3BCC908
+SAMPLE_KEY = 0xBB67AE8584CAA73B
+GEMM_SAMPLES = 8
+
+
+def position_digest(words, chunk: int = 1 << 24) -> int:
+    """sum_i (s_i | 1) * w_i mod 2^64 over 32-bit words w (uint32 array, or
+    an fp32 array taken by its bit patterns), s_i = SplitMix64 output i for
+    state DIGEST_KEY.  The multipliers are odd, so changing one word always
+    changes the digest."""
+    w = np.ascontiguousarray(words)
+    if w.dtype == np.float32:
+        w = w.view(np.uint32)
+    w = w.astype(np.uint32, copy=False).ravel()
+    total = np.uint64(0)
+    with np.errstate(over="ignore"):
+        for s in range(0, w.size, chunk):
+            part = w[s:s + chunk].astype(np.uint64)
+            mult = splitmix64_state(DIGEST_KEY, np.arange(s, s + part.size, dtype=np.uint64))
+            total = total + np.sum((mult | np.uint64(1)) * part, dtype=np.uint64)
+    return int(total)
+
+
+def gemm_sample_positions(seed: int, N: int):
+    """Row-major positions of the GEMM_SAMPLES entries of C reported for a
+    GEMM job: SplitMix64 output k for state (seed << 32) ^ SAMPLE_KEY, mod N^2;
+    returned as (rows, cols)."""
+    s0 = ((int(seed) << 32) ^ SAMPLE_KEY) & 0xFFFFFFFFFFFFFFFF
+    p = splitmix64_state(s0, np.arange(GEMM_SAMPLES, dtype=np.uint64)) % np.uint64(N * N)
+    p = p.astype(np.int64)
+    return p // N, p % N

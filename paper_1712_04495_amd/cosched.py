@@ -70,7 +70,7 @@ class sched_slab_info_t(C.Structure):
 class sched_serve_opts_t(C.Structure):
     _fields_ = [("mode", i32), ("n_streams", i32), ("serial", i32), ("batch_small", i32),
                 ("small_bytes", i64), ("iters", i32), ("digest", i32), ("time_scale", C.c_double),
-                ("use_graph", i32), ("pad", i32), ("tune_cache", C.c_char_p)]
+                ("use_graph", i32), ("max_placed", i32), ("tune_cache", C.c_char_p)]
 
 
 class sched_serve_summary_t(C.Structure):
@@ -80,8 +80,10 @@ class sched_serve_summary_t(C.Structure):
                                       "batched_jobs", "peak_used", "max_running", "tuned_block",
                                       "tuned_chunk", "tuned_per_cu")]
                 + [(n, C.c_double) for n in ("host_pass_s", "host_launch_s", "host_poll_s",
-                                             "host_idle_s", "dev_busy_s", "host_alloc_s")]
-                + [("deferred", i64), ("tuned_from_cache", i64)])
+                                             "host_idle_s", "dev_busy_s")]
+                + [(n, i64) for n in ("tuned_from_cache", "slot_waits", "placements",
+                                      "placement_slots", "pool_pages", "peak_pages", "pages_left",
+                                      "charged_left", "page_check")])
 
 
 SCHED_JOB_TRIAD = 0
@@ -93,9 +95,14 @@ SCHED_SERVE_VIRTUAL = 1
 # numpy layout of sched_job_result_t
 import numpy as _np  # noqa: E402
 
-RESULT_DTYPE = _np.dtype([("t_arrive", "<f8"), ("t_admit", "<f8"), ("t_start", "<f8"),
-                          ("t_end", "<f8"), ("digest", "<u8"), ("status", "<i4"),
-                          ("batched", "<i4")])
+SCHED_GEMM_SAMPLES = 8
+# numpy layout of sched_job_desc_t
+JOB_DTYPE = _np.dtype([("arrival_s", "<f8"), ("vdur_s", "<f8"), ("demand", "<i8"), ("size", "<i8"),
+                       ("kind", "<i4"), ("priority", "<i4"), ("seed", "<u8")])
+RESULT_DTYPE = _np.dtype([("t_arrive", "<f8"), ("t_admit", "<f8"), ("t_place", "<f8"),
+                          ("t_start", "<f8"), ("t_end", "<f8"), ("digest", "<u8"),
+                          ("status", "<i4"), ("batched", "<i4"),
+                          ("sample", "<f4", (SCHED_GEMM_SAMPLES,))])
 
 # name -> (restype, argtypes); mirrors include/cosched.h
 _SIGS = {
@@ -140,7 +147,17 @@ _SIGS = {
     "sched_serve": (i32, [vp, i64, vp, C.POINTER(sched_serve_opts_t), vp,
                           C.POINTER(sched_serve_summary_t)]),
     "sched_version": (C.c_char_p, []),
+    "sched_abi_sizeof": (i64, [i32]),
 }
+
+
+def abi_layouts():
+    """(library sizeof, binding sizeof) of every structure the ABI passes."""
+    mine = [C.sizeof(sched_config_t), C.sizeof(sched_stats_t), C.sizeof(sched_pass_result_t),
+            JOB_DTYPE.itemsize, RESULT_DTYPE.itemsize, C.sizeof(sched_serve_opts_t),
+            C.sizeof(sched_serve_summary_t), C.sizeof(sched_slab_info_t),
+            C.sizeof(sched_scan_result_t)]
+    return [(int(lib().sched_abi_sizeof(k)), m) for k, m in enumerate(mine)]
 
 _lib = None
 
@@ -419,14 +436,14 @@ def sched_profile_read(kernel):
 # ---------------------------------------------------------- serving loop
 def sched_serve(ctx, jobs, mode=SCHED_SERVE_REALTIME, n_streams=8, serial=0, batch_small=0,
                 small_bytes=16 << 20, iters=10, digest=0, time_scale=1.0, use_graph=1,
-                tune_cache=None):
+                tune_cache=None, max_placed=0):
     """jobs: numpy structured array in the layout of sched_job_desc_t
     (workloads.job_table).  Returns (rc, results structured array, summary dict)."""
     jobs = _np.ascontiguousarray(jobs)
-    assert jobs.dtype.itemsize == 48
+    assert jobs.dtype == JOB_DTYPE, jobs.dtype
     res = _np.zeros(jobs.shape[0], dtype=RESULT_DTYPE)
     o = sched_serve_opts_t(mode, n_streams, serial, batch_small, small_bytes, iters, digest,
-                           time_scale, use_graph, 0,
+                           time_scale, use_graph, max_placed,
                            tune_cache.encode() if tune_cache else None)
     sm = sched_serve_summary_t()
     rc = lib().sched_serve(ctx, jobs.shape[0], jobs.ctypes.data, C.byref(o), res.ctypes.data,

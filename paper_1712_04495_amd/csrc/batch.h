@@ -4,31 +4,35 @@
 #include <vector>
 
 #include "common.h"
+#include "pages.h"
 #include "prof.h"
 
 namespace schedk {
 
 struct BatchDesc {
-  float *a, *b, *c;            // output and inputs, n fp32 each
+  uint64_t oa, ob, oc;         // logical offsets (multiples of 4096) of output and inputs
   int64_t n;                   // elements
   uint64_t seed;               // input contents: SplitMix64 state seed << 32
   int32_t iters;               // triad sweeps
   int32_t pad;
-  unsigned long long *digest;  // += sum of the bit patterns of a[]
+  unsigned long long *digest;  // += position-keyed digest of a[] (pages.h)
 };
 
 // Header followed by max_desc descriptors and max_desc + 1 item offsets; the
 // pointers inside are valid in the address space of whoever reads the table.
+// The jobs of a batch share one placement, mapped by `map`.
 struct BatchTable {
   int32_t n_desc;
   int32_t pad;
   int64_t n_items;
-  int64_t chunk;               // elements per work item
+  int64_t chunk;               // elements per work item (a multiple of the block size)
   unsigned long long work;     // next work item
   BatchDesc *desc;
   int64_t *item_off;           // first work item of each job; [n_desc] = total
-  static size_t desc_offset() { return 64; }
-  static size_t off_offset(int max_desc) { return 64 + sizeof(BatchDesc) * size_t(max_desc); }
+  PageMap map;
+  int64_t need;                // pages the batch's jobs touch
+  static size_t desc_offset() { return 128; }
+  static size_t off_offset(int max_desc) { return 128 + sizeof(BatchDesc) * size_t(max_desc); }
   static size_t bytes_for(int max_desc) { return off_offset(max_desc) + 8 * size_t(max_desc + 1); }
   static void layout_at(BatchTable *t, char *base, int max_desc) {
     t->desc = (BatchDesc *)(base + desc_offset());
@@ -36,6 +40,7 @@ struct BatchTable {
   }
   static void layout(BatchTable *t, int max_desc) { layout_at(t, (char *)t, max_desc); }
 };
+static_assert(sizeof(BatchTable) <= 128, "the descriptors start at byte 128");
 
 struct BatchGraph {
   int block = 0, grid = 0;
@@ -61,7 +66,8 @@ struct BatchEngine {
 
 int batch_init(BatchEngine &b, int device, int max_desc);
 void batch_free(BatchEngine &b);
-int batch_fill(BatchEngine &b, const std::vector<BatchDesc> &descs, int64_t chunk);
+int batch_fill(BatchEngine &b, const std::vector<BatchDesc> &descs, int64_t chunk, const PageMap &map,
+               int64_t need);
 int batch_launch(BatchEngine &b, hipStream_t s, bool use_graph);
 int batch_autotune(BatchEngine &b, const char *cache_path, hipStream_t s);
 

@@ -43,6 +43,8 @@ __global__ void k_batch_stage(const BatchTable *__restrict__ host, BatchTable *_
     dev->n_desc = n;
     dev->n_items = host->n_items;
     dev->chunk = host->chunk;
+    dev->map = host->map;
+    dev->need = host->need;
     dev->work = 0;
   }
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
@@ -51,11 +53,18 @@ __global__ void k_batch_stage(const BatchTable *__restrict__ host, BatchTable *_
     dev->item_off[i] = host->item_off[i];
 }
 
+// A chunk starts at a multiple of the block size and a row of blockDim.x
+// elements (at most 4 KiB) starts at a multiple of its own size inside a
+// 4 KiB-aligned array, so a row never straddles a page: one translation per
+// row and array.
 __global__ void k_batch_run(BatchTable *__restrict__ t) {
   __shared__ long long s_item;
   const int64_t n_items = t->n_items;
   const int n_desc = t->n_desc;
   const int64_t chunk = t->chunk;
+  const PageMap m = t->map;
+  if (pm_pages(m) < t->need) return;  // the placement failed: nothing is mapped
+  const int bd = blockDim.x;
   for (;;) {
     if (threadIdx.x == 0) {
       const unsigned long long it = add_relaxed(&t->work, 1ULL);
@@ -76,21 +85,34 @@ __global__ void k_batch_run(BatchTable *__restrict__ t) {
     const int64_t e0 = (item - t->item_off[lo]) * chunk;
     const int64_t e1 = e0 + chunk < d.n ? e0 + chunk : d.n;
     const uint64_t s0 = d.seed << 32;
-    float *a = d.a, *b = d.b, *c = d.c;
     // input fill (same element -> same thread in every step below)
-    for (int64_t i = e0 + threadIdx.x; i < e1; i += blockDim.x) {
-      const uint64_t h = splitmix(s0, uint64_t(i));
-      b[i] = 1.0f + float(h & 0xFFFF) * (1.0f / 65536.0f);
-      c[i] = 1.0f + float((h >> 16) & 0xFFFF) * (1.0f / 65536.0f);
+    for (int64_t r = e0; r < e1; r += bd) {
+      const int64_t i = r + threadIdx.x;
+      float *b = reinterpret_cast<float *>(pm_addr(m, d.ob + uint64_t(r) * 4));
+      float *c = reinterpret_cast<float *>(pm_addr(m, d.oc + uint64_t(r) * 4));
+      if (i < e1) {
+        const uint64_t h = splitmix(s0, uint64_t(i));
+        b[threadIdx.x] = 1.0f + float(h & 0xFFFF) * (1.0f / 65536.0f);
+        c[threadIdx.x] = 1.0f + float((h >> 16) & 0xFFFF) * (1.0f / 65536.0f);
+      }
     }
     for (int it = 0; it < d.iters; ++it) {
-      for (int64_t i = e0 + threadIdx.x; i < e1; i += blockDim.x) a[i] = b[i] + 3.0f * c[i];
+      for (int64_t r = e0; r < e1; r += bd) {
+        float *a = reinterpret_cast<float *>(pm_addr(m, d.oa + uint64_t(r) * 4));
+        const float *b = reinterpret_cast<const float *>(pm_addr(m, d.ob + uint64_t(r) * 4));
+        const float *c = reinterpret_cast<const float *>(pm_addr(m, d.oc + uint64_t(r) * 4));
+        if (r + threadIdx.x < e1) a[threadIdx.x] = b[threadIdx.x] + 3.0f * c[threadIdx.x];
+      }
     }
     unsigned long long dg = 0;
-    for (int64_t i = e0 + threadIdx.x; i < e1; i += blockDim.x) dg += __float_as_uint(a[i]);
+    for (int64_t r = e0; r < e1; r += bd) {
+      const float *a = reinterpret_cast<const float *>(pm_addr(m, d.oa + uint64_t(r) * 4));
+      if (r + threadIdx.x < e1)
+        dg += digest_term(uint64_t(r + threadIdx.x), __float_as_uint(a[threadIdx.x]));
+    }
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) dg += __shfl_xor(dg, off, WAVE);
-    if ((threadIdx.x & (WAVE - 1)) == 0 && dg) add_relaxed(d.digest, dg);
+    if (d.digest && (threadIdx.x & (WAVE - 1)) == 0 && dg) add_relaxed(d.digest, dg);
   }
 }
 
@@ -160,11 +182,19 @@ static int graph_for(BatchEngine &b, int block, int grid, hipStream_t s, hipGrap
 }
 
 // Fills the pinned table from descriptors; chunk in elements.
-int batch_fill(BatchEngine &b, const std::vector<BatchDesc> &descs, int64_t chunk) {
+int batch_fill(BatchEngine &b, const std::vector<BatchDesc> &descs, int64_t chunk, const PageMap &map,
+               int64_t need) {
   if ((int)descs.size() > b.max_desc) return SCHED_E_INVALID;
+  // rows of up to 4 KiB at multiples of their own size: see k_batch_run
+  const int block = b.block > 0 ? b.block : 256;
+  if (block > 1024 || (block & (block - 1)) || chunk <= 0 || chunk % block) return SCHED_E_INVALID;
+  for (const BatchDesc &d : descs)
+    if ((d.oa | d.ob | d.oc) & 4095) return SCHED_E_INVALID;
   BatchTable *t = b.h_table;
   t->n_desc = int(descs.size());
   t->chunk = chunk;
+  t->map = map;
+  t->need = need;
   int64_t acc = 0;
   BatchDesc *hd = (BatchDesc *)((char *)t + BatchTable::desc_offset());
   int64_t *ho = (int64_t *)((char *)t + BatchTable::off_offset(b.max_desc));
@@ -217,15 +247,18 @@ int batch_autotune(BatchEngine &b, const char *cache_path, hipStream_t s) {
   }
   const int n_jobs = std::min(b.max_desc, 256);
   const int64_t job_elems = (4 << 20) / 12;  // 4 MiB triads
-  float *arena = nullptr;
+  const int64_t arr = (job_elems * 4 + 4095) / 4096 * 4096;
+  char *arena = nullptr;
   unsigned long long *dig = nullptr;
-  SCHED_HIP_TRY(hipMalloc(&arena, sizeof(float) * 3 * job_elems * n_jobs));
+  SCHED_HIP_TRY(hipMalloc(&arena, 3 * arr * n_jobs));
   SCHED_HIP_TRY(hipMalloc(&dig, sizeof(unsigned long long) * n_jobs));
+  PgIdentity idm;
+  if (int rc = pg_identity(arena, 3 * arr * n_jobs, s, &idm)) return rc;
+  const int64_t need = (3 * arr * n_jobs + PG_BYTES - 1) / PG_BYTES;
   std::vector<BatchDesc> ds(n_jobs);
   for (int i = 0; i < n_jobs; ++i) {
-    float *base = arena + int64_t(i) * 3 * job_elems;
-    ds[i] = BatchDesc{base, base + job_elems, base + 2 * job_elems, job_elems, uint64_t(i + 1), 10, 0,
-                      dig + i};
+    const uint64_t base = uint64_t(i) * 3 * arr;
+    ds[i] = BatchDesc{base, base + arr, base + 2 * arr, job_elems, uint64_t(i + 1), 10, 0, dig + i};
   }
   const int blocks[] = {256, 512, 1024};
   const int64_t chunks[] = {1 << 14, 1 << 16, 1 << 18};
@@ -240,7 +273,7 @@ int batch_autotune(BatchEngine &b, const char *cache_path, hipStream_t s) {
         if (blk * per > 2048) continue;  // at most 32 waves per CU
         b.block = blk;
         b.per_cu = per;
-        if (int rc = batch_fill(b, ds, ch)) return rc;
+        if (int rc = batch_fill(b, ds, ch, idm.map, need)) return rc;
         if (int rc = batch_launch(b, s, false)) return rc;  // warm
         SCHED_HIP_TRY(hipEventRecord(e0, s));
         for (int r = 0; r < 3; ++r)
@@ -263,6 +296,7 @@ int batch_autotune(BatchEngine &b, const char *cache_path, hipStream_t s) {
   b.tune_ms = best / 3;
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
+  pg_identity_free(&idm);
   (void)hipFree(arena);
   (void)hipFree(dig);
   if (cache_path && *cache_path) {

@@ -7,6 +7,7 @@
 #include <vector>
 
 #include "admission.h"
+#include "pages.h"
 
 struct SlabState;
 
@@ -50,9 +51,13 @@ struct sched_ctx {
   int64_t h_adm_cap = 0;
   sched_stats_t stats{};
 
-  // priority ordering scratch
+  // priority ordering: workspace (priority policies only, sized for the
+  // queue at creation), the range of every known job's priority, and the
+  // tail at the last ordering (the queue is still ordered while it holds)
   void *prio_tmp = nullptr;
   size_t prio_tmp_bytes = 0;
+  int32_t prio_lo = INT32_MAX, prio_hi = INT32_MIN;
+  int64_t prio_sorted_tail = 0;
 
   SlabState *slab = nullptr;
 
@@ -64,7 +69,26 @@ int sched_run_pass_locked(sched_ctx *c, hipStream_t s, sched_pass_result_t *res)
 // Waits for a reset still in flight on the context stream (mutex held).
 int sched_settle_reset_locked(sched_ctx *c);
 int sched_priority_reorder_locked(sched_ctx *c, hipStream_t s);
+int sched_priority_alloc(sched_ctx *c);
+void sched_priority_note(sched_ctx *c, int32_t prio);
 
 int sched_slab_init(sched_ctx *c, int64_t pool_bytes, int32_t n_tenants);
+
+// Page tier (slab.hip): a pool of pool_pages pages and n_slots placement
+// slots; tenants are the slab's (jobs), quotas their reservations.
+struct PageTier;
+int pg_create(sched_ctx *c, int64_t pool_pages, int32_t n_slots, hipStream_t s, PageTier **out);
+void pg_destroy(PageTier *t);
+// job_status[j] (may be NULL) receives 0 for every job of a placement that
+// succeeded, else the placement's status.
+int pg_place(sched_ctx *c, PageTier *t, int32_t n, const schedk::PgReq *reqs, const int32_t *jobs,
+             const int64_t *bytes, int32_t *job_status, hipStream_t s);
+int pg_release(sched_ctx *c, PageTier *t, int32_t n, const schedk::PgReq *reqs,
+               const int32_t *jobs, const int64_t *bytes, hipStream_t s);
+schedk::PageMap pg_map(const PageTier *t, int32_t slot, int64_t pages);
+int pg_counters(PageTier *t, hipStream_t s, schedk::PgCounters *out);
+int pg_check_free(PageTier *t, hipStream_t s, int64_t *bad);
 void sched_slab_free(sched_ctx *c);
 int64_t sched_slab_pool_used(sched_ctx *c);
+// Tenants are the context's jobs and their quotas the jobs' reservations.
+bool sched_slab_quota_is_reservation(sched_ctx *c);

@@ -151,6 +151,9 @@ extern "C" int sched_create(const sched_config_t *cfg, sched_ctx_t **out) {
     k_set_capacity<<<1, 1, 0, c->stream>>>(c->eng.d_ctl, capacity);
     if (hipGetLastError() != hipSuccess) rc = SCHED_E_INTERNAL;
   }
+  if (rc == SCHED_OK &&
+      (c->policy == SCHED_POLICY_PRIO_FIFO || c->policy == SCHED_POLICY_PRIO_MMU))
+    rc = sched_priority_alloc(c);
   if (rc == SCHED_OK && cfg->slab_pool_bytes > 0) {
     const int32_t T = cfg->max_tenants > 0 ? cfg->max_tenants : cfg->max_jobs;
     rc = sched_slab_init(c, cfg->slab_pool_bytes, T);
@@ -187,6 +190,7 @@ static int register_locked(sched_ctx *c, int32_t n, int32_t priority, int32_t ti
     c->prio[j0 + i] = priority;
     c->timeout_ms[j0 + i] = timeout_ms;
   }
+  sched_priority_note(c, priority);
   SCHED_HIP_TRY(hipSetDevice(c->device));
   // device copy of the priorities of the new jobs
   std::vector<int32_t> pr(n, priority);
@@ -718,6 +722,7 @@ extern "C" int sched_reset(sched_ctx_t *c) {
   for (const auto &kv : c->host_seq) c->pending[kv.second] = 0;
   c->host_seq.clear();
   c->head_h = c->tail_h = c->used_h = 0;
+  c->prio_sorted_tail = 0;  // an empty queue is ordered
   c->last_A = 0;
   c->rel_jobs_seen = c->rel_bytes_seen = 0;
   c->cv.notify_all();
@@ -730,7 +735,22 @@ extern "C" int sched_set_lookback_polls(int32_t polls) {
   return SCHED_OK;
 }
 
-extern "C" const char *sched_version(void) { return "sched-mi355x 0.1 (gfx950)"; }
+extern "C" const char *sched_version(void) { return "sched-mi355x 0.2 (gfx950)"; }
+
+extern "C" int64_t sched_abi_sizeof(int32_t which) {
+  switch (which) {
+    case 0: return sizeof(sched_config_t);
+    case 1: return sizeof(sched_stats_t);
+    case 2: return sizeof(sched_pass_result_t);
+    case 3: return sizeof(sched_job_desc_t);
+    case 4: return sizeof(sched_job_result_t);
+    case 5: return sizeof(sched_serve_opts_t);
+    case 6: return sizeof(sched_serve_summary_t);
+    case 7: return sizeof(sched_slab_info_t);
+    case 8: return sizeof(sched_scan_result_t);
+    default: return -1;
+  }
+}
 
 // ---------------------------------------------------------------------------
 // Checkpoint and restore (Sec. III-B, first and second robustness features:
@@ -966,6 +986,7 @@ extern "C" int sched_restore(sched_ctx_t *c, const void *buf, size_t bytes) {
   if (rc) return rc;
   for (int32_t j = 0; j < h.n_jobs; ++j) {
     c->prio[j] = jobs[j].prio;
+    sched_priority_note(c, jobs[j].prio);
     c->timeout_ms[j] = jobs[j].timeout_ms;
     c->owner[j] = jobs[j].owner;
     if (jobs[j].owner > 0) c->owned.push_back(j);

@@ -9,6 +9,17 @@
 // whenever something changed and launches the admitted jobs -- large ones on
 // a pool of streams, small ones packed into one persistent batched launch.
 //
+// Memory: an admitted job (or a batch of small ones) is placed in the page
+// tier (pages.h) right after the pass that admitted it: one placement kernel
+// per launch round charges each job's buffers to its reservation and maps
+// their pages; the job's kernels wait for it with an event and address their
+// buffers through the page table.  Admission keeps the charged bytes within
+// the capacity and the pool holds one spare page per placement slot, so a
+// placement of an admitted job cannot fail; the device counts any that does
+// as a memory-safety violation.  When a job's completion is observed its
+// placement is released (pages pushed back, charges returned) and then its
+// reservation, both on the control stream, in that order.
+//
 // Two clocks:
 //  * real time: arrivals follow their timestamps, durations are measured;
 //  * virtual: events are processed one at a time in the order (time,
@@ -23,7 +34,6 @@
 #include <cmath>
 #include <deque>
 #include <iterator>
-#include <map>
 #include <queue>
 #include <thread>
 #include <tuple>
@@ -58,33 +68,35 @@ __global__ void k_release_list(DevCtl *c, JobArrays jb, const int32_t *__restric
   }
 }
 
-__global__ void k_digest(const uint32_t *__restrict__ w, int64_t n, unsigned long long *out) {
-  unsigned long long s = 0;
-  for (int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; i < n;
-       i += int64_t(gridDim.x) * blockDim.x)
-    s += w[i];
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, WAVE);
-  if ((threadIdx.x & (WAVE - 1)) == 0 && s) add_relaxed(out, s);
-}
-
 __global__ void k_zero_u64(unsigned long long *p, int64_t n) {
   for (int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; i < n;
        i += int64_t(gridDim.x) * blockDim.x)
     p[i] = 0;
 }
 
+__global__ void k_fill_i32(int32_t *p, int64_t n, int32_t v) {
+  for (int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; i < n;
+       i += int64_t(gridDim.x) * blockDim.x)
+    p[i] = v;
+}
+
 int64_t rup(int64_t x, int64_t a) { return (x + a - 1) / a * a; }
 
-// Buffer bytes a job allocates; must not exceed its declared demand.
+// Buffer bytes a job allocates (each array rounded up to 4 KiB); must not
+// exceed its declared demand.  A GEMM's N must be a power of two in
+// [256, 16384] (every operand row inside one page).
 int64_t job_bytes(const sched_job_desc_t &j) {
   switch (j.kind) {
-    case SCHED_JOB_TRIAD: return 3 * rup(4 * j.size, 4096);
-    case SCHED_JOB_GEMM: return 2 * rup(2 * j.size * j.size, 4096) + rup(4 * j.size * j.size, 4096);
-    case SCHED_JOB_HIST: return rup(4 * j.size, 4096) + rup(4 * SCHED_HIST_BINS, 4096);
+    case SCHED_JOB_TRIAD: return j.size > 0 ? 3 * rup(4 * j.size, 4096) : -1;
+    case SCHED_JOB_GEMM:
+      if (j.size < 256 || j.size > 16384 || (j.size & (j.size - 1))) return -1;
+      return 2 * rup(2 * j.size * j.size, 4096) + rup(4 * j.size * j.size, 4096);
+    case SCHED_JOB_HIST: return j.size > 0 ? rup(4 * j.size, 4096) + rup(4 * SCHED_HIST_BINS, 4096) : -1;
     default: return -1;
   }
 }
+
+int64_t pages_of(int64_t bytes) { return (bytes + PG_BYTES - 1) / PG_BYTES; }
 
 int grid_of(int64_t n, int cap) {
   int64_t g = (n + 255) / 256;
@@ -94,70 +106,44 @@ int grid_of(int64_t n, int cap) {
 struct Running {
   int32_t job;          // -1 for a batch
   int32_t batch;        // index into batch_jobs, -1 for a single job
-  uint64_t off, len;    // arena range (len 0: none)
+  int32_t slot;         // placement slot
   hipEvent_t ev_start, ev_end;
   hipStream_t stream;
 };
 
-// Device memory of the admitted jobs: one allocation of the scheduler's
-// capacity, carved on the host best fit with coalescing of free neighbours
-// (4 KiB granules).  Admission keeps the sum of the live demands within the
-// capacity; a job whose demand fits but finds no contiguous range waits
-// until a running job ends (when nothing runs the arena is one free range,
-// so every admitted job eventually gets its memory).  A range returns to the
-// arena only when its job's completion has been observed.
-class Arena {
- public:
-  char *base = nullptr;
-  uint64_t size = 0;
-  bool alloc(uint64_t len, uint64_t *off) {
-    auto it = by_len.lower_bound(len);
-    if (it == by_len.end()) return false;
-    const uint64_t L = it->first, o = it->second;
-    by_len.erase(it);
-    by_off.erase(o);
-    if (L > len) put(o + len, L - len);
-    *off = o;
-    return true;
-  }
-  void release(uint64_t off, uint64_t len) {
-    auto nx = by_off.lower_bound(off);
-    if (nx != by_off.end() && off + len == nx->first) {
-      drop_len(nx->second, nx->first);
-      len += nx->second;
-      nx = by_off.erase(nx);
-    }
-    if (nx != by_off.begin()) {
-      auto pv = std::prev(nx);
-      if (pv->first + pv->second == off) {
-        drop_len(pv->second, pv->first);
-        off = pv->first;
-        len += pv->second;
-        by_off.erase(pv);
-      }
-    }
-    put(off, len);
-  }
-  void reset() {
-    by_off.clear();
-    by_len.clear();
-    if (size) put(0, size);
-  }
+// A placement to launch after the round's placement kernel.
+struct Pending {
+  int32_t job;          // -1: the batch in batch_take
+  int32_t slot;
+  int64_t pages;
+  size_t si;            // stream index (single jobs)
+};
 
- private:
-  std::map<uint64_t, uint64_t> by_off;       // offset -> length
-  std::multimap<uint64_t, uint64_t> by_len;  // length -> offset
-  void put(uint64_t off, uint64_t len) {
-    by_off.emplace(off, len);
-    by_len.emplace(len, off);
+// Pinned, host-mapped staging for the placement and release kernels' inputs
+// (the kernels read it directly).  Reset only after the control stream has
+// synchronised, when every kernel that read it has run.
+struct Staging {
+  char *h = nullptr, *d = nullptr;
+  size_t cap = 0, used = 0;
+  int init(size_t bytes) {
+    SCHED_HIP_TRY(hipHostMalloc(&h, bytes, hipHostMallocMapped));
+    SCHED_HIP_TRY(hipHostGetDevicePointer((void **)&d, h, 0));
+    cap = bytes;
+    return SCHED_OK;
   }
-  void drop_len(uint64_t len, uint64_t off) {
-    auto r = by_len.equal_range(len);
-    for (auto it = r.first; it != r.second; ++it)
-      if (it->second == off) {
-        by_len.erase(it);
-        return;
-      }
+  // host and device views of `bytes` bytes, 16-B aligned; nullptr when full
+  template <typename T>
+  T *take(size_t count, T **dev) {
+    const size_t b = (sizeof(T) * count + 15) / 16 * 16;
+    if (used + b > cap) return nullptr;
+    T *p = (T *)(h + used);
+    *dev = (T *)(d + used);
+    used += b;
+    return p;
+  }
+  void free_() {
+    if (h) (void)hipHostFree(h);
+    h = d = nullptr;
   }
 };
 
@@ -175,6 +161,8 @@ struct Serve {
   hipEvent_t ev0 = nullptr;
   std::chrono::steady_clock::time_point h0;
   unsigned long long *d_digest = nullptr;
+  float *d_samples = nullptr;
+  int32_t *d_place_st = nullptr;   // per job: placement status (-1: never placed)
   std::vector<hipEvent_t> ev_free;
   // in-flight work per stream, oldest first (one extra queue for batches):
   // work on one stream completes in order, so only heads are polled
@@ -190,8 +178,16 @@ struct Serve {
   BatchEngine *beng = nullptr;
   int64_t finished = 0;
   int64_t cur_running = 0;
-  Arena arena;
-  std::deque<int32_t> deferred;  // admitted, waiting for a contiguous range
+  // page tier
+  PageTier *pt = nullptr;
+  Staging stage;
+  std::vector<int32_t> free_slots;
+  std::deque<int32_t> slot_wait;                // admitted, waiting for a placement slot
+  hipEvent_t ev_placed = nullptr;
+  std::vector<Pending> round;                   // placements of the current launch round
+  std::vector<int32_t> batch_take;              // jobs of the batch in `round`
+  std::vector<int32_t> released_slots;          // completions of the current poll
+  std::vector<std::vector<int32_t>> slot_jobs;  // jobs charged by each live slot
 
   double host_now() const {
     return std::chrono::duration<double>(std::chrono::steady_clock::now() - h0).count();
@@ -232,14 +228,27 @@ struct Serve {
     streams.resize(ns);
     for (auto &s : streams) SCHED_HIP_TRY(hipStreamCreate(&s));
     inflight.resize(ns + 1);
-    if (o.mode == SCHED_SERVE_REALTIME) {
-      arena.size = uint64_t(rup(c->capacity, 4096));
-      SCHED_HIP_TRY(hipMalloc(&arena.base, arena.size));
-      arena.reset();
-    }
     SCHED_HIP_TRY(hipMalloc(&d_digest, sizeof(unsigned long long) * std::max<int64_t>(n, 1)));
     k_zero_u64<<<grid_of(n, 1024), 256, 0, stream_ctl>>>(d_digest, n);
     SCHED_HIP_TRY(hipGetLastError());
+    SCHED_HIP_TRY(hipMalloc(&d_samples, sizeof(float) * GEMM_SAMPLES * std::max<int64_t>(n, 1)));
+    SCHED_HIP_TRY(hipMalloc(&d_place_st, sizeof(int32_t) * std::max<int64_t>(n, 1)));
+    k_fill_i32<<<grid_of(n, 1024), 256, 0, stream_ctl>>>(d_place_st, n, -1);
+    SCHED_HIP_TRY(hipGetLastError());
+    if (o.mode == SCHED_SERVE_REALTIME) {
+      // placement slots: one spare page each on top of the capacity
+      const int64_t want = o.max_placed > 0 ? o.max_placed : std::min<int64_t>(n, 16384);
+      const int32_t slots = int32_t(std::max<int64_t>(1, std::min<int64_t>(want, 1 << 20)));
+      const int64_t pages = pages_of(c->capacity) + slots;
+      if (int rc = pg_create(c, pages, slots, stream_ctl, &pt)) return rc;
+      free_slots.resize(slots);
+      for (int32_t i = 0; i < slots; ++i) free_slots[i] = slots - 1 - i;
+      slot_jobs.resize(slots);
+      if (int rc = stage.init(size_t(8) << 20)) return rc;
+      SCHED_HIP_TRY(hipEventCreateWithFlags(&ev_placed, hipEventDisableTiming));
+      sum.pool_pages = pages;
+      sum.placement_slots = slots;
+    }
     h_cap = std::max<int64_t>(n, 1);
     SCHED_HIP_TRY(hipHostMalloc(&h_job, sizeof(int32_t) * h_cap, hipHostMallocDefault));
     SCHED_HIP_TRY(hipHostMalloc(&h_dem, sizeof(int64_t) * h_cap, hipHostMallocDefault));
@@ -249,7 +258,10 @@ struct Serve {
     SCHED_HIP_TRY(hipHostMalloc(&h_rel, sizeof(int32_t) * h_cap, hipHostMallocDefault));
     SCHED_HIP_TRY(hipMalloc(&d_rel, sizeof(int32_t) * h_cap));
     // priorities of jobs 0..n-1
-    for (int64_t i = 0; i < n; ++i) h_job[i] = J[i].priority;
+    for (int64_t i = 0; i < n; ++i) {
+      h_job[i] = J[i].priority;
+      sched_priority_note(c, J[i].priority);
+    }
     SCHED_HIP_TRY(hipMemcpyAsync(c->d_prio_of_job, h_job, sizeof(int32_t) * n, hipMemcpyHostToDevice,
                                  stream_ctl));
     if (o.batch_small && !o.serial) {
@@ -278,18 +290,18 @@ struct Serve {
       }
     for (auto e : ev_free) (void)hipEventDestroy(e);
     for (auto s : streams) (void)hipStreamDestroy(s);
-    if (arena.base) (void)hipFree(arena.base);
-    arena.base = nullptr;
     if (bstream) (void)hipStreamDestroy(bstream);
     if (ev0) (void)hipEventDestroy(ev0);
-    if (d_digest) (void)hipFree(d_digest);
-    if (h_job) (void)hipHostFree(h_job);
-    if (h_dem) (void)hipHostFree(h_dem);
-    if (h_adm) (void)hipHostFree(h_adm);
-    if (d_job) (void)hipFree(d_job);
-    if (d_dem) (void)hipFree(d_dem);
-    if (h_rel) (void)hipHostFree(h_rel);
-    if (d_rel) (void)hipFree(d_rel);
+    if (ev_placed) (void)hipEventDestroy(ev_placed);
+    if (pt) pg_destroy(pt);
+    pt = nullptr;
+    stage.free_();
+    void *dev[] = {d_digest, d_samples, d_place_st, d_job, d_dem, d_rel};
+    for (void *p : dev)
+      if (p) (void)hipFree(p);
+    void *host[] = {h_job, h_dem, h_adm, h_rel};
+    for (void *p : host)
+      if (p) (void)hipHostFree(p);
     if (beng) {
       batch_free(*beng);
       delete beng;
@@ -312,6 +324,7 @@ struct Serve {
     return SCHED_OK;
   }
 
+  // Returns the reservations of k finished jobs (staged in h_rel).
   int release(int64_t k) {
     if (k == 0) return SCHED_OK;
     SCHED_HIP_TRY(hipMemcpyAsync(d_rel, h_rel, sizeof(int32_t) * k, hipMemcpyHostToDevice, stream_ctl));
@@ -321,6 +334,7 @@ struct Serve {
   }
 
   // One admission pass; the admitted job ids (queue order) land in h_adm.
+  // The pass synchronises the control stream, so the staging is free again.
   int pass(int64_t *n_adm) {
     sched_pass_result_t pr{};
     if (int rc = sched_run_pass_locked(c, stream_ctl, &pr)) return rc;
@@ -330,96 +344,184 @@ struct Serve {
                                    stream_ctl));
       SCHED_HIP_TRY(hipStreamSynchronize(stream_ctl));
     }
+    stage.used = 0;
     sum.passes += 1;
     sum.peak_used = std::max<int64_t>(sum.peak_used, c->used_h);
     *n_adm = A;
     return SCHED_OK;
   }
 
-  // Buffers and work of one job on stream s.  Returns the allocation so the
-  // caller can free it after completion (stream-ordered free is enqueued
-  // here as well).
-  int launch_single(int32_t j, hipStream_t s, Running *r) {
+  // Staging room for `reqs` requests and `jobs` job entries; synchronises the
+  // control stream to recycle the staging when it is full.
+  int stage_room(size_t reqs, size_t jobs) {
+    const size_t need = (sizeof(PgReq) * reqs + 15) / 16 * 16 + (4 * jobs + 15) / 16 * 16 +
+                        (8 * jobs + 15) / 16 * 16;
+    if (need > stage.cap) return SCHED_E_INVALID;
+    if (stage.used + need > stage.cap) {
+      SCHED_HIP_TRY(hipStreamSynchronize(stream_ctl));
+      stage.used = 0;
+    }
+    return SCHED_OK;
+  }
+
+  // The placement kernel for the requests of this launch round, then the
+  // event every job stream of the round waits on.
+  int place_round() {
+    if (round.empty()) return SCHED_OK;
+    size_t n_jobs = 0;
+    for (const Pending &p : round) n_jobs += p.job >= 0 ? 1 : batch_take.size();
+    if (int rc = stage_room(round.size(), n_jobs)) return rc;
+    PgReq *d_rq;
+    int32_t *d_j;
+    int64_t *d_b;
+    PgReq *rq = stage.take<PgReq>(round.size(), &d_rq);
+    int32_t *hj = stage.take<int32_t>(n_jobs, &d_j);
+    int64_t *hb = stage.take<int64_t>(n_jobs, &d_b);
+    size_t off = 0;
+    for (size_t i = 0; i < round.size(); ++i) {
+      const Pending &p = round[i];
+      const size_t k = p.job >= 0 ? 1 : batch_take.size();
+      rq[i] = PgReq{p.slot, int32_t(k), p.pages, int64_t(off)};
+      for (size_t q = 0; q < k; ++q) {
+        const int32_t j = p.job >= 0 ? p.job : batch_take[q];
+        hj[off + q] = j;
+        hb[off + q] = job_bytes(J[j]);
+      }
+      off += k;
+    }
+    if (int rc = pg_place(c, pt, int32_t(round.size()), d_rq, d_j, d_b, d_place_st, stream_ctl))
+      return rc;
+    SCHED_HIP_TRY(hipEventRecord(ev_placed, stream_ctl));
+    sum.placements += int64_t(round.size());
+    return SCHED_OK;
+  }
+
+  // Buffers and work of one placed job on stream s.
+  int launch_single(int32_t j, int32_t slot, int64_t pages, hipStream_t s, Running *r) {
     const sched_job_desc_t &d = J[j];
     r->job = j;
     r->batch = -1;
+    r->slot = slot;
     r->stream = s;
-    const int64_t bytes = job_bytes(d);
-    if (bytes < 0 || bytes > d.demand) return SCHED_E_INVALID;
-    const uint64_t len = uint64_t(rup(std::max<int64_t>(bytes, 1), 4096));
-    uint64_t off = 0;
-    const double ta = host_now();
-    const bool got = arena.alloc(len, &off);
-    sum.host_alloc_s += host_now() - ta;
-    if (!got) return SCHED_NOT_READY;  // no contiguous range yet: the caller defers
-    r->off = off;
-    r->len = len;
     r->ev_start = take_event();
     r->ev_end = take_event();
+    const PageMap m = pg_map(pt, slot, pages);
     SCHED_HIP_TRY(hipEventRecord(r->ev_start, s));
-    char *p = arena.base + off;
     unsigned long long *dg = d_digest + j;
     if (d.kind == SCHED_JOB_TRIAD) {
-      const int64_t n4 = rup(4 * d.size, 4096);
-      float *a = (float *)p, *b = (float *)(p + n4), *cc = (float *)(p + 2 * n4);
-      if (int rc = sched_triad_fill(b, cc, d.size, d.seed, s)) return rc;
-      if (int rc = sched_triad(a, b, cc, 3.0f, d.size, o.iters, s)) return rc;
-      if (o.digest) k_digest<<<grid_of(d.size, 2048), 256, 0, s>>>((const uint32_t *)a, d.size, dg);
+      const uint64_t arr = uint64_t(rup(4 * d.size, 4096));
+      if (int rc = pgt_triad_fill(m, arr, 2 * arr, d.size, d.seed, s)) return rc;
+      if (int rc = pgt_triad(m, 0, arr, 2 * arr, 3.0f, d.size, o.iters, s)) return rc;
+      if (o.digest)
+        if (int rc = pgt_digest(m, 0, d.size, dg, s)) return rc;
     } else if (d.kind == SCHED_JOB_GEMM) {
-      const int64_t N = d.size, ab = rup(2 * N * N, 4096);
-      uint16_t *A = (uint16_t *)p, *B = (uint16_t *)(p + ab);
-      float *C = (float *)(p + 2 * ab);
-      if (int rc = sched_gemm_fill(A, N, N, 2 * d.seed, s)) return rc;
-      if (int rc = sched_gemm_fill(B, N, N, 2 * d.seed + 1, s)) return rc;
-      if (int rc = sched_gemm_bf16(A, B, C, N, N, N, s)) return rc;
-      if (o.digest) k_digest<<<grid_of(N * N, 2048), 256, 0, s>>>((const uint32_t *)C, N * N, dg);
+      const int64_t N = d.size;
+      const uint64_t ab = uint64_t(rup(2 * N * N, 4096));
+      if (int rc = pgt_gemm_fill(m, 0, N, N, 2 * d.seed, s)) return rc;
+      if (int rc = pgt_gemm_fill(m, ab, N, N, 2 * d.seed + 1, s)) return rc;
+      if (int rc = pgt_gemm(m, 0, ab, 2 * ab, N, s)) return rc;
+      if (o.digest) {
+        if (int rc = pgt_digest(m, 2 * ab, N * N, dg, s)) return rc;
+        if (int rc = pgt_gemm_samples(m, 2 * ab, N, d.seed, d_samples + int64_t(j) * GEMM_SAMPLES, s))
+          return rc;
+      }
     } else {
-      const int64_t kb = rup(4 * d.size, 4096);
-      uint32_t *keys = (uint32_t *)p, *bins = (uint32_t *)(p + kb);
-      if (int rc = sched_hist_fill(keys, d.size, d.seed, s)) return rc;
-      if (int rc = sched_hist(keys, d.size, SCHED_HIST_BINS - 1, bins, s)) return rc;
-      if (o.digest) k_digest<<<1, 256, 0, s>>>(bins, SCHED_HIST_BINS, dg);
+      const uint64_t kb = uint64_t(rup(4 * d.size, 4096));
+      if (int rc = pgt_hist_fill(m, 0, d.size, d.seed, s)) return rc;
+      if (int rc = pgt_hist(m, 0, d.size, SCHED_HIST_BINS - 1, kb, s)) return rc;
+      if (o.digest)
+        if (int rc = pgt_digest(m, kb, SCHED_HIST_BINS, dg, s)) return rc;
     }
-    SCHED_HIP_TRY(hipGetLastError());
     SCHED_HIP_TRY(hipEventRecord(r->ev_end, s));
     return SCHED_OK;
   }
 
-  // Small triads admitted together: one arena, one persistent launch.
-  int launch_batch(const std::vector<int32_t> &jobs, Running *r) {
+  // Small triads admitted together: one placement, one persistent launch.
+  int launch_batch(const std::vector<int32_t> &jobs, int32_t slot, int64_t pages, Running *r) {
     r->job = -1;
     r->batch = int32_t(batch_jobs.size());
+    r->slot = slot;
     r->stream = bstream;
-    uint64_t total = 0;
-    for (int32_t j : jobs) total += uint64_t(job_bytes(J[j]));  // whole pages per array
-    uint64_t off = 0;
-    const double ta = host_now();
-    const bool got = arena.alloc(std::max<uint64_t>(total, 4096), &off);
-    sum.host_alloc_s += host_now() - ta;
-    if (!got) return SCHED_NOT_READY;
-    r->off = off;
-    r->len = std::max<uint64_t>(total, 4096);
     r->ev_start = take_event();
     r->ev_end = take_event();
     SCHED_HIP_TRY(hipEventRecord(r->ev_start, bstream));
     std::vector<BatchDesc> ds;
     ds.reserve(jobs.size());
-    char *p = arena.base + off;
+    uint64_t base = 0;
     for (int32_t j : jobs) {
-      const int64_t n4 = rup(4 * J[j].size, 4096);
-      ds.push_back(BatchDesc{(float *)p, (float *)(p + n4), (float *)(p + 2 * n4), J[j].size,
-                             J[j].seed, o.iters, 0, d_digest + j});
+      const uint64_t arr = uint64_t(rup(4 * J[j].size, 4096));
+      ds.push_back(BatchDesc{base, base + arr, base + 2 * arr, J[j].size, J[j].seed, o.iters, 0,
+                             o.digest ? d_digest + j : nullptr});
       res[j].batched = 1;
-      p += job_bytes(J[j]);
+      base += uint64_t(job_bytes(J[j]));
     }
     // the pinned table is rewritten only when no batch is in flight
-    if (int rc = batch_fill(*beng, ds, beng->chunk)) return rc;
+    if (int rc = batch_fill(*beng, ds, beng->chunk, pg_map(pt, slot, pages), pages)) return rc;
     if (int rc = batch_launch(*beng, bstream, o.use_graph != 0)) return rc;
     SCHED_HIP_TRY(hipEventRecord(r->ev_end, bstream));
     batch_running = true;
     sum.batches += 1;
     sum.batched_jobs += int64_t(jobs.size());
     batch_jobs.push_back(jobs);
+    return SCHED_OK;
+  }
+
+  // A free placement slot, or -1.
+  int32_t take_slot() {
+    if (free_slots.empty()) return -1;
+    const int32_t s = free_slots.back();
+    free_slots.pop_back();
+    return s;
+  }
+
+  // Queues admitted job j for placement in this launch round, or for a slot
+  // (behind the jobs already waiting for one, in admission order).
+  void plan_single(int32_t j) {
+    if (!slot_wait.empty() || free_slots.empty()) {
+      slot_wait.push_back(j);
+      sum.slot_waits += 1;
+      return;
+    }
+    place_single(j, take_slot());
+  }
+
+  void place_single(int32_t j, int32_t slot) {
+    const size_t si = pick_stream();
+    round.push_back(Pending{j, slot, pages_of(job_bytes(J[j])), si});
+    slot_jobs[slot].assign(1, j);
+    res[j].t_place = host_now();
+    ++next_stream;
+    // the stream's nominal backlog includes the job from now on
+    pending_backlog[si] += J[j].vdur_s;
+  }
+
+  // Placement kernel, then the work of every job of the round.
+  int launch_round() {
+    if (round.empty()) return SCHED_OK;
+    if (int rc = place_round()) return rc;
+    std::vector<char> waited(streams.size() + 1, 0);
+    for (const Pending &p : round) {
+      Running r{};
+      if (p.job >= 0) {
+        hipStream_t s = streams[p.si];
+        if (!waited[p.si]) {
+          SCHED_HIP_TRY(hipStreamWaitEvent(s, ev_placed, 0));
+          waited[p.si] = 1;
+        }
+        if (int rc = launch_single(p.job, p.slot, p.pages, s, &r)) return rc;
+        inflight[p.si].push_back(r);
+        pending_backlog[p.si] -= J[p.job].vdur_s;
+        cur_running += 1;
+      } else {
+        SCHED_HIP_TRY(hipStreamWaitEvent(bstream, ev_placed, 0));
+        if (int rc = launch_batch(batch_take, p.slot, p.pages, &r)) return rc;
+        inflight.back().push_back(r);
+        cur_running += int64_t(batch_take.size());
+      }
+    }
+    round.clear();
+    batch_take.clear();
+    sum.max_running = std::max<int64_t>(sum.max_running, cur_running);
     return SCHED_OK;
   }
 
@@ -431,22 +533,19 @@ struct Serve {
         pending_small.push_back(j);
         continue;
       }
-      if (!deferred.empty()) {  // keep admission order behind jobs already waiting
-        deferred.push_back(j);
-        continue;
-      }
-      if (int rc = start_single(j)) return rc;
+      plan_single(j);
     }
-    if (int rc = maybe_launch_batch()) return rc;
-    sum.max_running = std::max<int64_t>(sum.max_running, cur_running);
-    return SCHED_OK;
+    plan_batch();
+    return launch_round();
   }
 
   // The job stream with the least expected backlog: the sum of the nominal
   // durations of the jobs still in flight on it (ties in round-robin order).
   // Streams run their jobs in order, so a short job placed behind a long one
   // would hold its reservation until the long one ends.
-  size_t pick_stream() const {
+  std::vector<double> pending_backlog;
+  size_t pick_stream() {
+    if (pending_backlog.size() != streams.size()) pending_backlog.assign(streams.size(), 0.0);
     size_t best = next_stream % streams.size();
     double best_load = backlog(best);
     for (size_t k = 1; k < streams.size(); ++k) {
@@ -460,66 +559,43 @@ struct Serve {
     return best;
   }
   double backlog(size_t si) const {
-    double t = 0.0;
+    double t = si < pending_backlog.size() ? pending_backlog[si] : 0.0;
     for (const Running &r : inflight[si])
       if (r.job >= 0) t += J[r.job].vdur_s;
     return t;
   }
 
-  // Launches admitted job j, or defers it while no contiguous range fits.
-  int start_single(int32_t j) {
-    Running r{};
-    const size_t si = pick_stream();
-    const int rc = launch_single(j, streams[si], &r);
-    if (rc == SCHED_NOT_READY) {
-      deferred.push_back(j);
-      sum.deferred += 1;
-      return SCHED_OK;
+  // Jobs waiting for a slot, oldest first, while slots are free.
+  int launch_slot_waiters() {
+    while (!slot_wait.empty() && !free_slots.empty()) {
+      const int32_t j = slot_wait.front();
+      slot_wait.pop_front();
+      place_single(j, take_slot());
     }
-    if (rc) return rc;
-    ++next_stream;
-    inflight[si].push_back(r);
-    cur_running += 1;
     return SCHED_OK;
   }
 
-  // Deferred jobs, oldest first, as long as ranges fit.
-  int launch_deferred() {
-    while (!deferred.empty()) {
-      const int32_t j = deferred.front();
-      Running r{};
-      const size_t si = pick_stream();
-      const int rc = launch_single(j, streams[si], &r);
-      if (rc == SCHED_NOT_READY) break;
-      if (rc) return rc;
-      deferred.pop_front();
-      ++next_stream;
-      inflight[si].push_back(r);
-      cur_running += 1;
+  // The waiting small jobs (at most what one placement maps) as one batch
+  // placement of this round, when no batch is in flight.
+  void plan_batch() {
+    if (!beng || batch_running || pending_small.empty() || !batch_take.empty()) return;
+    const int32_t slot = take_slot();
+    if (slot < 0) return;  // retried after the next completion
+    int64_t bytes = 0;
+    size_t k = 0;
+    while (k < pending_small.size() && k < size_t(beng->max_desc)) {
+      const int64_t b = job_bytes(J[pending_small[k]]);
+      if (pages_of(bytes + b) > PG_MAX_PAGES) break;
+      bytes += b;
+      ++k;
     }
-    sum.max_running = std::max<int64_t>(sum.max_running, cur_running);
-    return SCHED_OK;
-  }
-
-  int maybe_launch_batch() {
-    if (!beng || batch_running || pending_small.empty()) return SCHED_OK;
-    // as many of the waiting small jobs as one contiguous range holds
-    size_t k = std::min<size_t>(pending_small.size(), size_t(beng->max_desc));
-    Running r{};
-    std::vector<int32_t> take;
-    for (;;) {
-      take.assign(pending_small.begin(), pending_small.begin() + k);
-      const int rc = launch_batch(take, &r);
-      if (rc == SCHED_OK) break;
-      if (rc != SCHED_NOT_READY) return rc;
-      if (k == 1) return SCHED_OK;  // retried after the next completion
-      k /= 2;
-    }
+    batch_take.assign(pending_small.begin(), pending_small.begin() + k);
     pending_small.erase(pending_small.begin(), pending_small.begin() + k);
-    inflight.back().push_back(r);
-    cur_running += int64_t(take.size());
-    sum.max_running = std::max<int64_t>(sum.max_running, cur_running);
-    return SCHED_OK;
+    slot_jobs[slot] = batch_take;
+    const double now = host_now();
+    for (int32_t j : batch_take) res[j].t_place = now;
+    round.push_back(Pending{-1, slot, pages_of(bytes), 0});
+    batch_running = true;
   }
 
   // Completed jobs -> results + staged releases; returns how many staged.
@@ -544,13 +620,48 @@ struct Serve {
         } else {
           done_one(r.job);
         }
-        if (r.len) arena.release(r.off, r.len);
+        released_slots.push_back(r.slot);
         ev_free.push_back(r.ev_start);
         ev_free.push_back(r.ev_end);
         q.pop_front();
       }
     }
     return k;
+  }
+
+  // Releases the placements of the completed jobs: pages back to the pool,
+  // charges back to the jobs.  Comes before the release of their
+  // reservations on the same stream.
+  int release_placements() {
+    if (released_slots.empty()) return SCHED_OK;
+    size_t n_jobs = 0;
+    for (int32_t s : released_slots) n_jobs += slot_jobs[s].size();
+    if (int rc = stage_room(released_slots.size(), n_jobs)) return rc;
+    PgReq *d_rq;
+    int32_t *d_j;
+    int64_t *d_b;
+    PgReq *rq = stage.take<PgReq>(released_slots.size(), &d_rq);
+    int32_t *hj = stage.take<int32_t>(n_jobs, &d_j);
+    int64_t *hb = stage.take<int64_t>(n_jobs, &d_b);
+    size_t off = 0;
+    for (size_t i = 0; i < released_slots.size(); ++i) {
+      const int32_t s = released_slots[i];
+      const std::vector<int32_t> &js = slot_jobs[s];
+      rq[i] = PgReq{s, int32_t(js.size()), 0, int64_t(off)};
+      for (size_t q = 0; q < js.size(); ++q) {
+        hj[off + q] = js[q];
+        hb[off + q] = job_bytes(J[js[q]]);
+      }
+      off += js.size();
+    }
+    if (int rc = pg_release(c, pt, int32_t(released_slots.size()), d_rq, d_j, d_b, stream_ctl))
+      return rc;
+    for (int32_t s : released_slots) {
+      slot_jobs[s].clear();
+      free_slots.push_back(s);
+    }
+    released_slots.clear();
+    return SCHED_OK;
   }
 
   int run_realtime() {
@@ -563,7 +674,8 @@ struct Serve {
       while (ai < n && J[ai].arrival_s * scale <= now) {
         res[ai].t_arrive = J[ai].arrival_s * scale;
         const int64_t d = demand_of(ai);
-        if (d > c->capacity || job_bytes(J[ai]) < 0 || job_bytes(J[ai]) > J[ai].demand) {
+        const int64_t jb = job_bytes(J[ai]);
+        if (d > c->capacity || jb < 0 || jb > J[ai].demand || pages_of(jb) > PG_MAX_PAGES) {
           res[ai].status = d > c->capacity ? SCHED_E_TOOBIG : SCHED_E_INVALID;
           sum.rejected += 1;
           finished += 1;
@@ -581,14 +693,17 @@ struct Serve {
       double t1 = host_now();
       const int64_t r = poll_completions();
       if (r) {
+        if (int rc = release_placements()) return rc;
         if (int rc = release(r)) return rc;
         changed = true;
       }
       double t2 = host_now();
       sum.host_poll_s += t2 - t1;
-      if (r)
-        if (int rc = launch_deferred()) return rc;
-      if (int rc = maybe_launch_batch()) return rc;
+      if (r) {
+        if (int rc = launch_slot_waiters()) return rc;
+        plan_batch();
+        if (int rc = launch_round()) return rc;
+      }
       t1 = host_now();
       sum.host_launch_s += t1 - t2;
       if (changed) {
@@ -647,10 +762,51 @@ struct Serve {
       for (int64_t i = 0; i < A; ++i) {
         const int32_t a = h_adm[i];
         res[a].t_admit = t;
+        res[a].t_place = t;
         res[a].t_start = t;
         pq.emplace(t + J[a].vdur_s, 0, int64_t(a));
       }
     }
+    return SCHED_OK;
+  }
+
+  // Device-side results: digests, GEMM samples, placement statuses, and the
+  // page tier's counters and end-of-run check.
+  int collect() {
+    SCHED_HIP_TRY(hipDeviceSynchronize());
+    if (o.digest && n > 0) {
+      std::vector<unsigned long long> dg(n);
+      std::vector<float> sp(size_t(n) * GEMM_SAMPLES);
+      SCHED_HIP_TRY(hipMemcpy(dg.data(), d_digest, sizeof(unsigned long long) * n,
+                              hipMemcpyDeviceToHost));
+      SCHED_HIP_TRY(hipMemcpy(sp.data(), d_samples, sizeof(float) * sp.size(), hipMemcpyDeviceToHost));
+      for (int64_t i = 0; i < n; ++i) {
+        res[i].digest = dg[i];
+        if (J[i].kind == SCHED_JOB_GEMM)
+          for (int k = 0; k < GEMM_SAMPLES; ++k) res[i].sample[k] = sp[size_t(i) * GEMM_SAMPLES + k];
+      }
+    }
+    if (!pt) return SCHED_OK;
+    std::vector<int32_t> st(std::max<int64_t>(n, 1));
+    SCHED_HIP_TRY(hipMemcpy(st.data(), d_place_st, sizeof(int32_t) * n, hipMemcpyDeviceToHost));
+    for (int64_t i = 0; i < n; ++i)
+      if (res[i].status == SCHED_OK && st[i] > 0) {  // admitted but not placed
+        res[i].status = SCHED_E_NOMEM;
+        sum.completed -= 1;
+      }
+    PgCounters pc{};
+    if (int rc = pg_counters(pt, stream_ctl, &pc)) return rc;
+    sum.violations += pc.violations + pc.over_admitted;
+    sum.peak_pages = pc.peak_pages;
+    sum.pages_left = pc.pages_used;
+    sum.charged_left = pc.charged;
+    int64_t bad = 0;
+    if (pc.pages_used == 0 && pc.nodes_used == 0) {
+      if (int rc = pg_check_free(pt, stream_ctl, &bad)) return rc;
+    } else {
+      bad = -1;  // placements left: the check needs every page back
+    }
+    sum.page_check = bad;
     return SCHED_OK;
   }
 
@@ -659,7 +815,7 @@ struct Serve {
     double last = 0.0;
     for (int64_t j = 0; j < n; ++j) {
       if (res[j].status != SCHED_OK) continue;
-      waits.push_back(res[j].t_admit - res[j].t_arrive);
+      waits.push_back(res[j].t_place - res[j].t_arrive);
       turns.push_back(res[j].t_end - res[j].t_arrive);
       last = std::max(last, res[j].t_end);
     }
@@ -705,12 +861,19 @@ extern "C" int sched_serve(sched_ctx_t *c, int64_t n, const sched_job_desc_t *jo
   if (!c || n < 0 || (n > 0 && (!jobs || !results)) || !opts) return SCHED_E_INVALID;
   std::unique_lock<std::mutex> lk(c->mu);
   if (int rc = sched_settle_reset_locked(c)) return rc;
-  if (n > c->jb.max_jobs) return SCHED_E_INVALID;
+  if (n > c->jb.max_jobs || opts->max_placed < 0) return SCHED_E_INVALID;
   for (int64_t i = 0; i < n; ++i)
     if (jobs[i].demand <= 0 || jobs[i].kind < 0 || jobs[i].kind > SCHED_JOB_HIST ||
         (i > 0 && jobs[i].arrival_s < jobs[i - 1].arrival_s))
       return SCHED_E_INVALID;
   SCHED_HIP_TRY(hipSetDevice(c->device));
+  // tenant charges live in the slab's per-tenant counters (tenants = jobs,
+  // quotas = reservations); a context without a slab gets a small one
+  if (!c->slab) {
+    if (int rc = sched_slab_init(c, 13 << 20, c->jb.max_jobs)) return rc;
+  } else if (!sched_slab_quota_is_reservation(c)) {
+    return SCHED_E_INVALID;
+  }
   lk.unlock();
   if (int rc = sched_reset(c)) return rc;
   lk.lock();
@@ -726,14 +889,7 @@ extern "C" int sched_serve(sched_ctx_t *c, int64_t n, const sched_job_desc_t *jo
   s.res = results;
   int rc = s.init();
   if (rc == SCHED_OK) rc = opts->mode == SCHED_SERVE_VIRTUAL ? s.run_virtual() : s.run_realtime();
-  if (rc == SCHED_OK && opts->digest && n > 0) {
-    std::vector<unsigned long long> dg(n);
-    if (hipMemcpy(dg.data(), s.d_digest, sizeof(unsigned long long) * n, hipMemcpyDeviceToHost) ==
-        hipSuccess)
-      for (int64_t i = 0; i < n; ++i) results[i].digest = dg[i];
-    else
-      rc = SCHED_E_INTERNAL;
-  }
+  if (rc == SCHED_OK) rc = s.collect();
   s.summarize();
   s.sum.wall_s = s.host_now();
   s.fini();

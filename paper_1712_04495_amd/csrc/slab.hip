@@ -497,6 +497,10 @@ void sched_slab_free(sched_ctx *c) {
   c->slab = nullptr;
 }
 
+bool sched_slab_quota_is_reservation(sched_ctx *c) {
+  return c->slab && !c->slab->explicit_quota && c->slab->dev.n_tenants >= c->jb.max_jobs;
+}
+
 int64_t sched_slab_pool_used(sched_ctx *c) {
   if (!c->slab) return 0;
   int64_t v = 0;
@@ -714,3 +718,399 @@ extern "C" int sched_slab_reset(sched_ctx_t *c) {
   return SCHED_OK;
 }
 
+
+// ======================================================================
+// Page tier (see pages.h): the serving loop's tenant memory.
+// ======================================================================
+namespace {
+
+constexpr int PG_THREADS = 256;
+constexpr int PG_MAX_JOBS_PER_PLACEMENT = PG_THREADS * 64;  // one 64-bit mask per thread
+
+// Control words of the page tier.
+enum : int {
+  PGC_PAGES = 0,     // pages in use (the free stack holds n_pages - this)
+  PGC_NODES = 1,     // nodes in use
+  PGC_CHARGED = 2,   // bytes charged over all live placements
+  PGC_VIOL = 3,      // placements of admitted jobs that failed
+  PGC_PLACED = 4,    // placements made
+  PGC_RELEASED = 5,  // placements released
+  PGC_INV = 6,       // charged total seen above the admitted total
+  PGC_PEAK = 7,      // most pages in use at once
+  PGC_N = 8
+};
+
+constexpr int32_t PG_ST_PLACED = 0, PG_ST_QUOTA = 1, PG_ST_POOL = 2, PG_ST_NODES = 3,
+                  PG_ST_INVALID = 5, PG_ST_RELEASED = 6;
+
+struct PageTierDev {
+  char *pool;
+  uint32_t *stack;   // free pages: entries [0, n_pages - ctl[PGC_PAGES])
+  uint32_t *nstack;  // free nodes: entries [0, n_nodes - ctl[PGC_NODES])
+  uint32_t *nodes;   // n_nodes * PG_NODE page numbers
+  uint32_t *dirs;    // n_slots * PG_DIR entries
+  PlaceRec *recs;    // n_slots
+  int64_t *ctl;      // PGC_N words
+  int64_t n_pages, n_nodes;
+  int32_t n_slots;
+};
+
+// Like charge(), returning the counter's value before the charge.
+__device__ __forceinline__ bool charge_from(int64_t *ctr, int64_t v, int64_t limit, int64_t *before) {
+  int64_t cur = ld_relaxed(ctr);
+  for (;;) {
+    if (cur + v > limit) return false;
+    if (__hip_atomic_compare_exchange_strong(ctr, &cur, cur + v, __ATOMIC_RELAXED,
+                                             __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+      *before = cur;
+      return true;
+    }
+  }
+}
+
+__global__ void k_pg_init(PageTierDev d) {
+  for (int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; i < d.n_pages;
+       i += int64_t(gridDim.x) * blockDim.x)
+    d.stack[i] = uint32_t(i);
+  for (int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; i < d.n_nodes;
+       i += int64_t(gridDim.x) * blockDim.x)
+    d.nstack[i] = uint32_t(i);
+  for (int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; i < d.n_slots;
+       i += int64_t(gridDim.x) * blockDim.x)
+    d.recs[i] = PlaceRec{0, 0, 0, PG_ST_RELEASED};
+  if (blockIdx.x == 0 && threadIdx.x < PGC_N) d.ctl[threadIdx.x] = 0;
+}
+
+// One workgroup per placement request.  Charges every job of the placement
+// against its quota (the job's admitted reservation), takes the pages (and
+// nodes) with one compare-and-swap each, and writes the page table.  Any
+// failure returns what was taken, leaves the placement empty and counts a
+// violation: admission guarantees that it cannot happen.
+__global__ __launch_bounds__(PG_THREADS) void k_pg_place(PageTierDev d, SlabDev s,
+                                                         const int64_t *__restrict__ used,
+                                                         const PgReq *__restrict__ reqs,
+                                                         const int32_t *__restrict__ jobs,
+                                                         const int64_t *__restrict__ bytes,
+                                                         int32_t *__restrict__ job_status) {
+  __shared__ int s_fail;
+  __shared__ int32_t s_status;
+  __shared__ int64_t s_pbase, s_nbase, s_bytes;
+  const PgReq r = reqs[blockIdx.x];
+  const int tid = threadIdx.x;
+  if (tid == 0) {
+    s_fail = 0;
+    s_bytes = 0;
+    s_status = PG_ST_PLACED;
+  }
+  __syncthreads();
+  const bool valid = r.slot >= 0 && r.slot < d.n_slots && r.pages >= 0 &&
+                     r.pages <= PG_MAX_PAGES && r.n_jobs >= 0 &&
+                     r.n_jobs <= PG_MAX_JOBS_PER_PLACEMENT;
+  const int64_t k = valid ? r.pages : 0;
+  const int32_t nn = k > PG_DIR ? int32_t((k + PG_NODE - 1) / PG_NODE) : 0;
+  // 1. the quota of every job of the placement
+  uint64_t got = 0;
+  int64_t mine = 0;
+  if (valid) {
+    int bit = 0;
+    for (int64_t i = tid; i < r.n_jobs; i += PG_THREADS, ++bit) {
+      const int32_t j = jobs[r.job_off + i];
+      const int64_t b = bytes[r.job_off + i];
+      if (j < 0 || j >= s.n_tenants || b < 0 || !charge(&s.charged[j], b, s.quota[j])) {
+        atomicOr(&s_fail, 1);
+      } else {
+        got |= 1ULL << bit;
+        mine += b;
+      }
+    }
+  } else if (tid == 0) {
+    s_fail = 1;
+  }
+  if (mine) atomicAdd((unsigned long long *)&s_bytes, (unsigned long long)mine);
+  __syncthreads();
+  // 2. pages and nodes
+  if (tid == 0) {
+    if (s_fail) {
+      s_status = valid ? PG_ST_QUOTA : PG_ST_INVALID;
+    } else {
+      int64_t before = 0;
+      if (!charge_from(&d.ctl[PGC_PAGES], k, d.n_pages, &before)) {
+        s_status = PG_ST_POOL;
+      } else {
+        s_pbase = d.n_pages - before - k;
+        max_relaxed(&d.ctl[PGC_PEAK], before + k);
+        if (nn) {
+          int64_t nb = 0;
+          if (!charge_from(&d.ctl[PGC_NODES], int64_t(nn), d.n_nodes, &nb)) {
+            add_relaxed(&d.ctl[PGC_PAGES], -k);
+            s_status = PG_ST_NODES;
+          } else {
+            s_nbase = d.n_nodes - nb - nn;
+          }
+        }
+      }
+      if (s_status != PG_ST_PLACED) s_fail = 1;
+    }
+  }
+  __syncthreads();
+  PlaceRec *rec = d.recs + (valid ? r.slot : 0);
+  if (s_fail) {
+    // return the quota charges this thread took
+    if (valid) {
+      int bit = 0;
+      for (int64_t i = tid; i < r.n_jobs; i += PG_THREADS, ++bit)
+        if ((got >> bit) & 1) add_relaxed(&s.charged[jobs[r.job_off + i]], -bytes[r.job_off + i]);
+    }
+    if (valid && job_status)
+      for (int64_t i = tid; i < r.n_jobs; i += PG_THREADS) {
+        const int32_t j = jobs[r.job_off + i];
+        if (j >= 0 && j < s.n_tenants) job_status[j] = s_status;
+      }
+    if (tid == 0) {
+      add_relaxed(&d.ctl[PGC_VIOL], int64_t(1));
+      if (valid) *rec = PlaceRec{0, 0, 0, s_status};
+    }
+    return;
+  }
+  // 3. the page table
+  uint32_t *dir = d.dirs + int64_t(r.slot) * PG_DIR;
+  const int64_t pb = s_pbase, nb = s_nbase;
+  for (int64_t i = tid; i < k; i += PG_THREADS) {
+    const uint32_t pg = d.stack[pb + i];
+    if (!nn) {
+      dir[i] = pg;
+    } else {
+      const uint32_t node = d.nstack[nb + (i >> PG_NODE_SHIFT)];
+      d.nodes[uint64_t(node) * PG_NODE + (i & (PG_NODE - 1))] = pg;
+      if ((i & (PG_NODE - 1)) == 0) dir[i >> PG_NODE_SHIFT] = node;
+    }
+  }
+  if (job_status)
+    for (int64_t i = tid; i < r.n_jobs; i += PG_THREADS) job_status[jobs[r.job_off + i]] = PG_ST_PLACED;
+  __syncthreads();
+  if (tid == 0) {
+    *rec = PlaceRec{k, s_bytes, nn, PG_ST_PLACED};
+    const int64_t tot = add_relaxed(&d.ctl[PGC_CHARGED], s_bytes) + s_bytes;
+    add_relaxed(&d.ctl[PGC_PLACED], int64_t(1));
+    // the bytes charged over all live placements never exceed the admitted
+    // reservations (every placement is released before its reservation is)
+    if (tot > ld_relaxed(used)) add_relaxed(&d.ctl[PGC_INV], int64_t(1));
+  }
+}
+
+// One workgroup per released slot: pushes its pages and nodes back and
+// returns its jobs' charges.
+__global__ __launch_bounds__(PG_THREADS) void k_pg_release(PageTierDev d, SlabDev s,
+                                                           const PgReq *__restrict__ reqs,
+                                                           const int32_t *__restrict__ jobs,
+                                                           const int64_t *__restrict__ bytes) {
+  __shared__ int64_t s_pbase, s_nbase;
+  __shared__ PlaceRec s_rec;
+  const PgReq r = reqs[blockIdx.x];
+  const int tid = threadIdx.x;
+  if (r.slot < 0 || r.slot >= d.n_slots) return;
+  PlaceRec *rec = d.recs + r.slot;
+  if (tid == 0) s_rec = *rec;
+  __syncthreads();
+  if (s_rec.status != PG_ST_PLACED) return;  // nothing mapped, no charge held
+  const int64_t k = s_rec.pages;
+  const int32_t nn = s_rec.nodes;
+  if (tid == 0) {
+    s_pbase = d.n_pages - add_relaxed(&d.ctl[PGC_PAGES], -k);
+    if (nn) s_nbase = d.n_nodes - add_relaxed(&d.ctl[PGC_NODES], -int64_t(nn));
+  }
+  __syncthreads();
+  const uint32_t *dir = d.dirs + int64_t(r.slot) * PG_DIR;
+  for (int64_t i = tid; i < k; i += PG_THREADS)
+    d.stack[s_pbase + i] =
+        nn ? d.nodes[uint64_t(dir[i >> PG_NODE_SHIFT]) * PG_NODE + (i & (PG_NODE - 1))] : dir[i];
+  for (int32_t i = tid; i < nn; i += PG_THREADS) d.nstack[s_nbase + i] = dir[i];
+  if (r.n_jobs >= 0 && r.n_jobs <= PG_MAX_JOBS_PER_PLACEMENT)
+    for (int64_t i = tid; i < r.n_jobs; i += PG_THREADS) {
+      const int32_t j = jobs[r.job_off + i];
+      if (j >= 0 && j < s.n_tenants) add_relaxed(&s.charged[j], -bytes[r.job_off + i]);
+    }
+  __syncthreads();
+  if (tid == 0) {
+    add_relaxed(&d.ctl[PGC_CHARGED], -s_rec.bytes);
+    add_relaxed(&d.ctl[PGC_RELEASED], int64_t(1));
+    *rec = PlaceRec{0, 0, 0, PG_ST_RELEASED};
+  }
+}
+
+// Free-stack check when nothing is placed: every page (node) number appears
+// exactly once.  seen[] is zero on entry; bad[0] counts duplicates and
+// out-of-range entries.
+__global__ void k_pg_check(const uint32_t *__restrict__ st, int64_t n, uint32_t *seen,
+                           unsigned long long *bad) {
+  for (int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; i < n;
+       i += int64_t(gridDim.x) * blockDim.x) {
+    const uint32_t p = st[i];
+    if (p >= uint64_t(n)) {
+      atomicAdd(bad, 1ULL);
+      continue;
+    }
+    const uint32_t bit = 1u << (p & 31);
+    if (atomicOr(&seen[p >> 5], bit) & bit) atomicAdd(bad, 1ULL);
+  }
+}
+
+// Identity page table over a contiguous buffer of k pages (for kernels that
+// run outside a placement).
+__global__ void k_pg_identity(uint32_t *dir, uint32_t *nodes, int64_t k) {
+  for (int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; i < k;
+       i += int64_t(gridDim.x) * blockDim.x) {
+    if (k <= PG_DIR) {
+      dir[i] = uint32_t(i);
+    } else {
+      nodes[i] = uint32_t(i);
+      if ((i & (PG_NODE - 1)) == 0) dir[i >> PG_NODE_SHIFT] = uint32_t(i >> PG_NODE_SHIFT);
+    }
+  }
+}
+
+}  // namespace
+
+struct PageTier {
+  PageTierDev dev{};
+  int device = 0;
+};
+
+int pg_create(sched_ctx *c, int64_t pool_pages, int32_t n_slots, hipStream_t s, PageTier **out) {
+  if (!c->slab || pool_pages <= 0 || pool_pages > (int64_t(1) << 32) || n_slots <= 0)
+    return SCHED_E_INVALID;
+  PageTier *t = new PageTier();
+  t->device = c->device;
+  PageTierDev &d = t->dev;
+  d.n_pages = pool_pages;
+  d.n_nodes = 2 * ((pool_pages + PG_NODE - 1) / PG_NODE) + 2;
+  d.n_slots = n_slots;
+  auto fail = [&](hipError_t e) {
+    sched_note_hip_error(e, "page tier allocation", __FILE__, __LINE__);
+    pg_destroy(t);
+    return SCHED_E_INTERNAL;
+  };
+  hipError_t e = hipMalloc(&d.pool, size_t(pool_pages) << PG_SHIFT);
+  if (e == hipSuccess) e = hipMalloc(&d.stack, sizeof(uint32_t) * pool_pages);
+  if (e == hipSuccess) e = hipMalloc(&d.nstack, sizeof(uint32_t) * d.n_nodes);
+  if (e == hipSuccess) e = hipMalloc(&d.nodes, sizeof(uint32_t) * d.n_nodes * PG_NODE);
+  if (e == hipSuccess) e = hipMalloc(&d.dirs, sizeof(uint32_t) * int64_t(n_slots) * PG_DIR);
+  if (e == hipSuccess) e = hipMalloc(&d.recs, sizeof(PlaceRec) * n_slots);
+  if (e == hipSuccess) e = hipMalloc(&d.ctl, sizeof(int64_t) * PGC_N);
+  if (e != hipSuccess) return fail(e);
+  k_pg_init<<<1024, 256, 0, s>>>(d);
+  if ((e = hipGetLastError()) != hipSuccess) return fail(e);
+  *out = t;
+  return SCHED_OK;
+}
+
+void pg_destroy(PageTier *t) {
+  if (!t) return;
+  PageTierDev &d = t->dev;
+  void *p[] = {d.pool, d.stack, d.nstack, d.nodes, d.dirs, d.recs, d.ctl};
+  for (void *q : p)
+    if (q) (void)hipFree(q);
+  delete t;
+}
+
+int pg_place(sched_ctx *c, PageTier *t, int32_t n, const PgReq *reqs, const int32_t *jobs,
+             const int64_t *bytes, int32_t *job_status, hipStream_t s) {
+  if (n <= 0) return SCHED_OK;
+  SCHED_PROF_LAUNCH("k_pg_place", s,
+                    (k_pg_place<<<n, PG_THREADS, 0, s>>>(t->dev, c->slab->dev, &c->eng.d_ctl->used,
+                                                         reqs, jobs, bytes, job_status)));
+  SCHED_HIP_TRY(hipGetLastError());
+  return SCHED_OK;
+}
+
+int pg_release(sched_ctx *c, PageTier *t, int32_t n, const PgReq *reqs, const int32_t *jobs,
+               const int64_t *bytes, hipStream_t s) {
+  if (n <= 0) return SCHED_OK;
+  SCHED_PROF_LAUNCH("k_pg_release", s,
+                    (k_pg_release<<<n, PG_THREADS, 0, s>>>(t->dev, c->slab->dev, reqs, jobs, bytes)));
+  SCHED_HIP_TRY(hipGetLastError());
+  return SCHED_OK;
+}
+
+PageMap pg_map(const PageTier *t, int32_t slot, int64_t pages) {
+  PageMap m{};
+  m.pool = t->dev.pool;
+  m.dir = t->dev.dirs + int64_t(slot) * PG_DIR;
+  m.nodes = t->dev.nodes;
+  m.rec = t->dev.recs + slot;
+  m.direct = pages <= PG_DIR ? 1 : 0;
+  return m;
+}
+
+int pg_counters(PageTier *t, hipStream_t s, PgCounters *out) {
+  int64_t v[PGC_N] = {0};
+  SCHED_HIP_TRY(hipStreamSynchronize(s));
+  SCHED_HIP_TRY(hipMemcpy(v, t->dev.ctl, sizeof(v), hipMemcpyDeviceToHost));
+  out->pages_used = v[PGC_PAGES];
+  out->nodes_used = v[PGC_NODES];
+  out->charged = v[PGC_CHARGED];
+  out->violations = v[PGC_VIOL];
+  out->placed = v[PGC_PLACED];
+  out->released = v[PGC_RELEASED];
+  out->over_admitted = v[PGC_INV];
+  out->peak_pages = v[PGC_PEAK];
+  out->pool_pages = t->dev.n_pages;
+  return SCHED_OK;
+}
+
+int pg_check_free(PageTier *t, hipStream_t s, int64_t *bad) {
+  const PageTierDev &d = t->dev;
+  uint32_t *seen = nullptr;
+  unsigned long long *d_bad = nullptr;
+  const int64_t words = (std::max(d.n_pages, d.n_nodes) + 31) / 32;
+  SCHED_HIP_TRY(hipMalloc(&seen, sizeof(uint32_t) * words));
+  SCHED_HIP_TRY(hipMalloc(&d_bad, sizeof(unsigned long long)));
+  unsigned long long h = 0;
+  hipError_t e = hipMemsetAsync(d_bad, 0, sizeof(unsigned long long), s);
+  const uint32_t *stacks[2] = {d.stack, d.nstack};
+  const int64_t sizes[2] = {d.n_pages, d.n_nodes};
+  for (int k = 0; k < 2 && e == hipSuccess; ++k) {
+    e = hipMemsetAsync(seen, 0, sizeof(uint32_t) * words, s);
+    if (e == hipSuccess) {
+      k_pg_check<<<1024, 256, 0, s>>>(stacks[k], sizes[k], seen, d_bad);
+      e = hipGetLastError();
+    }
+  }
+  if (e == hipSuccess) e = hipMemcpyAsync(&h, d_bad, sizeof(h), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  (void)hipFree(seen);
+  (void)hipFree(d_bad);
+  if (e != hipSuccess) {
+    sched_note_hip_error(e, "page tier check", __FILE__, __LINE__);
+    return SCHED_E_INTERNAL;
+  }
+  *bad = int64_t(h);
+  return SCHED_OK;
+}
+
+namespace schedk {
+
+int pg_identity(char *base, int64_t bytes, hipStream_t s, PgIdentity *out) {
+  const int64_t k = (bytes + PG_BYTES - 1) / PG_BYTES;
+  if (k <= 0 || k > PG_MAX_PAGES) return SCHED_E_INVALID;
+  *out = PgIdentity{};
+  SCHED_HIP_TRY(hipMalloc(&out->dir, sizeof(uint32_t) * PG_DIR));
+  if (k > PG_DIR) SCHED_HIP_TRY(hipMalloc(&out->nodes, sizeof(uint32_t) * k));
+  SCHED_HIP_TRY(hipMalloc(&out->rec, sizeof(PlaceRec)));
+  const PlaceRec r{k, 0, k > PG_DIR ? int32_t((k + PG_NODE - 1) / PG_NODE) : 0, PG_ST_PLACED};
+  SCHED_HIP_TRY(hipMemcpyAsync(out->rec, &r, sizeof(r), hipMemcpyHostToDevice, s));
+  k_pg_identity<<<int(std::min<int64_t>((k + 255) / 256, 1024)), 256, 0, s>>>(out->dir, out->nodes, k);
+  SCHED_HIP_TRY(hipGetLastError());
+  SCHED_HIP_TRY(hipStreamSynchronize(s));
+  out->map = PageMap{base, out->dir, out->nodes, out->rec, k <= PG_DIR ? 1 : 0, 0};
+  return SCHED_OK;
+}
+
+void pg_identity_free(PgIdentity *m) {
+  void *p[] = {m->dir, m->nodes, m->rec};
+  for (void *q : p)
+    if (q) (void)hipFree(q);
+  *m = PgIdentity{};
+}
+
+}  // namespace schedk

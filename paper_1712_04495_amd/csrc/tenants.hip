@@ -9,7 +9,10 @@
 #include <algorithm>
 
 #include "common.h"
+#include "pages.h"
 #include "prof.h"
+
+using namespace schedk;
 
 namespace {
 
@@ -285,14 +288,28 @@ constexpr int BUF_RSRC_DW3 = 0x00020000;  // raw buffer, 32-bit dword format
 
 typedef __attribute__((address_space(3))) void lds_void;
 
+// PAGED: the operands live in a page-mapped placement (pages.h) at logical
+// offsets oa, ob, oc instead of at A, Bt, C.  Every operand row then lies in
+// one page (the host checks that 2K and 4N divide the page size and that the
+// three arrays start at page boundaries), so each of the tile's 256 A rows,
+// 256 B rows and 256 C rows is translated once, by one thread, into a table
+// in LDS; the loads become global loads with the LDS flag from per-lane
+// 64-bit addresses, the rest of the kernel is unchanged.
+template <bool PAGED>
 __global__ __launch_bounds__(GT2, 1) void k_gemm_bf16_256(const uint16_t *__restrict__ A,
                                                           const uint16_t *__restrict__ Bt,
                                                           float *__restrict__ C, int64_t M,
-                                                          int64_t N, int64_t K) {
+                                                          int64_t N, int64_t K, PageMap pm,
+                                                          int64_t need, uint64_t oa, uint64_t ob,
+                                                          uint64_t oc) {
   __shared__ __attribute__((aligned(1024))) uint16_t sA0[BM2 * ROW2];
   __shared__ __attribute__((aligned(1024))) uint16_t sA1[BM2 * ROW2];
   __shared__ __attribute__((aligned(1024))) uint16_t sB0[BN2 * ROW2];
   __shared__ __attribute__((aligned(1024))) uint16_t sB1[BN2 * ROW2];
+  __shared__ char *s_row[PAGED ? BM2 + BN2 : 1];
+  if constexpr (PAGED) {
+    if (pm_pages(pm) < need) return;  // the placement failed: nothing is mapped
+  }
   const int64_t tiles_m = M / BM2, tiles_n = N / BN2;
   const int64_t b = blockIdx.x;
   int64_t bm, bn;
@@ -323,21 +340,42 @@ __global__ __launch_bounds__(GT2, 1) void k_gemm_bf16_256(const uint16_t *__rest
   // byte size fits the 32-bit range); lane offsets are fixed, the k advance
   // rides in the scalar offset.
   const int nk = int(K / BK);
-  const __amdgpu_buffer_rsrc_t rsA =
-      __builtin_amdgcn_make_buffer_rsrc((void *)(A + m0 * K), 0, int(BM2 * K * 2), BUF_RSRC_DW3);
-  const __amdgpu_buffer_rsrc_t rsB =
-      __builtin_amdgcn_make_buffer_rsrc((void *)(Bt + n0 * K), 0, int(BN2 * K * 2), BUF_RSRC_DW3);
+  // (PAGED: unused resources over no memory)
+  const __amdgpu_buffer_rsrc_t rsA = __builtin_amdgcn_make_buffer_rsrc(
+      PAGED ? nullptr : (void *)(A + m0 * K), 0, PAGED ? 0 : int(BM2 * K * 2), BUF_RSRC_DW3);
+  const __amdgpu_buffer_rsrc_t rsB = __builtin_amdgcn_make_buffer_rsrc(
+      PAGED ? nullptr : (void *)(Bt + n0 * K), 0, PAGED ? 0 : int(BN2 * K * 2), BUF_RSRC_DW3);
   int voff[4];
+  const char *gA[4], *gB[4];  // PAGED: per-lane addresses of the rows this lane loads
+  if constexpr (!PAGED) {
 #pragma unroll
-  for (int j = 0; j < 4; ++j) {
-    const int r = 8 * (wave + 8 * j) + (lane >> 3);  // wave instruction j fills rows 8G .. 8G + 7
-    voff[j] = (r * int(K) + ((lane & 7) ^ ((r >> 1) & 7)) * 8) * 2;
+    for (int j = 0; j < 4; ++j) {
+      const int r = 8 * (wave + 8 * j) + (lane >> 3);  // wave instruction j fills rows 8G .. 8G + 7
+      voff[j] = (r * int(K) + ((lane & 7) ^ ((r >> 1) & 7)) * 8) * 2;
+    }
+  } else {
+    const int t = threadIdx.x;
+    s_row[t] = t < BM2 ? pm_addr(pm, oa + uint64_t(m0 + t) * uint64_t(K) * 2)
+                       : pm_addr(pm, ob + uint64_t(n0 + t - BM2) * uint64_t(K) * 2);
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int r = 8 * (wave + 8 * j) + (lane >> 3);
+      const int cb = ((lane & 7) ^ ((r >> 1) & 7)) * 16;
+      gA[j] = s_row[r] + cb;
+      gB[j] = s_row[BM2 + r] + cb;
+    }
   }
-  auto fill = [&](__amdgpu_buffer_rsrc_t rs, uint16_t *stage, int kbyte) {
+  auto fill = [&](__amdgpu_buffer_rsrc_t rs, const char *const *g, uint16_t *stage, int kbyte) {
 #pragma unroll
-    for (int j = 0; j < 4; ++j)
-      __builtin_amdgcn_raw_ptr_buffer_load_lds(rs, (lds_void *)(stage + (wave + 8 * j) * 8 * ROW2),
-                                               16, voff[j], kbyte, 0, 0);
+    for (int j = 0; j < 4; ++j) {
+      if constexpr (!PAGED)
+        __builtin_amdgcn_raw_ptr_buffer_load_lds(rs, (lds_void *)(stage + (wave + 8 * j) * 8 * ROW2),
+                                                 16, voff[j], kbyte, 0, 0);
+      else
+        __builtin_amdgcn_global_load_lds((const void *)(g[j] + kbyte),
+                                         (lds_void *)(stage + (wave + 8 * j) * 8 * ROW2), 16, 0, 0);
+    }
   };
   bf16x8 fa[2][2], fb[2][4];
   auto frag = [&](bf16x8 *xa, bf16x8 *xb, const uint16_t *a_s, const uint16_t *b_s, int step) {
@@ -350,11 +388,11 @@ __global__ __launch_bounds__(GT2, 1) void k_gemm_bf16_256(const uint16_t *__rest
       xb[j] = *reinterpret_cast<const bf16x8 *>(b_s + (wn + 32 * j + frow) * ROW2 + p);
   };
 
-  fill(rsA, sA0, 0);
-  fill(rsB, sB0, 0);
+  fill(rsA, gA, sA0, 0);
+  fill(rsB, gB, sB0, 0);
   if (nk > 1) {
-    fill(rsA, sA1, BK * 2);
-    fill(rsB, sB1, BK * 2);
+    fill(rsA, gA, sA1, BK * 2);
+    fill(rsB, gB, sB1, BK * 2);
   }
   asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
   __syncthreads();
@@ -391,8 +429,8 @@ __global__ __launch_bounds__(GT2, 1) void k_gemm_bf16_256(const uint16_t *__rest
         // tile (in bounds) into it, which no one reads, so the block stays
         // branch free for the interleaving below
         const int kbyte = (t + 2 < nk ? t + 2 : nk - 1) * BK * 2;
-        fill(rsA, a_s, kbyte);
-        fill(rsB, b_s, kbyte);
+        fill(rsA, gA, a_s, kbyte);
+        fill(rsB, gB, b_s, kbyte);
 #pragma unroll
         for (int i = 0; i < 2; ++i)
 #pragma unroll
@@ -409,18 +447,219 @@ __global__ __launch_bounds__(GT2, 1) void k_gemm_bf16_256(const uint16_t *__rest
     }
   }
   asm volatile("s_waitcnt vmcnt(0)" ::: "memory");  // no load may still target LDS at exit
+  if constexpr (!PAGED) {
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
+    for (int i = 0; i < 2; ++i)
 #pragma unroll
-    for (int j = 0; j < 4; ++j)
+      for (int j = 0; j < 4; ++j)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+          const int64_t row = m0 + wm + 32 * i + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+          const int64_t col = n0 + wn + 32 * j + (lane & 31);
+          __builtin_nontemporal_store(acc[i][j][r], C + row * N + col);
+        }
+  } else {
+    __syncthreads();  // every lane has its A and B row addresses in registers
+    if (threadIdx.x < BM2)
+      s_row[threadIdx.x] = pm_addr(pm, oc + uint64_t(m0 + threadIdx.x) * uint64_t(N) * 4);
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
 #pragma unroll
       for (int r = 0; r < 16; ++r) {
-        const int64_t row = m0 + wm + 32 * i + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
-        const int64_t col = n0 + wn + 32 * j + (lane & 31);
-        __builtin_nontemporal_store(acc[i][j][r], C + row * N + col);
+        const int rr = wm + 32 * i + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+        float *crow = reinterpret_cast<float *>(s_row[rr]);
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+          __builtin_nontemporal_store(acc[i][j][r], crow + n0 + wn + 32 * j + (lane & 31));
       }
+  }
 }
 
+
+// ------------------------------------------------ paged tenant work (pages.h)
+// A unit is 4 KiB of one array (1024 32-bit words or 2048 bf16): it never
+// straddles a page, so it is translated once.  Each kernel returns at once
+// when the placement maps fewer than `need` pages (a failed placement maps
+// none).
+constexpr int64_t UNIT_W = 1024;  // 32-bit words per unit
+constexpr int PGT_U = 4;          // units per workgroup step (loads in flight)
+
+__device__ __forceinline__ bool pg_ok(const PageMap &m, int64_t need) { return pm_pages(m) >= need; }
+
+__global__ __launch_bounds__(256) void k_pg_triad_fill(PageMap m, int64_t need, uint64_t ob,
+                                                       uint64_t oc, int64_t n, uint64_t s0) {
+  if (!pg_ok(m, need)) return;
+  const int64_t units = (n + UNIT_W - 1) / UNIT_W;
+  for (int64_t u = blockIdx.x; u < units; u += gridDim.x) {
+    float *b = reinterpret_cast<float *>(pm_addr(m, ob + uint64_t(u) * 4096));
+    float *c = reinterpret_cast<float *>(pm_addr(m, oc + uint64_t(u) * 4096));
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int w = q * 256 + threadIdx.x;
+      const int64_t i = u * UNIT_W + w;
+      if (i < n) {
+        const uint64_t h = splitmix(s0, uint64_t(i));
+        b[w] = 1.0f + float(h & 0xFFFF) * (1.0f / 65536.0f);
+        c[w] = 1.0f + float((h >> 16) & 0xFFFF) * (1.0f / 65536.0f);
+      }
+    }
+  }
+}
+
+// a = b + s * c; thread t of a unit handles its words 4t .. 4t + 3 as one
+// 16-byte vector (elementwise in the array's last, partial vector).
+__global__ __launch_bounds__(256) void k_pg_triad(PageMap m, int64_t need, uint64_t oa, uint64_t ob,
+                                                  uint64_t oc, float s, int64_t n) {
+  if (!pg_ok(m, need)) return;
+  const int64_t units = (n + UNIT_W - 1) / UNIT_W;
+  for (int64_t u0 = int64_t(blockIdx.x) * PGT_U; u0 < units; u0 += int64_t(gridDim.x) * PGT_U) {
+    f32x4 x[PGT_U], y[PGT_U];
+    f32x4 *pa[PGT_U];
+#pragma unroll
+    for (int v = 0; v < PGT_U; ++v) {
+      const int64_t u = u0 + v;
+      pa[v] = nullptr;
+      if (u < units && u * UNIT_W + 4 * threadIdx.x + 3 < n) {
+        const f32x4 *pb = reinterpret_cast<const f32x4 *>(pm_addr(m, ob + uint64_t(u) * 4096));
+        const f32x4 *pc = reinterpret_cast<const f32x4 *>(pm_addr(m, oc + uint64_t(u) * 4096));
+        pa[v] = reinterpret_cast<f32x4 *>(pm_addr(m, oa + uint64_t(u) * 4096)) + threadIdx.x;
+        x[v] = __builtin_nontemporal_load(pb + threadIdx.x);
+        y[v] = __builtin_nontemporal_load(pc + threadIdx.x);
+      }
+    }
+#pragma unroll
+    for (int v = 0; v < PGT_U; ++v)
+      if (pa[v]) __builtin_nontemporal_store(x[v] + s * y[v], pa[v]);
+  }
+  // the partial vector at the end of the array
+  const int64_t t0 = n & ~int64_t(3);
+  if (blockIdx.x == 0 && threadIdx.x < (n & 3)) {
+    const int64_t i = t0 + threadIdx.x;
+    const uint64_t o = uint64_t(i) * 4;
+    *reinterpret_cast<float *>(pm_addr(m, oa + o)) =
+        *reinterpret_cast<const float *>(pm_addr(m, ob + o)) +
+        s * *reinterpret_cast<const float *>(pm_addr(m, oc + o));
+  }
+}
+
+__global__ __launch_bounds__(256) void k_pg_hist_fill(PageMap m, int64_t need, uint64_t ok_,
+                                                      int64_t n, uint64_t s0) {
+  if (!pg_ok(m, need)) return;
+  const int64_t units = (n + UNIT_W - 1) / UNIT_W;
+  for (int64_t u = blockIdx.x; u < units; u += gridDim.x) {
+    uint32_t *k = reinterpret_cast<uint32_t *>(pm_addr(m, ok_ + uint64_t(u) * 4096));
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int w = q * 256 + threadIdx.x;
+      const int64_t i = u * UNIT_W + w;
+      if (i < n) k[w] = uint32_t(splitmix(s0, uint64_t(i)));
+    }
+  }
+}
+
+__global__ void k_pg_zero(PageMap m, int64_t need, uint64_t off, int64_t n_words) {
+  if (!pg_ok(m, need)) return;
+  for (int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; i < n_words;
+       i += int64_t(gridDim.x) * blockDim.x)
+    *reinterpret_cast<uint32_t *>(pm_addr(m, off + uint64_t(i) * 4)) = 0;
+}
+
+// Same LDS scheme as k_hist; keys are read a unit (one 16-byte vector per
+// thread) at a time, PGT_U units in flight.
+__global__ __launch_bounds__(HIST_THREADS) void k_pg_hist(PageMap m, int64_t need, uint64_t ok_,
+                                                          int64_t n, uint32_t mask, uint64_t ob) {
+  if (!pg_ok(m, need)) return;
+  __shared__ uint32_t h[HIST_COPIES][SCHED_HIST_BINS];
+  for (int i = threadIdx.x; i < HIST_COPIES * SCHED_HIST_BINS; i += HIST_THREADS)
+    (&h[0][0])[i] = 0;
+  __syncthreads();
+  uint32_t *mine = h[(threadIdx.x / 64) % HIST_COPIES];
+  const int64_t units = (n + UNIT_W - 1) / UNIT_W;
+  for (int64_t u0 = int64_t(blockIdx.x) * PGT_U; u0 < units; u0 += int64_t(gridDim.x) * PGT_U) {
+    u32x4 v[PGT_U];
+    int cnt[PGT_U];
+#pragma unroll
+    for (int q = 0; q < PGT_U; ++q) {
+      const int64_t u = u0 + q, e = u * UNIT_W + 4 * threadIdx.x;
+      cnt[q] = u < units ? int(e + 4 <= n ? 4 : (e < n ? n - e : 0)) : 0;
+      if (cnt[q] == 4) {
+        v[q] = __builtin_nontemporal_load(
+            reinterpret_cast<const u32x4 *>(pm_addr(m, ok_ + uint64_t(u) * 4096)) + threadIdx.x);
+      } else if (cnt[q] > 0) {
+        const uint32_t *k = reinterpret_cast<const uint32_t *>(pm_addr(m, ok_ + uint64_t(u) * 4096)) +
+                            4 * threadIdx.x;
+        v[q] = u32x4{k[0], cnt[q] > 1 ? k[1] : 0u, cnt[q] > 2 ? k[2] : 0u, 0u};
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < PGT_U; ++q) {
+      if (cnt[q] > 0) atomicAdd(&mine[v[q].x & mask], 1u);
+      if (cnt[q] > 1) atomicAdd(&mine[v[q].y & mask], 1u);
+      if (cnt[q] > 2) atomicAdd(&mine[v[q].z & mask], 1u);
+      if (cnt[q] > 3) atomicAdd(&mine[v[q].w & mask], 1u);
+    }
+  }
+  __syncthreads();
+  for (int b = threadIdx.x; b < SCHED_HIST_BINS; b += HIST_THREADS) {
+    uint32_t sum = 0;
+#pragma unroll
+    for (int k = 0; k < HIST_COPIES; ++k) sum += h[k][b];
+    if (sum) atomicAdd(reinterpret_cast<uint32_t *>(pm_addr(m, ob + uint64_t(b) * 4)), sum);
+  }
+}
+
+// bf16 operand rows * K elements; a unit holds 2048 of them (8 per thread).
+__global__ __launch_bounds__(256) void k_pg_gemm_fill(PageMap m, int64_t need, uint64_t off,
+                                                      int64_t n, uint64_t s0) {
+  if (!pg_ok(m, need)) return;
+  const int64_t units = (n + 2 * UNIT_W - 1) / (2 * UNIT_W);
+  for (int64_t u = blockIdx.x; u < units; u += gridDim.x) {
+    uint16_t *x = reinterpret_cast<uint16_t *>(pm_addr(m, off + uint64_t(u) * 4096));
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const int w = q * 256 + threadIdx.x;
+      const int64_t i = u * 2 * UNIT_W + w;
+      if (i < n) {
+        const uint64_t hh = splitmix(s0, uint64_t(i));
+        const float v = (float(int(hh & 0xFF)) - 128.0f) * (1.0f / 64.0f);
+        x[w] = uint16_t(__float_as_uint(v) >> 16);
+      }
+    }
+  }
+}
+
+// *out += sum over words i of (s_i | 1) * w_i (pages.h); one atomic per wave.
+__global__ __launch_bounds__(256) void k_pg_digest(PageMap m, int64_t need, uint64_t off,
+                                                   int64_t n, unsigned long long *out) {
+  if (!pg_ok(m, need)) return;
+  const int64_t units = (n + UNIT_W - 1) / UNIT_W;
+  unsigned long long acc = 0;
+  for (int64_t u = blockIdx.x; u < units; u += gridDim.x) {
+    const uint32_t *w = reinterpret_cast<const uint32_t *>(pm_addr(m, off + uint64_t(u) * 4096));
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int k = q * 256 + threadIdx.x;
+      const int64_t i = u * UNIT_W + k;
+      if (i < n) acc += digest_term(uint64_t(i), w[k]);
+    }
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, WAVE);
+  if ((threadIdx.x & (WAVE - 1)) == 0 && acc) atomicAdd(out, acc);
+}
+
+__global__ void k_pg_gemm_samples(PageMap m, int64_t need, uint64_t oc, int64_t N, uint64_t seed,
+                                  float *out) {
+  const int k = threadIdx.x;
+  if (k >= GEMM_SAMPLES) return;
+  if (!pg_ok(m, need)) {
+    out[k] = __int_as_float(0x7fc00000);  // NaN: nothing was computed
+    return;
+  }
+  const uint64_t p = splitmix_at((seed << 32) ^ SAMPLE_KEY, uint64_t(k)) % uint64_t(N * N);
+  out[k] = *reinterpret_cast<const float *>(pm_addr(m, oc + p * 4));
+}
 }  // namespace
 
 extern "C" int sched_triad_fill(float *b, float *c, int64_t n, uint64_t seed, sched_stream_t st) {
@@ -486,7 +725,8 @@ extern "C" int sched_gemm_bf16(const uint16_t *A, const uint16_t *Bt, float *C, 
     const int64_t blocks = (M / BM2) * (N / BN2);
     if (blocks > 0x7fffffff) return SCHED_E_INVALID;
     SCHED_PROF_LAUNCH("k_gemm_bf16", (hipStream_t)st,
-                      (k_gemm_bf16_256<<<int(blocks), GT2, 0, (hipStream_t)st>>>(A, Bt, C, M, N, K)));
+                      (k_gemm_bf16_256<false><<<int(blocks), GT2, 0, (hipStream_t)st>>>(
+                          A, Bt, C, M, N, K, PageMap{}, 0, 0, 0, 0)));
     SCHED_HIP_TRY(hipGetLastError());
     return SCHED_OK;
   }
@@ -497,3 +737,110 @@ extern "C" int sched_gemm_bf16(const uint16_t *A, const uint16_t *Bt, float *C, 
   SCHED_HIP_TRY(hipGetLastError());
   return SCHED_OK;
 }
+
+// ---------------------------------------------------------- paged wrappers
+namespace schedk {
+
+namespace {
+int64_t pages_to(uint64_t off, int64_t bytes) {
+  return bytes > 0 ? int64_t((off + uint64_t(bytes) - 1) >> PG_SHIFT) + 1 : 0;
+}
+int units_grid(int64_t units, int per, int cap) {
+  return int(std::max<int64_t>(1, std::min<int64_t>((units + per - 1) / per, cap)));
+}
+bool off_ok(uint64_t off) { return (off & 4095) == 0; }
+}  // namespace
+
+int pgt_triad_fill(const PageMap &m, uint64_t ob, uint64_t oc, int64_t n, uint64_t seed,
+                   hipStream_t s) {
+  if (n <= 0) return n == 0 ? SCHED_OK : SCHED_E_INVALID;
+  if (!off_ok(ob) || !off_ok(oc)) return SCHED_E_INVALID;
+  const int64_t need = std::max(pages_to(ob, 4 * n), pages_to(oc, 4 * n));
+  k_pg_triad_fill<<<units_grid((n + UNIT_W - 1) / UNIT_W, 1, 8192), 256, 0, s>>>(m, need, ob, oc, n,
+                                                                                 seed << 32);
+  SCHED_HIP_TRY(hipGetLastError());
+  return SCHED_OK;
+}
+
+int pgt_triad(const PageMap &m, uint64_t oa, uint64_t ob, uint64_t oc, float sc, int64_t n,
+              int32_t iters, hipStream_t s) {
+  if (n < 0 || iters < 0 || !off_ok(oa) || !off_ok(ob) || !off_ok(oc)) return SCHED_E_INVALID;
+  if (n == 0) return SCHED_OK;
+  const int64_t need =
+      std::max(pages_to(oa, 4 * n), std::max(pages_to(ob, 4 * n), pages_to(oc, 4 * n)));
+  const int grid = units_grid((n + UNIT_W - 1) / UNIT_W, PGT_U, 1 << 30);
+  for (int32_t it = 0; it < iters; ++it) {
+    SCHED_PROF_LAUNCH("k_pg_triad", s,
+                      (k_pg_triad<<<grid, 256, 0, s>>>(m, need, oa, ob, oc, sc, n)));
+    SCHED_HIP_TRY(hipGetLastError());
+  }
+  return SCHED_OK;
+}
+
+int pgt_hist_fill(const PageMap &m, uint64_t ok_, int64_t n, uint64_t seed, hipStream_t s) {
+  if (n < 0 || !off_ok(ok_)) return SCHED_E_INVALID;
+  if (n == 0) return SCHED_OK;
+  k_pg_hist_fill<<<units_grid((n + UNIT_W - 1) / UNIT_W, 1, 8192), 256, 0, s>>>(
+      m, pages_to(ok_, 4 * n), ok_, n, seed << 32);
+  SCHED_HIP_TRY(hipGetLastError());
+  return SCHED_OK;
+}
+
+int pgt_hist(const PageMap &m, uint64_t ok_, int64_t n, uint32_t mask, uint64_t ob, hipStream_t s) {
+  if (n < 0 || mask >= SCHED_HIST_BINS || !off_ok(ok_) || !off_ok(ob)) return SCHED_E_INVALID;
+  const int64_t need_b = pages_to(ob, 4 * SCHED_HIST_BINS);
+  k_pg_zero<<<4, 256, 0, s>>>(m, need_b, ob, SCHED_HIST_BINS);
+  SCHED_HIP_TRY(hipGetLastError());
+  if (n == 0) return SCHED_OK;
+  const int64_t need = std::max(need_b, pages_to(ok_, 4 * n));
+  SCHED_PROF_LAUNCH("k_pg_hist", s,
+                    (k_pg_hist<<<units_grid((n + UNIT_W - 1) / UNIT_W, PGT_U * 4, 256 * HIST_PER_CU),
+                                 HIST_THREADS, 0, s>>>(m, need, ok_, n, mask, ob)));
+  SCHED_HIP_TRY(hipGetLastError());
+  return SCHED_OK;
+}
+
+int pgt_gemm_fill(const PageMap &m, uint64_t off, int64_t rows, int64_t K, uint64_t seed,
+                  hipStream_t s) {
+  const int64_t n = rows * K;
+  if (rows < 0 || K < 0 || !off_ok(off)) return SCHED_E_INVALID;
+  if (n == 0) return SCHED_OK;
+  k_pg_gemm_fill<<<units_grid((n + 2 * UNIT_W - 1) / (2 * UNIT_W), 1, 8192), 256, 0, s>>>(
+      m, pages_to(off, 2 * n), off, n, seed << 32);
+  SCHED_HIP_TRY(hipGetLastError());
+  return SCHED_OK;
+}
+
+int pgt_gemm(const PageMap &m, uint64_t oa, uint64_t ob, uint64_t oc, int64_t N, hipStream_t s) {
+  // each operand row inside one page: 2N and 4N divide the page size, and
+  // the arrays start at page boundaries
+  if (N < BM2 || N > (PG_BYTES / 4) || (N & (N - 1)) || ((oa | ob | oc) & (PG_BYTES - 1)))
+    return SCHED_E_INVALID;
+  const int64_t need = std::max(pages_to(oa, 2 * N * N),
+                                std::max(pages_to(ob, 2 * N * N), pages_to(oc, 4 * N * N)));
+  const int64_t blocks = (N / BM2) * (N / BN2);
+  SCHED_PROF_LAUNCH("k_gemm_bf16_paged", s,
+                    (k_gemm_bf16_256<true><<<int(blocks), GT2, 0, s>>>(nullptr, nullptr, nullptr, N,
+                                                                       N, N, m, need, oa, ob, oc)));
+  SCHED_HIP_TRY(hipGetLastError());
+  return SCHED_OK;
+}
+
+int pgt_digest(const PageMap &m, uint64_t off, int64_t n, unsigned long long *out, hipStream_t s) {
+  if (n < 0 || !off_ok(off) || !out) return SCHED_E_INVALID;
+  if (n == 0) return SCHED_OK;
+  k_pg_digest<<<units_grid((n + UNIT_W - 1) / UNIT_W, 1, 2048), 256, 0, s>>>(
+      m, pages_to(off, 4 * n), off, n, out);
+  SCHED_HIP_TRY(hipGetLastError());
+  return SCHED_OK;
+}
+
+int pgt_gemm_samples(const PageMap &m, uint64_t oc, int64_t N, uint64_t seed, float *out,
+                     hipStream_t s) {
+  if (N <= 0 || !off_ok(oc) || !out) return SCHED_E_INVALID;
+  k_pg_gemm_samples<<<1, 64, 0, s>>>(m, pages_to(oc, 4 * N * N), oc, N, seed, out);
+  SCHED_HIP_TRY(hipGetLastError());
+  return SCHED_OK;
+}
+
+}  // namespace schedk

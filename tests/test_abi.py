@@ -46,3 +46,12 @@ def test_binding_covers_exports(lib):
     for n in cosched._SIGS:
         assert hasattr(lib, n)
     assert cosched.sched_version().startswith("sched-mi355x")
+
+
+def test_struct_layouts_match_binding(lib):
+    """Every structure the ABI passes has the size the binding assumes
+    (a host-only call: no device is touched)."""
+    from paper_1712_04495_amd import cosched
+    for k, (theirs, mine) in enumerate(cosched.abi_layouts()):
+        assert theirs == mine, (k, theirs, mine)
+    assert cosched.lib().sched_abi_sizeof(99) == -1

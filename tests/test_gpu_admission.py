@@ -441,6 +441,57 @@ def test_lifecycle_random_vs_oracle(cs, policy):
         cs.sched_destroy(ctx)
 
 
+@pytest.mark.parametrize("policy", [2, 3])
+@pytest.mark.parametrize("span", [3, 140_001])
+def test_priority_order_large_queue(cs, policy, span):
+    """Policies 3/4 over queues of several 4096-entry tiles with ragged tails:
+    the device orders the live queue by (priority, arrival) -- one digit pass
+    for three priorities, five for a span of 140 001 -- and every pass admits
+    exactly what the oracle's pass over the (priority, arrival) order admits,
+    in that order.  A second batch appended behind the leftovers of the first
+    pass is ordered together with them."""
+    rng = np.random.default_rng(span + policy)
+    n_jobs = 300
+    prio_of = rng.integers(-(span // 2), span - span // 2, n_jobs).astype(np.int64)
+    for n1, n2 in ((1, 1), (4095, 4097), (3 * 4096 + 17, 5000)):
+        d1 = rng.integers(1, 1000, n1).astype(np.int64)
+        d2 = rng.integers(1, 1000, n2).astype(np.int64)
+        C = max(int(d1.sum() * 2 // 5), 1000) + 1   # every demand (< 1000) fits alone
+        rc, ctx = cs.sched_create(policy=policy, capacity_bytes=C, max_jobs=n_jobs,
+                                  queue_capacity=1 << 15)
+        assert rc == 0
+        try:
+            for p in prio_of:
+                assert cs.sched_register(ctx, int(p), 60000)[0] == 0
+            pend_job = np.zeros(0, np.int32)
+            pend_dem = np.zeros(0, np.int64)
+            used = 0
+            for d in (d1, d2):
+                j = rng.integers(0, n_jobs, d.size).astype(np.int32)
+                assert cs.sched_enqueue_batch(ctx, torch.from_numpy(j).to(DEV),
+                                              torch.from_numpy(d).to(DEV)) == 0
+                pend_job = np.concatenate([pend_job, j])
+                pend_dem = np.concatenate([pend_dem, d])
+                rc, res = cs.sched_pass(ctx)
+                assert rc == 0
+                order = S.priority_order(prio_of[pend_job])
+                a, R2 = (S.fifo_pass if policy == 2 else S.mmu_pass)(pend_dem[order], C - used)
+                print(f"  policy={policy} span={span} n={pend_job.size} admitted={int(a.sum())}",
+                      flush=True)
+                assert res["admitted"] == int(a.sum()) and res["free_after"] == R2
+                k = int(a.sum())
+                out = torch.full((max(k, 1),), -1, dtype=torch.int32, device=DEV)
+                rc, n = cs.sched_last_admitted(ctx, out)
+                assert rc == 0 and n == k
+                assert np.array_equal(out.cpu().numpy()[:k], pend_job[order][a])
+                keep = np.ones(pend_job.size, bool)
+                keep[order[a]] = False
+                pend_job, pend_dem = pend_job[keep], pend_dem[keep]
+                used = C - R2
+        finally:
+            cs.sched_destroy(ctx)
+
+
 def test_lifecycle_errors_and_timeout(cs):
     rc, ctx = cs.sched_create(policy=1, capacity_bytes=1000, max_jobs=4, queue_capacity=64)
     assert rc == 0

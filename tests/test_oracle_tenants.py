@@ -72,3 +72,57 @@ def test_gemm_small_brute_force():
     mi = np.array([0, 2, 1, 2])
     ni = np.array([3, 0, 1, 3])
     assert np.array_equal(T.gemm_ref_entries(1, 2, K, mi, ni), C[mi, ni])
+
+
+# ---- output digest (position-keyed) ---------------------------------------
+def test_position_digest_single_word_and_zeros():
+    # one word: (s_0 | 1) * w mod 2^64, s_0 the first SplitMix64 output of the
+    # key state; all-zero output digests to 0
+    s0 = int(T.splitmix64_state(T.DIGEST_KEY, np.arange(1))[0])
+    for w in (1, 7, 0xFFFFFFFF):
+        assert T.position_digest(np.array([w], np.uint32)) == ((s0 | 1) * w) % 2**64
+    assert T.position_digest(np.zeros(1000, np.uint32)) == 0
+
+
+def test_position_digest_sees_every_change():
+    rng = np.random.default_rng(3)
+    w = rng.integers(0, 2**32, 777, dtype=np.uint64).astype(np.uint32)
+    d = T.position_digest(w)
+    for i in range(w.size):
+        for delta in (1, 2**31, int(rng.integers(1, 2**32))):
+            v = w.copy()
+            v[i] = np.uint32((int(v[i]) + delta) % 2**32)
+            assert T.position_digest(v) != d, (i, delta)
+    # moving words: swaps of unequal words and a rotation are seen
+    for _ in range(500):
+        i, j = rng.integers(0, w.size, 2)
+        if w[i] == w[j]:
+            continue
+        v = w.copy()
+        v[i], v[j] = v[j], v[i]
+        assert T.position_digest(v) != d
+    assert T.position_digest(np.roll(w, 1)) != d
+
+
+def test_position_digest_is_linear_and_chunk_free():
+    # additive in the words (mod 2^64) and independent of the chunking
+    rng = np.random.default_rng(4)
+    a = rng.integers(0, 2**31, 5000, dtype=np.uint64).astype(np.uint32)
+    b = rng.integers(0, 2**31, 5000, dtype=np.uint64).astype(np.uint32)
+    assert T.position_digest(a + b) == (T.position_digest(a) + T.position_digest(b)) % 2**64
+    assert T.position_digest(a, chunk=7) == T.position_digest(a)
+    f = np.array([1.0, 4.5, 7.25], np.float32)
+    assert T.position_digest(f) == T.position_digest(f.view(np.uint32))
+
+
+def test_gemm_sample_positions_in_range_and_seeded():
+    for N in (256, 1024, 8192):
+        r, c = T.gemm_sample_positions(5, N)
+        assert r.size == T.GEMM_SAMPLES and np.all((r >= 0) & (r < N) & (c >= 0) & (c < N))
+    r1, c1 = T.gemm_sample_positions(5, 4096)
+    r2, c2 = T.gemm_sample_positions(6, 4096)
+    assert not (np.array_equal(r1, r2) and np.array_equal(c1, c2))
+    # position k is SplitMix64 output k of the keyed state, row-major
+    s0 = ((5 << 32) ^ T.SAMPLE_KEY) % 2**64
+    p = [int(x) % (4096 * 4096) for x in T.splitmix64_state(s0, np.arange(T.GEMM_SAMPLES))]
+    assert [int(a) * 4096 + int(b) for a, b in zip(r1, c1)] == p
