@@ -25,7 +25,7 @@ struct BatchTable {
   int32_t n_desc;
   int32_t pad;
   int64_t n_items;
-  int64_t chunk;               // elements per work item (a multiple of the block size)
+  int64_t chunk;               // elements per work item (a divisor of 16384)
   unsigned long long work;     // next work item
   BatchDesc *desc;
   int64_t *item_off;           // first work item of each job; [n_desc] = total
@@ -56,7 +56,7 @@ struct BatchEngine {
   BatchTable *d_table = nullptr;      // device copy
   int cus = 0;
   int block = 256, per_cu = 4;
-  int64_t chunk = 1 << 16;
+  int64_t chunk = 1 << 14;
   int best_block = 256, best_per_cu = 4;
   bool tuned = false;
   bool from_cache = false;     // the shape was read from the tuner's cache file

@@ -53,18 +53,20 @@ __global__ void k_batch_stage(const BatchTable *__restrict__ host, BatchTable *_
     dev->item_off[i] = host->item_off[i];
 }
 
-// A chunk starts at a multiple of the block size and a row of blockDim.x
-// elements (at most 4 KiB) starts at a multiple of its own size inside a
-// 4 KiB-aligned array, so a row never straddles a page: one translation per
-// row and array.
+// A work item is `chunk` elements of one job, chunk a divisor of 16384, so
+// the item lies inside one 64 KiB window of each of its arrays (which start
+// at 4 KiB boundaries): the item resolves its three windows once (pages.h)
+// and every step below addresses through them.
 __global__ void k_batch_run(BatchTable *__restrict__ t) {
   __shared__ long long s_item;
+  __shared__ uint32_t sdir[PG_DIR];
   const int64_t n_items = t->n_items;
   const int n_desc = t->n_desc;
   const int64_t chunk = t->chunk;
   const PageMap m = t->map;
-  if (pm_pages(m) < t->need) return;  // the placement failed: nothing is mapped
-  const int bd = blockDim.x;
+  const int64_t mapped = pm_pages(m);
+  if (mapped < t->need) return;  // the placement failed: nothing is mapped
+  const PgView v = pg_view(m, sdir, mapped);
   for (;;) {
     if (threadIdx.x == 0) {
       const unsigned long long it = add_relaxed(&t->work, 1ULL);
@@ -85,31 +87,30 @@ __global__ void k_batch_run(BatchTable *__restrict__ t) {
     const int64_t e0 = (item - t->item_off[lo]) * chunk;
     const int64_t e1 = e0 + chunk < d.n ? e0 + chunk : d.n;
     const uint64_t s0 = d.seed << 32;
+    const uint64_t wbase = uint64_t(4 * e0) & ~uint64_t(PG_BYTES - 1), end = uint64_t(4 * d.n);
+    const uint32_t b0 = uint32_t(uint64_t(4 * e0) - wbase);
+    const PgWin A = pg_win(v, d.oa + wbase, d.oa + end), B = pg_win(v, d.ob + wbase, d.ob + end),
+                C = pg_win(v, d.oc + wbase, d.oc + end);
     // input fill (same element -> same thread in every step below)
-    for (int64_t r = e0; r < e1; r += bd) {
-      const int64_t i = r + threadIdx.x;
-      float *b = reinterpret_cast<float *>(pm_addr(m, d.ob + uint64_t(r) * 4));
-      float *c = reinterpret_cast<float *>(pm_addr(m, d.oc + uint64_t(r) * 4));
-      if (i < e1) {
-        const uint64_t h = splitmix(s0, uint64_t(i));
-        b[threadIdx.x] = 1.0f + float(h & 0xFFFF) * (1.0f / 65536.0f);
-        c[threadIdx.x] = 1.0f + float((h >> 16) & 0xFFFF) * (1.0f / 65536.0f);
-      }
+    for (int64_t i = e0 + threadIdx.x; i < e1; i += blockDim.x) {
+      const uint32_t byte = b0 + 4 * uint32_t(i - e0);
+      const uint64_t h = splitmix(s0, uint64_t(i));
+      *reinterpret_cast<float *>(B.at(byte)) = 1.0f + float(h & 0xFFFF) * (1.0f / 65536.0f);
+      *reinterpret_cast<float *>(C.at(byte)) = 1.0f + float((h >> 16) & 0xFFFF) * (1.0f / 65536.0f);
     }
     for (int it = 0; it < d.iters; ++it) {
-      for (int64_t r = e0; r < e1; r += bd) {
-        float *a = reinterpret_cast<float *>(pm_addr(m, d.oa + uint64_t(r) * 4));
-        const float *b = reinterpret_cast<const float *>(pm_addr(m, d.ob + uint64_t(r) * 4));
-        const float *c = reinterpret_cast<const float *>(pm_addr(m, d.oc + uint64_t(r) * 4));
-        if (r + threadIdx.x < e1) a[threadIdx.x] = b[threadIdx.x] + 3.0f * c[threadIdx.x];
+      for (int64_t i = e0 + threadIdx.x; i < e1; i += blockDim.x) {
+        const uint32_t byte = b0 + 4 * uint32_t(i - e0);
+        *reinterpret_cast<float *>(A.at(byte)) = *reinterpret_cast<const float *>(B.at(byte)) +
+                                                 3.0f * *reinterpret_cast<const float *>(C.at(byte));
       }
     }
     unsigned long long dg = 0;
-    for (int64_t r = e0; r < e1; r += bd) {
-      const float *a = reinterpret_cast<const float *>(pm_addr(m, d.oa + uint64_t(r) * 4));
-      if (r + threadIdx.x < e1)
-        dg += digest_term(uint64_t(r + threadIdx.x), __float_as_uint(a[threadIdx.x]));
-    }
+    if (d.digest)
+      for (int64_t i = e0 + threadIdx.x; i < e1; i += blockDim.x) {
+        const uint32_t byte = b0 + 4 * uint32_t(i - e0);
+        dg += digest_term(uint64_t(i), *reinterpret_cast<const uint32_t *>(A.at(byte)));
+      }
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) dg += __shfl_xor(dg, off, WAVE);
     if (d.digest && (threadIdx.x & (WAVE - 1)) == 0 && dg) add_relaxed(d.digest, dg);
@@ -185,9 +186,8 @@ static int graph_for(BatchEngine &b, int block, int grid, hipStream_t s, hipGrap
 int batch_fill(BatchEngine &b, const std::vector<BatchDesc> &descs, int64_t chunk, const PageMap &map,
                int64_t need) {
   if ((int)descs.size() > b.max_desc) return SCHED_E_INVALID;
-  // rows of up to 4 KiB at multiples of their own size: see k_batch_run
-  const int block = b.block > 0 ? b.block : 256;
-  if (block > 1024 || (block & (block - 1)) || chunk <= 0 || chunk % block) return SCHED_E_INVALID;
+  // a work item inside one 64 KiB window of each array: see k_batch_run
+  if (chunk <= 0 || chunk > PG_BYTES / 4 || (PG_BYTES / 4) % chunk) return SCHED_E_INVALID;
   for (const BatchDesc &d : descs)
     if ((d.oa | d.ob | d.oc) & 4095) return SCHED_E_INVALID;
   BatchTable *t = b.h_table;
@@ -235,7 +235,7 @@ int batch_autotune(BatchEngine &b, const char *cache_path, hipStream_t s) {
                  *pp = strstr(buf, "\"per_cu\":");
       if (pb && pc && pp && sscanf(pb, "\"block\": %d", &blk) == 1 &&
           sscanf(pc, "\"chunk\": %lld", &ch) == 1 && sscanf(pp, "\"per_cu\": %d", &per) == 1 &&
-          blk > 0 && ch > 0 && per > 0) {
+          blk > 0 && per > 0 && ch > 0 && ch <= PG_BYTES / 4 && (PG_BYTES / 4) % ch == 0) {
         b.block = blk;
         b.chunk = ch;
         b.per_cu = per;
@@ -261,7 +261,7 @@ int batch_autotune(BatchEngine &b, const char *cache_path, hipStream_t s) {
     ds[i] = BatchDesc{base, base + arr, base + 2 * arr, job_elems, uint64_t(i + 1), 10, 0, dig + i};
   }
   const int blocks[] = {256, 512, 1024};
-  const int64_t chunks[] = {1 << 14, 1 << 16, 1 << 18};
+  const int64_t chunks[] = {1 << 12, 1 << 13, 1 << 14};  // divisors of a 64 KiB window
   const int pers[] = {2, 4, 8};
   double best = 1e30;
   hipEvent_t e0, e1;

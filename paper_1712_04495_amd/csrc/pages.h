@@ -60,9 +60,31 @@ struct PageMap {
   int32_t pad;
 };
 
+// Page tables do not change while a placement's kernels run, so they are
+// read through the constant address space: a wave-uniform lookup becomes a
+// scalar load.
+typedef const __attribute__((address_space(4))) uint32_t cst_u32;
+
 __device__ __forceinline__ uint32_t pm_page(const PageMap &m, uint64_t lp) {
-  if (m.direct) return m.dir[lp];
-  return m.nodes[uint64_t(m.dir[lp >> PG_NODE_SHIFT]) * PG_NODE + (lp & (PG_NODE - 1))];
+  cst_u32 *dir = (cst_u32 *)m.dir;
+  if (m.direct) return dir[lp];
+  const uint32_t node = dir[lp >> PG_NODE_SHIFT];
+  return ((cst_u32 *)m.nodes)[uint64_t(node) * PG_NODE + (lp & (PG_NODE - 1))];
+}
+
+// The same lookup when the kind of table is known at compile time (no
+// branch, so independent lookups issue back to back).
+template <bool DIRECT>
+__device__ __forceinline__ char *pm_addr_t(const PageMap &m, uint64_t off) {
+  cst_u32 *dir = (cst_u32 *)m.dir;
+  const uint64_t lp = off >> PG_SHIFT;
+  uint32_t pg;
+  if constexpr (DIRECT) {
+    pg = dir[lp];
+  } else {
+    pg = ((cst_u32 *)m.nodes)[uint64_t(dir[lp >> PG_NODE_SHIFT]) * PG_NODE + (lp & (PG_NODE - 1))];
+  }
+  return m.pool + (uint64_t(pg) << PG_SHIFT) + (off & (PG_BYTES - 1));
 }
 
 // Device address of logical offset `off` (the page must be mapped).
@@ -73,6 +95,65 @@ __device__ __forceinline__ char *pm_addr(const PageMap &m, uint64_t off) {
 // Logical pages the placement has mapped (0 after a failed placement).
 __device__ __forceinline__ int64_t pm_pages(const PageMap &m) {
   return __hip_atomic_load(&m.rec->pages, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// ---- windows: the fast path of the streaming kernels ----------------------
+// A kernel copies the placement's directory (at most PG_DIR entries) into LDS
+// once; then a 64 KiB window of an array that starts at a 4 KiB boundary
+// covers at most two pages, so its two bases are resolved once per window
+// (directory from LDS, plus one node load for a placement of more than
+// PG_DIR pages) and every access inside it is a compare and an add.
+typedef const __attribute__((address_space(3))) uint32_t lds_u32;
+
+struct PgView {
+  lds_u32 *sdir;          // LDS copy of the directory
+  const uint32_t *nodes;
+  char *pool;
+  int32_t direct;
+  __device__ __forceinline__ uint32_t page(uint64_t lp) const {
+    if (direct) return sdir[lp];
+    const uint32_t node = sdir[lp >> PG_NODE_SHIFT];
+    return nodes[uint64_t(node) * PG_NODE + (lp & (PG_NODE - 1))];
+  }
+  __device__ __forceinline__ char *addr(uint64_t off) const {
+    return pool + (uint64_t(page(off >> PG_SHIFT)) << PG_SHIFT) + (off & (PG_BYTES - 1));
+  }
+};
+
+// Loads the directory entries a placement of `pages` pages uses; the whole
+// workgroup calls it (it ends with a barrier).  sdir: a __shared__ array of
+// PG_DIR entries.
+__device__ __forceinline__ PgView pg_view(const PageMap &m, uint32_t *sdir, int64_t pages) {
+  const int64_t e = m.direct ? pages : (pages + PG_NODE - 1) >> PG_NODE_SHIFT;
+  for (int64_t i = threadIdx.x; i < e && i < PG_DIR; i += blockDim.x) sdir[i] = m.dir[i];
+  __syncthreads();
+  return PgView{(lds_u32 *)sdir, m.nodes, m.pool, m.direct};
+}
+
+// The physical runs behind logical bytes [off, off + 64 KiB) of an array
+// that starts at a 4 KiB boundary and ends at logical offset `end`: bytes
+// below `split` at b0, the rest at b1.  The second page is looked up only if
+// the array reaches it.  `split` is a multiple of 4 KiB, so each 4 KiB unit
+// of the window lies in one run: unit(q) is the same for every thread.
+struct PgWin {
+  char *b0, *b1;
+  uint32_t split;
+  __device__ __forceinline__ char *at(uint32_t byte) const {
+    return byte < split ? b0 + byte : b1 + (byte - split);
+  }
+  __device__ __forceinline__ char *unit(uint32_t q) const {
+    const uint32_t byte = q << 12;
+    return byte < split ? b0 + byte : b1 + (byte - split);
+  }
+};
+__device__ __forceinline__ PgWin pg_win(const PgView &v, uint64_t off, uint64_t end) {
+  const uint32_t in = uint32_t(off & (PG_BYTES - 1));
+  PgWin w;
+  w.b0 = v.addr(off);
+  w.split = uint32_t(PG_BYTES) - in;
+  const uint64_t next = (off >> PG_SHIFT) + 1;
+  w.b1 = in && (next << PG_SHIFT) < end ? v.pool + (uint64_t(v.page(next)) << PG_SHIFT) : w.b0 + w.split;
+  return w;
 }
 
 // Position-keyed digest of 32-bit words: sum over i of (s_i | 1) * w_i mod

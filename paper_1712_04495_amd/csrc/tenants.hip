@@ -478,83 +478,131 @@ __global__ __launch_bounds__(GT2, 1) void k_gemm_bf16_256(const uint16_t *__rest
 
 
 // ------------------------------------------------ paged tenant work (pages.h)
-// A unit is 4 KiB of one array (1024 32-bit words or 2048 bf16): it never
-// straddles a page, so it is translated once.  Each kernel returns at once
-// when the placement maps fewer than `need` pages (a failed placement maps
-// none).
+// Work is cut into 4 KiB units of each array (1024 words, 2048 bf16): a unit
+// never straddles a page, so it is translated once.  The streaming kernels
+// make each unit a buffer resource (see k_pg_triad).  Each kernel returns at
+// once when the placement maps fewer than `need` pages (a failed placement
+// maps none).
 constexpr int64_t UNIT_W = 1024;  // 32-bit words per unit
-constexpr int PGT_U = 4;          // units per workgroup step (loads in flight)
+constexpr int PGT_U = 4;          // vectors in flight per thread
 
 __device__ __forceinline__ bool pg_ok(const PageMap &m, int64_t need) { return pm_pages(m) >= need; }
 
-__global__ __launch_bounds__(256) void k_pg_triad_fill(PageMap m, int64_t need, uint64_t ob,
-                                                       uint64_t oc, int64_t n, uint64_t s0) {
-  if (!pg_ok(m, need)) return;
-  const int64_t units = (n + UNIT_W - 1) / UNIT_W;
-  for (int64_t u = blockIdx.x; u < units; u += gridDim.x) {
-    float *b = reinterpret_cast<float *>(pm_addr(m, ob + uint64_t(u) * 4096));
-    float *c = reinterpret_cast<float *>(pm_addr(m, oc + uint64_t(u) * 4096));
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int w = q * 256 + threadIdx.x;
-      const int64_t i = u * UNIT_W + w;
-      if (i < n) {
-        const uint64_t h = splitmix(s0, uint64_t(i));
-        b[w] = 1.0f + float(h & 0xFFFF) * (1.0f / 65536.0f);
-        c[w] = 1.0f + float((h >> 16) & 0xFFFF) * (1.0f / 65536.0f);
-      }
-    }
-  }
+constexpr int BUF_NT = 2;  // buffer instruction aux: non-temporal
+
+template <bool DIRECT>
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t unit_rsrc(const PageMap &m, uint64_t base,
+                                                            int64_t o, int64_t bytes) {
+  // a unit past the end maps unit 0 (always mapped) with an empty range
+  const bool in = o < bytes;
+  const int64_t valid = in ? ((bytes - o < 4096 ? bytes - o : 4096) & ~int64_t(15)) : 0;
+  return __builtin_amdgcn_make_buffer_rsrc(pm_addr_t<DIRECT>(m, base + (in ? o : 0)), 0, int(valid),
+                                           BUF_RSRC_DW3);
 }
 
-// a = b + s * c; thread t of a unit handles its words 4t .. 4t + 3 as one
-// 16-byte vector (elementwise in the array's last, partial vector).
-__global__ __launch_bounds__(256) void k_pg_triad(PageMap m, int64_t need, uint64_t oa, uint64_t ob,
-                                                  uint64_t oc, float s, int64_t n) {
-  if (!pg_ok(m, need)) return;
-  const int64_t units = (n + UNIT_W - 1) / UNIT_W;
-  for (int64_t u0 = int64_t(blockIdx.x) * PGT_U; u0 < units; u0 += int64_t(gridDim.x) * PGT_U) {
-    f32x4 x[PGT_U], y[PGT_U];
-    f32x4 *pa[PGT_U];
+// Fills in the shape of the triad: workgroup g writes item g (PGT_U units of
+// 4 KiB per array), thread t one 16-byte vector per unit.
+template <bool DIRECT>
+__global__ __launch_bounds__(256) void k_pg_triad_fill(PageMap m, int64_t need, uint64_t ob,
+                                                       uint64_t oc, int64_t n, uint64_t s0) {
+  if (pm_pages(m) < need) return;
+  const int64_t bytes = 4 * n;
+  const int64_t n_item = (bytes + PGT_U * 4096 - 1) / (PGT_U * 4096);
+  const int tb = 16 * int(threadIdx.x);
+  for (int64_t it = blockIdx.x; it < n_item; it += gridDim.x) {
 #pragma unroll
-    for (int v = 0; v < PGT_U; ++v) {
-      const int64_t u = u0 + v;
-      pa[v] = nullptr;
-      if (u < units && u * UNIT_W + 4 * threadIdx.x + 3 < n) {
-        const f32x4 *pb = reinterpret_cast<const f32x4 *>(pm_addr(m, ob + uint64_t(u) * 4096));
-        const f32x4 *pc = reinterpret_cast<const f32x4 *>(pm_addr(m, oc + uint64_t(u) * 4096));
-        pa[v] = reinterpret_cast<f32x4 *>(pm_addr(m, oa + uint64_t(u) * 4096)) + threadIdx.x;
-        x[v] = __builtin_nontemporal_load(pb + threadIdx.x);
-        y[v] = __builtin_nontemporal_load(pc + threadIdx.x);
+    for (int u = 0; u < PGT_U; ++u) {
+      const int64_t o = (it * PGT_U + u) << 12;
+      const __amdgpu_buffer_rsrc_t rb = unit_rsrc<DIRECT>(m, ob, o, bytes);
+      const __amdgpu_buffer_rsrc_t rc = unit_rsrc<DIRECT>(m, oc, o, bytes);
+      f32x4 vb, vc;
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const uint64_t h = splitmix(s0, uint64_t((o + tb) / 4 + e));
+        vb[e] = 1.0f + float(h & 0xFFFF) * (1.0f / 65536.0f);
+        vc[e] = 1.0f + float((h >> 16) & 0xFFFF) * (1.0f / 65536.0f);
       }
+      __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u32x4, vb), rb, tb, 0, 0);
+      __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u32x4, vc), rc, tb, 0, 0);
     }
-#pragma unroll
-    for (int v = 0; v < PGT_U; ++v)
-      if (pa[v]) __builtin_nontemporal_store(x[v] + s * y[v], pa[v]);
   }
-  // the partial vector at the end of the array
+  // the partial vector at the end
   const int64_t t0 = n & ~int64_t(3);
   if (blockIdx.x == 0 && threadIdx.x < (n & 3)) {
     const int64_t i = t0 + threadIdx.x;
-    const uint64_t o = uint64_t(i) * 4;
+    const uint64_t h = splitmix(s0, uint64_t(i));
+    *reinterpret_cast<float *>(pm_addr(m, ob + uint64_t(i) * 4)) = 1.0f + float(h & 0xFFFF) * (1.0f / 65536.0f);
+    *reinterpret_cast<float *>(pm_addr(m, oc + uint64_t(i) * 4)) =
+        1.0f + float((h >> 16) & 0xFFFF) * (1.0f / 65536.0f);
+  }
+}
+
+// a = b + s * c in the shape of k_triad: workgroup g streams item g, 16 KiB
+// (PGT_U units of 4 KiB) of each array, thread t one 16-byte vector per unit.
+// A unit never straddles a page, so each unit is one buffer resource whose
+// base comes from a uniform (scalar) lookup -- all twelve of an item issued
+// back to back -- and whose range stops at the array's last whole vector:
+// lanes past it read zero and their stores are dropped, so no lane branches.
+// The partial vector at the end is done elementwise.
+template <bool DIRECT>
+__global__ __launch_bounds__(256) void k_pg_triad(PageMap m, int64_t need, uint64_t oa, uint64_t ob,
+                                                  uint64_t oc, float s, int64_t n) {
+  if (pm_pages(m) < need) return;
+  const int64_t bytes = 4 * n;
+  const int64_t n_item = (bytes + PGT_U * 4096 - 1) / (PGT_U * 4096);
+  const int tb = 16 * int(threadIdx.x);
+  for (int64_t it = blockIdx.x; it < n_item; it += gridDim.x) {
+    __amdgpu_buffer_rsrc_t ra[PGT_U], rb[PGT_U], rc[PGT_U];
+#pragma unroll
+    for (int u = 0; u < PGT_U; ++u) {
+      const int64_t o = (it * PGT_U + u) << 12;
+      ra[u] = unit_rsrc<DIRECT>(m, oa, o, bytes);
+      rb[u] = unit_rsrc<DIRECT>(m, ob, o, bytes);
+      rc[u] = unit_rsrc<DIRECT>(m, oc, o, bytes);
+    }
+    u32x4 x[PGT_U], y[PGT_U];
+#pragma unroll
+    for (int u = 0; u < PGT_U; ++u) {
+      x[u] = __builtin_amdgcn_raw_buffer_load_b128(rb[u], tb, 0, BUF_NT);
+      y[u] = __builtin_amdgcn_raw_buffer_load_b128(rc[u], tb, 0, BUF_NT);
+    }
+#pragma unroll
+    for (int u = 0; u < PGT_U; ++u) {
+      const f32x4 r = __builtin_bit_cast(f32x4, x[u]) + s * __builtin_bit_cast(f32x4, y[u]);
+      __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u32x4, r), ra[u], tb, 0, BUF_NT);
+    }
+  }
+  const int64_t t0 = n & ~int64_t(3);
+  if (blockIdx.x == 0 && threadIdx.x < (n & 3)) {
+    const uint64_t o = uint64_t(t0 + threadIdx.x) * 4;
     *reinterpret_cast<float *>(pm_addr(m, oa + o)) =
         *reinterpret_cast<const float *>(pm_addr(m, ob + o)) +
         s * *reinterpret_cast<const float *>(pm_addr(m, oc + o));
   }
 }
 
+template <bool DIRECT>
 __global__ __launch_bounds__(256) void k_pg_hist_fill(PageMap m, int64_t need, uint64_t ok_,
                                                       int64_t n, uint64_t s0) {
-  if (!pg_ok(m, need)) return;
-  const int64_t units = (n + UNIT_W - 1) / UNIT_W;
-  for (int64_t u = blockIdx.x; u < units; u += gridDim.x) {
-    uint32_t *k = reinterpret_cast<uint32_t *>(pm_addr(m, ok_ + uint64_t(u) * 4096));
+  if (pm_pages(m) < need) return;
+  const int64_t bytes = 4 * n;
+  const int64_t n_item = (bytes + PGT_U * 4096 - 1) / (PGT_U * 4096);
+  const int tb = 16 * int(threadIdx.x);
+  for (int64_t it = blockIdx.x; it < n_item; it += gridDim.x) {
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int w = q * 256 + threadIdx.x;
-      const int64_t i = u * UNIT_W + w;
-      if (i < n) k[w] = uint32_t(splitmix(s0, uint64_t(i)));
+    for (int u = 0; u < PGT_U; ++u) {
+      const int64_t o = (it * PGT_U + u) << 12;
+      const __amdgpu_buffer_rsrc_t rk = unit_rsrc<DIRECT>(m, ok_, o, bytes);
+      u32x4 k;
+#pragma unroll
+      for (int e = 0; e < 4; ++e) k[e] = uint32_t(splitmix(s0, uint64_t((o + tb) / 4 + e)));
+      __builtin_amdgcn_raw_buffer_store_b128(k, rk, tb, 0, 0);
     }
+  }
+  const int64_t t0 = n & ~int64_t(3);
+  if (blockIdx.x == 0 && threadIdx.x < (n & 3)) {
+    const int64_t i = t0 + threadIdx.x;
+    *reinterpret_cast<uint32_t *>(pm_addr(m, ok_ + uint64_t(i) * 4)) = uint32_t(splitmix(s0, uint64_t(i)));
   }
 }
 
@@ -565,41 +613,45 @@ __global__ void k_pg_zero(PageMap m, int64_t need, uint64_t off, int64_t n_words
     *reinterpret_cast<uint32_t *>(pm_addr(m, off + uint64_t(i) * 4)) = 0;
 }
 
-// Same LDS scheme as k_hist; keys are read a unit (one 16-byte vector per
-// thread) at a time, PGT_U units in flight.
+// Same LDS scheme as k_hist: a capped grid walks items of PGT_U units of
+// keys (one 16-byte vector per thread per unit, buffer resources over the
+// units as in the triad, so a lane past the end reads nothing it counts);
+// the partial vector at the end elementwise.
+template <bool DIRECT>
 __global__ __launch_bounds__(HIST_THREADS) void k_pg_hist(PageMap m, int64_t need, uint64_t ok_,
                                                           int64_t n, uint32_t mask, uint64_t ob) {
-  if (!pg_ok(m, need)) return;
   __shared__ uint32_t h[HIST_COPIES][SCHED_HIST_BINS];
+  if (pm_pages(m) < need) return;
   for (int i = threadIdx.x; i < HIST_COPIES * SCHED_HIST_BINS; i += HIST_THREADS)
     (&h[0][0])[i] = 0;
   __syncthreads();
   uint32_t *mine = h[(threadIdx.x / 64) % HIST_COPIES];
-  const int64_t units = (n + UNIT_W - 1) / UNIT_W;
-  for (int64_t u0 = int64_t(blockIdx.x) * PGT_U; u0 < units; u0 += int64_t(gridDim.x) * PGT_U) {
-    u32x4 v[PGT_U];
-    int cnt[PGT_U];
+  const int64_t bytes = 4 * n;
+  const int64_t n_item = (bytes + PGT_U * 4096 - 1) / (PGT_U * 4096);
+  const int tb = 16 * int(threadIdx.x);
+  const int64_t full = bytes & ~int64_t(15);  // bytes of whole vectors
+  for (int64_t it = blockIdx.x; it < n_item; it += gridDim.x) {
+    __amdgpu_buffer_rsrc_t rk[PGT_U];
 #pragma unroll
-    for (int q = 0; q < PGT_U; ++q) {
-      const int64_t u = u0 + q, e = u * UNIT_W + 4 * threadIdx.x;
-      cnt[q] = u < units ? int(e + 4 <= n ? 4 : (e < n ? n - e : 0)) : 0;
-      if (cnt[q] == 4) {
-        v[q] = __builtin_nontemporal_load(
-            reinterpret_cast<const u32x4 *>(pm_addr(m, ok_ + uint64_t(u) * 4096)) + threadIdx.x);
-      } else if (cnt[q] > 0) {
-        const uint32_t *k = reinterpret_cast<const uint32_t *>(pm_addr(m, ok_ + uint64_t(u) * 4096)) +
-                            4 * threadIdx.x;
-        v[q] = u32x4{k[0], cnt[q] > 1 ? k[1] : 0u, cnt[q] > 2 ? k[2] : 0u, 0u};
+    for (int u = 0; u < PGT_U; ++u) rk[u] = unit_rsrc<DIRECT>(m, ok_, (it * PGT_U + u) << 12, bytes);
+    u32x4 x[PGT_U];
+#pragma unroll
+    for (int u = 0; u < PGT_U; ++u) x[u] = __builtin_amdgcn_raw_buffer_load_b128(rk[u], tb, 0, BUF_NT);
+#pragma unroll
+    for (int u = 0; u < PGT_U; ++u) {
+      if (((it * PGT_U + u) << 12) + tb + 16 <= full) {
+        atomicAdd(&mine[x[u].x & mask], 1u);
+        atomicAdd(&mine[x[u].y & mask], 1u);
+        atomicAdd(&mine[x[u].z & mask], 1u);
+        atomicAdd(&mine[x[u].w & mask], 1u);
       }
     }
-#pragma unroll
-    for (int q = 0; q < PGT_U; ++q) {
-      if (cnt[q] > 0) atomicAdd(&mine[v[q].x & mask], 1u);
-      if (cnt[q] > 1) atomicAdd(&mine[v[q].y & mask], 1u);
-      if (cnt[q] > 2) atomicAdd(&mine[v[q].z & mask], 1u);
-      if (cnt[q] > 3) atomicAdd(&mine[v[q].w & mask], 1u);
-    }
   }
+  const int64_t t0 = n & ~int64_t(3);
+  if (blockIdx.x == 0 && threadIdx.x < (n & 3))
+    atomicAdd(&mine[*reinterpret_cast<const uint32_t *>(pm_addr(m, ok_ + uint64_t(t0 + threadIdx.x) * 4)) &
+                    mask],
+              1u);
   __syncthreads();
   for (int b = threadIdx.x; b < SCHED_HIST_BINS; b += HIST_THREADS) {
     uint32_t sum = 0;
@@ -609,23 +661,42 @@ __global__ __launch_bounds__(HIST_THREADS) void k_pg_hist(PageMap m, int64_t nee
   }
 }
 
-// bf16 operand rows * K elements; a unit holds 2048 of them (8 per thread).
+// bf16 operand of n elements: items of PGT_U units (2048 elements each),
+// thread t one 16-byte vector (8 elements) per unit.
+template <bool DIRECT>
 __global__ __launch_bounds__(256) void k_pg_gemm_fill(PageMap m, int64_t need, uint64_t off,
                                                       int64_t n, uint64_t s0) {
-  if (!pg_ok(m, need)) return;
-  const int64_t units = (n + 2 * UNIT_W - 1) / (2 * UNIT_W);
-  for (int64_t u = blockIdx.x; u < units; u += gridDim.x) {
-    uint16_t *x = reinterpret_cast<uint16_t *>(pm_addr(m, off + uint64_t(u) * 4096));
+  if (pm_pages(m) < need) return;
+  const int64_t bytes = 2 * n;
+  const int64_t n_item = (bytes + PGT_U * 4096 - 1) / (PGT_U * 4096);
+  const int tb = 16 * int(threadIdx.x);
+  for (int64_t it = blockIdx.x; it < n_item; it += gridDim.x) {
 #pragma unroll
-    for (int q = 0; q < 8; ++q) {
-      const int w = q * 256 + threadIdx.x;
-      const int64_t i = u * 2 * UNIT_W + w;
-      if (i < n) {
-        const uint64_t hh = splitmix(s0, uint64_t(i));
-        const float v = (float(int(hh & 0xFF)) - 128.0f) * (1.0f / 64.0f);
-        x[w] = uint16_t(__float_as_uint(v) >> 16);
+    for (int u = 0; u < PGT_U; ++u) {
+      const int64_t o = (it * PGT_U + u) << 12;
+      const __amdgpu_buffer_rsrc_t rx = unit_rsrc<DIRECT>(m, off, o, bytes);
+      u32x4 w;
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        uint32_t pair = 0;
+#pragma unroll
+        for (int hh = 0; hh < 2; ++hh) {
+          const uint64_t z = splitmix(s0, uint64_t((o + tb) / 2 + 2 * e + hh));
+          const float f = (float(int(z & 0xFF)) - 128.0f) * (1.0f / 64.0f);
+          pair |= (__float_as_uint(f) >> 16) << (16 * hh);
+        }
+        w[e] = pair;
       }
+      __builtin_amdgcn_raw_buffer_store_b128(w, rx, tb, 0, 0);
     }
+  }
+  // elements of the partial vector at the end
+  const int64_t t0 = n & ~int64_t(7);
+  if (blockIdx.x == 0 && threadIdx.x < (n & 7)) {
+    const int64_t i = t0 + threadIdx.x;
+    const uint64_t z = splitmix(s0, uint64_t(i));
+    const float f = (float(int(z & 0xFF)) - 128.0f) * (1.0f / 64.0f);
+    *reinterpret_cast<uint16_t *>(pm_addr(m, off + uint64_t(i) * 2)) = uint16_t(__float_as_uint(f) >> 16);
   }
 }
 
@@ -756,8 +827,11 @@ int pgt_triad_fill(const PageMap &m, uint64_t ob, uint64_t oc, int64_t n, uint64
   if (n <= 0) return n == 0 ? SCHED_OK : SCHED_E_INVALID;
   if (!off_ok(ob) || !off_ok(oc)) return SCHED_E_INVALID;
   const int64_t need = std::max(pages_to(ob, 4 * n), pages_to(oc, 4 * n));
-  k_pg_triad_fill<<<units_grid((n + UNIT_W - 1) / UNIT_W, 1, 8192), 256, 0, s>>>(m, need, ob, oc, n,
-                                                                                 seed << 32);
+  const int grid = units_grid((4 * n + PGT_U * 4096 - 1) / (PGT_U * 4096), 1, 1 << 30);
+  if (m.direct)
+    k_pg_triad_fill<true><<<grid, 256, 0, s>>>(m, need, ob, oc, n, seed << 32);
+  else
+    k_pg_triad_fill<false><<<grid, 256, 0, s>>>(m, need, ob, oc, n, seed << 32);
   SCHED_HIP_TRY(hipGetLastError());
   return SCHED_OK;
 }
@@ -768,10 +842,14 @@ int pgt_triad(const PageMap &m, uint64_t oa, uint64_t ob, uint64_t oc, float sc,
   if (n == 0) return SCHED_OK;
   const int64_t need =
       std::max(pages_to(oa, 4 * n), std::max(pages_to(ob, 4 * n), pages_to(oc, 4 * n)));
-  const int grid = units_grid((n + UNIT_W - 1) / UNIT_W, PGT_U, 1 << 30);
+  const int grid = units_grid((4 * n + PGT_U * 4096 - 1) / (PGT_U * 4096), 1, 1 << 30);
   for (int32_t it = 0; it < iters; ++it) {
-    SCHED_PROF_LAUNCH("k_pg_triad", s,
-                      (k_pg_triad<<<grid, 256, 0, s>>>(m, need, oa, ob, oc, sc, n)));
+    if (m.direct)
+      SCHED_PROF_LAUNCH("k_pg_triad", s,
+                        (k_pg_triad<true><<<grid, 256, 0, s>>>(m, need, oa, ob, oc, sc, n)));
+    else
+      SCHED_PROF_LAUNCH("k_pg_triad", s,
+                        (k_pg_triad<false><<<grid, 256, 0, s>>>(m, need, oa, ob, oc, sc, n)));
     SCHED_HIP_TRY(hipGetLastError());
   }
   return SCHED_OK;
@@ -780,8 +858,11 @@ int pgt_triad(const PageMap &m, uint64_t oa, uint64_t ob, uint64_t oc, float sc,
 int pgt_hist_fill(const PageMap &m, uint64_t ok_, int64_t n, uint64_t seed, hipStream_t s) {
   if (n < 0 || !off_ok(ok_)) return SCHED_E_INVALID;
   if (n == 0) return SCHED_OK;
-  k_pg_hist_fill<<<units_grid((n + UNIT_W - 1) / UNIT_W, 1, 8192), 256, 0, s>>>(
-      m, pages_to(ok_, 4 * n), ok_, n, seed << 32);
+  const int grid = units_grid((4 * n + PGT_U * 4096 - 1) / (PGT_U * 4096), 1, 1 << 30);
+  if (m.direct)
+    k_pg_hist_fill<true><<<grid, 256, 0, s>>>(m, pages_to(ok_, 4 * n), ok_, n, seed << 32);
+  else
+    k_pg_hist_fill<false><<<grid, 256, 0, s>>>(m, pages_to(ok_, 4 * n), ok_, n, seed << 32);
   SCHED_HIP_TRY(hipGetLastError());
   return SCHED_OK;
 }
@@ -793,9 +874,13 @@ int pgt_hist(const PageMap &m, uint64_t ok_, int64_t n, uint32_t mask, uint64_t 
   SCHED_HIP_TRY(hipGetLastError());
   if (n == 0) return SCHED_OK;
   const int64_t need = std::max(need_b, pages_to(ok_, 4 * n));
-  SCHED_PROF_LAUNCH("k_pg_hist", s,
-                    (k_pg_hist<<<units_grid((n + UNIT_W - 1) / UNIT_W, PGT_U * 4, 256 * HIST_PER_CU),
-                                 HIST_THREADS, 0, s>>>(m, need, ok_, n, mask, ob)));
+  const int grid = units_grid((4 * n + PGT_U * 4096 - 1) / (PGT_U * 4096), 1, 256 * HIST_PER_CU);
+  if (m.direct)
+    SCHED_PROF_LAUNCH("k_pg_hist", s,
+                      (k_pg_hist<true><<<grid, HIST_THREADS, 0, s>>>(m, need, ok_, n, mask, ob)));
+  else
+    SCHED_PROF_LAUNCH("k_pg_hist", s,
+                      (k_pg_hist<false><<<grid, HIST_THREADS, 0, s>>>(m, need, ok_, n, mask, ob)));
   SCHED_HIP_TRY(hipGetLastError());
   return SCHED_OK;
 }
@@ -805,8 +890,11 @@ int pgt_gemm_fill(const PageMap &m, uint64_t off, int64_t rows, int64_t K, uint6
   const int64_t n = rows * K;
   if (rows < 0 || K < 0 || !off_ok(off)) return SCHED_E_INVALID;
   if (n == 0) return SCHED_OK;
-  k_pg_gemm_fill<<<units_grid((n + 2 * UNIT_W - 1) / (2 * UNIT_W), 1, 8192), 256, 0, s>>>(
-      m, pages_to(off, 2 * n), off, n, seed << 32);
+  const int grid = units_grid((2 * n + PGT_U * 4096 - 1) / (PGT_U * 4096), 1, 1 << 30);
+  if (m.direct)
+    k_pg_gemm_fill<true><<<grid, 256, 0, s>>>(m, pages_to(off, 2 * n), off, n, seed << 32);
+  else
+    k_pg_gemm_fill<false><<<grid, 256, 0, s>>>(m, pages_to(off, 2 * n), off, n, seed << 32);
   SCHED_HIP_TRY(hipGetLastError());
   return SCHED_OK;
 }
