@@ -293,7 +293,8 @@ typedef struct {
   int64_t last_admitted;   /* index of the last admitted entry, -1 if none     */
 } sched_scan_result_t;
 
-/* Bytes of device workspace sched_scan needs for n entries. */
+/* Bytes of device workspace sched_scan needs for n entries: a control block,
+ * a pass summary and one look-back flag per 4096-entry tile (+1). */
 size_t sched_scan_workspace_size(int64_t n);
 
 /* One pass of policy SCHED_POLICY_FIFO or SCHED_POLICY_MMU (Sec. V) over d_demand[n]
@@ -302,9 +303,12 @@ size_t sched_scan_workspace_size(int64_t n);
  * for every admitted entry and writes 0 to entries it rejects; entries after
  * the point where the pass stopped are written only when write_all != 0, so
  * callers that read the whole vector either zero it first or pass
- * write_all = 1.  d_ws is device workspace of sched_scan_workspace_size(n)
- * bytes, or NULL to use a workspace the library allocates and keeps for the
- * device.  The pass runs entirely in the grid-wide round kernel (decoupled
+ * write_all = 1.  d_ws is device workspace of at least
+ * sched_scan_workspace_size(n) bytes, 256-byte aligned (the call then
+ * allocates nothing; it clears the part it uses on the stream first, so the
+ * memory may hold anything; calls sharing one workspace must not overlap), or
+ * NULL to use a workspace the library allocates and keeps for the device.
+ * The pass runs entirely in the grid-wide round kernel (decoupled
  * look-back scan); single-workgroup windows are used first when
  * window_limit > 0.  Synchronises the stream; *out is a host pointer.
  * Errors: SCHED_E_INVALID for bad sizes, policy or R. */

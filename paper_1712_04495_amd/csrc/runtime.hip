@@ -644,34 +644,62 @@ struct ScanWs {
   int64_t cap_entries = 0;
 };
 ScanWs g_scan[64];
-}  // namespace
 
-extern "C" size_t sched_scan_workspace_size(int64_t n) {
+constexpr size_t align256(size_t x) { return (x + 255) / 256 * 256; }
+
+// Workspace of a scan over up to n entries: control block, pass summary,
+// one look-back flag per tile (+1).
+size_t scan_ws_bytes(int64_t n, size_t *off_sum, size_t *off_flags) {
   if (n < 0) n = 0;
-  return 256 + sizeof(unsigned long long) * size_t((n + TILE - 1) / TILE + 1);
+  const size_t o_sum = align256(sizeof(DevCtl));
+  const size_t o_flags = o_sum + align256(sizeof(PassSummary));
+  if (off_sum) *off_sum = o_sum;
+  if (off_flags) *off_flags = o_flags;
+  return o_flags + sizeof(unsigned long long) * size_t((n + TILE - 1) / TILE + 1);
 }
 
-extern "C" int sched_scan(int32_t policy, int64_t n, const int64_t *d_demand, int64_t R,
-                          uint8_t *d_decision, int32_t write_all, int32_t window_limit, void *d_ws,
-                          size_t ws_bytes, sched_stream_t stream, sched_scan_result_t *out) {
-  if (!out || n < 0 || R < 0 || R > MAX_FREE) return SCHED_E_INVALID;
-  if (policy != SCHED_POLICY_FIFO && policy != SCHED_POLICY_MMU) return SCHED_E_INVALID;
-  if (n > 0 && (!d_demand || !d_decision)) return SCHED_E_INVALID;
-  (void)d_ws;
-  (void)ws_bytes;
-  int dev = 0;
-  SCHED_HIP_TRY(hipGetDevice(&dev));
-  if (dev < 0 || dev >= 64) return SCHED_E_INVALID;
-  ScanWs &w = g_scan[dev];
-  std::lock_guard<std::mutex> g(w.mu);
-  if (w.cap_entries < n || !w.eng.d_ctl) {
-    adm_engine_free(w.eng);
-    if (int rc = adm_engine_init(w.eng, dev, std::max<int64_t>(n, 1 << 20))) return rc;
-    w.cap_entries = std::max<int64_t>(n, 1 << 20);
+// The round grid per device (an occupancy query; cached).
+int scan_grid(int dev, int *grid) {
+  static std::mutex mu;
+  static int cached[64] = {0};
+  std::lock_guard<std::mutex> g(mu);
+  if (!cached[dev]) {
+    AdmEngine tmp;
+    if (int rc = adm_engine_grid(tmp, dev)) return rc;
+    cached[dev] = tmp.round_grid;
   }
-  hipStream_t s = (hipStream_t)stream;
+  *grid = cached[dev];
+  return SCHED_OK;
+}
+
+// A scan engine over `bytes` of device memory at `base` for n entries (no
+// allocation): the pass summary is plain device memory copied into
+// *host_sum; the control block and the flags of the tiles the scan uses are
+// zeroed on stream s, so a fresh epoch sequence is safe whatever the memory
+// held.
+int scan_engine_over(char *base, size_t bytes, int64_t n, int dev, PassSummary *host_sum,
+                     hipStream_t s, AdmEngine *e) {
+  size_t o_sum = 0, o_flags = 0;
+  if (scan_ws_bytes(n, &o_sum, &o_flags) > bytes || (uintptr_t(base) & 255)) return SCHED_E_INVALID;
+  *e = AdmEngine{};
+  e->device = dev;
+  e->d_ctl = reinterpret_cast<DevCtl *>(base);
+  e->d_sum = reinterpret_cast<PassSummary *>(base + o_sum);
+  e->h_sum = host_sum;
+  e->sum_copy = true;
+  e->d_flags = reinterpret_cast<unsigned long long *>(base + o_flags);
+  e->max_tiles = (n + TILE - 1) / TILE + 1;
+  if (int rc = scan_grid(dev, &e->round_grid)) return rc;
+  if (int rc = adm_fill_u64(reinterpret_cast<unsigned long long *>(base), int64_t(o_sum / 8), 0ULL, s))
+    return rc;
+  return adm_fill_u64(e->d_flags, e->max_tiles, 0ULL, s);
+}
+
+int scan_finish(AdmEngine &eng, int32_t policy, int64_t n, const int64_t *d_demand, int64_t R,
+                uint8_t *d_decision, int32_t write_all, int32_t window_limit, hipStream_t s,
+                sched_scan_result_t *out) {
   PassOut po{};
-  if (int rc = adm_scan(w.eng, policy, d_demand, d_decision, 0, n, R, window_limit, s, &po)) return rc;
+  if (int rc = adm_scan(eng, policy, d_demand, d_decision, 0, n, R, window_limit, s, &po)) return rc;
   if (write_all && po.start_final < n) {
     if (int rc = adm_zero_decisions(d_decision + po.start_final, n - po.start_final, s)) return rc;
     SCHED_HIP_TRY(hipStreamSynchronize(s));
@@ -682,6 +710,35 @@ extern "C" int sched_scan(int32_t policy, int64_t n, const int64_t *d_demand, in
   out->rounds = po.rounds;
   out->last_admitted = po.hi - 1 >= 0 && po.admitted > 0 ? po.hi - 1 : -1;
   return SCHED_OK;
+}
+}  // namespace
+
+extern "C" size_t sched_scan_workspace_size(int64_t n) { return scan_ws_bytes(n, nullptr, nullptr); }
+
+extern "C" int sched_scan(int32_t policy, int64_t n, const int64_t *d_demand, int64_t R,
+                          uint8_t *d_decision, int32_t write_all, int32_t window_limit, void *d_ws,
+                          size_t ws_bytes, sched_stream_t stream, sched_scan_result_t *out) {
+  if (!out || n < 0 || R < 0 || R > MAX_FREE) return SCHED_E_INVALID;
+  if (policy != SCHED_POLICY_FIFO && policy != SCHED_POLICY_MMU) return SCHED_E_INVALID;
+  if (n > 0 && (!d_demand || !d_decision)) return SCHED_E_INVALID;
+  int dev = 0;
+  SCHED_HIP_TRY(hipGetDevice(&dev));
+  if (dev < 0 || dev >= 64) return SCHED_E_INVALID;
+  hipStream_t s = (hipStream_t)stream;
+  if (d_ws) {  // the caller's workspace: nothing is allocated
+    AdmEngine eng;
+    PassSummary hs{};
+    if (int rc = scan_engine_over((char *)d_ws, ws_bytes, n, dev, &hs, s, &eng)) return rc;
+    return scan_finish(eng, policy, n, d_demand, R, d_decision, write_all, window_limit, s, out);
+  }
+  ScanWs &w = g_scan[dev];
+  std::lock_guard<std::mutex> g(w.mu);
+  if (w.cap_entries < n || !w.eng.d_ctl) {
+    adm_engine_free(w.eng);
+    if (int rc = adm_engine_init(w.eng, dev, std::max<int64_t>(n, 1 << 20))) return rc;
+    w.cap_entries = std::max<int64_t>(n, 1 << 20);
+  }
+  return scan_finish(w.eng, policy, n, d_demand, R, d_decision, write_all, window_limit, s, out);
 }
 
 // Reservations, states and the queue's decision bytes (q_cap of them, a power

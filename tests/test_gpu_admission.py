@@ -402,6 +402,34 @@ def test_enqueue_batch_rejects_invalid(cs):
         cs.sched_destroy(ctx)
 
 
+def test_scan_caller_workspace_equals_library_workspace(cs):
+    """sched_scan with the caller's workspace (filled with garbage, reused by
+    two calls in a row, the second smaller) decides exactly as with the
+    library's own workspace and as the oracle."""
+    for n, R, pol, wl in ((3 * 4096 + 17, 10**6, 1, 0), (5000, 3 * 10**5, 0, 4),
+                          (70_000, 10**7, 1, 2), (257, 4000, 1, 0)):
+        q = random_queue(n, n, 1000, holes=0.05)
+        d = torch.from_numpy(q).to(DEV)
+        ws_n = cs.sched_scan_workspace_size(70_000)
+        ws = torch.full((ws_n,), 0xA5, dtype=torch.uint8, device=DEV)
+        dec_a = torch.full((n,), 7, dtype=torch.uint8, device=DEV)
+        dec_b = torch.full((n,), 7, dtype=torch.uint8, device=DEV)
+        rc, ra = cs.sched_scan(pol, d, R, dec_a, write_all=1, window_limit=wl)
+        assert rc == 0
+        rc, rb = cs.sched_scan(pol, d, R, dec_b, write_all=1, window_limit=wl, d_ws=ws,
+                               ws_bytes=ws_n)
+        assert rc == 0
+        assert ra == rb
+        assert torch.equal(dec_a, dec_b)
+        ref, R2 = (S.fifo_pass if pol == 0 else S.mmu_pass)(q, R)
+        assert np.array_equal(dec_b.cpu().numpy().astype(bool), ref) and rb["free_after"] == R2
+    # too small a workspace is refused
+    d = torch.ones(10_000, dtype=torch.int64, device=DEV)
+    dec = torch.zeros(10_000, dtype=torch.uint8, device=DEV)
+    small = torch.zeros(256, dtype=torch.uint8, device=DEV)
+    assert cs.sched_scan(1, d, 100, dec, d_ws=small, ws_bytes=256)[0] == cs.SCHED_E_INVALID
+
+
 # --------------------------------------------------------------------------
 # Life-cycle API vs the oracle state machine
 # --------------------------------------------------------------------------
