@@ -316,6 +316,20 @@ int sched_scan(int32_t policy, int64_t n, const int64_t *d_demand, int64_t R, ui
                int32_t write_all, int32_t window_limit, void *d_ws, size_t ws_bytes,
                sched_stream_t stream, sched_scan_result_t *out);
 
+/* sched_scan for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): the same pass with the same arguments and results, its
+ * workspace a fixed device array the library holds on each GPU for the life
+ * of the process, sized for n <= 2^28 entries (about 512 KiB); larger n is
+ * SCHED_E_INVALID.  It calls no hipMalloc, hipFree or other allocating
+ * routine.  Calls on one GPU share that array: the library runs them one at
+ * a time (each returns after its kernels have finished), and the part of
+ * the array a call uses is cleared on the stream first, so what an earlier
+ * call left behind does not matter.  Synchronises the stream. */
+int sched_scan_noalloc(int32_t policy, int64_t n, const int64_t *d_demand, int64_t R,
+                       uint8_t *d_decision, int32_t write_all, int32_t window_limit,
+                       sched_stream_t stream, sched_scan_result_t *out);
+
 /* Look-back bound of the grid rounds (the HBM-bound part of a pass: a
  * single-pass prefix scan across workgroups, Sec. V policies).  A tile waits
  * for a predecessor's published sum at most `polls` polls (default 256),

@@ -126,6 +126,7 @@ _SIGS = {
     "sched_restore": (i32, [vp, vp, C.c_size_t]),
     "sched_scan_workspace_size": (C.c_size_t, [i64]),
     "sched_set_lookback_polls": (i32, [i32]),
+    "sched_scan_noalloc": (i32, [i32, i64, vp, i64, vp, i32, i32, vp, C.POINTER(sched_scan_result_t)]),
     "sched_scan": (i32, [i32, i64, vp, i64, vp, i32, i32, vp, C.c_size_t, vp,
                          C.POINTER(sched_scan_result_t)]),
     "sched_alloc": (i32, [vp, i32, C.c_size_t, C.POINTER(vp)]),
@@ -341,6 +342,14 @@ def sched_scan(policy, d_demand, R, d_decision, write_all=0, window_limit=0, d_w
     n = int(d_demand.numel())
     rc = lib().sched_scan(policy, n, _ptr(d_demand), int(R), _ptr(d_decision), write_all,
                           window_limit, _ptr(d_ws), ws_bytes, _stream(stream), C.byref(r))
+    return rc, {k: getattr(r, k) for k, _ in sched_scan_result_t._fields_}
+
+
+def sched_scan_noalloc(policy, d_demand, R, d_decision, write_all=0, window_limit=0, stream=None):
+    r = sched_scan_result_t()
+    n = int(d_demand.numel())
+    rc = lib().sched_scan_noalloc(policy, n, _ptr(d_demand), int(R), _ptr(d_decision), write_all,
+                                  window_limit, _stream(stream), C.byref(r))
     return rc, {k: getattr(r, k) for k, _ in sched_scan_result_t._fields_}
 
 

@@ -741,6 +741,49 @@ extern "C" int sched_scan(int32_t policy, int64_t n, const int64_t *d_demand, in
   return scan_finish(w.eng, policy, n, d_demand, R, d_decision, write_all, window_limit, s, out);
 }
 
+// ---------------------------------------------------------------------------
+// Stateless scan without allocation
+// ---------------------------------------------------------------------------
+// The workspace lives in a file-scope device array of fixed size: each GPU
+// the library runs on holds its own copy for the life of the process.  Host
+// code never passes the array's name to a kernel; it uses the device address
+// hipGetSymbolAddress returns for the current device, taken once per device.
+namespace {
+constexpr int64_t NOALLOC_MAX_N = int64_t(1) << 28;
+constexpr size_t NOALLOC_BYTES =
+    align256(sizeof(DevCtl)) + align256(sizeof(PassSummary)) +
+    sizeof(unsigned long long) * size_t((NOALLOC_MAX_N + TILE - 1) / TILE + 1);
+}  // namespace
+
+static __device__ __align__(256) unsigned char scratch[NOALLOC_BYTES];
+
+namespace {
+struct NoAllocDev {
+  std::mutex mu;
+  char *ptr = nullptr;  // this device's copy of `scratch`
+};
+NoAllocDev g_noalloc[64];
+}  // namespace
+
+extern "C" int sched_scan_noalloc(int32_t policy, int64_t n, const int64_t *d_demand, int64_t R,
+                                  uint8_t *d_decision, int32_t write_all, int32_t window_limit,
+                                  sched_stream_t stream, sched_scan_result_t *out) {
+  if (!out || n < 0 || n > NOALLOC_MAX_N || R < 0 || R > MAX_FREE) return SCHED_E_INVALID;
+  if (policy != SCHED_POLICY_FIFO && policy != SCHED_POLICY_MMU) return SCHED_E_INVALID;
+  if (n > 0 && (!d_demand || !d_decision)) return SCHED_E_INVALID;
+  int dev = 0;
+  SCHED_HIP_TRY(hipGetDevice(&dev));
+  if (dev < 0 || dev >= 64) return SCHED_E_INVALID;
+  NoAllocDev &g = g_noalloc[dev];
+  std::lock_guard<std::mutex> lk(g.mu);  // calls on one GPU share its array: one at a time
+  if (!g.ptr) SCHED_HIP_TRY(hipGetSymbolAddress((void **)&g.ptr, HIP_SYMBOL(scratch)));
+  hipStream_t s = (hipStream_t)stream;
+  AdmEngine eng;
+  PassSummary hs{};
+  if (int rc = scan_engine_over(g.ptr, NOALLOC_BYTES, n, dev, &hs, s, &eng)) return rc;
+  return scan_finish(eng, policy, n, d_demand, R, d_decision, write_all, window_limit, s, out);
+}
+
 // Reservations, states and the queue's decision bytes (q_cap of them, a power
 // of two >= 256, 16-byte aligned) to zero in one launch.
 __global__ void k_reset_jobs(DevCtl *c, JobArrays jb, uint8_t *decision, int64_t q_cap) {
