@@ -142,6 +142,30 @@ int sched_register(sched_ctx_t *ctx, int32_t priority, int32_t timeout_ms, sched
 int sched_register_batch(sched_ctx_t *ctx, int32_t n, int32_t priority, int32_t timeout_ms,
                          sched_job_t *out_first);
 
+/* Sharing a context between processes (Sec. III-B: clients in separate
+ * processes share one structure; the paper's shared-memory approach).
+ * sched_share publishes ctx under `name` (a POSIX shared-memory name such as
+ * "/sched-demo"): the host side of the state moves into that shared-memory
+ * object, guarded by a process-shared robust mutex and condition variable,
+ * and the device arrays (queue, reservations, job states, control block,
+ * look-back flags) are exported as HIP IPC handles (each allocation must be
+ * under 2 GiB: queue_capacity <= 2^27).  Only a context without a slab pool
+ * and with no request waiting can be shared; SCHED_E_INVALID otherwise, or
+ * if the name exists.  The process that shared it destroys it last
+ * (sched_destroy also removes the name).
+ * sched_attach opens the context shared under `name` in another process (on
+ * the device with the same PCI bus id) and returns a handle to it.  On a
+ * shared or attached context the life-cycle calls (register, admit, wait,
+ * release, set_owner, sanity_check, stats, reservation) and the pass entry
+ * points (sched_pass, sched_enqueue_batch, sched_last_admitted) work across
+ * processes: job handles are common to all, a request made in one process
+ * can be admitted by a pass another runs, and a blocked waiter in any
+ * process wakes up.  sched_serve, sched_pass_chain, sched_reset,
+ * sched_checkpoint and sched_restore return SCHED_E_INVALID there.
+ * sched_destroy on an attached handle detaches it. */
+int sched_share(sched_ctx_t *ctx, const char *name);
+int sched_attach(const char *name, sched_ctx_t **out);
+
 /* Pre-allocation (Sec. IV): checks the device and the size, queues the
  * request behind the waiting ones, runs one admission pass of the context's
  * policy over the whole queue (Sec. V) and reports whether THIS request was

@@ -149,6 +149,8 @@ _SIGS = {
                           C.POINTER(sched_serve_summary_t)]),
     "sched_version": (C.c_char_p, []),
     "sched_abi_sizeof": (i64, [i32]),
+    "sched_share": (i32, [vp, C.c_char_p]),
+    "sched_attach": (i32, [C.c_char_p, C.POINTER(vp)]),
 }
 
 
@@ -203,6 +205,16 @@ def sched_create(device=0, policy=SCHED_POLICY_MMU, capacity_bytes=0, headroom_b
     out = vp()
     rc = lib().sched_create(C.byref(cfg), C.byref(out))
     return rc, out.value
+
+
+def sched_share(ctx, name):
+    return lib().sched_share(ctx, name.encode())
+
+
+def sched_attach(name):
+    h = vp()
+    rc = lib().sched_attach(name.encode(), C.byref(h))
+    return rc, h.value
 
 
 def sched_destroy(ctx):

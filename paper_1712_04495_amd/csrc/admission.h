@@ -94,6 +94,10 @@ struct AdmEngine {
 };
 
 int adm_engine_init(AdmEngine &e, int device, int64_t max_entries);
+// An engine over another process's control block and look-back flags (HIP
+// IPC mappings): only the host-side buffers are allocated here.
+int adm_engine_attach(AdmEngine &e, int device, DevCtl *d_ctl, unsigned long long *d_flags,
+                      int64_t max_tiles);
 // The round kernel's persistent grid for the device (sets e.round_grid).
 int adm_engine_grid(AdmEngine &e, int device);
 int adm_fill_u64(unsigned long long *p, int64_t n, unsigned long long v, hipStream_t s);

@@ -1176,6 +1176,23 @@ int adm_engine_init(AdmEngine &e, int device, int64_t max_entries) {
   return SCHED_OK;
 }
 
+int adm_engine_attach(AdmEngine &e, int device, DevCtl *d_ctl, unsigned long long *d_flags,
+                      int64_t max_tiles) {
+  e.device = device;
+  e.max_tiles = max_tiles;
+  SCHED_HIP_TRY(hipHostMalloc(&e.h_ctl, sizeof(DevCtl), hipHostMallocDefault));
+  memset(e.h_ctl, 0, sizeof(DevCtl));
+  SCHED_HIP_TRY(hipHostMalloc(&e.h_sum, sizeof(PassSummary) * MAX_CHAIN, hipHostMallocMapped));
+  memset(e.h_sum, 0, sizeof(PassSummary) * MAX_CHAIN);
+  SCHED_HIP_TRY(hipHostGetDevicePointer((void **)&e.d_sum, e.h_sum, 0));
+  SCHED_HIP_TRY(hipHostMalloc(&e.h_flag, 64, hipHostMallocMapped));
+  memset(e.h_flag, 0, 64);
+  SCHED_HIP_TRY(hipHostGetDevicePointer((void **)&e.d_flag, e.h_flag, 0));
+  e.d_ctl = d_ctl;
+  e.d_flags = d_flags;
+  return adm_engine_grid(e, device);
+}
+
 int adm_engine_grid(AdmEngine &e, int device) {
   int cus = 0;
   SCHED_HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device));

@@ -264,27 +264,27 @@ int sched_priority_alloc(sched_ctx *c) {
 }
 
 void sched_priority_note(sched_ctx *c, int32_t prio) {
-  c->prio_lo = std::min(c->prio_lo, prio);
-  c->prio_hi = std::max(c->prio_hi, prio);
+  c->sh->prio_lo = std::min(c->sh->prio_lo, prio);
+  c->sh->prio_hi = std::max(c->sh->prio_hi, prio);
 }
 
 int sched_priority_reorder_locked(sched_ctx *c, hipStream_t s) {
-  const int64_t n = c->tail_h - c->head_h;
-  if (c->prio_sorted_tail == c->tail_h) return SCHED_OK;  // nothing appended since
-  if (n <= 1 || c->prio_hi <= c->prio_lo) {
-    c->prio_sorted_tail = c->tail_h;
+  const int64_t n = c->sh->tail_h - c->sh->head_h;
+  if (c->sh->prio_sorted_tail == c->sh->tail_h) return SCHED_OK;  // nothing appended since
+  if (n <= 1 || c->sh->prio_hi <= c->sh->prio_lo) {
+    c->sh->prio_sorted_tail = c->sh->tail_h;
     return SCHED_OK;
   }
   if (!c->prio_tmp) return SCHED_E_INTERNAL;
   PrioWs w;
   ws_layout(c->q.capacity, (char *)c->prio_tmp, &w);
-  const uint64_t span = uint64_t(int64_t(c->prio_hi) - int64_t(c->prio_lo));
+  const uint64_t span = uint64_t(int64_t(c->sh->prio_hi) - int64_t(c->sh->prio_lo));
   int bits = 0;
   while (bits < 32 && (span >> bits) != 0) ++bits;
   const int passes = (bits + PR_BITS - 1) / PR_BITS;
   const int64_t tiles = (n + PR_TILE - 1) / PR_TILE;
   const int grid = int(std::min<int64_t>((n + 255) / 256, 2048));
-  k_prio_keys<<<grid, PR_THREADS, 0, s>>>(c->q, c->head_h, n, c->prio_lo, w.key[0], w.idx[0]);
+  k_prio_keys<<<grid, PR_THREADS, 0, s>>>(c->q, c->sh->head_h, n, c->sh->prio_lo, w.key[0], w.idx[0]);
   SCHED_HIP_TRY(hipGetLastError());
   int cur = 0;
   for (int p = 0; p < passes; ++p) {
@@ -298,12 +298,12 @@ int sched_priority_reorder_locked(sched_ctx *c, hipStream_t s) {
     SCHED_HIP_TRY(hipGetLastError());
     cur ^= 1;
   }
-  k_prio_permute<<<grid, PR_THREADS, 0, s>>>(c->q, c->head_h, n, w.idx[cur], w.t_dem, w.t_job,
+  k_prio_permute<<<grid, PR_THREADS, 0, s>>>(c->q, c->sh->head_h, n, w.idx[cur], w.t_dem, w.t_job,
                                              w.t_prio, w.t_seq);
   SCHED_HIP_TRY(hipGetLastError());
-  k_prio_store<<<grid, PR_THREADS, 0, s>>>(c->q, c->head_h, n, w.t_dem, w.t_job, w.t_prio,
+  k_prio_store<<<grid, PR_THREADS, 0, s>>>(c->q, c->sh->head_h, n, w.t_dem, w.t_job, w.t_prio,
                                            w.t_seq);
   SCHED_HIP_TRY(hipGetLastError());
-  c->prio_sorted_tail = c->tail_h;
+  c->sh->prio_sorted_tail = c->sh->tail_h;
   return SCHED_OK;
 }

@@ -1,25 +1,60 @@
 // Context layout shared by the runtime translation units.
 #pragma once
 
-#include <condition_variable>
+#include <chrono>
 #include <mutex>
-#include <unordered_map>
+#include <string>
 #include <vector>
 
 #include "admission.h"
 #include "pages.h"
+#include "shared.h"
 
 struct SlabState;
+struct sched_ctx;
+
+// The context's lock (the mutex of its host block): taking it loads the
+// admission engine's launch counter and look-back epoch from the block,
+// releasing it stores them back; on a shared context it also waits for the
+// process's own device work, so the next holder, in any process, sees it.
+// A holder that died with the lock leaves it to the next taker (robust mutex).
+class CtxLock {
+ public:
+  explicit CtxLock(sched_ctx *c) : c_(c) {}
+  void lock();
+  void unlock();
+  // for CtxCond: what lock() and unlock() do around the mutex itself
+  void enter();
+  void leave();
+
+ private:
+  sched_ctx *c_;
+};
+
+class CtxCond {
+ public:
+  explicit CtxCond(sched_ctx *c) : c_(c) {}
+  void notify_all();
+  // waits until notified or `until` (steady clock), the lock held on entry and exit
+  void wait_until(std::unique_lock<CtxLock> &lk, std::chrono::steady_clock::time_point until);
+
+ private:
+  sched_ctx *c_;
+};
 
 struct sched_ctx {
-  std::mutex mu;
-  std::condition_variable cv;
+  CtxLock mu{this};
+  CtxCond cv{this};
+  SharedHost *sh = nullptr;  // host state (private block, or the shared mapping)
+  bool attached = false;     // opened with sched_attach: device arrays are IPC mappings
+  void *shm_map = nullptr;   // the shared mapping (when shared or attached)
+  size_t shm_bytes = 0;
+  std::string shm_name;      // set in the process that shared the context
   sched_config_t cfg{};
   int device = 0;
   int64_t capacity = 0;
   int policy = SCHED_POLICY_MMU;
   int window_limit = 16;
-  bool closing = false;
   // sched_reset only orders its kernels on `stream`; until something waits for
   // them, calls that could observe the state by another route settle first
   bool reset_pending = false;
@@ -33,34 +68,19 @@ struct sched_ctx {
   void *d_scratch = nullptr;   // 4 KiB of small device staging
   void *h_stage = nullptr;     // 4 KiB of pinned host staging
 
-  // host-side bookkeeping
-  int32_t n_jobs = 0;
-  std::vector<int32_t> prio, timeout_ms, pending;
-  // owner[j]: process holding job j's memory (0: none); owned: the jobs whose
-  // owner was set, for the sanity check (entries cleared since are skipped)
-  std::vector<int32_t> owner, owned;
-  std::unordered_map<int64_t, int32_t> host_seq;  // waiting requests made with sched_admit
   std::vector<int64_t> last_admitted_seqs;
-  int64_t seq_next = 0;
-  int64_t head_h = 0, tail_h = 0, used_h = 0;
-  int64_t last_A = 0;
-  int64_t rel_jobs_seen = 0, rel_bytes_seen = 0;  // release totals at the last pass result
-  int64_t last_adm_off = 0;
   int32_t *h_adm_job = nullptr;
   int64_t *h_adm_seq = nullptr;
   int64_t h_adm_cap = 0;
-  sched_stats_t stats{};
 
-  // priority ordering: workspace (priority policies only, sized for the
-  // queue at creation), the range of every known job's priority, and the
-  // tail at the last ordering (the queue is still ordered while it holds)
+  // priority ordering workspace (priority policies only, sized for the queue
+  // at creation); the ordering state itself is in the host block
   void *prio_tmp = nullptr;
   size_t prio_tmp_bytes = 0;
-  int32_t prio_lo = INT32_MAX, prio_hi = INT32_MIN;
-  int64_t prio_sorted_tail = 0;
 
   SlabState *slab = nullptr;
 
+  bool shared() const { return sh && sh->shared; }
   void note_admitted(int64_t seq);
   ~sched_ctx();
 };

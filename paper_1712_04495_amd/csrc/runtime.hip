@@ -8,15 +8,24 @@
 // context mutex serialises the calls (the role the file lock plays in the
 // paper), admission passes run on the device, and waiters block on a
 // condition variable that every pass signals (the role of the user signal).
+// The host side of the state is one block (shared.h) that other processes
+// can map once the context is shared; they then open the device arrays
+// through HIP IPC handles and take the same lock.
+#include <fcntl.h>
 #include <signal.h>
+#include <sys/mman.h>
+#include <sys/stat.h>
+#include <time.h>
+#include <unistd.h>
+
 #include <cerrno>
 #include <algorithm>
 #include <chrono>
-#include <condition_variable>
+#include <climits>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <mutex>
-#include <unordered_map>
 #include <vector>
 
 #include "admission.h"
@@ -27,6 +36,171 @@ using namespace schedk;
 void sched_note_hip_error(hipError_t e, const char *what, const char *file, int line) {
   fprintf(stderr, "[sched] HIP error %d (%s) at %s:%d: %s\n", int(e), hipGetErrorString(e), file,
           line, what);
+}
+
+// ---------------------------------------------------------------------------
+// Host block (shared.h)
+// ---------------------------------------------------------------------------
+namespace {
+size_t up64(size_t x) { return (x + 63) / 64 * 64; }
+int64_t req_slots(int64_t q_cap) {
+  int64_t n = 1024;
+  while (n < 2 * q_cap && n < (int64_t(1) << 22)) n <<= 1;
+  return n;
+}
+}  // namespace
+
+size_t SharedHost::size_for(int32_t max_jobs, int64_t q_cap) {
+  size_t o = up64(sizeof(SharedHost));
+  o += 4 * up64(sizeof(int32_t) * size_t(max_jobs));  // prio, timeout, pending, owner
+  o += up64(sizeof(int32_t) * size_t(max_jobs));      // owned
+  o += up64(sizeof(SeqEntry) * size_t(req_slots(q_cap)));
+  return o;
+}
+
+SharedHost *SharedHost::init_at(void *zeroed, size_t bytes, int32_t max_jobs, int64_t q_cap,
+                                bool pshared) {
+  SharedHost *h = static_cast<SharedHost *>(zeroed);
+  h->magic = SHARED_MAGIC;
+  h->version = SHARED_VERSION;
+  h->bytes = bytes;
+  h->max_jobs = max_jobs;
+  h->q_capacity = q_cap;
+  size_t o = up64(sizeof(SharedHost));
+  const size_t arr = up64(sizeof(int32_t) * size_t(max_jobs));
+  h->off_prio = o;
+  h->off_timeout = o += arr;
+  h->off_pending = o += arr;
+  h->off_owner = o += arr;
+  h->off_owned = o += arr;
+  h->off_req = o += arr;
+  h->req_cap = req_slots(q_cap);
+  h->prio_lo = INT32_MAX;
+  h->prio_hi = INT32_MIN;
+  for (int32_t j = 0; j < max_jobs; ++j) h->timeout_ms()[j] = 60000;
+  init_sync(h, pshared);
+  return h;
+}
+
+void SharedHost::init_sync(SharedHost *h, bool pshared) {
+  pthread_mutexattr_t ma;
+  pthread_mutexattr_init(&ma);
+  pthread_mutexattr_setrobust(&ma, PTHREAD_MUTEX_ROBUST);
+  if (pshared) pthread_mutexattr_setpshared(&ma, PTHREAD_PROCESS_SHARED);
+  pthread_mutex_init(&h->mu, &ma);
+  pthread_mutexattr_destroy(&ma);
+  pthread_condattr_t ca;
+  pthread_condattr_init(&ca);
+  pthread_condattr_setclock(&ca, CLOCK_MONOTONIC);
+  if (pshared) pthread_condattr_setpshared(&ca, PTHREAD_PROCESS_SHARED);
+  pthread_cond_init(&h->cv, &ca);
+  pthread_condattr_destroy(&ca);
+}
+
+bool SharedHost::req_contains(int64_t seq) {
+  const SeqEntry *t = req();
+  const int64_t m = req_cap - 1;
+  for (int64_t i = seq & m, k = 0; k < req_cap; i = (i + 1) & m, ++k) {
+    if (t[i].key == 0) return false;
+    if (t[i].key == seq + 1) return true;
+  }
+  return false;
+}
+
+bool SharedHost::req_put(int64_t seq, int32_t job) {
+  if (4 * (req_used + 1) > 3 * req_cap) req_rebuild();
+  if (4 * (req_used + 1) > 3 * req_cap) return false;
+  SeqEntry *t = req();
+  const int64_t m = req_cap - 1;
+  int64_t i = seq & m;
+  while (t[i].key > 0) i = (i + 1) & m;
+  if (t[i].key == 0) ++req_used;
+  t[i].key = seq + 1;
+  t[i].job = job;
+  ++req_live;
+  return true;
+}
+
+bool SharedHost::req_take(int64_t seq, int32_t *job) {
+  SeqEntry *t = req();
+  const int64_t m = req_cap - 1;
+  for (int64_t i = seq & m, k = 0; k < req_cap; i = (i + 1) & m, ++k) {
+    if (t[i].key == 0) return false;
+    if (t[i].key == seq + 1) {
+      *job = t[i].job;
+      t[i].key = -1;
+      --req_live;
+      return true;
+    }
+  }
+  return false;
+}
+
+void SharedHost::req_erase_job(int32_t job) {
+  SeqEntry *t = req();
+  for (int64_t i = 0; i < req_cap; ++i)
+    if (t[i].key > 0 && t[i].job == job) {
+      t[i].key = -1;
+      --req_live;
+    }
+}
+
+void SharedHost::req_clear() {
+  if (req_used) memset(req(), 0, sizeof(SeqEntry) * size_t(req_cap));
+  req_live = req_used = 0;
+}
+
+void SharedHost::req_rebuild() {
+  std::vector<SeqEntry> live;
+  live.reserve(size_t(req_live));
+  req_for_each([&](int64_t seq, int32_t job) { live.push_back(SeqEntry{seq, job, 0}); });
+  req_clear();
+  for (const SeqEntry &e : live) req_put(e.key, e.job);
+}
+
+// ---- the context lock -------------------------------------------------------
+namespace {
+void mutex_acquire(pthread_mutex_t *m) {
+  if (pthread_mutex_lock(m) == EOWNERDEAD) pthread_mutex_consistent(m);  // holder died
+}
+}  // namespace
+
+void CtxLock::enter() {
+  c_->eng.launch = c_->sh->eng_launch;
+  c_->eng.epoch = c_->sh->eng_epoch;
+}
+
+void CtxLock::leave() {
+  c_->sh->eng_launch = c_->eng.launch;
+  c_->sh->eng_epoch = c_->eng.epoch;
+  if (c_->shared()) (void)hipStreamSynchronize(c_->stream);
+}
+
+void CtxLock::lock() {
+  mutex_acquire(&c_->sh->mu);
+  enter();
+}
+
+void CtxLock::unlock() {
+  leave();
+  pthread_mutex_unlock(&c_->sh->mu);
+}
+
+void CtxCond::notify_all() { pthread_cond_broadcast(&c_->sh->cv); }
+
+void CtxCond::wait_until(std::unique_lock<CtxLock> &, std::chrono::steady_clock::time_point until) {
+  c_->mu.leave();
+  const auto left = until - std::chrono::steady_clock::now();
+  const int64_t ns =
+      std::max<int64_t>(0, std::chrono::duration_cast<std::chrono::nanoseconds>(left).count());
+  timespec ts;
+  clock_gettime(CLOCK_MONOTONIC, &ts);
+  const int64_t t = int64_t(ts.tv_nsec) + ns % 1000000000;
+  ts.tv_sec += time_t(ns / 1000000000 + t / 1000000000);
+  ts.tv_nsec = long(t % 1000000000);
+  if (pthread_cond_timedwait(&c_->sh->cv, &c_->sh->mu, &ts) == EOWNERDEAD)
+    pthread_mutex_consistent(&c_->sh->mu);
+  c_->mu.enter();
 }
 
 namespace {
@@ -71,6 +245,16 @@ int64_t pow2_at_least(int64_t x) {
 
 sched_ctx::~sched_ctx() {}
 
+// Staging every process keeps for itself.
+static int ctx_alloc_private(sched_ctx *c) {
+  SCHED_HIP_TRY(hipMalloc(&c->d_scratch, 4096));
+  SCHED_HIP_TRY(hipHostMalloc(&c->h_stage, 4096, hipHostMallocDefault));
+  c->h_adm_cap = 1 << 16;
+  SCHED_HIP_TRY(hipHostMalloc(&c->h_adm_job, sizeof(int32_t) * c->h_adm_cap, hipHostMallocDefault));
+  SCHED_HIP_TRY(hipHostMalloc(&c->h_adm_seq, sizeof(int64_t) * c->h_adm_cap, hipHostMallocDefault));
+  return SCHED_OK;
+}
+
 static int ctx_alloc(sched_ctx *c) {
   const int64_t Q = c->q.capacity;
   const int32_t J = c->jb.max_jobs;
@@ -91,15 +275,38 @@ static int ctx_alloc(sched_ctx *c) {
   SCHED_HIP_TRY(hipMemset(c->d_prio_of_job, 0, sizeof(int32_t) * J));
   // running jobs at the start of a chain (<= J) plus its admissions (<= Q)
   SCHED_HIP_TRY(hipMalloc(&c->d_run_list, sizeof(int32_t) * (int64_t(J) + Q)));
-  SCHED_HIP_TRY(hipMalloc(&c->d_scratch, 4096));
-  SCHED_HIP_TRY(hipHostMalloc(&c->h_stage, 4096, hipHostMallocDefault));
-  c->h_adm_cap = 1 << 16;
-  SCHED_HIP_TRY(hipHostMalloc(&c->h_adm_job, sizeof(int32_t) * c->h_adm_cap, hipHostMallocDefault));
-  SCHED_HIP_TRY(hipHostMalloc(&c->h_adm_seq, sizeof(int64_t) * c->h_adm_cap, hipHostMallocDefault));
-  return SCHED_OK;
+  return ctx_alloc_private(c);
+}
+
+// The device arrays another process opens through IPC, in IpcArr order.
+static void **shared_arrays(sched_ctx *c, void **out[IPC_N]) {
+  out[IPC_DEMAND] = (void **)&c->q.demand;
+  out[IPC_JOB] = (void **)&c->q.job;
+  out[IPC_PRIO] = (void **)&c->q.prio;
+  out[IPC_SEQ] = (void **)&c->q.seq;
+  out[IPC_DECISION] = (void **)&c->q.decision;
+  out[IPC_ADM_JOB] = (void **)&c->q.adm_job;
+  out[IPC_ADM_DEMAND] = (void **)&c->q.adm_demand;
+  out[IPC_ADM_SEQ] = (void **)&c->q.adm_seq;
+  out[IPC_RES] = (void **)&c->jb.res;
+  out[IPC_STATE] = (void **)&c->jb.state;
+  out[IPC_PRIO_OF_JOB] = (void **)&c->d_prio_of_job;
+  out[IPC_RUN_LIST] = (void **)&c->d_run_list;
+  out[IPC_CTL] = (void **)&c->eng.d_ctl;
+  out[IPC_FLAGS] = (void **)&c->eng.d_flags;
+  return out[0];
 }
 
 static void ctx_free(sched_ctx *c) {
+  if (c->attached) {  // arrays opened through IPC are closed, not freed
+    void **arr[IPC_N];
+    shared_arrays(c, arr);
+    for (int k = 0; k < IPC_N; ++k)
+      if (*arr[k]) {
+        (void)hipIpcCloseMemHandle(*arr[k]);
+        *arr[k] = nullptr;
+      }
+  }
   void *dev[] = {c->q.demand, c->q.job, c->q.prio, c->q.seq, c->q.decision, c->q.adm_job,
                  c->q.adm_demand, c->q.adm_seq, c->jb.res, c->jb.state, c->d_prio_of_job,
                  c->d_scratch, c->prio_tmp, c->d_run_list};
@@ -111,6 +318,15 @@ static void ctx_free(sched_ctx *c) {
   adm_engine_free(c->eng);
   sched_slab_free(c);
   if (c->stream) (void)hipStreamDestroy(c->stream);
+  if (c->shm_map) {
+    (void)munmap(c->shm_map, c->shm_bytes);
+    if (!c->shm_name.empty()) (void)shm_unlink(c->shm_name.c_str());
+  } else if (c->sh) {
+    pthread_mutex_destroy(&c->sh->mu);
+    pthread_cond_destroy(&c->sh->cv);
+    free(c->sh);
+  }
+  c->sh = nullptr;
 }
 
 extern "C" int sched_create(const sched_config_t *cfg, sched_ctx_t **out) {
@@ -139,10 +355,13 @@ extern "C" int sched_create(const sched_config_t *cfg, sched_ctx_t **out) {
   c->window_limit = cfg->window_limit > 0 ? cfg->window_limit : 64;
   c->q.capacity = pow2_at_least(std::max<int64_t>(cfg->queue_capacity, WIN));
   c->jb.max_jobs = cfg->max_jobs;
-  c->prio.assign(cfg->max_jobs, 0);
-  c->timeout_ms.assign(cfg->max_jobs, 60000);
-  c->pending.assign(cfg->max_jobs, 0);
-  c->owner.assign(cfg->max_jobs, 0);
+  const size_t hb = SharedHost::size_for(cfg->max_jobs, c->q.capacity);
+  void *mem = calloc(1, hb);
+  if (!mem) {
+    delete c;
+    return SCHED_E_INTERNAL;
+  }
+  c->sh = SharedHost::init_at(mem, hb, cfg->max_jobs, c->q.capacity, false);
   int rc = SCHED_OK;
   if (hipStreamCreate(&c->stream) != hipSuccess) rc = SCHED_E_INTERNAL;
   if (rc == SCHED_OK) rc = ctx_alloc(c);
@@ -164,6 +383,13 @@ extern "C" int sched_create(const sched_config_t *cfg, sched_ctx_t **out) {
     delete c;
     return rc;
   }
+  c->sh->device = c->device;
+  c->sh->policy = c->policy;
+  c->sh->window_limit = c->window_limit;
+  c->sh->capacity = capacity;
+  c->sh->max_tiles = c->eng.max_tiles;
+  c->sh->eng_launch = c->eng.launch;
+  c->sh->eng_epoch = c->eng.epoch;
   *out = c;
   return SCHED_OK;
 }
@@ -171,10 +397,14 @@ extern "C" int sched_create(const sched_config_t *cfg, sched_ctx_t **out) {
 extern "C" int sched_destroy(sched_ctx_t *c) {
   if (!c) return SCHED_E_INVALID;
   {
-    std::lock_guard<std::mutex> g(c->mu);
+    std::lock_guard<CtxLock> g(c->mu);
     (void)hipSetDevice(c->device);
     (void)hipStreamSynchronize(c->stream);
-    c->closing = true;
+    if (c->attached) {
+      c->sh->attached -= 1;  // a detach: the context goes on in the other processes
+    } else {
+      c->sh->closing = true;
+    }
   }
   c->cv.notify_all();
   ctx_free(c);
@@ -182,13 +412,145 @@ extern "C" int sched_destroy(sched_ctx_t *c) {
   return SCHED_OK;
 }
 
+// ---------------------------------------------------------------------------
+// Sharing between processes
+// ---------------------------------------------------------------------------
+extern "C" int sched_share(sched_ctx_t *c, const char *name) {
+  if (!c || !name || name[0] != '/' || strlen(name) > 200 || c->attached || c->shared() ||
+      c->slab)
+    return SCHED_E_INVALID;
+  SCHED_HIP_TRY(hipSetDevice(c->device));
+  SharedHost *old = c->sh;
+  mutex_acquire(&old->mu);
+  int rc = SCHED_OK;
+  if (!old->req_empty()) rc = SCHED_E_INVALID;  // no thread may wait on the private block
+  // every exported allocation stays below 2 GiB
+  const int64_t Q = c->q.capacity, J = c->jb.max_jobs;
+  const int64_t biggest =
+      std::max<int64_t>({8 * Q, 4 * (J + Q), 8 * int64_t(J), 8 * c->eng.max_tiles});
+  if (rc == SCHED_OK && biggest >= (int64_t(1) << 31)) rc = SCHED_E_INVALID;
+  int fd = -1;
+  void *map = MAP_FAILED;
+  if (rc == SCHED_OK) {
+    fd = shm_open(name, O_CREAT | O_EXCL | O_RDWR, 0600);
+    if (fd < 0 || ftruncate(fd, off_t(old->bytes)) != 0) rc = SCHED_E_INVALID;
+  }
+  if (rc == SCHED_OK) {
+    map = mmap(nullptr, old->bytes, PROT_READ | PROT_WRITE, MAP_SHARED, fd, 0);
+    if (map == MAP_FAILED) rc = SCHED_E_INTERNAL;
+  }
+  if (fd >= 0) close(fd);
+  if (rc == SCHED_OK) {
+    // the block as it stands, with a process-shared mutex and condition
+    memcpy(map, old, old->bytes);
+    SharedHost *h = static_cast<SharedHost *>(map);
+    memset(&h->mu, 0, sizeof(h->mu));
+    memset(&h->cv, 0, sizeof(h->cv));
+    SharedHost::init_sync(h, true);
+    h->eng_launch = c->eng.launch;
+    h->eng_epoch = c->eng.epoch;
+    h->owner_pid = int32_t(getpid());
+    if (hipDeviceGetPCIBusId(h->pci_bus_id, sizeof(h->pci_bus_id), c->device) != hipSuccess)
+      rc = SCHED_E_INTERNAL;
+    void **arr[IPC_N];
+    shared_arrays(c, arr);
+    for (int k = 0; k < IPC_N && rc == SCHED_OK; ++k)
+      if (hipIpcGetMemHandle(&h->ipc[k], *arr[k]) != hipSuccess) rc = SCHED_E_INTERNAL;
+    if (rc == SCHED_OK) {
+      h->shared = 1;
+      c->sh = h;
+      c->shm_map = map;
+      c->shm_bytes = old->bytes;
+      c->shm_name = name;
+    }
+  }
+  pthread_mutex_unlock(&old->mu);
+  if (rc == SCHED_OK) {
+    pthread_mutex_destroy(&old->mu);
+    pthread_cond_destroy(&old->cv);
+    free(old);
+  } else {
+    if (map != MAP_FAILED) (void)munmap(map, old->bytes);
+    (void)shm_unlink(name);
+  }
+  return rc;
+}
+
+extern "C" int sched_attach(const char *name, sched_ctx_t **out) {
+  if (!name || !out) return SCHED_E_INVALID;
+  const int fd = shm_open(name, O_RDWR, 0600);
+  if (fd < 0) return SCHED_E_INVALID;
+  struct stat st;
+  void *map = MAP_FAILED;
+  if (fstat(fd, &st) == 0 && size_t(st.st_size) >= sizeof(SharedHost))
+    map = mmap(nullptr, size_t(st.st_size), PROT_READ | PROT_WRITE, MAP_SHARED, fd, 0);
+  close(fd);
+  if (map == MAP_FAILED) return SCHED_E_INVALID;
+  SharedHost *h = static_cast<SharedHost *>(map);
+  if (h->magic != SHARED_MAGIC || h->version != SHARED_VERSION || !h->shared ||
+      h->bytes != size_t(st.st_size)) {
+    (void)munmap(map, size_t(st.st_size));
+    return SCHED_E_INVALID;
+  }
+  int dev = -1;
+  if (hipDeviceGetByPCIBusId(&dev, h->pci_bus_id) != hipSuccess || hipSetDevice(dev) != hipSuccess) {
+    (void)munmap(map, size_t(st.st_size));
+    return SCHED_E_INVALID;
+  }
+  sched_ctx *c = new sched_ctx();
+  c->sh = h;
+  c->attached = true;
+  c->shm_map = map;
+  c->shm_bytes = size_t(st.st_size);
+  c->device = dev;
+  c->capacity = h->capacity;
+  c->policy = h->policy;
+  c->window_limit = h->window_limit;
+  c->q.capacity = h->q_capacity;
+  c->jb.max_jobs = h->max_jobs;
+  c->cfg.device = dev;
+  c->cfg.policy = h->policy;
+  c->cfg.capacity_bytes = h->capacity;
+  c->cfg.max_jobs = h->max_jobs;
+  c->cfg.queue_capacity = h->q_capacity;
+  c->cfg.window_limit = h->window_limit;
+  int rc = SCHED_OK;
+  void **arr[IPC_N];
+  shared_arrays(c, arr);
+  for (int k = 0; k < IPC_N && rc == SCHED_OK; ++k)
+    if (hipIpcOpenMemHandle(arr[k], h->ipc[k], hipIpcMemLazyEnablePeerAccess) != hipSuccess) {
+      *arr[k] = nullptr;
+      rc = SCHED_E_INTERNAL;
+    }
+  if (rc == SCHED_OK && hipStreamCreate(&c->stream) != hipSuccess) rc = SCHED_E_INTERNAL;
+  if (rc == SCHED_OK) rc = ctx_alloc_private(c);
+  if (rc == SCHED_OK) rc = adm_engine_attach(c->eng, dev, c->eng.d_ctl, c->eng.d_flags, h->max_tiles);
+  if (rc == SCHED_OK &&
+      (c->policy == SCHED_POLICY_PRIO_FIFO || c->policy == SCHED_POLICY_PRIO_MMU))
+    rc = sched_priority_alloc(c);
+  if (rc != SCHED_OK) {
+    c->sh = nullptr;  // the block stays to the other processes
+    (void)munmap(map, c->shm_bytes);
+    c->shm_map = nullptr;
+    ctx_free(c);
+    delete c;
+    return rc;
+  }
+  {
+    std::lock_guard<CtxLock> g(c->mu);
+    h->attached += 1;
+  }
+  *out = c;
+  return SCHED_OK;
+}
+
 static int register_locked(sched_ctx *c, int32_t n, int32_t priority, int32_t timeout_ms,
                            sched_job_t *first) {
-  if (n <= 0 || c->n_jobs + int64_t(n) > c->jb.max_jobs) return SCHED_E_INVALID;
-  const int32_t j0 = c->n_jobs;
+  if (n <= 0 || c->sh->n_jobs + int64_t(n) > c->jb.max_jobs) return SCHED_E_INVALID;
+  const int32_t j0 = c->sh->n_jobs;
   for (int32_t i = 0; i < n; ++i) {
-    c->prio[j0 + i] = priority;
-    c->timeout_ms[j0 + i] = timeout_ms;
+    c->sh->prio()[j0 + i] = priority;
+    c->sh->timeout_ms()[j0 + i] = timeout_ms;
   }
   sched_priority_note(c, priority);
   SCHED_HIP_TRY(hipSetDevice(c->device));
@@ -197,7 +559,7 @@ static int register_locked(sched_ctx *c, int32_t n, int32_t priority, int32_t ti
   SCHED_HIP_TRY(hipMemcpyAsync(c->d_prio_of_job + j0, pr.data(), sizeof(int32_t) * n,
                                hipMemcpyHostToDevice, c->stream));
   SCHED_HIP_TRY(hipStreamSynchronize(c->stream));
-  c->n_jobs += n;
+  c->sh->n_jobs += n;
   *first = j0;
   return SCHED_OK;
 }
@@ -205,7 +567,7 @@ static int register_locked(sched_ctx *c, int32_t n, int32_t priority, int32_t ti
 extern "C" int sched_register(sched_ctx_t *c, int32_t priority, int32_t timeout_ms,
                               sched_job_t *out_job) {
   if (!c || !out_job) return SCHED_E_INVALID;
-  std::lock_guard<std::mutex> g(c->mu);
+  std::lock_guard<CtxLock> g(c->mu);
   if (int rc = sched_settle_reset_locked(c)) return rc;
   return register_locked(c, 1, priority, timeout_ms, out_job);
 }
@@ -213,7 +575,7 @@ extern "C" int sched_register(sched_ctx_t *c, int32_t priority, int32_t timeout_
 extern "C" int sched_register_batch(sched_ctx_t *c, int32_t n, int32_t priority,
                                     int32_t timeout_ms, sched_job_t *out_first) {
   if (!c || !out_first) return SCHED_E_INVALID;
-  std::lock_guard<std::mutex> g(c->mu);
+  std::lock_guard<CtxLock> g(c->mu);
   if (int rc = sched_settle_reset_locked(c)) return rc;
   return register_locked(c, n, priority, timeout_ms, out_first);
 }
@@ -221,19 +583,19 @@ extern "C" int sched_register_batch(sched_ctx_t *c, int32_t n, int32_t priority,
 // One admission pass + compaction + host bookkeeping.  Caller holds c->mu.
 int sched_run_pass_locked(sched_ctx *c, hipStream_t s, sched_pass_result_t *res) {
   auto t0 = std::chrono::steady_clock::now();
-  const int64_t head_before = c->head_h;
+  const int64_t head_before = c->sh->head_h;
   PassOut po{};
   const int pol = (c->policy == SCHED_POLICY_FIFO || c->policy == SCHED_POLICY_PRIO_FIFO) ? SCHED_POLICY_FIFO : SCHED_POLICY_MMU;
   if (c->policy == SCHED_POLICY_PRIO_FIFO || c->policy == SCHED_POLICY_PRIO_MMU) {
     if (int rc = sched_priority_reorder_locked(c, s)) return rc;
   }
-  if (int rc = adm_pass_ctx(c->eng, pol, c->q, c->jb, c->window_limit, c->tail_h - c->head_h, s,
+  if (int rc = adm_pass_ctx(c->eng, pol, c->q, c->jb, c->window_limit, c->sh->tail_h - c->sh->head_h, s,
                             &po))
     return rc;
   // read back the admitted list when host-side requests wait on it
   const int64_t A = po.admitted;
   const int64_t ncopy = std::min<int64_t>(A, c->h_adm_cap);
-  if (!c->host_seq.empty() && ncopy > 0) {
+  if (!c->sh->req_empty() && ncopy > 0) {
     SCHED_HIP_TRY(hipMemcpyAsync(c->h_adm_job, c->q.adm_job, sizeof(int32_t) * ncopy,
                                  hipMemcpyDeviceToHost, s));
     SCHED_HIP_TRY(hipMemcpyAsync(c->h_adm_seq, c->q.adm_seq, sizeof(int64_t) * ncopy,
@@ -241,7 +603,7 @@ int sched_run_pass_locked(sched_ctx *c, hipStream_t s, sched_pass_result_t *res)
     SCHED_HIP_TRY(hipStreamSynchronize(s));
   }
   c->last_admitted_seqs.clear();
-  if (!c->host_seq.empty()) {
+  if (!c->sh->req_empty()) {
     if (A > c->h_adm_cap) {
       // large admitted list: fetch it in full into a host vector
       std::vector<int32_t> jobs(A);
@@ -253,16 +615,16 @@ int sched_run_pass_locked(sched_ctx *c, hipStream_t s, sched_pass_result_t *res)
       for (int64_t i = 0; i < A; ++i) c->note_admitted(c->h_adm_seq[i]);
     }
   }
-  c->head_h = po.head;
-  c->tail_h = po.tail;
-  c->used_h = po.used;
-  c->last_A = A;
-  c->last_adm_off = 0;
-  c->stats.passes += 1;
-  c->stats.rounds += po.rounds;
-  c->stats.admitted += A;
+  c->sh->head_h = po.head;
+  c->sh->tail_h = po.tail;
+  c->sh->used_h = po.used;
+  c->sh->last_A = A;
+  c->sh->last_adm_off = 0;
+  c->sh->stats.passes += 1;
+  c->sh->stats.rounds += po.rounds;
+  c->sh->stats.admitted += A;
   auto t1 = std::chrono::steady_clock::now();
-  c->stats.last_pass_us_x1000 =
+  c->sh->stats.last_pass_us_x1000 =
       std::chrono::duration_cast<std::chrono::nanoseconds>(t1 - t0).count();
   if (res) {
     res->admitted = A;
@@ -273,40 +635,35 @@ int sched_run_pass_locked(sched_ctx *c, hipStream_t s, sched_pass_result_t *res)
     res->scanned = po.start_final - head_before;
     res->pending_after = po.tail - po.head;
     res->compacted = po.hi - head_before;
-    res->released = po.released_jobs - c->rel_jobs_seen;
-    res->released_bytes = po.released_bytes - c->rel_bytes_seen;
+    res->released = po.released_jobs - c->sh->rel_jobs_seen;
+    res->released_bytes = po.released_bytes - c->sh->rel_bytes_seen;
   }
-  c->rel_jobs_seen = po.released_jobs;
-  c->rel_bytes_seen = po.released_bytes;
+  c->sh->rel_jobs_seen = po.released_jobs;
+  c->sh->rel_bytes_seen = po.released_bytes;
   c->cv.notify_all();
   return SCHED_OK;
 }
 
 void sched_ctx::note_admitted(int64_t seq) {
-  auto it = host_seq.find(seq);
-  if (it == host_seq.end()) return;
-  const int32_t job = it->second;
-  host_seq.erase(it);
-  if (pending[job] > 0) pending[job] -= 1;
+  int32_t job = -1;
+  if (!sh->req_take(seq, &job)) return;
+  if (sh->pending()[job] > 0) sh->pending()[job] -= 1;
   last_admitted_seqs.push_back(seq);
 }
 
 static int withdraw_locked(sched_ctx *c, sched_job_t job) {
   unsigned long long *cnt = (unsigned long long *)c->d_scratch;
   SCHED_HIP_TRY(hipMemsetAsync(cnt, 0, sizeof(unsigned long long), c->stream));
-  const int64_t live = std::max<int64_t>(c->tail_h - c->head_h, 1);
+  const int64_t live = std::max<int64_t>(c->sh->tail_h - c->sh->head_h, 1);
   const int grid = int(std::min<int64_t>((live + 255) / 256, 1024));
   k_withdraw<<<grid, 256, 0, c->stream>>>(c->eng.d_ctl, c->q, job, (int64_t *)cnt);
   SCHED_HIP_TRY(hipGetLastError());
   unsigned long long n = 0;
   SCHED_HIP_TRY(hipMemcpyAsync(&n, cnt, sizeof(n), hipMemcpyDeviceToHost, c->stream));
   SCHED_HIP_TRY(hipStreamSynchronize(c->stream));
-  for (auto it = c->host_seq.begin(); it != c->host_seq.end();) {
-    if (it->second == job) it = c->host_seq.erase(it);
-    else ++it;
-  }
-  c->pending[job] = 0;
-  c->stats.withdrawn += int64_t(n);
+  c->sh->req_erase_job(job);
+  c->sh->pending()[job] = 0;
+  c->sh->stats.withdrawn += int64_t(n);
   return SCHED_OK;
 }
 
@@ -320,28 +677,28 @@ static bool pid_alive(int32_t pid) { return kill(pid, 0) == 0 || errno == EPERM;
 // when something was reclaimed).
 static int sanity_locked(sched_ctx *c, int64_t *out_jobs, int64_t *out_bytes) {
   int64_t nj = 0, nb = 0;
-  for (size_t k = 0; k < c->owned.size();) {
-    const int32_t j = c->owned[k];
-    if (c->owner[j] > 0 && pid_alive(c->owner[j])) {
+  int32_t *owned = c->sh->owned();
+  for (int32_t k = 0; k < c->sh->n_owned;) {
+    const int32_t j = owned[k];
+    if (c->sh->owner()[j] > 0 && pid_alive(c->sh->owner()[j])) {
       ++k;
       continue;
     }
-    if (c->owner[j] > 0) {
-      if (c->pending[j] > 0)
+    if (c->sh->owner()[j] > 0) {
+      if (c->sh->pending()[j] > 0)
         if (int rc = withdraw_locked(c, j)) return rc;
       int64_t res = 0;
       if (int rc = read_res(c, j, &res)) return rc;
       if (res > 0) {
         k_release_one<<<1, 1, 0, c->stream>>>(c->eng.d_ctl, c->jb, j, res);
         SCHED_HIP_TRY(hipGetLastError());
-        c->stats.released_bytes += res;
+        c->sh->stats.released_bytes += res;
         nb += res;
       }
-      c->owner[j] = 0;
+      c->sh->owner()[j] = 0;
       ++nj;
     }
-    c->owned[k] = c->owned.back();  // reclaimed now or cleared before
-    c->owned.pop_back();
+    owned[k] = owned[--c->sh->n_owned];  // reclaimed now or cleared before
   }
   if (nj) {
     if (int rc = sched_run_pass_locked(c, c->stream, nullptr)) return rc;
@@ -352,20 +709,20 @@ static int sanity_locked(sched_ctx *c, int64_t *out_jobs, int64_t *out_bytes) {
   return SCHED_OK;
 }
 
-static int wait_locked(sched_ctx *c, std::unique_lock<std::mutex> &lk, sched_job_t job,
+static int wait_locked(sched_ctx *c, std::unique_lock<CtxLock> &lk, sched_job_t job,
                        int32_t timeout_ms) {
-  if (timeout_ms < 0) timeout_ms = c->timeout_ms[job];
+  if (timeout_ms < 0) timeout_ms = c->sh->timeout_ms()[job];
   const auto deadline = std::chrono::steady_clock::now() + std::chrono::milliseconds(timeout_ms);
   // a blocked client checks every 50 ms that the holders are still alive
   const auto tick = std::chrono::milliseconds(50);
-  while (c->pending[job] > 0 && !c->closing) {
+  while (c->sh->pending()[job] > 0 && !c->sh->closing) {
     const auto now = std::chrono::steady_clock::now();
     if (now >= deadline) break;
     c->cv.wait_until(lk, std::min(deadline, now + tick));
-    if (c->pending[job] > 0 && !c->closing)
+    if (c->sh->pending()[job] > 0 && !c->sh->closing)
       if (int rc = sanity_locked(c, nullptr, nullptr)) return rc;
   }
-  if (c->pending[job] == 0) return SCHED_OK;
+  if (c->sh->pending()[job] == 0) return SCHED_OK;
   // timed out: withdraw under the mutex, so the request is either admitted
   // (by a pass that ran before this point) or withdrawn, never both
   if (int rc = withdraw_locked(c, job)) return rc;
@@ -375,11 +732,11 @@ static int wait_locked(sched_ctx *c, std::unique_lock<std::mutex> &lk, sched_job
 extern "C" int sched_admit(sched_ctx_t *c, sched_job_t job, int32_t device, int64_t bytes,
                            uint32_t flags) {
   if (!c) return SCHED_E_INVALID;
-  std::unique_lock<std::mutex> lk(c->mu);
+  std::unique_lock<CtxLock> lk(c->mu);
   if (int rc = sched_settle_reset_locked(c)) return rc;
-  if (job < 0 || job >= c->n_jobs || device != c->device || bytes <= 0) return SCHED_E_INVALID;
+  if (job < 0 || job >= c->sh->n_jobs || device != c->device || bytes <= 0) return SCHED_E_INVALID;
   if (bytes > c->capacity) return SCHED_E_TOOBIG;
-  if (c->tail_h - c->head_h + 1 > c->q.capacity) return SCHED_E_NOMEM;
+  if (c->sh->tail_h - c->sh->head_h + 1 > c->q.capacity) return SCHED_E_NOMEM;
   SCHED_HIP_TRY(hipSetDevice(c->device));
   // stage the request and append it at the queue tail
   int32_t *hj = (int32_t *)c->h_stage;
@@ -390,20 +747,20 @@ extern "C" int sched_admit(sched_ctx_t *c, sched_job_t job, int32_t device, int6
   int64_t *dd = (int64_t *)((char *)c->d_scratch + 512);
   SCHED_HIP_TRY(hipMemcpyAsync(dj, hj, sizeof(int32_t), hipMemcpyHostToDevice, c->stream));
   SCHED_HIP_TRY(hipMemcpyAsync(dd, hd, sizeof(int64_t), hipMemcpyHostToDevice, c->stream));
-  const int64_t seq = c->seq_next++;
-  if (int rc = adm_enqueue(c->eng, c->q, c->tail_h, 1, dj, dd, c->d_prio_of_job, seq, c->stream))
+  const int64_t seq = c->sh->seq_next++;
+  if (int rc = adm_enqueue(c->eng, c->q, c->sh->tail_h, 1, dj, dd, c->d_prio_of_job, seq, c->stream))
     return rc;
-  c->tail_h += 1;
-  c->host_seq[seq] = job;
-  c->pending[job] += 1;
+  c->sh->tail_h += 1;
+  if (!c->sh->req_put(seq, job)) return SCHED_E_NOMEM;
+  c->sh->pending()[job] += 1;
   if (int rc = sched_run_pass_locked(c, c->stream, nullptr)) return rc;
   // memory is insufficient: check whether the holders are still alive (a
   // reclaim runs a pass of its own)
-  if (c->host_seq.find(seq) != c->host_seq.end())
+  if (c->sh->req_contains(seq))
     if (int rc = sanity_locked(c, nullptr, nullptr)) return rc;
-  if (c->host_seq.find(seq) == c->host_seq.end()) {
+  if (!c->sh->req_contains(seq)) {
     // admitted in this pass; other requests of the job may still wait
-    if (c->pending[job] == 0 || (flags & SCHED_NONBLOCK)) return SCHED_OK;
+    if (c->sh->pending()[job] == 0 || (flags & SCHED_NONBLOCK)) return SCHED_OK;
   } else if (flags & SCHED_NONBLOCK) {
     return SCHED_NOT_READY;
   }
@@ -412,9 +769,9 @@ extern "C" int sched_admit(sched_ctx_t *c, sched_job_t job, int32_t device, int6
 
 extern "C" int sched_wait(sched_ctx_t *c, sched_job_t job, int32_t timeout_ms) {
   if (!c) return SCHED_E_INVALID;
-  std::unique_lock<std::mutex> lk(c->mu);
+  std::unique_lock<CtxLock> lk(c->mu);
   if (int rc = sched_settle_reset_locked(c)) return rc;
-  if (job < 0 || job >= c->n_jobs) return SCHED_E_INVALID;
+  if (job < 0 || job >= c->sh->n_jobs) return SCHED_E_INVALID;
   return wait_locked(c, lk, job, timeout_ms);
 }
 
@@ -428,9 +785,9 @@ static int read_res(sched_ctx *c, sched_job_t job, int64_t *v) {
 
 extern "C" int sched_release(sched_ctx_t *c, sched_job_t job, int32_t device, int64_t bytes) {
   if (!c) return SCHED_E_INVALID;
-  std::lock_guard<std::mutex> g(c->mu);
+  std::lock_guard<CtxLock> g(c->mu);
   if (int rc = sched_settle_reset_locked(c)) return rc;
-  if (job < 0 || job >= c->n_jobs || bytes < 0) return SCHED_E_INVALID;
+  if (job < 0 || job >= c->sh->n_jobs || bytes < 0) return SCHED_E_INVALID;
   if (device >= 0 && device != c->device) return SCHED_E_INVALID;
   SCHED_HIP_TRY(hipSetDevice(c->device));
   int64_t res = 0;
@@ -440,7 +797,7 @@ extern "C" int sched_release(sched_ctx_t *c, sched_job_t job, int32_t device, in
   if (amount > 0) {
     k_release_one<<<1, 1, 0, c->stream>>>(c->eng.d_ctl, c->jb, job, amount);
     SCHED_HIP_TRY(hipGetLastError());
-    c->stats.released_bytes += amount;
+    c->sh->stats.released_bytes += amount;
   }
   if (int rc = sched_run_pass_locked(c, c->stream, nullptr)) return rc;
   // releasing everything is the client's shutdown (Sec. IV): check the other
@@ -450,17 +807,17 @@ extern "C" int sched_release(sched_ctx_t *c, sched_job_t job, int32_t device, in
 
 extern "C" int sched_set_owner(sched_ctx_t *c, sched_job_t job, int32_t pid) {
   if (!c) return SCHED_E_INVALID;
-  std::lock_guard<std::mutex> g(c->mu);
-  if (job < 0 || job >= c->n_jobs || pid < 0) return SCHED_E_INVALID;
-  if (pid > 0 && c->owner[job] == 0) c->owned.push_back(job);
-  c->owner[job] = pid;
+  std::lock_guard<CtxLock> g(c->mu);
+  if (job < 0 || job >= c->sh->n_jobs || pid < 0) return SCHED_E_INVALID;
+  if (pid > 0 && c->sh->owner()[job] == 0) c->sh->owned()[c->sh->n_owned++] = job;
+  c->sh->owner()[job] = pid;
   return SCHED_OK;
 }
 
 extern "C" int sched_sanity_check(sched_ctx_t *c, int64_t *reclaimed_jobs,
                                   int64_t *reclaimed_bytes) {
   if (!c) return SCHED_E_INVALID;
-  std::lock_guard<std::mutex> g(c->mu);
+  std::lock_guard<CtxLock> g(c->mu);
   if (int rc = sched_settle_reset_locked(c)) return rc;
   SCHED_HIP_TRY(hipSetDevice(c->device));
   return sanity_locked(c, reclaimed_jobs, reclaimed_bytes);
@@ -468,39 +825,39 @@ extern "C" int sched_sanity_check(sched_ctx_t *c, int64_t *reclaimed_jobs,
 
 extern "C" int sched_reservation(sched_ctx_t *c, sched_job_t job, int64_t *out) {
   if (!c || !out) return SCHED_E_INVALID;
-  std::lock_guard<std::mutex> g(c->mu);
+  std::lock_guard<CtxLock> g(c->mu);
   if (int rc = sched_settle_reset_locked(c)) return rc;
-  if (job < 0 || job >= c->n_jobs) return SCHED_E_INVALID;
+  if (job < 0 || job >= c->sh->n_jobs) return SCHED_E_INVALID;
   SCHED_HIP_TRY(hipSetDevice(c->device));
   return read_res(c, job, out);
 }
 
 extern "C" int sched_stats(sched_ctx_t *c, sched_stats_t *out) {
   if (!c || !out) return SCHED_E_INVALID;
-  std::lock_guard<std::mutex> g(c->mu);
+  std::lock_guard<CtxLock> g(c->mu);
   if (int rc = sched_settle_reset_locked(c)) return rc;
   SCHED_HIP_TRY(hipSetDevice(c->device));
   SCHED_HIP_TRY(hipMemcpyAsync(c->eng.h_ctl, c->eng.d_ctl, sizeof(DevCtl), hipMemcpyDeviceToHost,
                                c->stream));
   SCHED_HIP_TRY(hipStreamSynchronize(c->stream));
   const DevCtl &h = *c->eng.h_ctl;
-  sched_stats_t s = c->stats;
+  sched_stats_t s = c->sh->stats;
   s.capacity = c->capacity;
   s.used = h.used;
   s.pending = h.tail - h.head;
   s.released_bytes = h.released_bytes;
   int64_t running = 0;
   {
-    std::vector<int32_t> st(c->n_jobs);
-    if (c->n_jobs) {
-      SCHED_HIP_TRY(hipMemcpy(st.data(), c->jb.state, sizeof(int32_t) * c->n_jobs,
+    std::vector<int32_t> st(c->sh->n_jobs);
+    if (c->sh->n_jobs) {
+      SCHED_HIP_TRY(hipMemcpy(st.data(), c->jb.state, sizeof(int32_t) * c->sh->n_jobs,
                               hipMemcpyDeviceToHost));
     }
     for (int32_t v : st) running += v != 0;
   }
   s.running = running;
   s.slab_pool_used = sched_slab_pool_used(c);
-  s.violations = c->stats.violations;
+  s.violations = c->sh->stats.violations;
   *out = s;
   return SCHED_OK;
 }
@@ -528,26 +885,26 @@ static int pick_ordered(sched_ctx *c, sched_stream_t s, hipStream_t *out) {
 extern "C" int sched_enqueue_batch(sched_ctx_t *c, int64_t n, const int32_t *d_job,
                                    const int64_t *d_demand, sched_stream_t stream) {
   if (!c || n < 0 || (n > 0 && (!d_job || !d_demand))) return SCHED_E_INVALID;
-  std::lock_guard<std::mutex> g(c->mu);
+  std::lock_guard<CtxLock> g(c->mu);
   if (n == 0) return SCHED_OK;
-  if (c->tail_h - c->head_h + n > c->q.capacity) return SCHED_E_INVALID;
+  if (c->sh->tail_h - c->sh->head_h + n > c->q.capacity) return SCHED_E_INVALID;
   SCHED_HIP_TRY(hipSetDevice(c->device));
   hipStream_t s;
   if (int rc = pick_ordered(c, stream, &s)) return rc;
   int64_t n_bad = 0;
-  if (int rc = adm_enqueue_checked(c->eng, c->q, c->tail_h, n, d_job, d_demand, c->d_prio_of_job,
-                                   c->seq_next, c->n_jobs, c->capacity, s, &n_bad))
+  if (int rc = adm_enqueue_checked(c->eng, c->q, c->sh->tail_h, n, d_job, d_demand, c->d_prio_of_job,
+                                   c->sh->seq_next, c->sh->n_jobs, c->capacity, s, &n_bad))
     return rc;
   if (s == c->stream) c->reset_pending = false;  // the intake synchronised the stream
   if (n_bad) return SCHED_E_INVALID;
-  c->seq_next += n;
-  c->tail_h += n;
+  c->sh->seq_next += n;
+  c->sh->tail_h += n;
   return SCHED_OK;
 }
 
 extern "C" int sched_pass(sched_ctx_t *c, sched_stream_t stream, sched_pass_result_t *out) {
   if (!c) return SCHED_E_INVALID;
-  std::lock_guard<std::mutex> g(c->mu);
+  std::lock_guard<CtxLock> g(c->mu);
   SCHED_HIP_TRY(hipSetDevice(c->device));
   sched_pass_result_t r{};
   hipStream_t s;
@@ -560,15 +917,15 @@ extern "C" int sched_pass(sched_ctx_t *c, sched_stream_t stream, sched_pass_resu
 extern "C" int sched_last_admitted(sched_ctx_t *c, int32_t *d_out, int64_t cap, int64_t *out_n,
                                    sched_stream_t stream) {
   if (!c || !out_n || cap < 0 || (cap > 0 && !d_out)) return SCHED_E_INVALID;
-  std::lock_guard<std::mutex> g(c->mu);
+  std::lock_guard<CtxLock> g(c->mu);
   SCHED_HIP_TRY(hipSetDevice(c->device));
-  const int64_t n = std::min<int64_t>(cap, c->last_A);
+  const int64_t n = std::min<int64_t>(cap, c->sh->last_A);
   hipStream_t s;
   if (int rc = pick_ordered(c, stream, &s)) return rc;
   if (n > 0)
-    SCHED_HIP_TRY(hipMemcpyAsync(d_out, c->q.adm_job + c->last_adm_off, sizeof(int32_t) * n,
+    SCHED_HIP_TRY(hipMemcpyAsync(d_out, c->q.adm_job + c->sh->last_adm_off, sizeof(int32_t) * n,
                                  hipMemcpyDeviceToDevice, s));
-  *out_n = c->last_A;
+  *out_n = c->sh->last_A;
   return SCHED_OK;
 }
 
@@ -577,16 +934,16 @@ extern "C" int sched_pass_chain(sched_ctx_t *c, int32_t rounds, const uint8_t *d
                                 int32_t *d_admitted, int64_t cap) {
   if (!c || rounds <= 0 || rounds > MAX_CHAIN || n_mask < 0 || (rounds > 1 && n_mask > 0 && !d_masks))
     return SCHED_E_INVALID;
-  if (cap < 0 || (cap > 0 && !d_admitted)) return SCHED_E_INVALID;
-  std::lock_guard<std::mutex> g(c->mu);
-  if (n_mask > c->n_jobs || !c->host_seq.empty()) return SCHED_E_INVALID;
+  if (cap < 0 || (cap > 0 && !d_admitted) || c->shared()) return SCHED_E_INVALID;
+  std::lock_guard<CtxLock> g(c->mu);
+  if (n_mask > c->sh->n_jobs || !c->sh->req_empty()) return SCHED_E_INVALID;
   if (c->policy != SCHED_POLICY_FIFO && c->policy != SCHED_POLICY_MMU) return SCHED_E_INVALID;
   SCHED_HIP_TRY(hipSetDevice(c->device));
   hipStream_t s;
   if (int rc = pick_ordered(c, stream, &s)) return rc;
   if (int rc = adm_chain(c->eng, c->policy, c->q, c->jb, rounds, d_masks, n_mask, c->d_run_list, s))
     return rc;
-  int64_t head_before = c->head_h, total = 0;
+  int64_t head_before = c->sh->head_h, total = 0;
   for (int r = 0; r < rounds; ++r) {
     const PassSummary &h = c->eng.h_sum[r];
     if (out) {
@@ -599,24 +956,24 @@ extern "C" int sched_pass_chain(sched_ctx_t *c, int32_t rounds, const uint8_t *d
       o.scanned = h.start_final - head_before;
       o.pending_after = h.tail - h.head;
       o.compacted = h.hi - head_before;
-      o.released = h.released_jobs - c->rel_jobs_seen;
-      o.released_bytes = h.released_bytes - c->rel_bytes_seen;
+      o.released = h.released_jobs - c->sh->rel_jobs_seen;
+      o.released_bytes = h.released_bytes - c->sh->rel_bytes_seen;
     }
-    c->rel_jobs_seen = h.released_jobs;
-    c->rel_bytes_seen = h.released_bytes;
+    c->sh->rel_jobs_seen = h.released_jobs;
+    c->sh->rel_bytes_seen = h.released_bytes;
     head_before = h.head;
     total += h.admitted;
-    c->stats.passes += 1;
-    c->stats.rounds += h.rounds;
-    c->stats.admitted += h.admitted;
+    c->sh->stats.passes += 1;
+    c->sh->stats.rounds += h.rounds;
+    c->sh->stats.admitted += h.admitted;
   }
   if (s == c->stream) c->reset_pending = false;  // the chain synchronised the stream
   const PassSummary &last = c->eng.h_sum[rounds - 1];
-  c->head_h = last.head;
-  c->tail_h = last.tail;
-  c->used_h = last.used;
-  c->last_A = last.admitted;
-  c->last_adm_off = last.adm_base - last.admitted;
+  c->sh->head_h = last.head;
+  c->sh->tail_h = last.tail;
+  c->sh->used_h = last.used;
+  c->sh->last_A = last.admitted;
+  c->sh->last_adm_off = last.adm_base - last.admitted;
   if (cap > 0 && total > 0)
     SCHED_HIP_TRY(hipMemcpyAsync(d_admitted, c->q.adm_job, sizeof(int32_t) * std::min(cap, total),
                                  hipMemcpyDeviceToDevice, s));
@@ -626,8 +983,8 @@ extern "C" int sched_pass_chain(sched_ctx_t *c, int32_t rounds, const uint8_t *d
 extern "C" int sched_release_masked(sched_ctx_t *c, const uint8_t *d_mask, int64_t n,
                                     sched_stream_t stream) {
   if (!c || n < 0 || (n > 0 && !d_mask)) return SCHED_E_INVALID;
-  std::lock_guard<std::mutex> g(c->mu);
-  if (n > c->n_jobs) return SCHED_E_INVALID;
+  std::lock_guard<CtxLock> g(c->mu);
+  if (n > c->sh->n_jobs) return SCHED_E_INVALID;
   SCHED_HIP_TRY(hipSetDevice(c->device));
   hipStream_t s;
   if (int rc = pick_ordered(c, stream, &s)) return rc;
@@ -807,8 +1164,8 @@ __global__ void k_reset_jobs(DevCtl *c, JobArrays jb, uint8_t *decision, int64_t
 }
 
 extern "C" int sched_reset(sched_ctx_t *c) {
-  if (!c) return SCHED_E_INVALID;
-  std::lock_guard<std::mutex> g(c->mu);
+  if (!c || c->shared()) return SCHED_E_INVALID;
+  std::lock_guard<CtxLock> g(c->mu);
   SCHED_HIP_TRY(hipSetDevice(c->device));
   {
     const int64_t items = std::max<int64_t>(c->jb.max_jobs, c->q.capacity / 16);
@@ -818,13 +1175,13 @@ extern "C" int sched_reset(sched_ctx_t *c) {
   SCHED_HIP_TRY(hipGetLastError());
   c->reset_pending = true;
   // pending[j] counts the host-side waiting requests of job j, which are
-  // exactly the entries of host_seq naming j
-  for (const auto &kv : c->host_seq) c->pending[kv.second] = 0;
-  c->host_seq.clear();
-  c->head_h = c->tail_h = c->used_h = 0;
-  c->prio_sorted_tail = 0;  // an empty queue is ordered
-  c->last_A = 0;
-  c->rel_jobs_seen = c->rel_bytes_seen = 0;
+  // exactly the entries of the request table naming j
+  c->sh->req_for_each([&](int64_t, int32_t j) { c->sh->pending()[j] = 0; });
+  c->sh->req_clear();
+  c->sh->head_h = c->sh->tail_h = c->sh->used_h = 0;
+  c->sh->prio_sorted_tail = 0;  // an empty queue is ordered
+  c->sh->last_A = 0;
+  c->sh->rel_jobs_seen = c->sh->rel_bytes_seen = 0;
   c->cv.notify_all();
   return SCHED_OK;
 }
@@ -943,8 +1300,8 @@ bool ckpt_parse(const unsigned char *in, size_t bytes, int32_t max_jobs, CkptHea
 }  // namespace
 
 extern "C" int sched_checkpoint(sched_ctx_t *c, void *buf, size_t cap, size_t *out_bytes) {
-  if (!c || !out_bytes) return SCHED_E_INVALID;
-  std::lock_guard<std::mutex> g(c->mu);
+  if (!c || !out_bytes || c->shared()) return SCHED_E_INVALID;
+  std::lock_guard<CtxLock> g(c->mu);
   if (int rc = sched_settle_reset_locked(c)) return rc;
   SCHED_HIP_TRY(hipSetDevice(c->device));
   SCHED_HIP_TRY(hipMemcpyAsync(c->eng.h_ctl, c->eng.d_ctl, sizeof(DevCtl), hipMemcpyDeviceToHost,
@@ -953,16 +1310,16 @@ extern "C" int sched_checkpoint(sched_ctx_t *c, void *buf, size_t cap, size_t *o
   const int64_t head = c->eng.h_ctl->head, tail = c->eng.h_ctl->tail, used = c->eng.h_ctl->used;
   const int64_t live = tail - head;
   if (live < 0 || live > c->q.capacity) return SCHED_E_INTERNAL;
-  const size_t bound = sizeof(CkptHeader) + sizeof(CkptJob) * size_t(c->n_jobs) +
+  const size_t bound = sizeof(CkptHeader) + sizeof(CkptJob) * size_t(c->sh->n_jobs) +
                        sizeof(CkptReq) * size_t(live);
   if (!buf) {  // size query: an upper bound (withdrawn entries are dropped)
     *out_bytes = bound;
     return SCHED_OK;
   }
-  std::vector<int64_t> res(c->n_jobs), dem(live), seq(live);
+  std::vector<int64_t> res(c->sh->n_jobs), dem(live), seq(live);
   std::vector<int32_t> job(live), pri(live);
-  if (c->n_jobs)
-    SCHED_HIP_TRY(hipMemcpy(res.data(), c->jb.res, sizeof(int64_t) * c->n_jobs,
+  if (c->sh->n_jobs)
+    SCHED_HIP_TRY(hipMemcpy(res.data(), c->jb.res, sizeof(int64_t) * c->sh->n_jobs,
                             hipMemcpyDeviceToHost));
   // the live ring range in at most two pieces
   const int64_t Q = c->q.capacity;
@@ -991,7 +1348,7 @@ extern "C" int sched_checkpoint(sched_ctx_t *c, void *buf, size_t cap, size_t *o
     return seq[a] < seq[b];
   });
   const int64_t waiting = int64_t(order.size());
-  const size_t bytes = sizeof(CkptHeader) + sizeof(CkptJob) * size_t(c->n_jobs) +
+  const size_t bytes = sizeof(CkptHeader) + sizeof(CkptJob) * size_t(c->sh->n_jobs) +
                        sizeof(CkptReq) * size_t(waiting);
   if (cap < bytes) return SCHED_E_INVALID;
   unsigned char *out = static_cast<unsigned char *>(buf);
@@ -1001,11 +1358,11 @@ extern "C" int sched_checkpoint(sched_ctx_t *c, void *buf, size_t cap, size_t *o
   h.policy = c->policy;
   h.capacity = c->capacity;
   h.used = used;
-  h.n_jobs = c->n_jobs;
+  h.n_jobs = c->sh->n_jobs;
   h.n_pending = waiting;
   size_t at = sizeof h;
-  for (int32_t j = 0; j < c->n_jobs; ++j) {
-    const CkptJob r{c->prio[j], c->timeout_ms[j], c->owner[j], 0, res[j]};
+  for (int32_t j = 0; j < c->sh->n_jobs; ++j) {
+    const CkptJob r{c->sh->prio()[j], c->sh->timeout_ms()[j], c->sh->owner()[j], 0, res[j]};
     memcpy(out + at, &r, sizeof r);
     at += sizeof r;
   }
@@ -1027,8 +1384,8 @@ extern "C" int sched_checkpoint(sched_ctx_t *c, void *buf, size_t cap, size_t *o
 }
 
 extern "C" int sched_restore(sched_ctx_t *c, const void *buf, size_t bytes) {
-  if (!c || !buf) return SCHED_E_INVALID;
-  std::lock_guard<std::mutex> g(c->mu);
+  if (!c || !buf || c->shared()) return SCHED_E_INVALID;
+  std::lock_guard<CtxLock> g(c->mu);
   if (int rc = sched_settle_reset_locked(c)) return rc;
   CkptHeader h;
   std::vector<CkptJob> jobs;
@@ -1036,8 +1393,8 @@ extern "C" int sched_restore(sched_ctx_t *c, const void *buf, size_t bytes) {
   if (!ckpt_parse(static_cast<const unsigned char *>(buf), bytes, c->jb.max_jobs, &h, &jobs, &reqs))
     return SCHED_E_INVALID;
   // the target is a fresh context of the same pool and policy
-  if (h.policy != c->policy || h.capacity != c->capacity || c->n_jobs != 0 ||
-      c->tail_h != c->head_h || h.n_pending > c->q.capacity)
+  if (h.policy != c->policy || h.capacity != c->capacity || c->sh->n_jobs != 0 ||
+      c->sh->tail_h != c->sh->head_h || h.n_pending > c->q.capacity)
     return SCHED_E_INVALID;
   // apply: the jobs, their reservations, the used total, the waiting queue
   SCHED_HIP_TRY(hipSetDevice(c->device));
@@ -1078,28 +1435,28 @@ extern "C" int sched_restore(sched_ctx_t *c, const void *buf, size_t bytes) {
     if (hipGetLastError() != hipSuccess) rc = SCHED_E_INTERNAL;
   }
   if (rc == SCHED_OK && h.n_pending)
-    rc = adm_enqueue(c->eng, c->q, c->tail_h, h.n_pending, dj, dd, c->d_prio_of_job, c->seq_next,
+    rc = adm_enqueue(c->eng, c->q, c->sh->tail_h, h.n_pending, dj, dd, c->d_prio_of_job, c->sh->seq_next,
                      c->stream);
   if (rc == SCHED_OK && hipStreamSynchronize(c->stream) != hipSuccess) rc = SCHED_E_INTERNAL;
   if (dj) (void)hipFree(dj);
   if (dd) (void)hipFree(dd);
   if (rc) return rc;
   for (int32_t j = 0; j < h.n_jobs; ++j) {
-    c->prio[j] = jobs[j].prio;
+    c->sh->prio()[j] = jobs[j].prio;
     sched_priority_note(c, jobs[j].prio);
-    c->timeout_ms[j] = jobs[j].timeout_ms;
-    c->owner[j] = jobs[j].owner;
-    if (jobs[j].owner > 0) c->owned.push_back(j);
+    c->sh->timeout_ms()[j] = jobs[j].timeout_ms;
+    c->sh->owner()[j] = jobs[j].owner;
+    if (jobs[j].owner > 0) c->sh->owned()[c->sh->n_owned++] = j;
   }
-  c->n_jobs = h.n_jobs;
+  c->sh->n_jobs = h.n_jobs;
   // the restored requests wait like requests made here: sched_wait works on
   // them and the passes report their admission
   for (int64_t i = 0; i < h.n_pending; ++i) {
-    c->host_seq[c->seq_next + i] = qj[i];
-    c->pending[qj[i]] += 1;
+    if (!c->sh->req_put(c->sh->seq_next + i, qj[i])) return SCHED_E_NOMEM;
+    c->sh->pending()[qj[i]] += 1;
   }
-  c->seq_next += h.n_pending;
-  c->tail_h += h.n_pending;
-  c->used_h = h.used;
+  c->sh->seq_next += h.n_pending;
+  c->sh->tail_h += h.n_pending;
+  c->sh->used_h = h.used;
   return SCHED_OK;
 }

@@ -313,14 +313,14 @@ struct Serve {
   // Request intake: appends k staged (job, demand) pairs to the queue.
   int enqueue(int64_t k) {
     if (k == 0) return SCHED_OK;
-    if (c->tail_h - c->head_h + k > c->q.capacity) return SCHED_E_NOMEM;
+    if (c->sh->tail_h - c->sh->head_h + k > c->q.capacity) return SCHED_E_NOMEM;
     SCHED_HIP_TRY(hipMemcpyAsync(d_job, h_job, sizeof(int32_t) * k, hipMemcpyHostToDevice, stream_ctl));
     SCHED_HIP_TRY(hipMemcpyAsync(d_dem, h_dem, sizeof(int64_t) * k, hipMemcpyHostToDevice, stream_ctl));
-    if (int rc = adm_enqueue(c->eng, c->q, c->tail_h, k, d_job, d_dem, c->d_prio_of_job, c->seq_next,
+    if (int rc = adm_enqueue(c->eng, c->q, c->sh->tail_h, k, d_job, d_dem, c->d_prio_of_job, c->sh->seq_next,
                              stream_ctl))
       return rc;
-    c->seq_next += k;
-    c->tail_h += k;
+    c->sh->seq_next += k;
+    c->sh->tail_h += k;
     return SCHED_OK;
   }
 
@@ -346,7 +346,7 @@ struct Serve {
     }
     stage.used = 0;
     sum.passes += 1;
-    sum.peak_used = std::max<int64_t>(sum.peak_used, c->used_h);
+    sum.peak_used = std::max<int64_t>(sum.peak_used, c->sh->used_h);
     *n_adm = A;
     return SCHED_OK;
   }
@@ -858,8 +858,8 @@ struct Serve {
 extern "C" int sched_serve(sched_ctx_t *c, int64_t n, const sched_job_desc_t *jobs,
                            const sched_serve_opts_t *opts, sched_job_result_t *results,
                            sched_serve_summary_t *summary) {
-  if (!c || n < 0 || (n > 0 && (!jobs || !results)) || !opts) return SCHED_E_INVALID;
-  std::unique_lock<std::mutex> lk(c->mu);
+  if (!c || n < 0 || (n > 0 && (!jobs || !results)) || !opts || c->shared()) return SCHED_E_INVALID;
+  std::unique_lock<CtxLock> lk(c->mu);
   if (int rc = sched_settle_reset_locked(c)) return rc;
   if (n > c->jb.max_jobs || opts->max_placed < 0) return SCHED_E_INVALID;
   for (int64_t i = 0; i < n; ++i)
@@ -878,7 +878,7 @@ extern "C" int sched_serve(sched_ctx_t *c, int64_t n, const sched_job_desc_t *jo
   if (int rc = sched_reset(c)) return rc;
   lk.lock();
   // jobs 0..n-1 are the serving run's jobs (priorities are uploaded by init)
-  if (c->n_jobs < n) c->n_jobs = int32_t(n);
+  if (c->sh->n_jobs < n) c->sh->n_jobs = int32_t(n);
   for (int64_t i = 0; i < n; ++i) results[i] = sched_job_result_t{};
   Serve s{};
   s.sum.tuned_from_cache = -1;
@@ -893,7 +893,7 @@ extern "C" int sched_serve(sched_ctx_t *c, int64_t n, const sched_job_desc_t *jo
   s.summarize();
   s.sum.wall_s = s.host_now();
   s.fini();
-  c->stats.violations += s.sum.violations;
+  c->sh->stats.violations += s.sum.violations;
   if (summary) *summary = s.sum;
   return rc;
 }

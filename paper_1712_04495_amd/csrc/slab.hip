@@ -556,9 +556,9 @@ static int slab_charge_locked(sched_ctx *c, int32_t t, int64_t v, int8_t *st) {
 
 extern "C" int sched_alloc(sched_ctx_t *c, sched_job_t job, size_t bytes, void **dev_ptr) {
   if (!c || !dev_ptr) return SCHED_E_INVALID;
-  std::lock_guard<std::mutex> g(c->mu);
+  std::lock_guard<CtxLock> g(c->mu);
   if (int rc = sched_settle_reset_locked(c)) return rc;
-  if (!c->slab || job < 0 || job >= c->n_jobs || job >= c->slab->dev.n_tenants || bytes == 0)
+  if (!c->slab || job < 0 || job >= c->sh->n_jobs || job >= c->slab->dev.n_tenants || bytes == 0)
     return SCHED_E_INVALID;
   SCHED_HIP_TRY(hipSetDevice(c->device));
   SlabState *s = c->slab;
@@ -566,7 +566,7 @@ extern "C" int sched_alloc(sched_ctx_t *c, sched_job_t job, size_t bytes, void *
     uint64_t p = 0;
     int8_t st = 0;
     if (int rc = slab_one_locked(c, job, int64_t(bytes), 0, 0, &p, &st)) return rc;
-    if (st == ST_NOMEM_POOL || st == ST_NOMEM_CLASS) c->stats.violations += 1;
+    if (st == ST_NOMEM_POOL || st == ST_NOMEM_CLASS) c->sh->stats.violations += 1;
     if (st != ST_OK) return to_status_code(st);
     *dev_ptr = (void *)p;
     return SCHED_OK;
@@ -581,7 +581,7 @@ extern "C" int sched_alloc(sched_ctx_t *c, sched_job_t job, size_t bytes, void *
     (void)hipGetLastError();
     int8_t st2;
     (void)slab_charge_locked(c, job, -charged, &st2);
-    c->stats.violations += 1;
+    c->sh->stats.violations += 1;
     return SCHED_E_NOMEM;
   }
   s->large.push_back({p, charged});
@@ -592,9 +592,9 @@ extern "C" int sched_alloc(sched_ctx_t *c, sched_job_t job, size_t bytes, void *
 
 extern "C" int sched_free(sched_ctx_t *c, sched_job_t job, void *dev_ptr) {
   if (!c) return SCHED_E_INVALID;
-  std::lock_guard<std::mutex> g(c->mu);
+  std::lock_guard<CtxLock> g(c->mu);
   if (int rc = sched_settle_reset_locked(c)) return rc;
-  if (!c->slab || job < 0 || job >= c->n_jobs || job >= c->slab->dev.n_tenants || !dev_ptr)
+  if (!c->slab || job < 0 || job >= c->sh->n_jobs || job >= c->slab->dev.n_tenants || !dev_ptr)
     return SCHED_E_INVALID;
   SCHED_HIP_TRY(hipSetDevice(c->device));
   SlabState *s = c->slab;
@@ -619,7 +619,7 @@ extern "C" int sched_free(sched_ctx_t *c, sched_job_t job, void *dev_ptr) {
 
 extern "C" int sched_slab_set_quotas(sched_ctx_t *c, int32_t n, const int64_t *h_quotas) {
   if (!c || n < 0 || (n > 0 && !h_quotas)) return SCHED_E_INVALID;
-  std::lock_guard<std::mutex> g(c->mu);
+  std::lock_guard<CtxLock> g(c->mu);
   if (int rc = sched_settle_reset_locked(c)) return rc;
   if (!c->slab || n > c->slab->dev.n_tenants) return SCHED_E_INVALID;
   for (int32_t i = 0; i < n; ++i)
@@ -642,7 +642,7 @@ extern "C" int sched_slab_ops(sched_ctx_t *c, int64_t begin, int64_t end, const 
   if (!c || begin < 0 || end < begin) return SCHED_E_INVALID;
   if (end > begin && (!d_kind || !d_tenant || !d_size || !d_ref || !d_ptr || !d_status))
     return SCHED_E_INVALID;
-  std::lock_guard<std::mutex> g(c->mu);
+  std::lock_guard<CtxLock> g(c->mu);
   if (int rc = sched_settle_reset_locked(c)) return rc;
   if (!c->slab) return SCHED_E_INVALID;
   if (end == begin) return SCHED_OK;
@@ -668,7 +668,7 @@ extern "C" int sched_slab_ops(sched_ctx_t *c, int64_t begin, int64_t end, const 
 
 extern "C" int sched_slab_info(sched_ctx_t *c, sched_slab_info_t *out) {
   if (!c || !out) return SCHED_E_INVALID;
-  std::lock_guard<std::mutex> g(c->mu);
+  std::lock_guard<CtxLock> g(c->mu);
   if (int rc = sched_settle_reset_locked(c)) return rc;
   if (!c->slab) return SCHED_E_INVALID;
   const SlabDev &d = c->slab->dev;
@@ -686,7 +686,7 @@ extern "C" int sched_slab_info(sched_ctx_t *c, sched_slab_info_t *out) {
 extern "C" int sched_slab_counters(sched_ctx_t *c, int32_t n, int64_t *h_charged,
                                    int64_t *h_pool_used) {
   if (!c || n < 0 || (n > 0 && !h_charged) || !h_pool_used) return SCHED_E_INVALID;
-  std::lock_guard<std::mutex> g(c->mu);
+  std::lock_guard<CtxLock> g(c->mu);
   if (int rc = sched_settle_reset_locked(c)) return rc;
   if (!c->slab || n > c->slab->dev.n_tenants) return SCHED_E_INVALID;
   SCHED_HIP_TRY(hipSetDevice(c->device));
@@ -699,7 +699,7 @@ extern "C" int sched_slab_counters(sched_ctx_t *c, int32_t n, int64_t *h_charged
 
 extern "C" int sched_slab_reset(sched_ctx_t *c) {
   if (!c) return SCHED_E_INVALID;
-  std::lock_guard<std::mutex> g(c->mu);
+  std::lock_guard<CtxLock> g(c->mu);
   if (int rc = sched_settle_reset_locked(c)) return rc;
   if (!c->slab) return SCHED_E_INVALID;
   SCHED_HIP_TRY(hipSetDevice(c->device));
