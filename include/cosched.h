@@ -466,9 +466,12 @@ int sched_gemm_bf16(const uint16_t *A, const uint16_t *Bt, float *C, int64_t M, 
  * of the context (any of the four of Sec. V) admits it,
  * runs concurrently with the other admitted jobs, and returns its
  * reservation when it ends (post-free).  Jobs run on a pool of streams; with
- * batch_small, admitted triads under small_bytes are packed into one
- * persistent launch (a HIP graph replay when use_graph) whose block and
- * chunk shape come from an autotuner (cached in tune_cache when non-NULL).
+ * batch_small, admitted jobs of every kind under small_bytes are packed into
+ * one persistent batched launch (a HIP graph replay when use_graph): a
+ * streaming phase, then, when the batch holds histograms or GEMMs, a phase of
+ * key chunks and GEMM output tiles and a phase of digests.  Its block, chunk,
+ * workgroups per CU and GEMM tile edge come from an autotuner (cached in
+ * tune_cache when non-NULL).
  *
  * Memory: right after the pass that admits it, a job (or a batch of small
  * ones) is placed in a device page pool of 64 KiB pages: its buffers (each
@@ -529,7 +532,7 @@ typedef struct {
                           work; each job goes to the stream with the least
                           nominal work still in flight                        */
   int32_t serial;      /* 1: every demand := capacity (exclusive execution)   */
-  int32_t batch_small; /* 1: persistent batched launch for small triads        */
+  int32_t batch_small; /* 1: persistent batched launch for small jobs          */
   int64_t small_bytes; /* demand threshold for batching                       */
   int32_t iters;       /* triad sweeps per job                                 */
   int32_t digest;      /* 1: compute each job's output digest                  */
@@ -563,6 +566,9 @@ typedef struct {
   int64_t pages_left, charged_left; /* at the end: both 0                     */
   int64_t page_check;      /* free-list entries duplicated or out of range at
                               the end (0), -1 if placements were left          */
+  /* batching: the autotuned GEMM output tile edge (64 or 128) and workgroups
+   * per CU of the batch's tile phase */
+  int64_t tuned_gemm_tile, tuned_gemm_per_cu;
 } sched_serve_summary_t;
 
 /* Runs n jobs (jobs[i] is job handle i; the context needs max_jobs >= n and

@@ -83,7 +83,8 @@ class sched_serve_summary_t(C.Structure):
                                              "host_idle_s", "dev_busy_s")]
                 + [(n, i64) for n in ("tuned_from_cache", "slot_waits", "placements",
                                       "placement_slots", "pool_pages", "peak_pages", "pages_left",
-                                      "charged_left", "page_check")])
+                                      "charged_left", "page_check", "tuned_gemm_tile",
+                                      "tuned_gemm_per_cu")])
 
 
 SCHED_JOB_TRIAD = 0

@@ -661,7 +661,8 @@ static int withdraw_locked(sched_ctx *c, sched_job_t job) {
   unsigned long long n = 0;
   SCHED_HIP_TRY(hipMemcpyAsync(&n, cnt, sizeof(n), hipMemcpyDeviceToHost, c->stream));
   SCHED_HIP_TRY(hipStreamSynchronize(c->stream));
-  c->sh->req_erase_job(job);
+  // the table holds the job's waiting requests only if it counts some
+  if (c->sh->pending()[job] > 0) c->sh->req_erase_job(job);
   c->sh->pending()[job] = 0;
   c->sh->stats.withdrawn += int64_t(n);
   return SCHED_OK;
@@ -1175,8 +1176,10 @@ extern "C" int sched_reset(sched_ctx_t *c) {
   SCHED_HIP_TRY(hipGetLastError());
   c->reset_pending = true;
   // pending[j] counts the host-side waiting requests of job j, which are
-  // exactly the entries of the request table naming j
-  c->sh->req_for_each([&](int64_t, int32_t j) { c->sh->pending()[j] = 0; });
+  // exactly the entries of the request table naming j (a scan of the whole
+  // table, so only when it holds any)
+  if (!c->sh->req_empty())
+    c->sh->req_for_each([&](int64_t, int32_t j) { c->sh->pending()[j] = 0; });
   c->sh->req_clear();
   c->sh->head_h = c->sh->tail_h = c->sh->used_h = 0;
   c->sh->prio_sorted_tail = 0;  // an empty queue is ordered

@@ -271,6 +271,8 @@ struct Serve {
       sum.tuned_block = beng->block;
       sum.tuned_chunk = beng->chunk;
       sum.tuned_per_cu = beng->per_cu;
+      sum.tuned_gemm_tile = beng->tile;
+      sum.tuned_gemm_per_cu = beng->per_cu1;
       sum.tuned_from_cache = beng->from_cache ? 1 : 0;
     }
     SCHED_HIP_TRY(hipDeviceSynchronize());
@@ -436,7 +438,9 @@ struct Serve {
     return SCHED_OK;
   }
 
-  // Small triads admitted together: one placement, one persistent launch.
+  // Small jobs admitted together: one placement, one persistent batched
+  // launch.  GEMM jobs come first in the placement: each takes a whole number
+  // of pages, so all their arrays start at page boundaries.
   int launch_batch(const std::vector<int32_t> &jobs, int32_t slot, int64_t pages, Running *r) {
     r->job = -1;
     r->batch = int32_t(batch_jobs.size());
@@ -448,13 +452,36 @@ struct Serve {
     std::vector<BatchDesc> ds;
     ds.reserve(jobs.size());
     uint64_t base = 0;
-    for (int32_t j : jobs) {
-      const uint64_t arr = uint64_t(rup(4 * J[j].size, 4096));
-      ds.push_back(BatchDesc{base, base + arr, base + 2 * arr, J[j].size, J[j].seed, o.iters, 0,
-                             o.digest ? d_digest + j : nullptr});
-      res[j].batched = 1;
-      base += uint64_t(job_bytes(J[j]));
-    }
+    for (int pass = 0; pass < 2; ++pass)
+      for (int32_t j : jobs) {
+        const sched_job_desc_t &jd = J[j];
+        if ((jd.kind == SCHED_JOB_GEMM) != (pass == 0)) continue;
+        BatchDesc d{};
+        d.n = jd.size;
+        d.seed = jd.seed;
+        d.kind = jd.kind;
+        d.digest = o.digest ? d_digest + j : nullptr;
+        if (jd.kind == SCHED_JOB_TRIAD) {
+          const uint64_t arr = uint64_t(rup(4 * jd.size, 4096));
+          d.o0 = base;
+          d.o1 = base + arr;
+          d.o2 = base + 2 * arr;
+          d.iters = o.iters;
+        } else if (jd.kind == SCHED_JOB_HIST) {
+          d.o0 = base;
+          d.o1 = base + uint64_t(rup(4 * jd.size, 4096));
+        } else {
+          const uint64_t ab = uint64_t(rup(2 * jd.size * jd.size, 4096));
+          if (base % PG_BYTES || job_bytes(jd) % PG_BYTES) return SCHED_E_INTERNAL;
+          d.o0 = base;
+          d.o1 = base + ab;
+          d.o2 = base + 2 * ab;
+          d.samples = o.digest ? d_samples + int64_t(j) * GEMM_SAMPLES : nullptr;
+        }
+        ds.push_back(d);
+        res[j].batched = 1;
+        base += uint64_t(job_bytes(jd));
+      }
     // the pinned table is rewritten only when no batch is in flight
     if (int rc = batch_fill(*beng, ds, beng->chunk, pg_map(pt, slot, pages), pages)) return rc;
     if (int rc = batch_launch(*beng, bstream, o.use_graph != 0)) return rc;
@@ -529,7 +556,7 @@ struct Serve {
     for (int64_t i = 0; i < A; ++i) {
       const int32_t j = h_adm[i];
       res[j].t_admit = now;
-      if (beng && J[j].kind == SCHED_JOB_TRIAD && J[j].demand < o.small_bytes) {
+      if (beng && J[j].demand < o.small_bytes) {
         pending_small.push_back(j);
         continue;
       }

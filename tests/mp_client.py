@@ -27,6 +27,8 @@ def main():
             out = {"rc": cs.sched_wait(ctx, a[0], a[1])}
         elif op == "release":
             out = {"rc": cs.sched_release(ctx, a[0], -1, a[1])}
+        elif op == "own":
+            out = {"rc": cs.sched_set_owner(ctx, a[0], os.getpid())}
         elif op == "reservation":
             rc, v = cs.sched_reservation(ctx, a[0])
             out = {"rc": rc, "res": v}

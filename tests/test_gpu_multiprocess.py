@@ -128,3 +128,58 @@ def test_two_processes_share_one_context(cs, policy):
         cs.sched_destroy(ctx)
     # the name is gone with the context
     assert cs.sched_attach(name)[0] == cs.SCHED_E_INVALID
+
+
+@pytest.mark.parametrize("policy", [0, 1])
+def test_dead_client_is_reclaimed(cs, policy):
+    """A client process that holds reservations and has a request waiting is
+    killed (SIGKILL: it runs no clean-up).  The sanity check of the process
+    that shares the context finds its jobs' owner gone, withdraws the waiting
+    request, returns the reservations and admits the request that waited
+    behind them -- as the oracle's sanity check does (Sec. III-B, third
+    robustness feature; Sec. IV)."""
+    import signal
+    C = 10_000
+    name = f"/sched-dead-{os.getpid()}-{policy}"
+    rc, ctx = cs.sched_create(policy=policy, capacity_bytes=C, max_jobs=16, queue_capacity=4096)
+    assert rc == 0
+    child = None
+    dead = set()
+    ref = S.Scheduler(C, policy, alive=lambda pid: pid not in dead)
+    try:
+        assert cs.sched_share(ctx, name) == 0
+        child = Child(name)
+        assert child.hello["rc"] == 0
+        pid = child.hello["pid"]
+        held = []
+        for b, want in ((3000, S.OK), (4000, S.OK), (5000, S.NOT_READY)):
+            r = child.call("register 0 60000")
+            assert r["rc"] == 0 and r["job"] == ref.register(0, 60000)
+            j = r["job"]
+            held.append(j)
+            assert child.call(f"own {j}")["rc"] == 0 and ref.set_owner(j, pid) == 0
+            got = child.call(f"admit {j} {b} {cs.SCHED_NONBLOCK}")["rc"]
+            assert got == ref.admit(j, 0, b) == want
+        rc, k = cs.sched_register(ctx, 0, 60000)
+        assert rc == 0 and k == ref.register(0, 60000)
+        # does not fit beside the child's 7000 bytes; the child is alive
+        assert cs.sched_admit(ctx, k, 0, 6000, cs.SCHED_NONBLOCK) == ref.admit(k, 0, 6000) \
+            == cs.SCHED_NOT_READY
+        assert cs.sched_stats(ctx)[1]["used"] == ref.used == 7000
+        child.p.send_signal(signal.SIGKILL)
+        assert child.p.wait(timeout=60) == -signal.SIGKILL
+        dead.add(pid)
+        rc, nj, nb = cs.sched_sanity_check(ctx)
+        assert rc == 0 and (nj, nb) == ref.sanity(ref.alive) == (3, 7000)
+        for j in held + [k]:
+            assert cs.sched_reservation(ctx, j) == (0, ref.jobs[j]["res"])
+        assert ref.jobs[k]["res"] == 6000
+        assert cs.sched_wait(ctx, k, 0) == S.OK            # nothing of k waits
+        assert cs.sched_stats(ctx)[1]["used"] == ref.used == 6000
+        # a second check finds nothing more
+        assert cs.sched_sanity_check(ctx)[:3] == (0, 0, 0)
+    finally:
+        if child and child.p.poll() is None:
+            child.p.kill()
+            child.p.wait(timeout=60)
+        cs.sched_destroy(ctx)

@@ -305,3 +305,63 @@ def test_batched_equals_unbatched(cs, tmp_path):
     for i in check:
         assert int(batched["digest"][i]) == _digest_ref(KIND_TRIAD, int(mix.size[i]),
                                                         int(jt["seed"][i])), i
+
+
+def _small_mix(seed):
+    """Small jobs of all three kinds (every one under 16 MiB, with ragged and
+    tiny sizes) and one larger job of each kind, arriving together."""
+    rng = np.random.default_rng(seed)
+    kinds = ([KIND_TRIAD] * 14 + [KIND_HIST] * 10 + [KIND_GEMM] * 9
+             + [KIND_TRIAD, KIND_HIST, KIND_GEMM])
+    sizes = ([int(x) for x in rng.integers(1, 1 << 20, 12)] + [1, 1001]
+             + [int(x) for x in rng.integers(3, 1 << 20, 8)] + [3, 4099]
+             + [256, 256, 256, 512, 512, 512, 1024, 1024, 1024]
+             + [1 << 22, 1 << 23, 2048])
+    order = rng.permutation(len(kinds))
+    kind = np.array(kinds, np.int32)[order]
+    size = np.array(sizes, np.int64)[order]
+    demand = np.where(kind == KIND_TRIAD, triad_demand(size),
+                      np.where(kind == KIND_GEMM, gemm_demand(size), hist_demand(size)))
+    return JobMix(seed, np.zeros(kind.size), kind, size, demand.astype(np.int64), 1 * GiB, "small")
+
+
+def test_batched_all_kinds_equals_unbatched(cs, tmp_path):
+    """Triads, histograms and GEMMs under 16 MiB packed into the persistent
+    batched launch (streaming, tile and digest phases; autotuned shapes) give
+    the same output as per-job launches -- every output word, through the
+    position-keyed digests, and the GEMM samples bit for bit -- and as the
+    oracle: triad and histogram digests exactly, GEMM samples within the
+    stated tolerance and the fp32 accumulation bound."""
+    mix = _small_mix(11)
+    small = mix.demand < 16 * MiB
+    assert small.sum() == 33 and set(mix.kind[small]) == {KIND_TRIAD, KIND_HIST, KIND_GEMM}
+    jt = job_table(mix)
+    ctx = _ctx(cs, 1, mix.capacity, mix.n)
+    try:
+        rc, per_job, sm1 = cs.sched_serve(ctx, jt, n_streams=4, digest=1)
+        assert rc == 0 and sm1["completed"] == mix.n
+        _check_memory(cs, ctx, sm1, mix.n)
+        rc, batched, sm2 = cs.sched_serve(ctx, jt, n_streams=4, digest=1, batch_small=1,
+                                          use_graph=1, tune_cache=str(tmp_path / "tune.json"))
+        assert rc == 0 and sm2["completed"] == mix.n
+        _check_memory(cs, ctx, sm2, mix.n)
+        # the second run reads the shapes from the cache
+        rc, cached, sm3 = cs.sched_serve(ctx, jt, n_streams=4, digest=1, batch_small=1,
+                                         use_graph=1, tune_cache=str(tmp_path / "tune.json"))
+        assert rc == 0 and sm3["completed"] == mix.n
+    finally:
+        cs.sched_destroy(ctx)
+    print(f"  batches={sm2['batches']} batched_jobs={sm2['batched_jobs']} "
+          f"gemm tile={sm2['tuned_gemm_tile']} per_cu={sm2['tuned_gemm_per_cu']}", flush=True)
+    assert sm2["tuned_from_cache"] == 0 and sm3["tuned_from_cache"] == 1
+    assert sm2["tuned_gemm_tile"] in (64, 128) and sm2["tuned_gemm_per_cu"] >= 1
+    assert (sm3["tuned_gemm_tile"], sm3["tuned_gemm_per_cu"]) == \
+        (sm2["tuned_gemm_tile"], sm2["tuned_gemm_per_cu"])
+    assert sm2["batched_jobs"] == int(small.sum())
+    assert np.array_equal(batched["batched"].astype(bool), small)
+    assert not per_job["batched"].any()
+    for r in (batched, cached):
+        assert np.array_equal(per_job["digest"], r["digest"])
+        g = mix.kind == KIND_GEMM
+        assert np.array_equal(per_job["sample"][g].view(np.uint32), r["sample"][g].view(np.uint32))
+    _check_results(mix, jt, batched)
