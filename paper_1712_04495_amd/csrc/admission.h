@@ -130,9 +130,9 @@ struct QueueArrays {
   int64_t *seq;
   uint8_t *decision;
   int64_t capacity;  // entries, a power of two; position p lives at p & (capacity - 1)
-  // admitted list of the last pass (queue order)
+  // admitted list of the last pass (queue order): job ids, and the request
+  // sequence numbers that match admissions to waiting sched_admit requests
   int32_t *adm_job;
-  int64_t *adm_demand;
   int64_t *adm_seq;
 };
 struct JobArrays {

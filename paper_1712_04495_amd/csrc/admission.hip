@@ -765,7 +765,6 @@ __device__ void compact_pass(DevCtl *c, const QueueArrays &q, const JobArrays &j
       if (adm[k]) {
         if (a_pos >= 0 && a_pos < q.capacity) {
           q.adm_job[a_pos] = jo[k];
-          q.adm_demand[a_pos] = d[k];
           q.adm_seq[a_pos] = sq[k];
         }
         ++a_pos;
@@ -978,11 +977,9 @@ __device__ void chain_compact(ChainState &L, const QueueArrays &q, const JobArra
       if (p >= chunk_hi) continue;
       q.decision[p & mask] = 0;
       if (adm[k]) {
-        if (a_pos >= 0 && a_pos < q.capacity) {
-          q.adm_job[a_pos] = jo[k];
-          q.adm_demand[a_pos] = d[k];
-          q.adm_seq[a_pos] = sq[k];
-        }
+        // the job id only: sequence numbers match admissions to waiting
+        // sched_admit requests, and none waits during a chain
+        if (a_pos >= 0 && a_pos < q.capacity) q.adm_job[a_pos] = jo[k];
         if (run_list) {
           const int64_t at = run_n + (a_pos - adm_base);
           if (at < run_cap) run_list[at] = jo[k] < n_mask ? jo[k] : -1;

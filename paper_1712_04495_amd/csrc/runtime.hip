@@ -265,7 +265,6 @@ static int ctx_alloc(sched_ctx *c) {
   SCHED_HIP_TRY(hipMalloc(&c->q.decision, Q));
   SCHED_HIP_TRY(hipMemset(c->q.decision, 0, Q));
   SCHED_HIP_TRY(hipMalloc(&c->q.adm_job, sizeof(int32_t) * Q));
-  SCHED_HIP_TRY(hipMalloc(&c->q.adm_demand, sizeof(int64_t) * Q));
   SCHED_HIP_TRY(hipMalloc(&c->q.adm_seq, sizeof(int64_t) * Q));
   SCHED_HIP_TRY(hipMalloc(&c->jb.res, sizeof(int64_t) * J));
   SCHED_HIP_TRY(hipMemset(c->jb.res, 0, sizeof(int64_t) * J));
@@ -286,7 +285,6 @@ static void **shared_arrays(sched_ctx *c, void **out[IPC_N]) {
   out[IPC_SEQ] = (void **)&c->q.seq;
   out[IPC_DECISION] = (void **)&c->q.decision;
   out[IPC_ADM_JOB] = (void **)&c->q.adm_job;
-  out[IPC_ADM_DEMAND] = (void **)&c->q.adm_demand;
   out[IPC_ADM_SEQ] = (void **)&c->q.adm_seq;
   out[IPC_RES] = (void **)&c->jb.res;
   out[IPC_STATE] = (void **)&c->jb.state;
@@ -308,7 +306,7 @@ static void ctx_free(sched_ctx *c) {
       }
   }
   void *dev[] = {c->q.demand, c->q.job, c->q.prio, c->q.seq, c->q.decision, c->q.adm_job,
-                 c->q.adm_demand, c->q.adm_seq, c->jb.res, c->jb.state, c->d_prio_of_job,
+                 c->q.adm_seq, c->jb.res, c->jb.state, c->d_prio_of_job,
                  c->d_scratch, c->prio_tmp, c->d_run_list};
   for (void *p : dev)
     if (p) (void)hipFree(p);

@@ -25,7 +25,6 @@ enum IpcArr : int {
   IPC_SEQ,
   IPC_DECISION,
   IPC_ADM_JOB,
-  IPC_ADM_DEMAND,
   IPC_ADM_SEQ,
   IPC_RES,
   IPC_STATE,
@@ -108,4 +107,4 @@ struct SharedHost {
 };
 
 constexpr uint64_t SHARED_MAGIC = 0x53434845445348ULL;  // "SCHEDSH"
-constexpr uint32_t SHARED_VERSION = 1;
+constexpr uint32_t SHARED_VERSION = 2;

@@ -365,3 +365,37 @@ def test_batched_all_kinds_equals_unbatched(cs, tmp_path):
         g = mix.kind == KIND_GEMM
         assert np.array_equal(per_job["sample"][g].view(np.uint32), r["sample"][g].view(np.uint32))
     _check_results(mix, jt, batched)
+
+
+@pytest.mark.parametrize("block,chunk,per_cu,tile,per_cu1", [
+    (256, 4096, 2, 64, 1), (1024, 16384, 1, 64, 4), (512, 8192, 4, 128, 1), (256, 16384, 8, 128, 3)])
+def test_batched_shapes_equal_unbatched(cs, tmp_path, block, chunk, per_cu, tile, per_cu1):
+    """Every launch shape the autotuner can choose gives the same outputs:
+    the shapes are forced through the tuner's cache file, and the batched
+    three-kind mix must equal the per-job launches word for word (digests)
+    and the GEMM samples bit for bit."""
+    import json
+    mix = _small_mix(13)
+    small = mix.demand < 16 * MiB
+    jt = job_table(mix)
+    cache = tmp_path / "shape.json"
+    cache.write_text(json.dumps({"block": block, "chunk": chunk, "per_cu": per_cu,
+                                 "gemm_tile": tile, "gemm_per_cu": per_cu1}))
+    ctx = _ctx(cs, 1, mix.capacity, mix.n)
+    try:
+        rc, per_job, _ = cs.sched_serve(ctx, jt, n_streams=4, digest=1)
+        assert rc == 0
+        rc, batched, sm = cs.sched_serve(ctx, jt, n_streams=4, digest=1, batch_small=1,
+                                         use_graph=1, tune_cache=str(cache))
+        assert rc == 0 and sm["completed"] == mix.n
+        _check_memory(cs, ctx, sm, mix.n)
+    finally:
+        cs.sched_destroy(ctx)
+    assert sm["tuned_from_cache"] == 1
+    assert (sm["tuned_block"], sm["tuned_chunk"], sm["tuned_per_cu"], sm["tuned_gemm_tile"],
+            sm["tuned_gemm_per_cu"]) == (block, chunk, per_cu, tile, per_cu1)
+    assert np.array_equal(batched["batched"].astype(bool), small)
+    assert np.array_equal(per_job["digest"], batched["digest"])
+    g = mix.kind == KIND_GEMM
+    assert np.array_equal(per_job["sample"][g].view(np.uint32), batched["sample"][g].view(np.uint32))
+    _check_results(mix, jt, batched)
