@@ -280,16 +280,18 @@ def test_ctx_chain_equals_oracle(cs, policy, seed, n):
         cs.sched_destroy(ctx)
 
 
-# (jobs, requests, rounds, capacity, demand bound): "few" repeats jobs often;
-# "many" admits tens of thousands of requests per pass, so the running list
-# outgrows the part the chain keeps in LDS and admissions reach past the queue
-# entries whose release bytes are fetched ahead
+# (jobs, requests, rounds, capacity, demand bound): "few" repeats jobs often
+# (a job holds several entries of the running list); "many" admits tens of
+# thousands of requests per pass; "grow" (4000 large requests, then 26000
+# small ones, one per job) runs ~2500 jobs for two rounds and then up to
+# ~18500, so the running list grows sevenfold within one chain
 CHAIN_SHAPES = {"few": (300, 2000, 12, 10**6, 10**6 // 40),
-                "many": (60_000, 60_000, 6, 2 * 10**7, 1000)}
+                "many": (60_000, 60_000, 6, 2 * 10**7, 1000),
+                "grow": (30_000, 30_000, 10, 10**6, 600)}
 
 
 @pytest.mark.parametrize("policy", [0, 1])
-@pytest.mark.parametrize("seed,shape", [(11, "few"), (12, "few"), (13, "many")])
+@pytest.mark.parametrize("seed,shape", [(11, "few"), (12, "few"), (13, "many"), (14, "grow")])
 def test_ctx_chain_repeated_jobs(cs, policy, seed, shape):
     """Chain rounds where jobs have several requests in the queue: a job can be
     released and admitted again within one chain, and several of its requests
@@ -298,8 +300,13 @@ def test_ctx_chain_repeated_jobs(cs, policy, seed, shape):
     one oracle pass (Sec. V) runs over the waiting requests in order."""
     rng = np.random.default_rng(seed)
     n_jobs, n_req, rounds, C, dmax = CHAIN_SHAPES[shape]
-    job = rng.integers(0, n_jobs, n_req).astype(np.int32)
-    dem = rng.integers(1, dmax, n_req).astype(np.int64)
+    if shape == "grow":
+        job = np.arange(n_req, dtype=np.int32)
+        dem = np.concatenate([rng.integers(200, dmax, 4000),
+                              rng.integers(10, 60, n_req - 4000)]).astype(np.int64)
+    else:
+        job = rng.integers(0, n_jobs, n_req).astype(np.int32)
+        dem = rng.integers(1, dmax, n_req).astype(np.int64)
     masks = (rng.random((rounds - 1, n_jobs)) < 0.4).astype(np.uint8)
     # reference
     res = np.zeros(n_jobs, np.int64)
@@ -327,6 +334,9 @@ def test_ctx_chain_repeated_jobs(cs, policy, seed, shape):
         ref.append((job[got].astype(np.int64), R2, rel_jobs, rel_bytes))
     if shape == "many":
         assert ref[0][0].size > 12288 and max(x[0].size for x in ref[1:]) > 1536
+    if shape == "grow":
+        running = np.cumsum([x[0].size - x[2] for x in ref])
+        assert running[0] < 4096 and running[1] < 4096 and running.max() > 16384, running
     rc, ctx = cs.sched_create(policy=policy, capacity_bytes=C, max_jobs=n_jobs,
                               queue_capacity=1 << int(np.ceil(np.log2(max(n_req, 4096)))))
     assert rc == 0
