@@ -213,11 +213,11 @@ def hol_run(cs, n_streams=3):
 
 def c2_step(cs, ctx, d_job, d_dem, coins):
     """reset + intake of the whole queue + the release/admit rounds chained
-    on the device.  Two host synchronisations per step: the intake waits for
-    its validity verdict, the chain for its round summaries."""
+    on the device.  Intake and chain are one call (sched_enqueue_chain): the
+    chain runs right behind the intake and checks its validity verdict on the
+    device, so the step has one host synchronisation, the chain's."""
     assert cs.sched_reset(ctx) == 0
-    assert cs.sched_enqueue_batch(ctx, d_job, d_dem) == 0
-    rc, res = cs.sched_pass_chain_array(ctx, coins.shape[0] + 1, coins)
+    rc, res = cs.sched_enqueue_chain_array(ctx, d_job, d_dem, coins.shape[0] + 1, coins)
     assert rc == 0
     return res
 
@@ -584,7 +584,7 @@ def main():
                    "policy": "mmu", "seed": args.seed,
                    "admissions_per_step": tot_adm // args.steps,
                    "us_per_pass": 1e6 * dt / args.steps / q.rounds,
-                   "step": "reset + intake of 2^20 requests + 8 rounds chained on the device",
+                   "step": "reset + intake of 2^20 requests + 8 rounds chained on the device (intake and chain in one call, one host synchronisation)",
                    "per_pass_host_api": {"admissions_per_s": sync_adm / sync_dt,
                                          "us_per_pass": 1e6 * sync_dt / args.steps / q.rounds}},
     }

@@ -298,6 +298,18 @@ int sched_pass_chain(sched_ctx_t *ctx, int32_t rounds, const uint8_t *d_masks, i
                      sched_stream_t stream, sched_pass_result_t *out, int32_t *d_admitted,
                      int64_t cap);
 
+/* sched_enqueue_batch of n requests (d_job[n], d_demand[n], device arrays)
+ * followed by sched_pass_chain, with one synchronisation instead of two:
+ * the chain is queued right behind the intake on the same stream and checks
+ * the intake's verdict on the device.  An invalid batch (as sched_enqueue_batch
+ * defines it) is refused whole: SCHED_E_INVALID, nothing is appended and no
+ * round runs, so the context is as before the call.  Other arguments and
+ * errors as for the two calls. */
+int sched_enqueue_chain(sched_ctx_t *ctx, int64_t n, const int32_t *d_job, const int64_t *d_demand,
+                        int32_t rounds, const uint8_t *d_masks, int64_t n_mask,
+                        sched_stream_t stream, sched_pass_result_t *out, int32_t *d_admitted,
+                        int64_t cap);
+
 /* Post-free for many jobs at once: every running job j < n whose byte
  * d_mask[j] (device array of n bytes) is non-zero returns its whole
  * reservation (Sec. IV, bytes == 0).  n must not exceed the number of

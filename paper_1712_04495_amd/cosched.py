@@ -121,6 +121,7 @@ _SIGS = {
     "sched_last_admitted": (i32, [vp, vp, i64, C.POINTER(i64), vp]),
     "sched_release_masked": (i32, [vp, vp, i64, vp]),
     "sched_pass_chain": (i32, [vp, i32, vp, i64, vp, vp, vp, i64]),
+    "sched_enqueue_chain": (i32, [vp, i64, vp, vp, i32, vp, i64, vp, vp, vp, i64]),
     "sched_set_owner": (i32, [vp, i32, i32]),
     "sched_sanity_check": (i32, [vp, vp, vp]),
     "sched_checkpoint": (i32, [vp, vp, C.c_size_t, C.POINTER(C.c_size_t)]),
@@ -342,6 +343,26 @@ def sched_pass_chain_array(ctx, rounds, d_masks=None, d_admitted=None, stream=No
                                 res.ctypes.data,
                                 _ptr(d_admitted), cap)
     return rc, res
+
+
+def sched_enqueue_chain_array(ctx, d_job, d_demand, rounds, d_masks=None, d_admitted=None,
+                              stream=None):
+    """sched_enqueue_batch + sched_pass_chain in one call (one synchronisation);
+    results as sched_pass_chain_array."""
+    import numpy as np
+    n = int(d_job.numel())
+    assert int(d_demand.numel()) == n
+    n_mask = 0 if d_masks is None else int(d_masks.shape[-1])
+    res = np.zeros((rounds, len(PASS_FIELDS)), dtype=np.int64)
+    cap = 0 if d_admitted is None else int(d_admitted.numel())
+    rc = lib().sched_enqueue_chain(ctx, n, _ptr(d_job), _ptr(d_demand), rounds, _ptr(d_masks), n_mask,
+                                   _stream(stream), res.ctypes.data, _ptr(d_admitted), cap)
+    return rc, res
+
+
+def sched_enqueue_chain(ctx, d_job, d_demand, rounds, d_masks=None, d_admitted=None, stream=None):
+    rc, arr = sched_enqueue_chain_array(ctx, d_job, d_demand, rounds, d_masks, d_admitted, stream)
+    return rc, [dict(zip(PASS_FIELDS, (int(v) for v in row))) for row in arr]
 
 
 # ---------------------------------------------------------- stateless scan

@@ -1037,8 +1037,18 @@ __global__ __launch_bounds__(CMP_THREADS) void k_chain(DevCtl *c, QueueArrays q,
                                                        const uint8_t *__restrict__ masks,
                                                        int64_t n_mask, int rounds, uint32_t L0,
                                                        int filter, PassSummary *out,
-                                                       int32_t *run_list, int64_t run_cap) {
+                                                       int32_t *run_list, int64_t run_cap,
+                                                       int gated) {
   __shared__ int64_t red[2 * CMP_THREADS / WAVE];
+  if (gated && c->chain_hold) {
+    // the intake launched right before was refused: no round runs, and the
+    // running list the list kernel gathered is dropped
+    if (threadIdx.x == 0) {
+      c->chain_hold = 0;
+      c->run_n = 0;
+    }
+    return;
+  }
   __shared__ ChainState L;
   // round summaries stay in LDS until the end: stores to host memory inside
   // the loop would be waited for at every barrier
@@ -1120,11 +1130,12 @@ __global__ __launch_bounds__(256) void k_enqueue_checked(DevCtl *c, QueueArrays 
   if (threadIdx.x == 0 && bad) add_relaxed(&c->enq_bad, (unsigned long long)bad);
 }
 
-__global__ void k_enqueue_commit(DevCtl *c, int64_t new_tail, int64_t *verdict) {
+__global__ void k_enqueue_commit(DevCtl *c, int64_t new_tail, int64_t *verdict, int hold) {
   if (threadIdx.x || blockIdx.x) return;
   const unsigned long long b = c->enq_bad;
   if (!b) c->tail = new_tail;
   c->enq_bad = 0;
+  if (hold) c->chain_hold = b ? 1 : 0;
   *verdict = int64_t(b);
 }
 
@@ -1366,7 +1377,7 @@ int adm_pass_ctx(AdmEngine &e, int policy, const QueueArrays &q, const JobArrays
 }
 
 int adm_chain(AdmEngine &e, int policy, const QueueArrays &q, const JobArrays &jb, int rounds,
-              const uint8_t *masks, int64_t n_mask, int32_t *run_list, hipStream_t s) {
+              const uint8_t *masks, int64_t n_mask, int32_t *run_list, hipStream_t s, bool gated) {
   if (rounds <= 0 || rounds > MAX_CHAIN) return SCHED_E_INVALID;
   const int filter = policy == SCHED_POLICY_MMU ? 1 : 0;
   const bool listed = rounds > 1 && masks && n_mask > 0;
@@ -1382,7 +1393,8 @@ int adm_chain(AdmEngine &e, int policy, const QueueArrays &q, const JobArrays &j
                     (k_chain<<<1, CMP_THREADS, 0, s>>>(e.d_ctl, q, jb, masks, listed ? n_mask : 0,
                                                        rounds, L0, filter, e.d_sum,
                                                        listed ? run_list : nullptr,
-                                                       int64_t(jb.max_jobs) + q.capacity)));
+                                                       int64_t(jb.max_jobs) + q.capacity,
+                                                       gated ? 1 : 0)));
   SCHED_HIP_TRY(hipGetLastError());
   e.launch += rounds;
   SCHED_HIP_TRY(hipStreamSynchronize(s));
@@ -1413,16 +1425,25 @@ int adm_enqueue(AdmEngine &e, const QueueArrays &q, int64_t at, int64_t n, const
   return SCHED_OK;
 }
 
-int adm_enqueue_checked(AdmEngine &e, const QueueArrays &q, int64_t at, int64_t n, const int32_t *job,
-                        const int64_t *demand, const int32_t *prio_of_job, int64_t seq0,
-                        int32_t n_jobs, int64_t capacity, hipStream_t s, int64_t *n_bad) {
+int adm_enqueue_launch(AdmEngine &e, const QueueArrays &q, int64_t at, int64_t n, const int32_t *job,
+                       const int64_t *demand, const int32_t *prio_of_job, int64_t seq0,
+                       int32_t n_jobs, int64_t capacity, hipStream_t s, int hold) {
   volatile int64_t *v = e.h_flag;
   *v = -1;
   k_enqueue_checked<<<grid_for(n, 256, 4096), 256, 0, s>>>(e.d_ctl, q, at, n, job, demand,
                                                            prio_of_job, seq0, n_jobs, capacity);
   SCHED_HIP_TRY(hipGetLastError());
-  k_enqueue_commit<<<1, 64, 0, s>>>(e.d_ctl, at + n, e.d_flag);
+  k_enqueue_commit<<<1, 64, 0, s>>>(e.d_ctl, at + n, e.d_flag, hold);
   SCHED_HIP_TRY(hipGetLastError());
+  return SCHED_OK;
+}
+
+int adm_enqueue_checked(AdmEngine &e, const QueueArrays &q, int64_t at, int64_t n, const int32_t *job,
+                        const int64_t *demand, const int32_t *prio_of_job, int64_t seq0,
+                        int32_t n_jobs, int64_t capacity, hipStream_t s, int64_t *n_bad) {
+  volatile int64_t *v = e.h_flag;
+  if (int rc = adm_enqueue_launch(e, q, at, n, job, demand, prio_of_job, seq0, n_jobs, capacity, s, 0))
+    return rc;
   SCHED_HIP_TRY(hipStreamSynchronize(s));
   const int64_t b = *v;
   if (b < 0) return SCHED_E_INTERNAL;

@@ -928,20 +928,11 @@ extern "C" int sched_last_admitted(sched_ctx_t *c, int32_t *d_out, int64_t cap, 
   return SCHED_OK;
 }
 
-extern "C" int sched_pass_chain(sched_ctx_t *c, int32_t rounds, const uint8_t *d_masks,
-                                int64_t n_mask, sched_stream_t stream, sched_pass_result_t *out,
-                                int32_t *d_admitted, int64_t cap) {
-  if (!c || rounds <= 0 || rounds > MAX_CHAIN || n_mask < 0 || (rounds > 1 && n_mask > 0 && !d_masks))
-    return SCHED_E_INVALID;
-  if (cap < 0 || (cap > 0 && !d_admitted) || c->shared()) return SCHED_E_INVALID;
-  std::lock_guard<CtxLock> g(c->mu);
-  if (n_mask > c->sh->n_jobs || !c->sh->req_empty()) return SCHED_E_INVALID;
-  if (c->policy != SCHED_POLICY_FIFO && c->policy != SCHED_POLICY_MMU) return SCHED_E_INVALID;
-  SCHED_HIP_TRY(hipSetDevice(c->device));
-  hipStream_t s;
-  if (int rc = pick_ordered(c, stream, &s)) return rc;
-  if (int rc = adm_chain(c->eng, c->policy, c->q, c->jb, rounds, d_masks, n_mask, c->d_run_list, s))
-    return rc;
+// The host side of a device chain that has finished (its summaries are in
+// the engine's host-mapped memory): per-round results, statistics, the
+// mirrored queue state and the admitted ids.
+static int chain_finish(sched_ctx *c, int32_t rounds, hipStream_t s, sched_pass_result_t *out,
+                        int32_t *d_admitted, int64_t cap) {
   int64_t head_before = c->sh->head_h, total = 0;
   for (int r = 0; r < rounds; ++r) {
     const PassSummary &h = c->eng.h_sum[r];
@@ -977,6 +968,65 @@ extern "C" int sched_pass_chain(sched_ctx_t *c, int32_t rounds, const uint8_t *d
     SCHED_HIP_TRY(hipMemcpyAsync(d_admitted, c->q.adm_job, sizeof(int32_t) * std::min(cap, total),
                                  hipMemcpyDeviceToDevice, s));
   return SCHED_OK;
+}
+
+static bool chain_args_ok(sched_ctx *c, int32_t rounds, const uint8_t *d_masks, int64_t n_mask,
+                          int32_t *d_admitted, int64_t cap) {
+  return c && rounds > 0 && rounds <= MAX_CHAIN && n_mask >= 0 &&
+         !(rounds > 1 && n_mask > 0 && !d_masks) && cap >= 0 && !(cap > 0 && !d_admitted) &&
+         !c->shared();
+}
+
+static bool chain_state_ok(sched_ctx *c, int64_t n_mask) {
+  return n_mask <= c->sh->n_jobs && c->sh->req_empty() &&
+         (c->policy == SCHED_POLICY_FIFO || c->policy == SCHED_POLICY_MMU);
+}
+
+extern "C" int sched_pass_chain(sched_ctx_t *c, int32_t rounds, const uint8_t *d_masks,
+                                int64_t n_mask, sched_stream_t stream, sched_pass_result_t *out,
+                                int32_t *d_admitted, int64_t cap) {
+  if (!chain_args_ok(c, rounds, d_masks, n_mask, d_admitted, cap)) return SCHED_E_INVALID;
+  std::lock_guard<CtxLock> g(c->mu);
+  if (!chain_state_ok(c, n_mask)) return SCHED_E_INVALID;
+  SCHED_HIP_TRY(hipSetDevice(c->device));
+  hipStream_t s;
+  if (int rc = pick_ordered(c, stream, &s)) return rc;
+  if (int rc = adm_chain(c->eng, c->policy, c->q, c->jb, rounds, d_masks, n_mask, c->d_run_list, s))
+    return rc;
+  return chain_finish(c, rounds, s, out, d_admitted, cap);
+}
+
+extern "C" int sched_enqueue_chain(sched_ctx_t *c, int64_t n, const int32_t *d_job,
+                                   const int64_t *d_demand, int32_t rounds, const uint8_t *d_masks,
+                                   int64_t n_mask, sched_stream_t stream, sched_pass_result_t *out,
+                                   int32_t *d_admitted, int64_t cap) {
+  if (!chain_args_ok(c, rounds, d_masks, n_mask, d_admitted, cap)) return SCHED_E_INVALID;
+  if (n < 0 || (n > 0 && (!d_job || !d_demand))) return SCHED_E_INVALID;
+  std::lock_guard<CtxLock> g(c->mu);
+  if (!chain_state_ok(c, n_mask)) return SCHED_E_INVALID;
+  if (c->sh->tail_h - c->sh->head_h + n > c->q.capacity) return SCHED_E_INVALID;
+  SCHED_HIP_TRY(hipSetDevice(c->device));
+  hipStream_t s;
+  if (int rc = pick_ordered(c, stream, &s)) return rc;
+  if (n > 0)
+    if (int rc = adm_enqueue_launch(c->eng, c->q, c->sh->tail_h, n, d_job, d_demand,
+                                    c->d_prio_of_job, c->sh->seq_next, c->sh->n_jobs, c->capacity, s,
+                                    1))
+      return rc;
+  // the chain is queued right behind the intake; a refused intake leaves it
+  // nothing to do (gated), and the one synchronisation is the chain's own
+  if (int rc = adm_chain(c->eng, c->policy, c->q, c->jb, rounds, d_masks, n_mask, c->d_run_list, s,
+                         n > 0))
+    return rc;
+  if (s == c->stream) c->reset_pending = false;
+  if (n > 0) {
+    const int64_t b = *reinterpret_cast<volatile int64_t *>(c->eng.h_flag);
+    if (b < 0) return SCHED_E_INTERNAL;
+    if (b) return SCHED_E_INVALID;
+    c->sh->seq_next += n;
+    c->sh->tail_h += n;
+  }
+  return chain_finish(c, rounds, s, out, d_admitted, cap);
 }
 
 extern "C" int sched_release_masked(sched_ctx_t *c, const uint8_t *d_mask, int64_t n,

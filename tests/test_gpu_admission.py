@@ -732,3 +732,92 @@ def test_sanity_while_waiting_and_explicit(cs):
         assert st["used"] == 0
     finally:
         cs.sched_destroy(ctx)
+
+
+@pytest.mark.parametrize("policy", [0, 1])
+def test_enqueue_chain_equals_separate_calls(cs, policy):
+    """The fused intake + chain gives what sched_enqueue_batch followed by
+    sched_pass_chain gives, round by round, and both equal the oracle's
+    release/admit rounds (Sec. IV post-free, Sec. V passes)."""
+    n = 1 << 14
+    q = c2_queue(seed=7, n=n, capacity=2 * 10**11)
+    rc, ctx = cs.sched_create(policy=policy, capacity_bytes=q.capacity, max_jobs=n,
+                              queue_capacity=n, window_limit=16)
+    assert rc == 0
+    try:
+        assert cs.sched_register_batch(ctx, n)[0] == 0
+        d_job = torch.arange(n, dtype=torch.int32, device=DEV)
+        d_dem = torch.from_numpy(q.demand).to(DEV)
+        coins = torch.from_numpy(q.coins).to(DEV)
+        adm1 = torch.full((n,), -1, dtype=torch.int32, device=DEV)
+        adm2 = torch.full((n,), -1, dtype=torch.int32, device=DEV)
+        assert cs.sched_reset(ctx) == 0
+        assert cs.sched_enqueue_batch(ctx, d_job, d_dem) == 0
+        rc, r1 = cs.sched_pass_chain_array(ctx, q.rounds, coins, adm1)
+        assert rc == 0
+        st1 = cs.sched_stats(ctx)[1]
+        assert cs.sched_reset(ctx) == 0
+        rc, r2 = cs.sched_enqueue_chain_array(ctx, d_job, d_dem, q.rounds, coins, adm2)
+        assert rc == 0
+        st2 = cs.sched_stats(ctx)[1]
+        torch.cuda.synchronize()
+        assert np.array_equal(r1, r2)
+        assert torch.equal(adm1, adm2)
+        assert st1["used"] == st2["used"] and st1["pending"] == st2["pending"]
+        ref = S.release_rounds(q.demand, q.capacity, q.coins, q.rounds, policy)
+        got = adm2.cpu().numpy().astype(np.int64)
+        col = {k: i for i, k in enumerate(cs.PASS_FIELDS)}
+        off = 0
+        for r, rr in enumerate(ref):
+            k = rr.admitted.size
+            assert r2[r, col["admitted"]] == k and np.array_equal(got[off:off + k], rr.admitted)
+            assert r2[r, col["free_after"]] == rr.R_after
+            off += k
+    finally:
+        cs.sched_destroy(ctx)
+
+
+def test_enqueue_chain_refused_batch_changes_nothing(cs):
+    """A fused call whose batch holds an invalid request (unknown job) is
+    refused whole: SCHED_E_INVALID, nothing appended, no round run (running
+    jobs keep their reservations although the masks would release them); the
+    calls after it behave as if it had never been made."""
+    C, n_jobs, n = 10_000, 64, 40
+    rng = np.random.default_rng(3)
+    rc, ctx = cs.sched_create(policy=cs.SCHED_POLICY_MMU, capacity_bytes=C, max_jobs=n_jobs,
+                              queue_capacity=4096)
+    assert rc == 0
+    try:
+        assert cs.sched_register_batch(ctx, n_jobs)[0] == 0
+        job = np.arange(n, dtype=np.int32)
+        dem = rng.integers(1, 800, n).astype(np.int64)
+        masks = np.ones((2, n_jobs), np.uint8)
+        d_masks = torch.from_numpy(masks).to(DEV)
+        # a first, valid fused call: jobs 0..39 queued, round 0 admits a prefix
+        rc, r0 = cs.sched_enqueue_chain_array(ctx, torch.from_numpy(job).to(DEV),
+                                              torch.from_numpy(dem).to(DEV), 1)
+        assert rc == 0
+        st0 = cs.sched_stats(ctx)[1]
+        res0 = [cs.sched_reservation(ctx, j)[1] for j in range(n_jobs)]
+        adm0, R0 = S.mmu_pass(dem, C)
+        assert st0["used"] == C - R0 and st0["pending"] == n - int(adm0.sum())
+        # refused: job 99 does not exist
+        bad = job.copy()
+        bad[7] = 99
+        rc, _ = cs.sched_enqueue_chain_array(ctx, torch.from_numpy(bad).to(DEV),
+                                             torch.from_numpy(dem).to(DEV), 3, d_masks)
+        assert rc == cs.SCHED_E_INVALID
+        st1 = cs.sched_stats(ctx)[1]
+        assert st1["used"] == st0["used"] and st1["pending"] == st0["pending"]
+        assert [cs.sched_reservation(ctx, j)[1] for j in range(n_jobs)] == res0
+        # a plain chain afterwards runs (the device flag was cleared): round 1
+        # releases every running job (mask 1) and admits from the waiting ones
+        rc, r2 = cs.sched_pass_chain_array(ctx, 2, d_masks)
+        assert rc == 0
+        col = {k: i for i, k in enumerate(cs.PASS_FIELDS)}
+        pend = dem[~adm0]
+        a1, R1 = S.mmu_pass(pend, C - (C - R0))      # round 0 of this chain: nothing freed yet
+        assert r2[0, col["admitted"]] == int(a1.sum())
+        assert r2[1, col["released"]] == int(adm0.sum()) + int(a1.sum())
+    finally:
+        cs.sched_destroy(ctx)
