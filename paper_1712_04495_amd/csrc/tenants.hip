@@ -489,6 +489,7 @@ constexpr int PGT_U = 4;          // vectors in flight per thread
 __device__ __forceinline__ bool pg_ok(const PageMap &m, int64_t need) { return pm_pages(m) >= need; }
 
 constexpr int BUF_NT = 2;  // buffer instruction aux: non-temporal
+constexpr int64_t PGT_ONE_LAUNCH = 65536;  // workgroups of a triad job launched at once
 
 template <bool DIRECT>
 __device__ __forceinline__ __amdgpu_buffer_rsrc_t unit_rsrc(const PageMap &m, uint64_t base,
@@ -539,6 +540,10 @@ __global__ __launch_bounds__(256) void k_pg_triad_fill(PageMap m, int64_t need, 
 
 // a = b + s * c in the shape of k_triad: workgroup g streams item g, 16 KiB
 // (PGT_U units of 4 KiB) of each array, thread t one 16-byte vector per unit.
+// A launch may cover several sweeps: workgroup g then takes item g % n_item
+// of sweep g / n_item.  Workgroups are dispatched in order, so the sweeps
+// stream one after the other as separate launches would; a sweep rewrites
+// the same values, so where two overlap at their boundary they agree.
 // A unit never straddles a page, so each unit is one buffer resource whose
 // base comes from a uniform (scalar) lookup -- all twelve of an item issued
 // back to back -- and whose range stops at the array's last whole vector:
@@ -551,7 +556,8 @@ __global__ __launch_bounds__(256) void k_pg_triad(PageMap m, int64_t need, uint6
   const int64_t bytes = 4 * n;
   const int64_t n_item = (bytes + PGT_U * 4096 - 1) / (PGT_U * 4096);
   const int tb = 16 * int(threadIdx.x);
-  for (int64_t it = blockIdx.x; it < n_item; it += gridDim.x) {
+  {
+    const int64_t it = int64_t(blockIdx.x % uint32_t(n_item));  // n_item <= the grid < 2^31
     __amdgpu_buffer_rsrc_t ra[PGT_U], rb[PGT_U], rc[PGT_U];
 #pragma unroll
     for (int u = 0; u < PGT_U; ++u) {
@@ -842,8 +848,15 @@ int pgt_triad(const PageMap &m, uint64_t oa, uint64_t ob, uint64_t oc, float sc,
   if (n == 0) return SCHED_OK;
   const int64_t need =
       std::max(pages_to(oa, 4 * n), std::max(pages_to(ob, 4 * n), pages_to(oc, 4 * n)));
-  const int grid = units_grid((4 * n + PGT_U * 4096 - 1) / (PGT_U * 4096), 1, 1 << 30);
-  for (int32_t it = 0; it < iters; ++it) {
+  // Jobs up to PGT_ONE_LAUNCH workgroups in all (~100 MiB per array over 10
+  // sweeps) run their sweeps in one launch (item-major inside a sweep, sweep
+  // after sweep): there the launches, not the bytes, cost the time.  Larger
+  // ones launch sweep by sweep, so that the admission kernels of the serving
+  // loop, which share the device, get workgroup slots between long launches.
+  const int64_t n_item = (4 * n + PGT_U * 4096 - 1) / (PGT_U * 4096);
+  const bool one = n_item * iters <= PGT_ONE_LAUNCH;
+  const int grid = int(one ? n_item * iters : n_item);
+  for (int32_t it = 0; it < (one ? (iters > 0 ? 1 : 0) : iters); ++it) {
     if (m.direct)
       SCHED_PROF_LAUNCH("k_pg_triad", s,
                         (k_pg_triad<true><<<grid, 256, 0, s>>>(m, need, oa, ob, oc, sc, n)));
