@@ -597,9 +597,11 @@ def main():
         # (25 B read + 24 B written per entry of [head, last admitted]) is
         # reported beside it, not counted in `achieved`.
         per_step_decide = 9 * prof["scanned"]
+        # (the running-list scan, 4 B of state per job, runs only when jobs
+        # may be running; after the step's reset the list starts empty)
         side = {"release_bytes": 9 * prof["considered"] + 20 * prof["released"],
                 "compaction_bytes": 49 * prof["compacted"],
-                "run_list_bytes": 4 * n * prof_steps}
+                "run_list_bytes": 4 * n * kern["k_run_list"][1] if "k_run_list" in kern else 0}
         alg = {"k_chain": per_step_decide, "k_run_list": side["run_list_bytes"]}
         dom = max(kern, key=lambda k: kern[k][0])
         ms, launches = kern[dom]

@@ -160,9 +160,12 @@ int adm_compact(AdmEngine &e, const QueueArrays &q, const JobArrays &j, hipStrea
 // gated: the chain first checks the device's verdict on a fused intake
 // launched right before it (adm_enqueue_launch with hold), and changes
 // nothing when that intake was refused.
+// none_running: the caller knows that no job is running (nothing admitted
+// since every job was reset), so the running list starts empty without the
+// list kernel's scan of the job states.
 int adm_chain(AdmEngine &e, int policy, const QueueArrays &q, const JobArrays &jb, int rounds,
               const uint8_t *masks, int64_t n_mask, int32_t *run_list, hipStream_t s,
-              bool gated = false);
+              bool gated = false, bool none_running = false);
 
 int adm_zero_decisions(uint8_t *decision, int64_t n, hipStream_t s);
 

@@ -1377,12 +1377,14 @@ int adm_pass_ctx(AdmEngine &e, int policy, const QueueArrays &q, const JobArrays
 }
 
 int adm_chain(AdmEngine &e, int policy, const QueueArrays &q, const JobArrays &jb, int rounds,
-              const uint8_t *masks, int64_t n_mask, int32_t *run_list, hipStream_t s, bool gated) {
+              const uint8_t *masks, int64_t n_mask, int32_t *run_list, hipStream_t s, bool gated,
+              bool none_running) {
   if (rounds <= 0 || rounds > MAX_CHAIN) return SCHED_E_INVALID;
   const int filter = policy == SCHED_POLICY_MMU ? 1 : 0;
   const bool listed = rounds > 1 && masks && n_mask > 0;
   if (listed && (!run_list || n_mask > jb.max_jobs)) return SCHED_E_INVALID;
-  if (listed) {
+  // (run_n is 0 between chains, so an empty list needs no kernel)
+  if (listed && !none_running) {
     SCHED_PROF_LAUNCH("k_run_list", s,
                       (k_run_list<<<grid_for(n_mask, 256, 1024), 256, 0, s>>>(e.d_ctl, jb.state,
                                                                               n_mask, run_list)));

@@ -58,6 +58,10 @@ struct sched_ctx {
   // sched_reset only orders its kernels on `stream`; until something waits for
   // them, calls that could observe the state by another route settle first
   bool reset_pending = false;
+  // no job has been admitted since the last sched_reset (the reset sets it;
+  // every pass, chain and restore clears it): a chain's running list then
+  // starts empty without scanning the job states
+  bool none_running = false;
   hipStream_t stream = nullptr;
 
   schedk::AdmEngine eng;

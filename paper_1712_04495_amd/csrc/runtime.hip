@@ -581,6 +581,7 @@ extern "C" int sched_register_batch(sched_ctx_t *c, int32_t n, int32_t priority,
 // One admission pass + compaction + host bookkeeping.  Caller holds c->mu.
 int sched_run_pass_locked(sched_ctx *c, hipStream_t s, sched_pass_result_t *res) {
   auto t0 = std::chrono::steady_clock::now();
+  c->none_running = false;
   const int64_t head_before = c->sh->head_h;
   PassOut po{};
   const int pol = (c->policy == SCHED_POLICY_FIFO || c->policy == SCHED_POLICY_PRIO_FIFO) ? SCHED_POLICY_FIFO : SCHED_POLICY_MMU;
@@ -991,7 +992,10 @@ extern "C" int sched_pass_chain(sched_ctx_t *c, int32_t rounds, const uint8_t *d
   SCHED_HIP_TRY(hipSetDevice(c->device));
   hipStream_t s;
   if (int rc = pick_ordered(c, stream, &s)) return rc;
-  if (int rc = adm_chain(c->eng, c->policy, c->q, c->jb, rounds, d_masks, n_mask, c->d_run_list, s))
+  const bool none = c->none_running;
+  c->none_running = false;
+  if (int rc = adm_chain(c->eng, c->policy, c->q, c->jb, rounds, d_masks, n_mask, c->d_run_list, s,
+                         false, none))
     return rc;
   return chain_finish(c, rounds, s, out, d_admitted, cap);
 }
@@ -1015,8 +1019,10 @@ extern "C" int sched_enqueue_chain(sched_ctx_t *c, int64_t n, const int32_t *d_j
       return rc;
   // the chain is queued right behind the intake; a refused intake leaves it
   // nothing to do (gated), and the one synchronisation is the chain's own
+  const bool none = c->none_running;
+  c->none_running = false;
   if (int rc = adm_chain(c->eng, c->policy, c->q, c->jb, rounds, d_masks, n_mask, c->d_run_list, s,
-                         n > 0))
+                         n > 0, none))
     return rc;
   if (s == c->stream) c->reset_pending = false;
   if (n > 0) {
@@ -1223,6 +1229,7 @@ extern "C" int sched_reset(sched_ctx_t *c) {
   }
   SCHED_HIP_TRY(hipGetLastError());
   c->reset_pending = true;
+  c->none_running = true;
   // pending[j] counts the host-side waiting requests of job j, which are
   // exactly the entries of the request table naming j (a scan of the whole
   // table, so only when it holds any)
@@ -1437,6 +1444,7 @@ extern "C" int sched_checkpoint(sched_ctx_t *c, void *buf, size_t cap, size_t *o
 extern "C" int sched_restore(sched_ctx_t *c, const void *buf, size_t bytes) {
   if (!c || !buf || c->shared()) return SCHED_E_INVALID;
   std::lock_guard<CtxLock> g(c->mu);
+  c->none_running = false;
   if (int rc = sched_settle_reset_locked(c)) return rc;
   CkptHeader h;
   std::vector<CkptJob> jobs;

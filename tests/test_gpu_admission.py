@@ -777,6 +777,53 @@ def test_enqueue_chain_equals_separate_calls(cs, policy):
         cs.sched_destroy(ctx)
 
 
+@pytest.mark.parametrize("policy", [0, 1])
+def test_chain_after_per_pass_calls_releases_their_jobs(cs, policy):
+    """After a reset, a chain whose running list may start empty (nothing
+    admitted yet) skips the list scan; once a per-pass call has admitted
+    jobs, a later chain must find them running.  Round 0 by sched_pass, the
+    release of round 1 by sched_release_masked, the remaining rounds by one
+    chain: every round equals the oracle's release/admit rounds."""
+    n = 1 << 14
+    q = c2_queue(seed=9, n=n, capacity=2 * 10**11)
+    rc, ctx = cs.sched_create(policy=policy, capacity_bytes=q.capacity, max_jobs=n,
+                              queue_capacity=n, window_limit=16)
+    assert rc == 0
+    try:
+        assert cs.sched_register_batch(ctx, n)[0] == 0
+        d_job = torch.arange(n, dtype=torch.int32, device=DEV)
+        d_dem = torch.from_numpy(q.demand).to(DEV)
+        coins = torch.from_numpy(q.coins).to(DEV)
+        adm = torch.full((n,), -1, dtype=torch.int32, device=DEV)
+        out = torch.empty(n, dtype=torch.int32, device=DEV)
+        ref = S.release_rounds(q.demand, q.capacity, q.coins, q.rounds, policy)
+        col = {k: i for i, k in enumerate(cs.PASS_FIELDS)}
+        for rep in range(2):
+            assert cs.sched_reset(ctx) == 0
+            assert cs.sched_enqueue_batch(ctx, d_job, d_dem) == 0
+            rc, r0 = cs.sched_pass(ctx)
+            assert rc == 0 and r0["admitted"] == ref[0].admitted.size
+            rc, na = cs.sched_last_admitted(ctx, out)
+            assert rc == 0 and np.array_equal(out[:na].cpu().numpy(), ref[0].admitted)
+            assert cs.sched_release_masked(ctx, coins[0]) == 0
+            rc, rr = cs.sched_pass_chain_array(ctx, q.rounds - 1, coins[1:].contiguous(), adm)
+            assert rc == 0
+            torch.cuda.synchronize()
+            got = adm.cpu().numpy().astype(np.int64)
+            off = 0
+            for r in range(1, q.rounds):
+                k = ref[r].admitted.size
+                assert rr[r - 1, col["admitted"]] == k, f"round {r}"
+                assert np.array_equal(got[off:off + k], ref[r].admitted), f"round {r}"
+                assert rr[r - 1, col["free_after"]] == ref[r].R_after
+                if r > 1:
+                    assert rr[r - 1, col["released"]] == ref[r].released.size, f"round {r}"
+                off += k
+            assert cs.sched_stats(ctx)[1]["used"] == ref[-1].used_after
+    finally:
+        cs.sched_destroy(ctx)
+
+
 def test_enqueue_chain_refused_batch_changes_nothing(cs):
     """A fused call whose batch holds an invalid request (unknown job) is
     refused whole: SCHED_E_INVALID, nothing appended, no round run (running
