@@ -40,6 +40,9 @@ def parse():
     ap.add_argument("--queue-log2", type=int, default=20)
     ap.add_argument("--dense-log2", type=int, default=26)
     ap.add_argument("--dense-reps", type=int, default=10)
+    ap.add_argument("--dense-sweep", default="24,26,28",
+                    help="log2 sizes of the C2-D sweep (FIFO pass deciding every entry, and "
+                         "first fit over 64 MiB-4 GiB demands); empty = none")
     ap.add_argument("--dense-window", type=int, default=64,
                     help="single-wave windows before the grid rounds take over")
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
@@ -306,6 +309,51 @@ def tenant_measure(cs, torch, dev):
                         "frac_of_peak": tf / 2500.0, "peak_TFLOPs": 2500.0}
     del A, B, C
     torch.cuda.empty_cache()
+    return out
+
+
+def dense_sweep(cs, torch, dev, sizes, seed, window, reps=5):
+    """C2-D at each size: (a) FIFO over a queue whose whole length is the
+    admitted prefix, (b) first fit over 64 MiB-4 GiB demands (every entry is
+    inspected).  Whole calls by the host clock, kernels by HIP events; each
+    result checked against the oracle's characterisation."""
+    from oracle import sched as S
+    from workloads import c2d_fifo_queue, c2d_queue
+    out = []
+    for lg in sizes:
+        n = 1 << lg
+        for name, pol, q in (("fifo_all", cs.SCHED_POLICY_FIFO, c2d_fifo_queue(seed=seed, n=n)),
+                             ("first_fit", cs.SCHED_POLICY_MMU, c2d_queue(seed=seed, n=n))):
+            dd = torch.from_numpy(q.demand).to(dev)
+            dec = torch.zeros(n, dtype=torch.uint8, device=dev)
+            rc, r = cs.sched_scan(pol, dd, q.capacity, dec, window_limit=window)
+            assert rc == 0
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            for _ in range(reps):
+                rc, r = cs.sched_scan(pol, dd, q.capacity, dec, window_limit=window)
+                assert rc == 0
+            torch.cuda.synchronize()
+            dt = (time.perf_counter() - t1) / reps
+            cs.sched_profile(True)
+            for _ in range(reps):
+                assert cs.sched_scan(pol, dd, q.capacity, dec, window_limit=window)[0] == 0
+            torch.cuda.synchronize()
+            ms = sum(cs.sched_profile_read(k)[1] for k in ("k_round", "k_window"))
+            cs.sched_profile(False)
+            a = dec.cpu().numpy().astype(bool)
+            ok = (bool(a.all()) and r["free_after"] == 0) if pol == cs.SCHED_POLICY_FIFO else \
+                S.first_fit_fixed_point(q.demand, q.capacity, a)
+            kern = ms * 1e-3 / reps
+            bytes_pass = 9 * n
+            out.append({"log2_n": lg, "pass": name, "pass_us": dt * 1e6, "kernels_us": kern * 1e6,
+                        "rounds": r["rounds"], "GBps_pass": bytes_pass / dt / 1e9,
+                        "GBps_kernels": bytes_pass / kern / 1e9,
+                        "frac_of_peak_kernels": bytes_pass / kern / 1e9 / HBM_PEAK_GBS,
+                        "frac_of_peak_pass": bytes_pass / dt / 1e9 / HBM_PEAK_GBS, "ok": bool(ok)})
+            print(f"[bench] dense sweep: {json.dumps(out[-1])}", file=sys.stderr, flush=True)
+            del dd, dec, q, a
+            torch.cuda.empty_cache()
     return out
 
 
@@ -667,6 +715,10 @@ def main():
             "round_traffic_bytes": traffic_for("k_round"), "round_algorithmic_bytes": bytes_pass}
         del dd, dec
 
+    if "dense" in extras and args.dense_sweep:
+        out["dense_sweep"] = dense_sweep(cs, torch, dev,
+                                         [int(x) for x in args.dense_sweep.split(",") if x],
+                                         args.seed, args.dense_window)
     if "tenants" in extras:
         out["tenants"] = tenant_measure(cs, torch, dev)
         # the triad over 6 GiB is the achievable-bandwidth reference: every

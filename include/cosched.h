@@ -346,7 +346,9 @@ size_t sched_scan_workspace_size(int64_t n);
  * NULL to use a workspace the library allocates and keeps for the device.
  * The pass runs entirely in the grid-wide round kernel (decoupled
  * look-back scan); single-workgroup windows are used first when
- * window_limit > 0.  Synchronises the stream; *out is a host pointer.
+ * window_limit > 0 (at most 2 under FIFO, whose first break ends the pass,
+ * so that a long admitted prefix goes to the grid at streaming rate).
+ * Synchronises the stream; *out is a host pointer.
  * Errors: SCHED_E_INVALID for bad sizes, policy or R. */
 int sched_scan(int32_t policy, int64_t n, const int64_t *d_demand, int64_t R, uint8_t *d_decision,
                int32_t write_all, int32_t window_limit, void *d_ws, size_t ws_bytes,

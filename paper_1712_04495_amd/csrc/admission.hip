@@ -1285,6 +1285,8 @@ static void fill_out(const PassSummary &h, PassOut *out) {
 // that predecessor's candidates itself (process-wide).
 static std::atomic<int32_t> g_lookback_polls{LOOKBACK_POLLS_DEFAULT};
 void adm_set_lookback_polls(int32_t polls) { g_lookback_polls.store(polls); }
+// windows a stateless FIFO scan walks before the grid rounds take over
+constexpr int FIFO_WALK_WINDOWS = 2;
 
 // Round kernels until the pass recorded in slot L & 3 is done; returns the
 // launch id whose slot holds the final state.
@@ -1331,6 +1333,12 @@ int adm_scan(AdmEngine &e, int policy, const int64_t *demand, uint8_t *decision,
              int64_t end, int64_t R0, int window_limit, hipStream_t s, PassOut *out) {
   uint32_t L = uint32_t(e.launch);
   const int filter = policy == SCHED_POLICY_MMU ? 1 : 0;
+  // Under FIFO the first break ends the pass, so one grid round decides
+  // whatever the walk leaves at streaming rate; the walk only pays when the
+  // break comes early.  A window without a break says it does not: past
+  // FIFO_WALK_WINDOWS windows the grid takes over (a FIFO pass over 2^26
+  // entries that are all admitted walked 64 windows, ~150 us, before).
+  if (!filter && window_limit > FIFO_WALK_WINDOWS) window_limit = FIFO_WALK_WINDOWS;
   // the grid rounds go right behind the window kernel without a host check in
   // between: when the window walk already finished the pass they return at
   // once (a few microseconds each, less than a synchronisation)

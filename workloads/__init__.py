@@ -82,6 +82,15 @@ def c2d_queue(seed: int = 2, n: int = 1 << 26, capacity: int = 280 * 10**9) -> A
     return AdmissionQueue(seed, demand, capacity, np.zeros((0, n), np.uint8), 1)
 
 
+def c2d_fifo_queue(seed: int = 2, n: int = 1 << 26) -> AdmissionQueue:
+    """C2-D (a), a FIFO pass that decides every entry: demands 4096 * U{1..64}
+    (4-256 KiB) and capacity equal to their sum, so the whole queue is the
+    admitted prefix (the sum stays below 2^46 up to n = 2^28)."""
+    rng = np.random.default_rng(seed + 1000)
+    demand = PAGE * rng.integers(1, 65, size=n, dtype=np.int64)
+    return AdmissionQueue(seed, demand, int(demand.sum()), np.zeros((0, n), np.uint8), 1)
+
+
 def random_queue(seed: int, n: int, max_demand: int, holes: float = 0.0):
     """Small random queue for parity sweeps: demands uniform in [1, max_demand],
     a fraction ``holes`` of entries marked withdrawn (demand -1)."""
