@@ -300,8 +300,8 @@ int sched_pass_chain(sched_ctx_t *ctx, int32_t rounds, const uint8_t *d_masks, i
 
 /* sched_enqueue_batch of n requests (d_job[n], d_demand[n], device arrays)
  * followed by sched_pass_chain, with one synchronisation instead of two:
- * the chain is queued right behind the intake on the same stream and checks
- * the intake's verdict on the device.  An invalid batch (as sched_enqueue_batch
+ * the chain is queued right behind the intake on the same stream and commits
+ * the intake on the device.  An invalid batch (as sched_enqueue_batch
  * defines it) is refused whole: SCHED_E_INVALID, nothing is appended and no
  * round runs, so the context is as before the call.  Other arguments and
  * errors as for the two calls. */

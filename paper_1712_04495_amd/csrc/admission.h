@@ -62,9 +62,6 @@ struct DevCtl {
   unsigned long long round_sum[4];   // candidate sums of those tiles
   int64_t run_n;                     // entries of the running list of a device chain
   unsigned long long enq_bad;        // invalid requests seen by a checked intake
-  int32_t chain_hold;                // 1: a fused intake was refused; the gated chain behind it
-                                     // runs no round (it clears the flag)
-  int32_t pad_hold;
 };
 
 // What a pass reports to the host; written by the device into host-mapped
@@ -157,15 +154,16 @@ int adm_compact(AdmEngine &e, const QueueArrays &q, const JobArrays &j, hipStrea
 // admitted lists of the rounds are appended one after the other.  run_list
 // is device scratch of jb.max_jobs + q.capacity int32 entries (the running
 // jobs a mask can name, plus every admission of the chain).
-// gated: the chain first checks the device's verdict on a fused intake
-// launched right before it (adm_enqueue_launch with hold), and changes
-// nothing when that intake was refused.
+// gated: an intake launched right before without its commit
+// (adm_enqueue_launch with commit = false) is committed by the chain: a
+// clean batch moves the tail to new_tail, the verdict goes to *e.h_flag, and
+// a refused batch leaves everything as it was (no round runs).
 // none_running: the caller knows that no job is running (nothing admitted
 // since every job was reset), so the running list starts empty without the
 // list kernel's scan of the job states.
 int adm_chain(AdmEngine &e, int policy, const QueueArrays &q, const JobArrays &jb, int rounds,
               const uint8_t *masks, int64_t n_mask, int32_t *run_list, hipStream_t s,
-              bool gated = false, bool none_running = false);
+              bool gated = false, bool none_running = false, int64_t new_tail = 0);
 
 int adm_zero_decisions(uint8_t *decision, int64_t n, hipStream_t s);
 
@@ -179,10 +177,11 @@ int adm_enqueue_checked(AdmEngine &e, const QueueArrays &q, int64_t at, int64_t 
                         int32_t n_jobs, int64_t capacity, hipStream_t s, int64_t *n_bad);
 // The same intake without the wait: the verdict (number of invalid
 // requests) lands in host-mapped *e.h_flag once the stream reaches it (-1
-// until then); hold != 0 also arms the device flag a gated chain checks.
+// until then).  commit = false leaves the commit (tail, verdict) to a gated
+// chain launched right behind.
 int adm_enqueue_launch(AdmEngine &e, const QueueArrays &q, int64_t at, int64_t n, const int32_t *job,
                        const int64_t *demand, const int32_t *prio_of_job, int64_t seq0,
-                       int32_t n_jobs, int64_t capacity, hipStream_t s, int hold);
+                       int32_t n_jobs, int64_t capacity, hipStream_t s, bool commit);
 int adm_release_masked(AdmEngine &e, const JobArrays &j, const uint8_t *mask, int64_t n,
                        hipStream_t s);
 int adm_enqueue(AdmEngine &e, const QueueArrays &q, int64_t at, int64_t n, const int32_t *job,

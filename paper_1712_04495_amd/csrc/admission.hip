@@ -1038,16 +1038,26 @@ __global__ __launch_bounds__(CMP_THREADS) void k_chain(DevCtl *c, QueueArrays q,
                                                        int64_t n_mask, int rounds, uint32_t L0,
                                                        int filter, PassSummary *out,
                                                        int32_t *run_list, int64_t run_cap,
-                                                       int gated) {
+                                                       int gated, int64_t new_tail,
+                                                       int64_t *verdict) {
   __shared__ int64_t red[2 * CMP_THREADS / WAVE];
-  if (gated && c->chain_hold) {
-    // the intake launched right before was refused: no round runs, and the
-    // running list the list kernel gathered is dropped
+  if (gated) {
+    // The intake launched right before has no commit of its own: its
+    // workgroups counted the invalid requests.  Every wave reads the count
+    // before thread 0 clears it (the barrier), so all take the same branch.
+    // A clean batch moves the tail; a refused one changes nothing, no round
+    // runs, and the running list the list kernel gathered is dropped.
+    const unsigned long long bad = c->enq_bad;
+    __syncthreads();
     if (threadIdx.x == 0) {
-      c->chain_hold = 0;
-      c->run_n = 0;
+      *verdict = int64_t(bad);
+      c->enq_bad = 0;
+      if (bad)
+        c->run_n = 0;
+      else
+        c->tail = new_tail;
     }
-    return;
+    if (bad) return;
   }
   __shared__ ChainState L;
   // round summaries stay in LDS until the end: stores to host memory inside
@@ -1057,7 +1067,7 @@ __global__ __launch_bounds__(CMP_THREADS) void k_chain(DevCtl *c, QueueArrays q,
     L.capacity = c->capacity;
     L.used = c->used;
     L.head = c->head;
-    L.tail = c->tail;
+    L.tail = gated ? new_tail : c->tail;
     L.adm_base = 0;
     L.rel_jobs = c->released_jobs;
     L.rel_bytes = c->released_bytes;
@@ -1130,12 +1140,11 @@ __global__ __launch_bounds__(256) void k_enqueue_checked(DevCtl *c, QueueArrays 
   if (threadIdx.x == 0 && bad) add_relaxed(&c->enq_bad, (unsigned long long)bad);
 }
 
-__global__ void k_enqueue_commit(DevCtl *c, int64_t new_tail, int64_t *verdict, int hold) {
+__global__ void k_enqueue_commit(DevCtl *c, int64_t new_tail, int64_t *verdict) {
   if (threadIdx.x || blockIdx.x) return;
   const unsigned long long b = c->enq_bad;
   if (!b) c->tail = new_tail;
   c->enq_bad = 0;
-  if (hold) c->chain_hold = b ? 1 : 0;
   *verdict = int64_t(b);
 }
 
@@ -1386,7 +1395,7 @@ int adm_pass_ctx(AdmEngine &e, int policy, const QueueArrays &q, const JobArrays
 
 int adm_chain(AdmEngine &e, int policy, const QueueArrays &q, const JobArrays &jb, int rounds,
               const uint8_t *masks, int64_t n_mask, int32_t *run_list, hipStream_t s, bool gated,
-              bool none_running) {
+              bool none_running, int64_t new_tail) {
   if (rounds <= 0 || rounds > MAX_CHAIN) return SCHED_E_INVALID;
   const int filter = policy == SCHED_POLICY_MMU ? 1 : 0;
   const bool listed = rounds > 1 && masks && n_mask > 0;
@@ -1404,7 +1413,7 @@ int adm_chain(AdmEngine &e, int policy, const QueueArrays &q, const JobArrays &j
                                                        rounds, L0, filter, e.d_sum,
                                                        listed ? run_list : nullptr,
                                                        int64_t(jb.max_jobs) + q.capacity,
-                                                       gated ? 1 : 0)));
+                                                       gated ? 1 : 0, new_tail, e.d_flag)));
   SCHED_HIP_TRY(hipGetLastError());
   e.launch += rounds;
   SCHED_HIP_TRY(hipStreamSynchronize(s));
@@ -1437,14 +1446,16 @@ int adm_enqueue(AdmEngine &e, const QueueArrays &q, int64_t at, int64_t n, const
 
 int adm_enqueue_launch(AdmEngine &e, const QueueArrays &q, int64_t at, int64_t n, const int32_t *job,
                        const int64_t *demand, const int32_t *prio_of_job, int64_t seq0,
-                       int32_t n_jobs, int64_t capacity, hipStream_t s, int hold) {
+                       int32_t n_jobs, int64_t capacity, hipStream_t s, bool commit) {
   volatile int64_t *v = e.h_flag;
   *v = -1;
   k_enqueue_checked<<<grid_for(n, 256, 4096), 256, 0, s>>>(e.d_ctl, q, at, n, job, demand,
                                                            prio_of_job, seq0, n_jobs, capacity);
   SCHED_HIP_TRY(hipGetLastError());
-  k_enqueue_commit<<<1, 64, 0, s>>>(e.d_ctl, at + n, e.d_flag, hold);
-  SCHED_HIP_TRY(hipGetLastError());
+  if (commit) {
+    k_enqueue_commit<<<1, 64, 0, s>>>(e.d_ctl, at + n, e.d_flag);
+    SCHED_HIP_TRY(hipGetLastError());
+  }
   return SCHED_OK;
 }
 
@@ -1452,7 +1463,8 @@ int adm_enqueue_checked(AdmEngine &e, const QueueArrays &q, int64_t at, int64_t 
                         const int64_t *demand, const int32_t *prio_of_job, int64_t seq0,
                         int32_t n_jobs, int64_t capacity, hipStream_t s, int64_t *n_bad) {
   volatile int64_t *v = e.h_flag;
-  if (int rc = adm_enqueue_launch(e, q, at, n, job, demand, prio_of_job, seq0, n_jobs, capacity, s, 0))
+  if (int rc = adm_enqueue_launch(e, q, at, n, job, demand, prio_of_job, seq0, n_jobs, capacity, s,
+                                  true))
     return rc;
   SCHED_HIP_TRY(hipStreamSynchronize(s));
   const int64_t b = *v;

@@ -1015,14 +1015,15 @@ extern "C" int sched_enqueue_chain(sched_ctx_t *c, int64_t n, const int32_t *d_j
   if (n > 0)
     if (int rc = adm_enqueue_launch(c->eng, c->q, c->sh->tail_h, n, d_job, d_demand,
                                     c->d_prio_of_job, c->sh->seq_next, c->sh->n_jobs, c->capacity, s,
-                                    1))
+                                    false))
       return rc;
-  // the chain is queued right behind the intake; a refused intake leaves it
-  // nothing to do (gated), and the one synchronisation is the chain's own
+  // the chain is queued right behind the intake and commits it (gated): a
+  // refused intake leaves it nothing to do, and the one synchronisation is
+  // the chain's own
   const bool none = c->none_running;
   c->none_running = false;
   if (int rc = adm_chain(c->eng, c->policy, c->q, c->jb, rounds, d_masks, n_mask, c->d_run_list, s,
-                         n > 0, none))
+                         n > 0, none, c->sh->tail_h + n))
     return rc;
   if (s == c->stream) c->reset_pending = false;
   if (n > 0) {
