@@ -404,40 +404,54 @@ __device__ __forceinline__ void round_load(const int64_t *__restrict__ demand, i
   }
 }
 
-// One tile of a round (whole workgroup).  raw: the tile's demands from
-// round_load.  Returns true when the tile lies past the round's break (so
-// does every later tile).
-__device__ __forceinline__ bool round_tile(DevCtl *c, const int64_t *__restrict__ demand,
-                                           uint8_t *__restrict__ decision, int64_t mask,
-                                           unsigned long long *flags, int s, int nx,
-                                           uint32_t epoch, int32_t polls, int64_t R, int64_t cap,
-                                           bool filter, int64_t start, int64_t end, long long t,
-                                           int64_t base, const int64_t (&raw)[RND_ITEMS],
-                                           int64_t *red, int64_t &s_E, int64_t &s_brk_sum,
-                                           int64_t &acc_sum, int64_t &acc_cnt, int64_t &acc_hi) {
-  const int tid = threadIdx.x;
-  int64_t x[RND_ITEMS];
+// A tile of a round is handled in two steps.  round_reduce takes its
+// candidates (bit j of the returned mask: this thread's item j) and their
+// sum, and publishes the sum at once for the tiles after it (tile 0, whose
+// prefix is 0, publishes it as inclusive).  round_finish then looks back for
+// the tile's exclusive prefix and decides it.  The round loop reduces a
+// workgroup's next tile before it finishes the current one, so a tile's sum
+// is out before the look-back of the tile before it has ended: the tiles
+// after it find it instead of waiting for it.
+// Candidates are clamped to cap = R + 1 (only FIFO, which does not filter,
+// sees larger ones): a prefix exceeds R exactly when the unclamped one does,
+// and every sum below stays under 2^59, so no addition can wrap whatever the
+// int64 demands are.
+__device__ __forceinline__ uint32_t round_reduce(unsigned long long *flags, uint32_t epoch,
+                                                 long long t, int64_t R, int64_t cap, bool filter,
+                                                 const int64_t (&raw)[RND_ITEMS], int64_t *red,
+                                                 int64_t &Araw) {
+  uint32_t cm = 0;
   int64_t tsum = 0;
-  // Candidates are clamped to cap = R + 1 (only FIFO, which does not filter,
-  // sees larger ones): a prefix exceeds R exactly when the unclamped one
-  // does, and every sum below stays under 2^59, so no addition can wrap
-  // whatever the int64 demands are.
 #pragma unroll
   for (int j = 0; j < RND_ITEMS; ++j) {
     const int64_t v = raw[j];
     const bool cd = v >= 0 && (!filter || v <= R);
-    const int64_t vc = v < cap ? v : cap;
-    x[j] = cd ? vc : -1;
-    tsum += cd ? vc : 0;
+    tsum += cd ? (v < cap ? v : cap) : 0;
+    cm |= uint32_t(cd) << j;
   }
-  const int64_t Araw = block_sum<RND_THREADS>(tsum, red);
+  Araw = block_sum<RND_THREADS>(tsum, red);
   const int64_t A = Araw < cap ? Araw : cap;
+  if (threadIdx.x == 0) st_relaxed(&flags[t], pack_flag(epoch, t == 0 ? FL_INC : FL_AGG, A));
+  return cm;
+}
 
+// The second step of tile t (whole workgroup): cm and Araw from
+// round_reduce.  Returns true when the tile lies past the round's break (so
+// does every later tile).
+__device__ __forceinline__ bool round_finish(DevCtl *c, const int64_t *__restrict__ demand,
+                                             uint8_t *__restrict__ decision, int64_t mask,
+                                             unsigned long long *flags, int s, int nx,
+                                             uint32_t epoch, int32_t polls, int64_t R, int64_t cap,
+                                             bool filter, int64_t start, int64_t end, long long t,
+                                             int64_t base, uint32_t cm, int64_t Araw, int64_t *red,
+                                             int64_t &s_E, int64_t &s_brk_sum, int64_t &acc_sum,
+                                             int64_t &acc_cnt, int64_t &acc_hi) {
+  const int tid = threadIdx.x;
+  const int64_t A = Araw < cap ? Araw : cap;
   if (Araw == 0) {
     // No candidate in this tile: every entry is rejected whatever the
-    // prefix before it is, so the tile needs no look-back.  It publishes
-    // its zero sum for the tiles after it (tile 0 knows its prefix is 0).
-    if (tid == 0) st_relaxed(&flags[t], pack_flag(epoch, t == 0 ? FL_INC : FL_AGG, 0));
+    // prefix before it is, so the tile needs no look-back (its zero sum is
+    // published already).
 #pragma unroll
     for (int j = 0; j < RND_ITEMS; ++j) {
       const int64_t p = base + int64_t(j) * RND_THREADS + tid;
@@ -455,10 +469,7 @@ __device__ __forceinline__ bool round_tile(DevCtl *c, const int64_t *__restrict_
     // the workgroup that owns that tile having started.
     const int lane = tid;
     int64_t E = 0;
-    if (t == 0) {
-      if (lane == 0) st_relaxed(&flags[t], pack_flag(epoch, FL_INC, A));
-    } else {
-      if (lane == 0) st_relaxed(&flags[t], pack_flag(epoch, FL_AGG, A));
+    if (t != 0) {
       long long p = t - 1;
       int32_t waited = 0;
       bool has_own = false;
@@ -540,7 +551,7 @@ __device__ __forceinline__ bool round_tile(DevCtl *c, const int64_t *__restrict_
     for (int j = 0; j < RND_ITEMS; ++j) {
       const int64_t p = base + int64_t(j) * RND_THREADS + tid;
       if (p < end) {
-        const bool a = x[j] >= 0;
+        const bool a = (cm >> j) & 1u;
         decision[p & mask] = a ? 1 : 0;
         if (a) {
           ++tcnt;
@@ -558,7 +569,16 @@ __device__ __forceinline__ bool round_tile(DevCtl *c, const int64_t *__restrict_
     return false;
   }
 
-  // This tile holds the break: scan it row by row in queue order.
+  // The break lies in this tile (one tile per round): its demands are read
+  // again, the candidates being those round_reduce took.
+  int64_t x[RND_ITEMS];
+#pragma unroll
+  for (int j = 0; j < RND_ITEMS; ++j) {
+    const int64_t p = base + int64_t(j) * RND_THREADS + tid;
+    const int64_t v = ((cm >> j) & 1u) ? demand[p & mask] : int64_t(-1);
+    x[j] = v >= 0 ? (v < cap ? v : cap) : -1;
+  }
+  // scan it row by row in queue order
   int64_t carry = E, brk = -1, brk_sum = 0;
   for (int j = 0; j < RND_ITEMS; ++j) {
     const int64_t p = base + int64_t(j) * RND_THREADS + tid;
@@ -610,17 +630,27 @@ __device__ __forceinline__ bool round_tile(DevCtl *c, const int64_t *__restrict_
   return false;
 }
 
-// Workgroup b of G decides tiles b, b + G, b + 2G, ... in that order, and
-// loads each tile while the one before it is decided.  It stops at the end of
-// the queue or past the round's break (the marker is read by one thread and
-// shared through LDS, so every thread takes the same branch).  The loop is
-// unrolled by two so that both tile buffers stay in registers.
-__global__ __launch_bounds__(RND_THREADS) void k_round(DevCtl *c, const int64_t *__restrict__ demand,
+// Workgroup b of G decides tiles b, b + G, b + 2G, ... in that order.  One
+// data buffer serves the whole sequence: at each step the next tile (already
+// loaded) is reduced, the buffer is refilled with the tile after it, and
+// only then is the current tile finished, so the refill lands while the
+// current tile looks back and its decisions are written.  The sequence
+// stops at the end of the queue or past the round's break (the marker is
+// read by one thread before a tile is finished and shared through LDS after
+// it; a marker set meanwhile is seen one tile later, and a tile past the
+// break finds that out in its look-back).  Words handed over through LDS
+// alternate by step parity: a word is written again only two steps on,
+// after a barrier every wave has passed.
+// Four workgroups per CU (at most 128 registers per lane): with one data
+// buffer per workgroup, the fourth keeps as many loads in flight as three
+// workgroups with two buffers did.
+__global__ __launch_bounds__(RND_THREADS) __attribute__((amdgpu_waves_per_eu(4, 4)))
+void k_round(DevCtl *c, const int64_t *__restrict__ demand,
                                                        uint8_t *__restrict__ decision, int64_t mask,
                                                        unsigned long long *flags, uint32_t L,
                                                        uint32_t epoch, int32_t polls) {
   __shared__ int64_t red[RND_THREADS / WAVE];
-  __shared__ long long s_bt;
+  __shared__ long long s_bt[2];
   __shared__ int64_t s_E;
   __shared__ int64_t s_brk_sum;
   const int tid = threadIdx.x;
@@ -638,40 +668,42 @@ __global__ __launch_bounds__(RND_THREADS) void k_round(DevCtl *c, const int64_t 
   const long long G = gridDim.x;
   // thread 0's totals over the whole tiles this workgroup decided
   int64_t acc_sum = 0, acc_cnt = 0, acc_hi = -1;
-  // The tile after t for this workgroup, or -1.  Thread 0 reads the break
-  // marker before t is decided (so the read overlaps that work; a marker
-  // set meanwhile is seen one tile later, and a tile past the break finds
-  // that out itself) and shares it through LDS after t, so that every
-  // thread takes the same branch.
-  long long bt = LLONG_MAX;
-  auto next_tile = [&](long long t) -> long long {
-    if (tid == 0) s_bt = bt;
-    __syncthreads();
-    const long long tn = t + G;
-    return (tn < n_tiles && tn <= s_bt) ? tn : -1;
-  };
 
   long long t = (long long)blockIdx.x < n_tiles ? (long long)blockIdx.x : -1;
-  int64_t xa[RND_ITEMS], xb[RND_ITEMS];
-  if (t >= 0) round_load(demand, mask, start + int64_t(t) * TILE, end, xa);
+  int64_t x[RND_ITEMS];
+  uint32_t cm = 0;
+  int64_t Araw = 0;
+  if (t >= 0) {
+    round_load(demand, mask, start + int64_t(t) * TILE, end, x);
+    cm = round_reduce(flags, epoch, t, R, cap, filter, x, red, Araw);
+  }
+  long long tn = t >= 0 && t + G < n_tiles ? t + G : -1;
+  if (tn >= 0) round_load(demand, mask, start + int64_t(tn) * TILE, end, x);
+  int par = 0;
   while (t >= 0) {
+    long long bt = LLONG_MAX;
     if (tid == 0) bt = ld_relaxed(&c->break_tile[s]);
-    long long tn = t + G < n_tiles ? t + G : -1;
-    if (tn >= 0) round_load(demand, mask, start + int64_t(tn) * TILE, end, xb);
-    if (round_tile(c, demand, decision, mask, flags, s, nx, epoch, polls, R, cap, filter, start,
-                   end, t, start + int64_t(t) * TILE, xa, red, s_E, s_brk_sum, acc_sum, acc_cnt,
-                   acc_hi))
+    // the next tile: reduced (its sum published) before this one finishes
+    uint32_t cm_n = 0;
+    int64_t Araw_n = 0;
+    long long tnn = -1;
+    if (tn >= 0) {
+      cm_n = round_reduce(flags, epoch, tn, R, cap, filter, x, red, Araw_n);
+      tnn = tn + G < n_tiles ? tn + G : -1;
+      if (tnn >= 0) round_load(demand, mask, start + int64_t(tnn) * TILE, end, x);
+    }
+    if (round_finish(c, demand, decision, mask, flags, s, nx, epoch, polls, R, cap, filter, start,
+                     end, t, start + int64_t(t) * TILE, cm, Araw, red, s_E, s_brk_sum, acc_sum,
+                     acc_cnt, acc_hi))
       break;
-    t = next_tile(t);
-    if (t < 0) break;
-    if (tid == 0) bt = ld_relaxed(&c->break_tile[s]);
-    tn = t + G < n_tiles ? t + G : -1;
-    if (tn >= 0) round_load(demand, mask, start + int64_t(tn) * TILE, end, xa);
-    if (round_tile(c, demand, decision, mask, flags, s, nx, epoch, polls, R, cap, filter, start,
-                   end, t, start + int64_t(t) * TILE, xb, red, s_E, s_brk_sum, acc_sum, acc_cnt,
-                   acc_hi))
-      break;
-    t = next_tile(t);
+    if (tid == 0) s_bt[par] = bt;
+    __syncthreads();
+    if (tn < 0 || tn > s_bt[par]) break;
+    par ^= 1;
+    t = tn;
+    cm = cm_n;
+    Araw = Araw_n;
+    tn = tnn;
   }
   if (tid == 0) {
     if (acc_cnt) {
@@ -1213,14 +1245,17 @@ int adm_engine_attach(AdmEngine &e, int device, DevCtl *d_ctl, unsigned long lon
 int adm_engine_grid(AdmEngine &e, int device) {
   int cus = 0;
   SCHED_HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device));
-  // The round grid: three workgroups per CU (at most what the device holds
-  // at once).  With tiles dealt in interleaved order a candidate-free round
-  // of 2^26 entries streams in ~111 us with three or four per CU and ~118 us
-  // with two: each workgroup keeps two tiles of loads in flight, so the
-  // third adds the memory parallelism a round needs; a fourth adds nothing.
+  // The round grid: four workgroups per CU (at most what the device holds
+  // at once).  Each workgroup keeps one tile of loads in flight while it
+  // finishes the tile before (the next tile is reduced first, so that its
+  // sum is published early); with tiles dealt in interleaved order a
+  // candidate-free round of 2^26 entries streams in ~113 us with four per
+  // CU, and a FIFO round in which every tile holds candidates (and so looks
+  // back) in ~180 us, against ~240 us when a tile's sum was published only
+  // once the tile before it had finished.
   int per_cu = 0;
   SCHED_HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_round, RND_THREADS, 0));
-  per_cu = per_cu < 1 ? 1 : (per_cu > 3 ? 3 : per_cu);
+  per_cu = per_cu < 1 ? 1 : (per_cu > 4 ? 4 : per_cu);
   e.round_grid = cus * per_cu;
   return SCHED_OK;
 }
