@@ -547,8 +547,8 @@ def main():
         return 0
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; the admission state is "
-                                   "per device (sharding across GPUs is not built)", "n_gpus": args.gpus}))
+        print(json.dumps({"error": "the benchmark runs on one GPU: the admission state is "
+                                   "per device, and sharding across GPUs is not implemented", "n_gpus": args.gpus}))
         return 2
 
     import numpy as np

@@ -857,7 +857,7 @@ def test_enqueue_chain_refused_batch_changes_nothing(cs):
         st1 = cs.sched_stats(ctx)[1]
         assert st1["used"] == st0["used"] and st1["pending"] == st0["pending"]
         assert [cs.sched_reservation(ctx, j)[1] for j in range(n_jobs)] == res0
-        # a plain chain afterwards runs (the device flag was cleared): round 1
+        # a plain chain afterwards runs (the refused intake left nothing behind): round 1
         # releases every running job (mask 1) and admits from the waiting ones
         rc, r2 = cs.sched_pass_chain_array(ctx, 2, d_masks)
         assert rc == 0
