@@ -69,19 +69,46 @@ __device__ __forceinline__ void reset_next_slot(DevCtl *c, uint32_t L) {
 // the count is.  No release/acquire is needed (at device scope that would
 // write back the whole L2 of the workgroup's XCD once per workgroup); plain
 // stores (decisions, records) are only read after the kernel ends.
+// The pass summary after a round, into host-mapped memory (thread 0 of the
+// workgroup that closes the round; the totals are read atomically, the
+// scheduler state was written by earlier launches).
+__device__ __forceinline__ void round_summary(DevCtl *c, int64_t R_after, int64_t start_final,
+                                              int32_t done, PassSummary *out) {
+  out->admitted = ld_relaxed(&c->p_admitted);
+  out->admitted_bytes = ld_relaxed(&c->p_admitted_bytes);
+  out->R0 = c->p_R0;
+  out->R_after = R_after;
+  out->rounds = ld_relaxed(&c->p_rounds);
+  out->start_final = start_final;
+  out->hi = ld_relaxed(&c->p_hi);
+  out->head = c->head;
+  out->tail = c->tail;
+  out->used = c->used;
+  out->adm_base = c->adm_base;
+  out->done = done;
+}
+
 __device__ __forceinline__ void block_done(DevCtl *c, int s, int nx, int64_t a, int64_t R,
-                                           int64_t end, unsigned n_blocks) {
+                                           int64_t end, unsigned n_blocks, PassSummary *out) {
   if (a) add_relaxed(&c->round_sum[s], (unsigned long long)a);
   asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
   const unsigned long long prev = add_relaxed(&c->tiles_done[s], 1ULL);
   if (prev + 1 != (unsigned long long)n_blocks) return;
-  if (ld_relaxed(&c->break_tile[s]) != LLONG_MAX) return;
+  if (ld_relaxed(&c->break_tile[s]) != LLONG_MAX) {
+    // the break tile wrote the next start state (atomically) before it
+    // counted itself out
+    round_summary(c, ld_relaxed(&c->rec[nx].R), ld_relaxed(&c->rec[nx].start),
+                  ld_relaxed(&c->rec[nx].done), out);
+    return;
+  }
   const int64_t sum = int64_t(ld_relaxed(&c->round_sum[s]));
   add_relaxed(&c->p_admitted_bytes, sum);
   add_relaxed(&c->p_rounds, (int64_t)1);
   c->rec[nx].R = R - sum;
   c->rec[nx].start = end;
   c->rec[nx].done = 1;
+  asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+  round_summary(c, R - sum, end, 1, out);
 }
 
 __device__ __forceinline__ void pass_init(DevCtl *c, uint32_t L, int filter, int from_state,
@@ -114,23 +141,6 @@ __global__ void k_prologue(DevCtl *c, uint32_t L, int filter, int from_state, in
   pass_init(c, L, filter, from_state, R0, start, end, 0);
 }
 
-// Pass summary into host-mapped memory (stateless scans).
-__global__ void k_summary(DevCtl *c, uint32_t L, PassSummary *out) {
-  if (threadIdx.x != 0) return;
-  const RoundRec &r = c->rec[L & 3];
-  out->admitted = c->p_admitted;
-  out->admitted_bytes = c->p_admitted_bytes;
-  out->R0 = c->p_R0;
-  out->R_after = r.R;
-  out->rounds = c->p_rounds;
-  out->start_final = r.start;
-  out->hi = c->p_hi;
-  out->head = c->head;
-  out->tail = c->tail;
-  out->used = c->used;
-  out->adm_base = c->adm_base;
-  out->done = r.done;
-}
 
 // ---------------------------------------------------------------------------
 // Single-wave windowed rounds
@@ -623,9 +633,9 @@ __device__ __forceinline__ bool round_finish(DevCtl *c, const int64_t *__restric
     add_relaxed(&c->p_admitted_bytes, brk_sum);
     add_relaxed(&c->p_rounds, (int64_t)1);
     const int64_t R2 = R - brk_sum;
-    c->rec[nx].R = R2;
-    c->rec[nx].start = brk + 1;
-    c->rec[nx].done = (!filter || R2 == 0 || brk + 1 >= end) ? 1 : 0;
+    st_relaxed(&c->rec[nx].R, R2);
+    st_relaxed(&c->rec[nx].start, brk + 1);
+    st_relaxed(&c->rec[nx].done, int32_t((!filter || R2 == 0 || brk + 1 >= end) ? 1 : 0));
   }
   return false;
 }
@@ -648,7 +658,8 @@ __global__ __launch_bounds__(RND_THREADS) __attribute__((amdgpu_waves_per_eu(4, 
 void k_round(DevCtl *c, const int64_t *__restrict__ demand,
                                                        uint8_t *__restrict__ decision, int64_t mask,
                                                        unsigned long long *flags, uint32_t L,
-                                                       uint32_t epoch, int32_t polls) {
+                                                       uint32_t epoch, int32_t polls,
+                                                       PassSummary *out) {
   __shared__ int64_t red[RND_THREADS / WAVE];
   __shared__ long long s_bt[2];
   __shared__ int64_t s_E;
@@ -658,7 +669,10 @@ void k_round(DevCtl *c, const int64_t *__restrict__ demand,
   const RoundRec r = c->rec[s];
   if (blockIdx.x == 0 && tid == 0) {
     reset_next_slot(c, L);
-    if (r.done) c->rec[nx] = r;
+    if (r.done) {
+      c->rec[nx] = r;
+      round_summary(c, r.R, r.start, 1, out);
+    }
   }
   if (r.done) return;
   const int64_t R = r.R, start = r.start, end = c->p_end;
@@ -710,7 +724,7 @@ void k_round(DevCtl *c, const int64_t *__restrict__ demand,
       add_relaxed(&c->p_admitted, acc_cnt);
       max_relaxed(&c->p_hi, acc_hi);
     }
-    block_done(c, s, nx, acc_sum, R, end, gridDim.x);
+    block_done(c, s, nx, acc_sum, R, end, gridDim.x, out);
   }
 }
 
@@ -1300,15 +1314,6 @@ static int next_epoch(AdmEngine &e, hipStream_t s, uint32_t *ep) {
   return SCHED_OK;
 }
 
-// Summary of the pass whose current state is in slot L & 3, into h_sum[0].
-static int read_summary(AdmEngine &e, uint32_t L, hipStream_t s) {
-  k_summary<<<1, 64, 0, s>>>(e.d_ctl, L, e.d_sum);
-  SCHED_HIP_TRY(hipGetLastError());
-  if (e.sum_copy)
-    SCHED_HIP_TRY(hipMemcpyAsync(e.h_sum, e.d_sum, sizeof(PassSummary), hipMemcpyDeviceToHost, s));
-  SCHED_HIP_TRY(hipStreamSynchronize(s));
-  return SCHED_OK;
-}
 
 static void fill_out(const PassSummary &h, PassOut *out) {
   out->admitted = h.admitted;
@@ -1349,11 +1354,14 @@ static int run_rounds(AdmEngine &e, const int64_t *demand, uint8_t *decision, in
       SCHED_PROF_LAUNCH("k_round", s,
                         (k_round<<<grid, RND_THREADS, 0, s>>>(e.d_ctl, demand, decision, mask,
                                                               e.d_flags, L, ep,
-                                                              g_lookback_polls.load())));
+                                                              g_lookback_polls.load(), e.d_sum)));
       SCHED_HIP_TRY(hipGetLastError());
       L = advance(e);
     }
-    if (int rc = read_summary(e, L, s)) return rc;
+    // the round that closed the batch wrote the pass summary
+    if (e.sum_copy)
+      SCHED_HIP_TRY(hipMemcpyAsync(e.h_sum, e.d_sum, sizeof(PassSummary), hipMemcpyDeviceToHost, s));
+    SCHED_HIP_TRY(hipStreamSynchronize(s));
     if (e.h_sum[0].done) break;
   }
   *Lio = L;
