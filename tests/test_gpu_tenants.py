@@ -87,6 +87,20 @@ def test_gemm_operands_exact(cs):
                                    (256, 512, 192), (512, 768, 320), (4096, 256, 576),
                                    (1024, 1024, 1024), (2048, 2048, 128)])
 def test_gemm_full(cs, M, N, K):
+    _check_full(cs, M, N, K)
+
+
+# Every entry of grids with more 256-tiles than the device has CUs, so that
+# CUs run tiles one after another: (4096, 8192, 192) is 512 tiles in the XCD
+# bands with an odd k-tile count, (8192, 4096, 64) 512 tiles of one k-tile
+# each, (3072, 6144, 128) 288 tiles in the plain order.
+@pytest.mark.parametrize("M,N,K", [(4096, 8192, 192), (8192, 4096, 64), (3072, 6144, 128)])
+def test_gemm_full_many_tiles(cs, M, N, K):
+    assert (M // 256) * (N // 256) > torch.cuda.get_device_properties(0).multi_processor_count
+    _check_full(cs, M, N, K)
+
+
+def _check_full(cs, M, N, K):
     _, _, C = _gemm(cs, M, N, K)
     ref = T.gemm_ref_full(1, 2, M, N, K)
     got = C.cpu().numpy().astype(np.float64)
