@@ -4,7 +4,7 @@ import pytest
 import torch
 
 from oracle import sched as S
-from workloads import c2_queue, c2d_queue, random_queue
+from workloads import c2_queue, c2d_fifo_queue, c2d_queue, random_queue
 
 pytestmark = pytest.mark.gpu
 
@@ -170,11 +170,32 @@ def test_scan_dense_fixed_point(cs, wl):
 
 
 @pytest.mark.slow
-def test_scan_dense_full_size(cs):
+@pytest.mark.parametrize("wl", [1, 64])
+def test_scan_dense_full_size(cs, wl):
+    """The dense first-fit pass at 2^26 entries, with the window walk the
+    benchmark times (64 windows) and with a single window.  Every decision is
+    checked by the first-fit fixed point, which is unique, so this equals the
+    sequential result entry for entry."""
     q = c2d_queue(seed=2, n=1 << 26)
-    dec, r = _scan(cs, cs.SCHED_POLICY_MMU, q.demand, q.capacity, 1)
+    dec, r = _scan(cs, cs.SCHED_POLICY_MMU, q.demand, q.capacity, wl)
+    assert set(np.unique(dec)) <= {0, 1}
     a = dec.astype(bool)
     assert S.first_fit_fixed_point(q.demand, q.capacity, a)
+    assert r["admitted"] == int(a.sum())
+    assert r["free_after"] == q.capacity - int(q.demand[a].sum())
+
+
+@pytest.mark.slow
+def test_scan_fifo_whole_queue_full_size(cs):
+    """FIFO over 2^26 entries whose demands sum to the capacity: the whole
+    queue is the admitted prefix and no memory is left (the FIFO case of the
+    dense sweep, with the window limit the benchmark passes, which a FIFO scan
+    caps at two windows, so every tile of the grid round looks back)."""
+    q = c2d_fifo_queue(seed=2, n=1 << 26)
+    dec, r = _scan(cs, cs.SCHED_POLICY_FIFO, q.demand, q.capacity, 64)
+    assert np.all(dec == 1)
+    assert r["admitted"] == q.n and r["free_after"] == 0
+    assert r["last_admitted"] == q.n - 1
 
 
 def test_scan_rejects_bad_args(cs):
