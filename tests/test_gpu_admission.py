@@ -186,6 +186,18 @@ def test_scan_dense_full_size(cs, wl):
 
 
 @pytest.mark.slow
+def test_scan_dense_largest_size(cs):
+    """The largest dense pass the benchmark sweeps, 2^28 entries (2 GiB of
+    demands), with its 64-window walk, checked over every entry."""
+    q = c2d_queue(seed=5, n=1 << 28)
+    dec, r = _scan(cs, cs.SCHED_POLICY_MMU, q.demand, q.capacity, 64)
+    a = dec.astype(bool)
+    assert S.first_fit_fixed_point(q.demand, q.capacity, a)
+    assert r["admitted"] == int(a.sum())
+    assert r["free_after"] == q.capacity - int(q.demand[a].sum())
+
+
+@pytest.mark.slow
 def test_scan_fifo_whole_queue_full_size(cs):
     """FIFO over 2^26 entries whose demands sum to the capacity: the whole
     queue is the admitted prefix and no memory is left (the FIFO case of the
