@@ -354,7 +354,8 @@ def dense_sweep(cs, torch, dev, sizes, seed, window, reps=5):
             for _ in range(reps):
                 assert cs.sched_scan(pol, dd, q.capacity, dec, window_limit=window)[0] == 0
             torch.cuda.synchronize()
-            ms = sum(cs.sched_profile_read(k)[1] for k in ("k_round", "k_window"))
+            ms = sum(cs.sched_profile_read(k)[1] for k in ("k_round", "k_window", "k_split_reduce",
+                                                           "k_split_scan", "k_split_write"))
             cs.sched_profile(False)
             a = dec.cpu().numpy().astype(bool)
             ok = (bool(a.all()) and r["free_after"] == 0) if pol == cs.SCHED_POLICY_FIFO else \

@@ -91,9 +91,18 @@ struct AdmEngine {
   int rounds_per_check = 1;         // round launches between host checks
   int device = 0;
   bool sum_copy = false;            // d_sum is plain device memory: copy it to h_sum
+  // split rounds (adm_split_init): tile sums, candidate bits, break record
+  bool split = false;
+  int64_t *d_agg = nullptr;
+  unsigned long long *d_bits = nullptr;
+  void *d_brk = nullptr;
 };
 
 int adm_engine_init(AdmEngine &e, int device, int64_t max_entries);
+// Buffers for split rounds (k_split_reduce / k_split_scan / k_split_write:
+// 8 B per tile and 1 bit per entry); the engine's FIFO scans use them from
+// then on instead of k_round.
+int adm_split_init(AdmEngine &e);
 // An engine over another process's control block and look-back flags (HIP
 // IPC mappings): only the host-side buffers are allocated here.
 int adm_engine_attach(AdmEngine &e, int device, DevCtl *d_ctl, unsigned long long *d_flags,

@@ -728,6 +728,275 @@ void k_round(DevCtl *c, const int64_t *__restrict__ demand,
   }
 }
 
+// ---------------------------------------------------------------------------
+// Split round: the same round in three launches, without look-back
+// ---------------------------------------------------------------------------
+// For the stateless scan, whose workspace the library owns, a round can be
+// taken apart: k_split_reduce reads every tile once and keeps its candidate
+// sum and candidate bits (1 bit per entry), k_split_scan (one workgroup) scans
+// the tile sums, finds the break and decides the break tile row by row, and
+// k_split_write writes the decision bytes of the tiles up to the break from
+// the bits.  No tile waits for another, and the demands are read in one
+// launch and the decisions written in another.  The round's record, slot and
+// summary protocol is k_round's: it reads rec[L & 3], writes rec[(L + 1) & 3],
+// and the last workgroup of k_split_write writes the pass summary.
+// It pays where k_round's look-back does not: in a FIFO pass whose tiles all
+// hold candidates (2^26 entries admitted whole: ~149 us against ~190 us per
+// call).  Where most tiles hold none (a first-fit round after the walk) the
+// three launches cost more than k_round's one (~149 us against ~133 us), so
+// only FIFO scans use it; the kernels take either policy.
+
+// Candidate sums (clamped to cap) and candidate bits of every tile of the
+// round; bit o of a tile's 64 words is the tile's entry o (queue order), so
+// the write pass can turn 16 bits into 16 contiguous decision bytes.  Two
+// data buffers: a tile's loads are in flight while the tile before it is
+// reduced.
+constexpr int SPLIT_WORDS = TILE / 64;  // candidate-bit words per tile
+
+__device__ __forceinline__ void split_tile(long long t, int64_t R, int64_t cap, bool filter,
+                                           const int64_t (&x)[RND_ITEMS], int64_t *red,
+                                           int64_t *__restrict__ agg,
+                                           unsigned long long *__restrict__ bits) {
+  const int tid = threadIdx.x, lane = tid & (WAVE - 1), w = tid / WAVE;
+  int64_t tsum = 0;
+  unsigned long long mine = 0;
+#pragma unroll
+  for (int j = 0; j < RND_ITEMS; ++j) {
+    const int64_t v = x[j];
+    const bool cd = v >= 0 && (!filter || v <= R);
+    tsum += cd ? (v < cap ? v : cap) : 0;  // <= 16 * cap: no overflow
+    // row j of the tile: entries j * RND_THREADS + tid, this wave's 64 of
+    // them one word; lane j keeps it
+    const unsigned long long m = __ballot(cd);
+    if (lane == j) mine = m;
+  }
+  if (lane < RND_ITEMS) bits[t * SPLIT_WORDS + lane * (RND_THREADS / WAVE) + w] = mine;
+  const int64_t A = block_sum<RND_THREADS>(tsum, red);  // <= TILE * cap < 2^59
+  if (tid == 0) agg[t] = A < cap ? A : cap;
+}
+
+__global__ __launch_bounds__(RND_THREADS) void k_split_reduce(const DevCtl *c,
+                                                              const int64_t *__restrict__ demand,
+                                                              int64_t mask, uint32_t L,
+                                                              int64_t *__restrict__ agg,
+                                                              unsigned long long *__restrict__ bits) {
+  __shared__ int64_t red[RND_THREADS / WAVE];
+  const RoundRec r = c->rec[L & 3];
+  if (r.done) return;
+  const int64_t R = r.R, start = r.start, end = c->p_end;
+  const int64_t cap = R + 1;
+  const bool filter = c->filter != 0;
+  const long long n_tiles = (end - start + TILE - 1) / TILE;
+  const long long G = gridDim.x;
+  long long t = blockIdx.x;
+  if (t >= n_tiles) return;
+  int64_t xa[RND_ITEMS], xb[RND_ITEMS];
+  round_load(demand, mask, start + int64_t(t) * TILE, end, xa);
+  for (;;) {
+    long long tn = t + G;
+    if (tn < n_tiles) round_load(demand, mask, start + int64_t(tn) * TILE, end, xb);
+    split_tile(t, R, cap, filter, xa, red, agg, bits);
+    if (tn >= n_tiles) break;
+    t = tn;
+    tn = t + G;
+    if (tn < n_tiles) round_load(demand, mask, start + int64_t(tn) * TILE, end, xa);
+    split_tile(t, R, cap, filter, xb, red, agg, bits);
+    if (tn >= n_tiles) break;
+    t = tn;
+  }
+}
+
+// Where a split round breaks (written by k_split_scan for k_split_write).
+struct SplitBreak {
+  int64_t tile;  // tiles before it admit all their candidates; n_tiles: no break
+  int64_t pos;   // the break entry (queue position); decisions are written up to it
+};
+
+constexpr int SPLIT_SCAN_THREADS = 1024;
+constexpr int SPLIT_BATCH = 16;  // tile sums a thread loads at once
+
+__global__ __launch_bounds__(SPLIT_SCAN_THREADS) void k_split_scan(
+    DevCtl *c, const int64_t *__restrict__ demand, int64_t mask, uint32_t L,
+    const int64_t *__restrict__ agg, SplitBreak *brk_out, PassSummary *out) {
+  constexpr int NT = SPLIT_SCAN_THREADS;
+  __shared__ int64_t red[NT / WAVE];
+  __shared__ int64_t s_b, s_E, s_brk, s_brk_sum;
+  const int tid = threadIdx.x;
+  const int s = L & 3, nx = (L + 1) & 3;
+  const RoundRec r = c->rec[s];
+  if (tid == 0) reset_next_slot(c, L);
+  if (r.done) {
+    if (tid == 0) {
+      c->rec[nx] = r;
+      round_summary(c, r.R, r.start, 1, out);
+    }
+    return;
+  }
+  const int64_t R = r.R, start = r.start, end = c->p_end;
+  const int64_t cap = R + 1;
+  const bool filter = c->filter != 0;
+  const long long n_tiles = (end - start + TILE - 1) / TILE;
+  // each thread sums a contiguous run of tile sums (loaded a batch at a
+  // time); one exclusive scan over the runs; the run holding the first tile
+  // whose inclusive prefix exceeds R walks its tiles to find it
+  const long long per = (n_tiles + NT - 1) / NT;
+  const long long lo = (long long)tid * per;
+  const long long hi = lo + per < n_tiles ? lo + per : n_tiles;
+  int64_t run = 0;
+  for (long long k0 = lo; k0 < hi; k0 += SPLIT_BATCH) {
+    int64_t v[SPLIT_BATCH];
+#pragma unroll
+    for (int u = 0; u < SPLIT_BATCH; ++u) v[u] = k0 + u < hi ? agg[k0 + u] : 0;
+#pragma unroll
+    for (int u = 0; u < SPLIT_BATCH; ++u) run = sat_add(run, v[u], cap);
+  }
+  int64_t total;
+  const int64_t before = block_excl_scan_sat<NT>(run, cap, red, &total);
+  // the run that crosses R (one at most), then the tile in it: the run's
+  // tile sums are loaded by one thread each and scanned together
+  const bool crosses = before <= R && sat_add(before, run, cap) > R;
+  const int64_t fr = block_min<NT>(crosses ? tid : NT, red);
+  if (tid == fr) s_E = before;
+  __syncthreads();
+  long long b = n_tiles;
+  if (fr < NT) {
+    const long long flo = fr * per;
+    const long long fhi = flo + per < n_tiles ? flo + per : n_tiles;
+    const int64_t a = flo + tid < fhi ? agg[flo + tid] : 0;  // per <= NT (checked on the host)
+    int64_t unused;
+    const int64_t e = sat_add(s_E, block_excl_scan_sat<NT>(a, cap, red, &unused), cap);
+    const int64_t fi = block_min<NT>(flo + tid < fhi && e <= R && sat_add(e, a, cap) > R ? tid : NT,
+                                     red);
+    if (tid == fi) s_E = e;
+    __syncthreads();
+    b = flo + fi;  // the run's inclusive prefix exceeds R, so fi < NT
+  }
+  int64_t brk, brk_sum;
+  if (b == n_tiles) {
+    // no break: every candidate up to the end is admitted
+    brk = end;
+    brk_sum = total;  // <= R
+  } else {
+    // decide the break tile row by row in queue order (the candidates are
+    // those k_split_reduce took); its inclusive prefix exceeds R, so some row
+    // holds the break
+    const int64_t base = start + int64_t(b) * TILE;
+    int64_t carry = s_E;
+    brk = end;
+    brk_sum = 0;
+    for (int j = 0; j < TILE / NT; ++j) {
+      const int64_t p = base + int64_t(j) * NT + tid;
+      int64_t v = p < end ? demand[p & mask] : int64_t(-1);
+      const bool cd = v >= 0 && (!filter || v <= R);
+      v = cd ? (v < cap ? v : cap) : 0;
+      int64_t rowtot;
+      const int64_t ex = block_excl_scan_sat<NT>(v, cap, red, &rowtot);
+      const int64_t P = sat_add(carry, sat_add(ex, v, cap), cap);
+      const int64_t f = block_min<NT>(cd && P > R ? tid : NT, red);
+      if (f < NT) {
+        if (tid == f) {
+          s_brk = p;
+          s_brk_sum = sat_add(carry, ex, cap);
+        }
+        __syncthreads();
+        brk = s_brk;
+        brk_sum = s_brk_sum;
+        break;
+      }
+      carry = sat_add(carry, rowtot, cap);
+    }
+  }
+  if (tid == 0) {
+    add_relaxed(&c->p_admitted_bytes, brk_sum);
+    add_relaxed(&c->p_rounds, (int64_t)1);
+    const int64_t R2 = R - brk_sum;
+    const int64_t nstart = b == n_tiles ? end : brk + 1;
+    c->rec[nx].R = R2;
+    c->rec[nx].start = nstart;
+    c->rec[nx].done = int32_t((!filter || R2 == 0 || nstart >= end) ? 1 : 0);
+    brk_out->tile = b;
+    brk_out->pos = brk;
+  }
+}
+
+// Decision bytes of the tiles up to the break, from the candidate bits: a
+// thread writes 16 contiguous entries, as one 16-byte store where the tile is
+// whole, admitted in full and 16-byte aligned; the workgroup that leaves last
+// writes the pass summary.
+__global__ __launch_bounds__(RND_THREADS) void k_split_write(
+    DevCtl *c, uint8_t *__restrict__ decision, int64_t mask, uint32_t L,
+    const unsigned long long *__restrict__ bits, const SplitBreak *brk_in, PassSummary *out) {
+  __shared__ int64_t red[RND_THREADS / WAVE];
+  const int s = L & 3, nx = (L + 1) & 3;
+  const RoundRec r = c->rec[s];
+  if (r.done) return;  // k_split_scan wrote the summary
+  const int64_t start = r.start, end = c->p_end;
+  const long long n_tiles = (end - start + TILE - 1) / TILE;
+  const long long b = brk_in->tile;
+  const int64_t bpos = brk_in->pos;
+  const long long n_dec = b < n_tiles ? b + 1 : n_tiles;
+  const int tid = threadIdx.x;
+  // contiguous positions map to contiguous bytes only without wrap-around
+  const bool vec = mask == -1 && ((uintptr_t(decision) + uint64_t(start)) & 15) == 0;
+  int64_t tcnt = 0, tmax = -1;
+  const long long G = gridDim.x;
+  for (long long t0 = blockIdx.x; t0 < n_dec; t0 += SPLIT_BATCH * G) {
+    // the bit words of a batch of this workgroup's tiles, loaded together
+    uint32_t mb[SPLIT_BATCH];
+#pragma unroll
+    for (int u = 0; u < SPLIT_BATCH; ++u) {
+      const long long t = t0 + u * G;
+      mb[u] = t < n_dec ? uint32_t(bits[t * SPLIT_WORDS + (tid >> 2)] >> (16 * (tid & 3))) & 0xFFFFu
+                        : 0u;
+    }
+#pragma unroll
+    for (int u = 0; u < SPLIT_BATCH; ++u) {
+    const long long t = t0 + u * G;
+    if (t >= n_dec) break;
+    const uint32_t m16 = mb[u];
+    const int64_t base = start + int64_t(t) * TILE;
+    const int64_t p0 = base + 16 * tid;
+    if (vec && t < b && base + TILE <= end) {
+      uint4 q;
+      uint32_t *qw = reinterpret_cast<uint32_t *>(&q);
+#pragma unroll
+      for (int k = 0; k < 4; ++k)
+        qw[k] = ((m16 >> (4 * k)) & 1u) | (((m16 >> (4 * k + 1)) & 1u) << 8) |
+                (((m16 >> (4 * k + 2)) & 1u) << 16) | (((m16 >> (4 * k + 3)) & 1u) << 24);
+      *reinterpret_cast<uint4 *>(decision + p0) = q;
+      tcnt += __builtin_popcount(m16);
+      if (m16) tmax = p0 + 31 - __builtin_clz(m16);
+    } else {
+#pragma unroll
+      for (int i = 0; i < 16; ++i) {
+        const int64_t p = p0 + i;
+        if (p < end && (t < b || p <= bpos)) {
+          const bool a = ((m16 >> i) & 1u) && (t < b || p < bpos);
+          decision[p & mask] = a ? 1 : 0;
+          if (a) {
+            ++tcnt;
+            tmax = p;
+          }
+        }
+      }
+    }
+    }
+  }
+  const int64_t cnt = block_sum<RND_THREADS>(tcnt, red);
+  const int64_t mx = block_max<RND_THREADS>(tmax, red);
+  if (tid == 0) {
+    if (cnt) {
+      add_relaxed(&c->p_admitted, cnt);
+      max_relaxed(&c->p_hi, mx + 1);
+    }
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");  // this workgroup's totals are in
+    const unsigned long long prev = add_relaxed(&c->tiles_done[s], 1ULL);
+    if (prev + 1 == (unsigned long long)gridDim.x)
+      round_summary(c, ld_relaxed(&c->rec[nx].R), ld_relaxed(&c->rec[nx].start),
+                    ld_relaxed(&c->rec[nx].done), out);
+  }
+}
+
 __global__ void k_fill_u64(unsigned long long *p, int64_t n, unsigned long long v) {
   for (int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; i < n;
        i += int64_t(gridDim.x) * blockDim.x)
@@ -1281,7 +1550,26 @@ int adm_fill_u64(unsigned long long *p, int64_t n, unsigned long long v, hipStre
   return SCHED_OK;
 }
 
+int adm_split_init(AdmEngine &e) {
+  // k_split_scan gives each of its threads at most one tile sum of the run
+  // that crosses R
+  const int64_t per = (e.max_tiles + SPLIT_SCAN_THREADS - 1) / SPLIT_SCAN_THREADS;
+  if (per > SPLIT_SCAN_THREADS) return SCHED_E_INVALID;
+  SCHED_HIP_TRY(hipMalloc(&e.d_agg, sizeof(int64_t) * e.max_tiles));
+  SCHED_HIP_TRY(hipMalloc(&e.d_bits, sizeof(unsigned long long) * SPLIT_WORDS * e.max_tiles));
+  SCHED_HIP_TRY(hipMalloc(&e.d_brk, sizeof(SplitBreak)));
+  e.split = true;
+  return SCHED_OK;
+}
+
 void adm_engine_free(AdmEngine &e) {
+  if (e.d_agg) (void)hipFree(e.d_agg);
+  if (e.d_bits) (void)hipFree(e.d_bits);
+  if (e.d_brk) (void)hipFree(e.d_brk);
+  e.d_agg = nullptr;
+  e.d_bits = nullptr;
+  e.d_brk = nullptr;
+  e.split = false;
   if (e.d_ctl) (void)hipFree(e.d_ctl);
   if (e.h_ctl) (void)hipHostFree(e.h_ctl);
   if (e.d_flags) (void)hipFree(e.d_flags);
@@ -1340,7 +1628,7 @@ constexpr int FIFO_WALK_WINDOWS = 2;
 // Round kernels until the pass recorded in slot L & 3 is done; returns the
 // launch id whose slot holds the final state.
 static int run_rounds(AdmEngine &e, const int64_t *demand, uint8_t *decision, int64_t mask,
-                      int64_t span_hint, hipStream_t s, uint32_t *Lio) {
+                      int64_t span_hint, hipStream_t s, uint32_t *Lio, bool split = false) {
   uint32_t L = *Lio;
   const int grid = grid_for(span_hint, TILE, e.round_grid);
   // every round decides at least one entry, so a pass needs at most
@@ -1349,6 +1637,23 @@ static int run_rounds(AdmEngine &e, const int64_t *demand, uint8_t *decision, in
   for (;;) {
     if ((budget -= e.rounds_per_check) < 0) return SCHED_E_INTERNAL;
     for (int i = 0; i < e.rounds_per_check; ++i) {
+      if (split) {
+        SplitBreak *brk = static_cast<SplitBreak *>(e.d_brk);
+        SCHED_PROF_LAUNCH("k_split_reduce", s,
+                          (k_split_reduce<<<grid, RND_THREADS, 0, s>>>(e.d_ctl, demand, mask, L,
+                                                                       e.d_agg, e.d_bits)));
+        SCHED_HIP_TRY(hipGetLastError());
+        SCHED_PROF_LAUNCH("k_split_scan", s,
+                          (k_split_scan<<<1, SPLIT_SCAN_THREADS, 0, s>>>(e.d_ctl, demand, mask, L,
+                                                                         e.d_agg, brk, e.d_sum)));
+        SCHED_HIP_TRY(hipGetLastError());
+        SCHED_PROF_LAUNCH("k_split_write", s,
+                          (k_split_write<<<grid, RND_THREADS, 0, s>>>(e.d_ctl, decision, mask, L,
+                                                                      e.d_bits, brk, e.d_sum)));
+        SCHED_HIP_TRY(hipGetLastError());
+        L = advance(e);
+        continue;
+      }
       uint32_t ep;
       if (int rc = next_epoch(e, s, &ep)) return rc;
       SCHED_PROF_LAUNCH("k_round", s,
@@ -1402,7 +1707,11 @@ int adm_scan(AdmEngine &e, int policy, const int64_t *demand, uint8_t *decision,
     k_prologue<<<1, 64, 0, s>>>(e.d_ctl, L, filter, 0, R0, start, end);
     SCHED_HIP_TRY(hipGetLastError());
   }
-  if (int rc = run_rounds(e, demand, decision, -1, end - start, s, &L)) return rc;
+  // FIFO scans take the split round where the engine has its buffers (one
+  // round: the first break ends the pass); first fit keeps k_round, which
+  // was faster for it
+  if (int rc = run_rounds(e, demand, decision, -1, end - start, s, &L, e.split && !filter))
+    return rc;
   fill_out(e.h_sum[0], out);
   return SCHED_OK;
 }

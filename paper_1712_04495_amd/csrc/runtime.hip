@@ -1149,6 +1149,9 @@ extern "C" int sched_scan(int32_t policy, int64_t n, const int64_t *d_demand, in
   if (w.cap_entries < n || !w.eng.d_ctl) {
     adm_engine_free(w.eng);
     if (int rc = adm_engine_init(w.eng, dev, std::max<int64_t>(n, 1 << 20))) return rc;
+    const char *split = getenv("SCHED_SCAN_SPLIT");
+    if (!(split && split[0] == '0'))
+      if (int rc = adm_split_init(w.eng)) return rc;
     w.cap_entries = std::max<int64_t>(n, 1 << 20);
   }
   return scan_finish(w.eng, policy, n, d_demand, R, d_decision, write_all, window_limit, s, out);

@@ -20,16 +20,23 @@ def cs():
     return cosched
 
 
-def _scan(cs, pol, d_np, R, window_limit, write_all=1):
+def _scan(cs, pol, d_np, R, window_limit, write_all=1, ws=False):
+    """ws: run in a workspace of the caller's (always k_round) instead of the
+    library's own (where FIFO scans take the split round)."""
     d = torch.from_numpy(np.ascontiguousarray(d_np, dtype=np.int64)).to(DEV)
     dec = torch.full((max(d_np.size, 1),), 7, dtype=torch.uint8, device=DEV)[: d_np.size]
-    rc, r = cs.sched_scan(pol, d, R, dec, write_all=write_all, window_limit=window_limit)
+    w, wb = None, 0
+    if ws:
+        wb = cs.sched_scan_workspace_size(d_np.size)
+        w = torch.empty(wb, dtype=torch.uint8, device=DEV)
+    rc, r = cs.sched_scan(pol, d, R, dec, write_all=write_all, window_limit=window_limit,
+                          d_ws=w, ws_bytes=wb)
     assert rc == 0
     return dec.cpu().numpy(), r
 
 
-def _check(cs, pol, d_np, R, wl):
-    dec, r = _scan(cs, pol, d_np, R, wl)
+def _check(cs, pol, d_np, R, wl, ws=False):
+    dec, r = _scan(cs, pol, d_np, R, wl, ws=ws)
     ref, R2 = (S.fifo_pass if pol == cs.SCHED_POLICY_FIFO else S.mmu_pass)(d_np, R)
     print(f"  pol={pol} n={d_np.size} R={R} wl={wl} admitted={int(ref.sum())}", flush=True)
     assert set(np.unique(dec)) <= {0, 1}
@@ -104,7 +111,9 @@ def test_scan_lookback_computes_missing_sums(cs, pol):
     """With no polling at all, a look-back that meets a predecessor tile which
     has not published its sum yet computes that sum from the tile's demands
     itself.  Decisions stay equal to the oracle's (1 to 80 tiles, grid rounds
-    from the start, breaks in many tiles)."""
+    from the start, breaks in many tiles).  Each case runs in the caller's
+    workspace (k_round, whatever the policy) and in the library's (a FIFO
+    scan there takes the split round)."""
     assert cs.sched_set_lookback_polls(-1) == cs.SCHED_E_INVALID
     assert cs.sched_set_lookback_polls(0) == 0
     try:
@@ -113,6 +122,7 @@ def test_scan_lookback_computes_missing_sums(cs, pol):
             d = random_queue(int(rng.integers(1 << 30)), n, 1000, holes=0.05)
             tot = int(d[d >= 0].sum())
             for R in sorted({999, tot // 3, max(tot - 1, 0), tot + 5}):
+                _check(cs, pol, d, R, 0, ws=True)
                 _check(cs, pol, d, R, 0)
     finally:
         assert cs.sched_set_lookback_polls(256) == 0      # the library default
