@@ -344,10 +344,13 @@ size_t sched_scan_workspace_size(int64_t n);
  * allocates nothing; it clears the part it uses on the stream first, so the
  * memory may hold anything; calls sharing one workspace must not overlap), or
  * NULL to use a workspace the library allocates and keeps for the device.
- * The pass runs entirely in the grid-wide round kernel (decoupled
- * look-back scan); single-workgroup windows are used first when
- * window_limit > 0 (at most 2 under FIFO, whose first break ends the pass,
- * so that a long admitted prefix goes to the grid at streaming rate).
+ * The pass runs in grid-wide rounds: a decoupled look-back scan, or, for a
+ * FIFO scan in the library's own workspace (d_ws NULL), one round in three
+ * launches (tile sums and candidate bits, the break found by one workgroup,
+ * the decisions written from the bits); results are the same either way.
+ * Single-workgroup windows are used first when window_limit > 0 (at most 2
+ * under FIFO, whose first break ends the pass, so that a long admitted
+ * prefix goes to the grid at streaming rate).
  * Synchronises the stream; *out is a host pointer.
  * Errors: SCHED_E_INVALID for bad sizes, policy or R. */
 int sched_scan(int32_t policy, int64_t n, const int64_t *d_demand, int64_t R, uint8_t *d_decision,
